@@ -1,0 +1,325 @@
+"""Finite-element layer of the oracle (TEST INFRASTRUCTURE, plain FP64).
+
+Follows the paper's FE discretization section: C^0 Lagrange basis of degree p
+on Gauss-Lobatto-Legendre (GLL) nodes, tensor product n_p^3 = (p+1)^3 per
+hexahedral cell; cell integrals by Gauss-Legendre quadrature with the affine
+Jacobian (eq. "Quadrature Integration"); cell Hamiltonian and overlap entries
+(eq. "FEM Ham entries" without the GGA term, eq. "FEM S_loc entries");
+GLL-lumped diagonal mass M_D used inside the approximate inverse overlap
+(approximation (i) after eq. "Delta Sinv").
+
+Everything is computed from its definition: basis values by the Lagrange
+product formula, element matrices by summing over all 3-D quadrature points
+(no sum factorization), global matrices by scipy.sparse assembly.
+
+Conventions (not fixed by the paper; chosen for this build):
+  cell e = i + nx*(j + ny*k), origin (i*hx, j*hy, k*hz)
+  local node l = a + np*(b + np*c), (a, b, c) in [0, p]^3, a along x
+  periodic DOF I = gx + Gx*(gy + Gy*gz), gx = (i*p + a) mod (nx*p)
+  quadrature point q = qx + nq*(qy + nq*qz)
+  1-D colour col(i, n) = 2 if (n odd and i == n-1) else i mod 2;
+  cell colour = col_x + cx*(col_y + cy*col_z), c_d = 2 (n_d even) or 3
+"""
+
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+from numpy.polynomial import legendre as npleg
+
+
+# ---------------------------------------------------------------------------
+# Reference element (FE discretization section: GLL nodal points)
+# ---------------------------------------------------------------------------
+
+def gll_nodes_weights(p):
+    """GLL nodes and weights on [-1, 1] for degree p (p+1 points).
+
+    Nodes: -1, the roots of P_p'(x), +1.  Weights 2 / (p (p+1) P_p(x_a)^2).
+    """
+    Pp = npleg.Legendre.basis(p)
+    inner = np.sort(np.real(Pp.deriv().roots())) if p > 1 else np.zeros(0)
+    x = np.concatenate([[-1.0], inner, [1.0]])
+    w = 2.0 / (p * (p + 1) * Pp(x) ** 2)
+    return x, w
+
+
+def gauss_nodes_weights(n):
+    """n-point Gauss-Legendre rule on [-1, 1] (eq. Quadrature Integration)."""
+    x, w = npleg.leggauss(n)
+    return x, w
+
+
+def lagrange_values(nodes, x):
+    """L[q, a] = l_a(x_q), the Lagrange polynomial through ``nodes``, by the product formula."""
+    nodes = np.asarray(nodes, dtype=np.float64)
+    x = np.atleast_1d(np.asarray(x, dtype=np.float64))
+    n = len(nodes)
+    L = np.ones((len(x), n))
+    for a in range(n):
+        for j in range(n):
+            if j != a:
+                L[:, a] *= (x - nodes[j]) / (nodes[a] - nodes[j])
+    return L
+
+
+def lagrange_derivs(nodes, x):
+    """D[q, a] = l_a'(x_q): derivative of the product formula by the product rule."""
+    nodes = np.asarray(nodes, dtype=np.float64)
+    x = np.atleast_1d(np.asarray(x, dtype=np.float64))
+    n = len(nodes)
+    D = np.zeros((len(x), n))
+    for a in range(n):
+        for m in range(n):
+            if m == a:
+                continue
+            term = np.full(len(x), 1.0 / (nodes[a] - nodes[m]))
+            for j in range(n):
+                if j != a and j != m:
+                    term *= (x - nodes[j]) / (nodes[a] - nodes[j])
+            D[:, a] += term
+    return D
+
+
+# ---------------------------------------------------------------------------
+# Mesh, DOF map and colouring
+# ---------------------------------------------------------------------------
+
+class Mesh:
+    """Uniform periodic orthorhombic hexahedral mesh with degree-p spectral elements."""
+
+    def __init__(self, ncell, box, degree):
+        self.ncell = tuple(int(n) for n in ncell)
+        if min(self.ncell) < 2:
+            raise ValueError("each direction needs at least 2 cells (periodic)")
+        self.box = np.asarray(box, dtype=np.float64)
+        self.p = int(degree)
+        self.np1 = self.p + 1
+        self.h = self.box / np.asarray(self.ncell)
+        self.E = int(np.prod(self.ncell))
+        self.G = tuple(n * self.p for n in self.ncell)
+        self.M = int(np.prod(self.G))
+        self.xi, self.rho = gll_nodes_weights(self.p)
+
+    def cell_ijk(self, e):
+        nx, ny, _ = self.ncell
+        return e % nx, (e // nx) % ny, e // (nx * ny)
+
+    def local_abc(self):
+        n = self.np1
+        l = np.arange(n ** 3)
+        return l % n, (l // n) % n, l // (n * n)
+
+    def cell_dofs(self):
+        """cell_dofs[e, l] (int32) per the periodic lexicographic rule."""
+        nx, ny, nz = self.ncell
+        Gx, Gy, Gz = self.G
+        p = self.p
+        a, b, c = self.local_abc()
+        out = np.empty((self.E, self.np1 ** 3), dtype=np.int64)
+        for e in range(self.E):
+            i, j, k = self.cell_ijk(e)
+            gx = (i * p + a) % Gx
+            gy = (j * p + b) % Gy
+            gz = (k * p + c) % Gz
+            out[e] = gx + Gx * (gy + Gy * gz)
+        return out.astype(np.int32)
+
+    def node_coords(self):
+        """Physical coordinates (E, n_p^3, 3) of every cell-local node (unwrapped)."""
+        a, b, c = self.local_abc()
+        out = np.empty((self.E, self.np1 ** 3, 3))
+        for e in range(self.E):
+            i, j, k = self.cell_ijk(e)
+            out[e, :, 0] = (i + 0.5 * (self.xi[a] + 1.0)) * self.h[0]
+            out[e, :, 1] = (j + 0.5 * (self.xi[b] + 1.0)) * self.h[1]
+            out[e, :, 2] = (k + 0.5 * (self.xi[c] + 1.0)) * self.h[2]
+        return out
+
+    @staticmethod
+    def _colour1d(i, n):
+        return 2 if (n % 2 == 1 and i == n - 1) else i % 2
+
+    def cell_colour(self):
+        nx, ny, nz = self.ncell
+        cx = 2 if nx % 2 == 0 else 3
+        cy = 2 if ny % 2 == 0 else 3
+        out = np.empty(self.E, dtype=np.int32)
+        for e in range(self.E):
+            i, j, k = self.cell_ijk(e)
+            out[e] = (self._colour1d(i, nx) + cx * (self._colour1d(j, ny)
+                      + cy * self._colour1d(k, nz)))
+        return out
+
+    def ncolours(self):
+        return int(np.prod([2 if n % 2 == 0 else 3 for n in self.ncell]))
+
+    def scatter_matrix(self):
+        """P^T as a sparse (M, E*n_p^3) 0/1 matrix: global = P^T @ cellwise."""
+        cd = self.cell_dofs().ravel().astype(np.int64)
+        n = cd.size
+        return sp.csr_matrix((np.ones(n), (cd, np.arange(n))), shape=(self.M, n))
+
+
+# ---------------------------------------------------------------------------
+# Quadrature data of one (affine, axis-aligned) cell
+# ---------------------------------------------------------------------------
+
+class CellQuadrature:
+    """Basis values and gradients at the n_q^3 Gauss points of a cell of size h.
+
+    N[q, l] = l_a(eta_qx) l_b(eta_qy) l_c(eta_qz);
+    dN[d, q, l] = physical derivative along d (J^{-1} = diag(2/h));
+    W[q] = w_qx w_qy w_qz det J, det J = hx hy hz / 8.
+    """
+
+    def __init__(self, mesh: Mesh, nq):
+        self.nq = int(nq)
+        eta, w = gauss_nodes_weights(self.nq)
+        self.eta, self.w = eta, w
+        L = lagrange_values(mesh.xi, eta)     # (nq, np)
+        dL = lagrange_derivs(mesh.xi, eta)
+        a, b, c = mesh.local_abc()
+        q = np.arange(self.nq ** 3)
+        qx, qy, qz = q % self.nq, (q // self.nq) % self.nq, q // (self.nq * self.nq)
+        h = mesh.h
+        nloc = mesh.np1 ** 3
+        N = np.empty((len(q), nloc))
+        dN = np.empty((3, len(q), nloc))
+        for l in range(nloc):
+            lx, ly, lz = L[qx, a[l]], L[qy, b[l]], L[qz, c[l]]
+            N[:, l] = lx * ly * lz
+            dN[0, :, l] = (2.0 / h[0]) * dL[qx, a[l]] * ly * lz
+            dN[1, :, l] = (2.0 / h[1]) * lx * dL[qy, b[l]] * lz
+            dN[2, :, l] = (2.0 / h[2]) * lx * ly * dL[qz, c[l]]
+        self.N, self.dN = N, dN
+        self.detJ = float(h[0] * h[1] * h[2] / 8.0)
+        self.W = w[qx] * w[qy] * w[qz] * self.detJ
+        self.qoff = np.stack([(eta[qx] + 1.0) * 0.5 * h[0],
+                              (eta[qy] + 1.0) * 0.5 * h[1],
+                              (eta[qz] + 1.0) * 0.5 * h[2]], axis=1)
+
+    def points(self, mesh: Mesh, e):
+        i, j, k = mesh.cell_ijk(e)
+        return self.qoff + np.array([i * mesh.h[0], j * mesh.h[1], k * mesh.h[2]])
+
+    def all_points(self, mesh: Mesh):
+        return np.stack([self.points(mesh, e) for e in range(mesh.E)])
+
+
+# ---------------------------------------------------------------------------
+# Element matrices (eq. FEM Ham entries / FEM S_loc entries)
+# ---------------------------------------------------------------------------
+
+def element_kinetic(cq: CellQuadrature):
+    """K^e_IJ = 1/2 sum_q W_q grad N_I . grad N_J."""
+    K = np.zeros((cq.N.shape[1],) * 2)
+    for d in range(3):
+        K += cq.dN[d].T @ (cq.W[:, None] * cq.dN[d])
+    return 0.5 * K
+
+
+def element_mass(cq: CellQuadrature):
+    """M^e_IJ = sum_q W_q N_I N_J (consistent mass, Gauss rule)."""
+    return cq.N.T @ (cq.W[:, None] * cq.N)
+
+
+def element_potential(cq: CellQuadrature, vq_e):
+    """V^e_IJ = sum_q W_q V(x_q) N_I N_J."""
+    return cq.N.T @ ((cq.W * vq_e)[:, None] * cq.N)
+
+
+def element_kterm(cq: CellQuadrature, k):
+    """1/2 |k|^2 M^e_IJ - i sum_q W_q N_I (k . grad N_J)  (complex, eq. hij)."""
+    k = np.asarray(k, dtype=np.float64)
+    G = sum(k[d] * (cq.N.T @ (cq.W[:, None] * cq.dN[d])) for d in range(3))
+    return 0.5 * float(k @ k) * element_mass(cq) - 1j * G
+
+
+def lumped_mass(mesh: Mesh):
+    """M_D[I] = sum_{e containing I} det J rho_a rho_b rho_c (GLL quadrature mass)."""
+    a, b, c = mesh.local_abc()
+    detJ = float(np.prod(mesh.h) / 8.0)
+    loc = detJ * mesh.rho[a] * mesh.rho[b] * mesh.rho[c]
+    md = np.zeros(mesh.M)
+    cd = mesh.cell_dofs()
+    for e in range(mesh.E):
+        np.add.at(md, cd[e], loc)
+    return md
+
+
+# ---------------------------------------------------------------------------
+# Local operators
+# ---------------------------------------------------------------------------
+
+class LocalOperator:
+    """H_loc = sum_e P_e^T (K^e + V^e [+ k terms]) P_e and M = sum_e P_e^T M^e P_e.
+
+    Applies are element-batched dense products (no sum factorization); small
+    meshes can also be assembled as scipy.sparse matrices.
+    """
+
+    def __init__(self, mesh: Mesh, nq, veff_q, kpoint=None):
+        self.mesh = mesh
+        self.cq = CellQuadrature(mesh, nq)
+        self.veff_q = np.asarray(veff_q, dtype=np.float64).reshape(mesh.E, -1)
+        assert self.veff_q.shape[1] == self.cq.nq ** 3
+        self.k = None if kpoint is None or not np.any(kpoint) else np.asarray(kpoint, float)
+        self.Ke = element_kinetic(self.cq)
+        self.Me = element_mass(self.cq)
+        self.KTe = None if self.k is None else element_kterm(self.cq, self.k)
+        self.cell_dofs = mesh.cell_dofs()
+        self.PT = mesh.scatter_matrix()
+
+    # -- cellwise pieces -----------------------------------------------------
+    def _gather(self, X):
+        return X[self.cell_dofs]                      # (E, nloc, ncol)
+
+    def _scatter(self, Ye):
+        E, nloc, ncol = Ye.shape
+        return self.PT @ Ye.reshape(E * nloc, ncol)
+
+    def apply_H(self, X):
+        X2 = X if X.ndim == 2 else X[:, None]
+        Xe = self._gather(X2)
+        Ye = self.Ke @ Xe                              # (E, nloc, ncol)
+        if self.KTe is not None:
+            Ye = Ye + self.KTe @ Xe
+        Uq = self.cq.N @ Xe                            # values at quadrature points
+        Uq = Uq * (self.cq.W[None, :] * self.veff_q)[:, :, None]
+        Ye = Ye + self.cq.N.T @ Uq
+        Y = self._scatter(Ye)
+        return Y if X.ndim == 2 else Y[:, 0]
+
+    def apply_M(self, X):
+        X2 = X if X.ndim == 2 else X[:, None]
+        Ye = self.Me @ self._gather(X2)
+        Y = self._scatter(Ye)
+        return Y if X.ndim == 2 else Y[:, 0]
+
+    # -- assembled (small meshes) ---------------------------------------------
+    def _assemble(self, elem):
+        rows, cols, vals = [], [], []
+        nloc = self.cell_dofs.shape[1]
+        for e in range(self.mesh.E):
+            A = elem(e)
+            cd = self.cell_dofs[e]
+            rows.append(np.repeat(cd, nloc))
+            cols.append(np.tile(cd, nloc))
+            vals.append(A.ravel())
+        dtype = np.complex128 if any(np.iscomplexobj(v) for v in vals) else np.float64
+        return sp.csr_matrix((np.concatenate(vals).astype(dtype),
+                              (np.concatenate(rows), np.concatenate(cols))),
+                             shape=(self.mesh.M, self.mesh.M))
+
+    def assemble_H(self):
+        def elem(e):
+            A = self.Ke + element_potential(self.cq, self.veff_q[e])
+            return A if self.KTe is None else A + self.KTe
+        return self._assemble(elem)
+
+    def assemble_K(self):
+        return self._assemble(lambda e: self.Ke)
+
+    def assemble_M(self):
+        return self._assemble(lambda e: self.Me)
