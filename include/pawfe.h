@@ -1,0 +1,231 @@
+/*
+ * pawfe.h -- C ABI of the MI355X PAW-FE residual-based Chebyshev filter.
+ *
+ * The library evaluates, on one AMD Instinct MI355X (gfx950), the hot path
+ * of the finite-element PAW eigensolver: the FE-discretized PAW operators
+ * H, S and the approximate inverse overlap Sinv_hat, the residual-based
+ * Chebyshev filtered subspace (Algorithm 2, "R-ChFSI"), the Rayleigh-Ritz
+ * step that consumes it (Algorithm 1, steps 4-6), the residual norms of the
+ * eigen-residual check, and the gradient of the band energy with respect
+ * to the effective potential and the PAW coupling Delta_H.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Mesh      periodic orthorhombic box [0,Lx)x[0,Ly)x[0,Lz), nx*ny*nz
+ *           uniform hexahedral cells, C0 Lagrange elements of degree p on
+ *           Gauss-Lobatto-Legendre nodes (FE discretization section).
+ *           cell e = i + nx*(j + ny*k); local node l = a + np*(b + np*c),
+ *           np = p+1, a along x; periodic DOF I = gx + Gx*(gy + Gy*gz),
+ *           gx = (i*p + a) mod (nx*p), Gx = nx*p.  ndof M = nx*ny*nz*p^3.
+ * Quadrature  nq Gauss-Legendre points per direction in every cell
+ *           (eq. "Quadrature Integration"); q = qx + nq*(qy + nq*qz).
+ * Multivectors  X[I*ld + n] for DOF I and column n (row-major, node-major,
+ *           columns contiguous), ld >= number of columns.  FP64 unless the
+ *           entry point says otherwise.  All multivectors are DEVICE memory
+ *           owned by the caller.
+ * Streams   every entry point enqueues its device work on the given
+ *           hipStream_t (passed as void*; NULL = the null stream) and
+ *           returns without synchronizing unless its comment says it does.
+ * Errors    argument errors are returned before anything is enqueued; a
+ *           HIP error returns PAWFE_EHIP.  No C++ exception crosses the
+ *           ABI.  pawfe_last_error() gives a message for the calling thread.
+ *           On a non-OK status the contents of output buffers are
+ *           unspecified.
+ * Ownership the caller owns every buffer it passes; the library owns only
+ *           the operator's tables (allocated by pawfe_build_operator, freed
+ *           by pawfe_destroy_operator) and a per-operator scratch area for
+ *           the stand-alone applies.  Calls on one operator must not run
+ *           concurrently (they share that scratch).
+ */
+#ifndef PAWFE_H
+#define PAWFE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pawfe_op pawfe_op;
+
+typedef int32_t pawfe_status;
+enum {
+  PAWFE_OK = 0,
+  PAWFE_EINVAL = 1,        /* bad argument (message in pawfe_last_error) */
+  PAWFE_ENOMEM = 2,        /* device or host allocation failed */
+  PAWFE_EHIP = 3,          /* a HIP runtime call failed */
+  PAWFE_ENOTSPD = 4,       /* I + G Delta_S singular, or S^p not positive definite */
+  PAWFE_ENONFINITE = 5,    /* NaN / Inf met where a finite value is required */
+  PAWFE_EUNSUPPORTED = 6   /* valid request this build does not implement */
+};
+
+/* Arithmetic of the filter's recurrence part (mixed-precision paragraph of
+ * the subspace-construction section).  PAWFE_FP64: everything FP64.
+ * PAWFE_FP32: the residual recurrence R and the operator applies inside the
+ * loop in FP32 with R stored in FP32, the Y*Lambda correction added in FP64
+ * (Y kept in FP64), the final Sinv_hat R in FP32 promoted before + X Lambda. */
+enum { PAWFE_FP64 = 0, PAWFE_FP32 = 1, PAWFE_BF16X3 = 2 };
+
+/* How G^a inside Delta_Sinv^a = (Delta_S^{a,-1} + G^a)^{-1} is formed
+ * (eq. "Delta Sinv" and the cheaper variant after it):
+ * EXACT_G: G^a = C^a^H M_D^{-1} C^a;  PP: G^a = <p_alpha | p_beta>. */
+enum { PAWFE_SINV_EXACT_G = 0, PAWFE_SINV_PP = 1 };
+
+/* Operator description.  All arrays are HOST memory, read during
+ * pawfe_build_operator only.
+ *
+ * veff_q     [E][nq^3] effective potential (Ha) at the Gauss points
+ *            (V_el + V_xc + V_z of eq. "FEM Ham entries").
+ * pos        [natoms][3] atom positions (bohr), any real values (wrapped).
+ * rcut       [natoms] augmentation radius r_c; needs r_c < min(L)/2.
+ * nproj      [natoms] projectors per atom (1..32).
+ * proj_l/proj_m/proj_sigma  per projector, atom after atom: channel
+ *            p(d) = S_lm(d) exp(-|d|^2/(2 sigma^2)) (1 - |d|^2/r_c^2)^2 for
+ *            |d| < r_c, else 0; S_lm the unnormalized real solid harmonics
+ *            l=0: 1; l=1, m=-1,0,1: y, z, x; l=2, m=-2..2: xy, yz,
+ *            3z^2-r^2, xz, x^2-y^2.
+ * dH, dS     Delta_H^a and Delta_S^a (eq. "FE nonlocal contribution"),
+ *            nproj[a]^2 row-major blocks, atom after atom.
+ * kpoint     Cartesian Bloch vector (bohr^-1); must be 0 unless is_complex.
+ * is_complex 1 for the complex (k-point) operator.  Not implemented in this
+ *            build: returns PAWFE_EUNSUPPORTED.
+ * Supported (degree, nq): (2,4) (3,5) (4,6) (5,7) (6,8); each n_d >= 2. */
+typedef struct {
+  int32_t ncell[3];
+  double box[3];
+  int32_t degree;
+  int32_t nq1d;
+  double kpoint[3];
+  int32_t is_complex;
+  const double* veff_q;
+  int32_t natoms;
+  const double* pos;
+  const double* rcut;
+  const int32_t* nproj;
+  const int32_t* proj_l;
+  const int32_t* proj_m;
+  const double* proj_sigma;
+  const double* dH;
+  const double* dS;
+  int32_t sinv_mode;
+} pawfe_op_desc;
+
+/* Builds the operator (FE discretization section; eq. "FEM Cmatrix" for the
+ * projector matrices C^a; eqs. "Sinvapprox"/"Delta Sinv" for Sinv_hat):
+ * DOF map, cell colouring, GLL/Gauss 1-D tables, V(q) W_q, per-atom
+ * support (cells with a Gauss point strictly inside r_c of the minimum
+ * image of the atom), C^a on the support nodes, lumped GLL mass M_D, the
+ * block-sparse G^{ab} = C^a^H M_D^{-1} C^b for atoms sharing support nodes,
+ * and Delta_Sinv^a = Delta_S^a (I + G^a Delta_S^a)^{-1}.  Host work, then
+ * upload on `stream`; synchronizes the stream before returning.
+ * *out receives the new operator (NULL on failure). */
+pawfe_status pawfe_build_operator(const pawfe_op_desc* desc, void* stream, pawfe_op** out);
+
+/* Frees the operator's device tables.  NULL is accepted. */
+pawfe_status pawfe_destroy_operator(pawfe_op* op);
+
+/* Sizes: ndof M, quadrature points E*nq^3, number of cell colours, total
+ * projectors sum_a nproj[a], total support cells and support nodes summed
+ * over atoms (sizes for pawfe_get_dofmap).  Any pointer may be NULL. */
+pawfe_status pawfe_query(const pawfe_op* op, int64_t* ndof, int64_t* nquad, int32_t* ncolour,
+                         int32_t* nproj_total, int64_t* nsupp_cells, int64_t* nsupp_nodes);
+
+/* Copies the builder's integer outputs to HOST arrays (any may be NULL):
+ * cell_dofs [E][np^3], cell_colour [E], supp_cell_off [natoms+1] and
+ * supp_cells (sorted per atom), supp_node_off [natoms+1] and supp_nodes
+ * (sorted unique DOFs of the support cells, per atom). */
+pawfe_status pawfe_get_dofmap(const pawfe_op* op, int32_t* cell_dofs, int32_t* cell_colour,
+                              int64_t* supp_cell_off, int64_t* supp_cells,
+                              int64_t* supp_node_off, int64_t* supp_nodes);
+
+/* Replaces V(q) (HOST array [E][nq^3]) / Delta_H (HOST, packed like desc.dH).
+ * Enqueued on `stream`, synchronizes it.  Delta_Sinv does not depend on
+ * either, so nothing else is rebuilt. */
+pawfe_status pawfe_set_veff(pawfe_op* op, const double* veff_q, void* stream);
+pawfe_status pawfe_set_dH(pawfe_op* op, const double* dH, void* stream);
+
+/* Y = A X for nvec columns (FE discretization section; cell-matrix AX
+ * product of the operator-action subsection):
+ *   apply_H:    H X = H_loc X + sum_a C^a Delta_H^a C^a^H X
+ *   apply_S:    S X = M X + sum_a C^a Delta_S^a C^a^H X   (consistent M)
+ *   apply_Sinv: Sinv_hat X = M_D^{-1} X - sum_a M_D^{-1} C^a Delta_Sinv^a
+ *               C^a^H M_D^{-1} X
+ * X, Y device, [ndof][ld]; FP64 (prec = PAWFE_FP64) or FP32 (PAWFE_FP32).
+ * X and Y must not overlap. */
+pawfe_status pawfe_apply_H(const pawfe_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy,
+                           int64_t nvec, int32_t prec, void* stream);
+pawfe_status pawfe_apply_S(const pawfe_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy,
+                           int64_t nvec, int32_t prec, void* stream);
+pawfe_status pawfe_apply_Sinv(const pawfe_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy,
+                              int64_t nvec, int32_t prec, void* stream);
+
+/* Local (cell) part only:  Y += alpha * A_loc X, A_loc = K + V (which = 0)
+ * or the consistent mass M (which = 1): the cell-level step of the
+ * operator-action subsection (extraction, per-cell contraction, assembly),
+ * without the non-local PAW term.  One launch per cell colour.  Used to
+ * time the dominant kernel in isolation.  Same layouts as pawfe_apply_H. */
+pawfe_status pawfe_apply_local(const pawfe_op* op, int32_t which, const void* X, int64_t ldx, void* Y,
+                               int64_t ldy, int64_t nvec, double alpha, int32_t prec, void* stream);
+
+/* Bytes of workspace pawfe_cheb_filter needs for blocks of `block` columns. */
+pawfe_status pawfe_cheb_filter_workspace(const pawfe_op* op, int64_t nvec, int32_t block,
+                                         int32_t prec, size_t* bytes);
+
+/* Algorithm 2 (residual-based Chebyshev filtered subspace), applied to the
+ * nvec columns in uncoupled blocks of `block` columns with one polynomial:
+ * e = (bU-bW)/2, c = (bU+bW)/2, zeta_1 = e/(b0-c); Y = H X - S X Lambda;
+ * R_Y = (zeta_1/e) Y; for theta = 2..degree the recurrence
+ * R_X <- a H Sinv_hat R_Y - a c R_Y - zeta zeta' R_X + a Y Lambda_Y with
+ * zeta' = 1/(2/zeta_1 - zeta), a = 2 zeta'/e, and the same recurrence on
+ * the diagonal Lambda; output Xout = Sinv_hat R_Y + X Lambda_Y.
+ * Xin, Xout: device FP64 [ndof][ld]; Xout may equal Xin (in place).
+ * lambda_in: device FP64 [nvec] (estimates of the eigenvalues).
+ * Requires b0 < bW < bU, degree >= 2, 1 <= block.  ws: device workspace of
+ * at least pawfe_cheb_filter_workspace bytes, 256-byte aligned. */
+pawfe_status pawfe_cheb_filter(const pawfe_op* op, const void* Xin, int64_t ldx, void* Xout,
+                               int64_t ldo, int64_t nvec, int32_t block, const double* lambda_in,
+                               int32_t degree, double b0, double bW, double bU, int32_t prec,
+                               void* ws, size_t ws_bytes, void* stream);
+
+/* Bytes of workspace pawfe_rayleigh_ritz needs. */
+pawfe_status pawfe_rayleigh_ritz_workspace(const pawfe_op* op, int64_t nvec, size_t* bytes);
+
+/* Rayleigh-Ritz (Algorithm 1 steps 4-6), FP64 throughout:
+ * H^p = X^H H X, S^p = X^H S X (lower triangles, then Hermitized), the
+ * projected generalized eigenproblem H^p Q = S^p Q Lambda, the rotation
+ * X <- X Q (in place), and resnorm[i] = ||H x_i - lambda_i S x_i||_2 (the
+ * eigen-residual check).  X device FP64 [ndof][ldx]; lambda (ascending)
+ * and resnorm: device FP64 [nvec].  Returns PAWFE_ENOTSPD if S^p is not
+ * positive definite. Synchronizes the stream (it reads the solver status). */
+pawfe_status pawfe_rayleigh_ritz(const pawfe_op* op, void* X, int64_t ldx, int64_t nvec,
+                                 double* lambda, double* resnorm, void* ws, size_t ws_bytes,
+                                 void* stream);
+
+/* Band energy E = sum_n occ_n x_n^H H x_n and its gradient (the density and
+ * projector contractions of the FE governing equations):
+ *   dE_dVq[e][q] = W_{e,q} sum_n occ_n |u_n(x_{e,q})|^2, u_n the FE field;
+ *   dE_dDH       = per atom sum_n occ_n conj(P_n) P_n^T, P_n = C^a^H x_n,
+ *                  packed like desc.dH (full-matrix gradient).
+ * X device FP64; occ device FP64 [nvec] or NULL (all ones); E device FP64
+ * scalar; dE_dVq device [E*nq^3]; dE_dDH device [sum nproj^2].  Any output
+ * may be NULL.  Nothing cell-local is stored between cell batches. */
+pawfe_status pawfe_band_energy_grad(const pawfe_op* op, const void* X, int64_t ldx, int64_t nvec,
+                                    const double* occ, double* E, double* dE_dVq, double* dE_dDH,
+                                    void* stream);
+
+/* k-step Lanczos on H Sinv_hat in the Sinv_hat inner product (bound
+ * estimate of Algorithm 1 step 1), seeded start vector.  HOST outputs:
+ * smallest and largest Ritz value and |beta_k|; an upper bound of the
+ * spectrum is theta_max + |beta_k|.  Synchronizes the stream. */
+pawfe_status pawfe_lanczos_bounds(const pawfe_op* op, int32_t k, uint64_t seed, double* theta_min,
+                                  double* theta_max, double* beta_k, void* stream);
+
+/* Message for the last non-OK status on the calling thread ("" if none). */
+const char* pawfe_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PAWFE_H */

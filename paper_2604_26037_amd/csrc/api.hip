@@ -1,0 +1,751 @@
+// C ABI of libpawfe: operator lifetime, applies, the residual-based
+// Chebyshev filter (Algorithm 2), Rayleigh-Ritz (Algorithm 1, steps 4-6),
+// the band-energy gradient and the Lanczos bound estimate.
+
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "kernels.h"
+
+namespace pawfe {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+pawfe_status fail(pawfe_status code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+namespace {
+
+hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+template <typename T>
+pawfe_status up(pawfe_op* op, T** dptr, const T* src, size_t n, hipStream_t s) {
+  const size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return fail(PAWFE_ENOMEM, "hipMalloc failed in operator upload");
+  op->allocations.push_back(p);
+  *dptr = static_cast<T*>(p);
+  if (n) PAWFE_HIP(hipMemcpyAsync(p, src, n * sizeof(T), hipMemcpyHostToDevice, s));
+  return PAWFE_OK;
+}
+
+template <typename T>
+pawfe_status up(pawfe_op* op, T** dptr, const std::vector<T>& v, hipStream_t s) {
+  return up(op, dptr, v.data(), v.size(), s);
+}
+
+std::vector<float> to_f32(const std::vector<double>& v) {
+  return std::vector<float>(v.begin(), v.end());
+}
+
+#define CHECK(x)                            \
+  do {                                      \
+    pawfe_status st_ = (x);                 \
+    if (st_ != PAWFE_OK) return st_;        \
+  } while (0)
+
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+// Bump allocator over a caller workspace.
+struct Carve {
+  char* base;
+  size_t off = 0, cap;
+  Carve(void* p, size_t c) : base((char*)p), cap(c) {}
+  template <typename T>
+  T* take(size_t n) {
+    T* r = (T*)(base + off);
+    off += align256(n * sizeof(T));
+    return r;
+  }
+  bool ok() const { return off <= cap; }
+};
+
+// Scratch of one apply over `ncols` columns: partial sums, c, d/q, t.
+size_t nl_scratch_bytes(const pawfe_op* op, int64_t ncols) {
+  return align256((size_t)op->item_rows_total * ncols * 8) + 3 * align256((size_t)op->npj_total * ncols * 8) + 256;
+}
+
+pawfe_status ensure_scratch(pawfe_op* op, size_t bytes) {
+  if (op->scratch_bytes >= bytes) return PAWFE_OK;
+  if (op->scratch) {
+    PAWFE_HIP(hipDeviceSynchronize());
+    (void)hipFree(op->scratch);
+    op->scratch = nullptr;
+    op->scratch_bytes = 0;
+  }
+  if (hipMalloc(&op->scratch, bytes) != hipSuccess) return fail(PAWFE_ENOMEM, "scratch allocation failed");
+  op->scratch_bytes = bytes;
+  return PAWFE_OK;
+}
+
+struct NlBufs {
+  double *part, *c, *d, *t;
+};
+
+NlBufs carve_nl(const pawfe_op* op, Carve& cv, int64_t ncols) {
+  NlBufs b;
+  b.part = cv.take<double>((size_t)std::max<int64_t>(op->item_rows_total, 1) * ncols);
+  b.c = cv.take<double>((size_t)std::max(op->npj_total, 1) * ncols);
+  b.d = cv.take<double>((size_t)std::max(op->npj_total, 1) * ncols);
+  b.t = cv.take<double>((size_t)std::max(op->npj_total, 1) * ncols);
+  return b;
+}
+
+// ---- building blocks (all enqueue on s) -------------------------------------
+
+template <typename T>
+pawfe_status do_apply(const pawfe_op* op, int which, const T* X, int64_t ldx, T* Y, int64_t ldy, int ncols,
+                      const NlBufs& b, hipStream_t s) {
+  if (which == 0 || which == 1) {   // H or S
+    CHECK(launch_nl_reduce<T>(op, X, ldx, ncols, false, b.part, b.c, s));
+    CHECK(launch_atom_mul(op, which == 0 ? op->d.dH : op->d.dS, nullptr, nullptr, 1.0, b.c, b.d, ncols, s));
+    if (op->natoms)
+      CHECK(launch_node_nl_init<T>(op, b.d, ncols, Y, ldy, s));
+    else
+      CHECK(launch_node_nl_init<T>(op, nullptr, ncols, Y, ldy, s));
+    return launch_cell<T>(op, which == 0 ? kModeH : kModeMass, X, ldx, Y, ldy, ncols, nullptr, 1.0, s);
+  }
+  // Sinv_hat
+  CHECK(launch_nl_reduce<T>(op, X, ldx, ncols, true, b.part, b.c, s));
+  CHECK(launch_atom_mul(op, op->d.dSinv, nullptr, nullptr, 1.0, b.c, b.d, ncols, s));
+  return launch_node_sinv<T>(op, X, ldx, b.d, ncols, Y, ldy, s);
+}
+
+// Y = H X - S X diag(lam), FP64
+pawfe_status do_residual(const pawfe_op* op, const double* X, int64_t ldx, const double* lam, double* Y, int64_t ldy,
+                         int ncols, const NlBufs& b, hipStream_t s) {
+  CHECK(launch_nl_reduce<double>(op, X, ldx, ncols, false, b.part, b.c, s));
+  CHECK(launch_atom_mul(op, op->d.dH, op->d.dS, lam, 1.0, b.c, b.d, ncols, s));
+  CHECK(launch_node_nl_init<double>(op, op->natoms ? b.d : nullptr, ncols, Y, ldy, s));
+  return launch_cell<double>(op, kModeHRes, X, ldx, Y, ldy, ncols, lam, 1.0, s);
+}
+
+pawfe_status check_prec(int32_t prec) {
+  if (prec == PAWFE_FP64 || prec == PAWFE_FP32) return PAWFE_OK;
+  if (prec == PAWFE_BF16X3) return fail(PAWFE_EUNSUPPORTED, "BF16X3 is not implemented for this entry point");
+  return fail(PAWFE_EINVAL, "unknown precision");
+}
+
+pawfe_status apply_entry(const pawfe_op* cop, int which, const void* X, int64_t ldx, void* Y, int64_t ldy,
+                         int64_t nvec, int32_t prec, void* stream) {
+  if (!cop) return fail(PAWFE_EINVAL, "op is NULL");
+  if (nvec < 0) return fail(PAWFE_EINVAL, "nvec < 0");
+  if (nvec == 0) return PAWFE_OK;
+  if (!X || !Y) return fail(PAWFE_EINVAL, "X or Y is NULL");
+  if (ldx < nvec || ldy < nvec) return fail(PAWFE_EINVAL, "leading dimension smaller than nvec");
+  CHECK(check_prec(prec));
+  pawfe_op* op = const_cast<pawfe_op*>(cop);
+  const int64_t chunk = 512;
+  const int64_t cmax = std::min<int64_t>(chunk, nvec);
+  CHECK(ensure_scratch(op, nl_scratch_bytes(op, cmax)));
+  Carve cv(op->scratch, op->scratch_bytes);
+  NlBufs b = carve_nl(op, cv, cmax);
+  hipStream_t s = S(stream);
+  for (int64_t j0 = 0; j0 < nvec; j0 += chunk) {
+    const int nc = (int)std::min<int64_t>(chunk, nvec - j0);
+    if (prec == PAWFE_FP64)
+      CHECK(do_apply<double>(op, which, (const double*)X + j0, ldx, (double*)Y + j0, ldy, nc, b, s));
+    else
+      CHECK(do_apply<float>(op, which, (const float*)X + j0, ldx, (float*)Y + j0, ldy, nc, b, s));
+  }
+  return PAWFE_OK;
+}
+
+// ---- filter ------------------------------------------------------------------
+
+size_t filter_ws_bytes(const pawfe_op* op, int64_t B, int32_t prec) {
+  const size_t tr = prec == PAWFE_FP64 ? 8 : 4;
+  size_t b = align256((size_t)op->M * B * 8);            // Y
+  b += 3 * align256((size_t)op->M * B * tr);            // RX, RY, T
+  b += nl_scratch_bytes(op, B);
+  b += 2 * align256((size_t)B * 8);                      // lamX, lamY
+  return b + 256;
+}
+
+template <typename TR>
+pawfe_status filter_block(const pawfe_op* op, const double* X, int64_t ldx, double* Xo, int64_t ldo, int nc,
+                          int64_t B, const double* lam_in, int m, double b0, double bW, double bU, Carve cv,
+                          hipStream_t s) {
+  double* Y = cv.take<double>((size_t)op->M * B);
+  TR* RX = cv.take<TR>((size_t)op->M * B);
+  TR* RY = cv.take<TR>((size_t)op->M * B);
+  TR* Tb = cv.take<TR>((size_t)op->M * B);
+  NlBufs nb = carve_nl(op, cv, B);
+  double* lamX = cv.take<double>(B);
+  double* lamY = cv.take<double>(B);
+  const int64_t ld = nc;   // block-local leading dimension
+  // step 1 (Algorithm 2): polynomial scalars
+  const double e = (bU - bW) / 2.0, c = (bU + bW) / 2.0;
+  double zeta = e / (b0 - c);
+  const double zeta1 = zeta, gamma = 2.0 / zeta1;
+  // step 2: residual of the input pairs, FP64
+  CHECK(do_residual(op, X, ldx, lam_in, Y, ld, nc, nb, s));
+  // step 3
+  CHECK(launch_cheb_init<TR>(op, Y, ld, RY, RX, ld, zeta1 / e, c, lam_in, lamY, lamX, nc, s));
+  // step 4
+  for (int theta = 2; theta <= m; ++theta) {
+    const double znew = 1.0 / (gamma - zeta);
+    const double a = 2.0 * znew / e;
+    // projector coefficients of Sinv_hat R_Y and of H's non-local term on T
+    CHECK(launch_nl_reduce<TR>(op, RY, ld, nc, true, nb.part, nb.c, s));
+    CHECK(launch_atom_mul(op, op->d.dSinv, nullptr, nullptr, 1.0, nb.c, nb.d, nc, s));
+    CHECK(launch_atom_gcorr(op, nb.c, nb.d, nb.t, nc, s));
+    CHECK(launch_atom_mul(op, op->d.dH, nullptr, nullptr, a, nb.t, nb.c, nc, s));   // q = a Dh t (into c)
+    // T = Sinv_hat R_Y; R_X <- -a c R_Y - zeta zeta' R_X + a C q + a Y Lambda_Y
+    CHECK(launch_node_cheb<TR>(op, RY, RX, Tb, ld, Y, ld, nb.d, nb.c, lamY, lamX, lam_in, a, a * c, zeta * znew,
+                               nc, s));
+    // R_X += a H_loc T
+    CHECK(launch_cell<TR>(op, kModeH, Tb, ld, RX, ld, nc, nullptr, a, s));
+    std::swap(RX, RY);
+    std::swap(lamX, lamY);
+    zeta = znew;
+  }
+  // step 5: Xout = Sinv_hat R_Y + X Lambda_Y
+  CHECK(launch_nl_reduce<TR>(op, RY, ld, nc, true, nb.part, nb.c, s));
+  CHECK(launch_atom_mul(op, op->d.dSinv, nullptr, nullptr, 1.0, nb.c, nb.d, nc, s));
+  return launch_node_finalize<TR>(op, RY, ld, nb.d, X, ldx, lamY, Xo, ldo, nc, s);
+}
+
+// ---- small host helpers -----------------------------------------------------
+
+// eigenvalues of a small symmetric tridiagonal matrix by cyclic Jacobi on the dense form
+std::vector<double> small_sym_eigvals(int n, std::vector<double> A) {
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = i + 1; j < n; ++j) off += A[i * n + j] * A[i * n + j];
+    if (off < 1e-30) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = A[p * n + q];
+        if (std::fabs(apq) < 1e-300) continue;
+        const double th = (A[q * n + q] - A[p * n + p]) / (2.0 * apq);
+        const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+        for (int k = 0; k < n; ++k) {
+          const double akp = A[k * n + p], akq = A[k * n + q];
+          A[k * n + p] = cs * akp - sn * akq;
+          A[k * n + q] = sn * akp + cs * akq;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double apk = A[p * n + k], aqk = A[q * n + k];
+          A[p * n + k] = cs * apk - sn * aqk;
+          A[q * n + k] = sn * apk + cs * aqk;
+        }
+      }
+  }
+  std::vector<double> ev(n);
+  for (int i = 0; i < n; ++i) ev[i] = A[i * n + i];
+  std::sort(ev.begin(), ev.end());
+  return ev;
+}
+
+__global__ void k_lincomb(int64_t n, double* __restrict__ y, double a, const double* __restrict__ x, double b,
+                          const double* __restrict__ z, double c) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = a * x[i] + (z ? b * z[i] : 0.0) + (c != 0.0 ? c * y[i] : 0.0);
+}
+
+__global__ void k_symmetrize(int N, double* __restrict__ A) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)N * N) return;
+  const int i = (int)(idx / N), j = (int)(idx % N);
+  if (j <= i) return;
+  const double v = 0.5 * (A[(int64_t)i * N + j] + A[(int64_t)j * N + i]);
+  A[(int64_t)i * N + j] = v;
+  A[(int64_t)j * N + i] = v;
+}
+
+}  // namespace
+
+// ---- upload / free ------------------------------------------------------------
+
+pawfe_status upload_veff(pawfe_op* op, hipStream_t s) {
+  std::vector<double> vw(op->veff.size());
+  for (int e = 0; e < op->E; ++e)
+    for (int q = 0; q < op->nq3; ++q) vw[(size_t)e * op->nq3 + q] = op->veff[(size_t)e * op->nq3 + q] * op->W3[q];
+  std::vector<float> vwf(vw.begin(), vw.end());
+  PAWFE_HIP(hipMemcpyAsync(op->d.Vw, vw.data(), vw.size() * 8, hipMemcpyHostToDevice, s));
+  PAWFE_HIP(hipMemcpyAsync(op->d.Vw_f, vwf.data(), vwf.size() * 4, hipMemcpyHostToDevice, s));
+  PAWFE_HIP(hipStreamSynchronize(s));
+  return PAWFE_OK;
+}
+
+pawfe_status upload(pawfe_op* op, hipStream_t s) {
+  DeviceTables& d = op->d;
+  const size_t nquad = (size_t)op->E * op->nq3;
+  {
+    void* p = nullptr;
+    if (hipMalloc(&p, nquad * 8) != hipSuccess) return fail(PAWFE_ENOMEM, "Vw");
+    op->allocations.push_back(p);
+    d.Vw = (double*)p;
+    if (hipMalloc(&p, nquad * 4) != hipSuccess) return fail(PAWFE_ENOMEM, "Vw_f");
+    op->allocations.push_back(p);
+    d.Vw_f = (float*)p;
+  }
+  {
+    Tab1D<double> t64{};
+    Tab1D<float> t32{};
+    const int np = op->np, nq = op->nq;
+    for (int i = 0; i < nq * np; ++i) t64.B[i] = op->B[i];
+    for (int i = 0; i < np * np; ++i) {
+      t64.K1[i] = op->K1[i];
+      t64.M1[i] = op->M1[i];
+    }
+    for (int k = 0; k < 3; ++k) t64.f[k] = 0.5 * op->detJ * (2.0 / op->h[k]) * (2.0 / op->h[k]);
+    t64.detJ = op->detJ;
+    for (int i = 0; i < kNqMax * kNpMax; ++i) t32.B[i] = (float)t64.B[i];
+    for (int i = 0; i < kNpMax * kNpMax; ++i) {
+      t32.K1[i] = (float)t64.K1[i];
+      t32.M1[i] = (float)t64.M1[i];
+    }
+    for (int k = 0; k < 3; ++k) t32.f[k] = (float)t64.f[k];
+    t32.detJ = (float)t64.detJ;
+    CHECK(up(op, &d.tab64, &t64, 1, s));
+    CHECK(up(op, &d.tab32, &t32, 1, s));
+  }
+  CHECK(up(op, &d.W3, op->W3, s));
+  std::vector<float> w3f = to_f32(op->W3);
+  CHECK(up(op, &d.W3_f, w3f, s));
+  std::vector<double> minv(op->M);
+  for (int64_t i = 0; i < op->M; ++i) minv[i] = 1.0 / op->MD[i];
+  CHECK(up(op, &d.Minv, minv, s));
+  std::vector<float> minvf = to_f32(minv);
+  CHECK(up(op, &d.Minv_f, minvf, s));
+  CHECK(up(op, &d.cells_by_colour, op->cells_by_colour, s));
+  CHECK(up(op, &d.node2srow, op->node2srow, s));
+  CHECK(up(op, &d.srow_ptr, op->srow_ptr, s));
+  CHECK(up(op, &d.srow_atom, op->srow_atom, s));
+  CHECK(up(op, &d.srow_coff, op->srow_coff, s));
+  CHECK(up(op, &d.Cvals, op->Cvals, s));
+  std::vector<float> cf = to_f32(op->Cvals);
+  CHECK(up(op, &d.Cvals_f, cf, s));
+  std::vector<int32_t> an(op->atom_nodes.begin(), op->atom_nodes.end());
+  CHECK(up(op, &d.atom_nodes, an, s));
+  CHECK(up(op, &d.item_atom, op->item_atom, s));
+  CHECK(up(op, &d.item_row0, op->item_row0, s));
+  CHECK(up(op, &d.item_row1, op->item_row1, s));
+  CHECK(up(op, &d.item_poff, op->item_poff, s));
+  CHECK(up(op, &d.item_ptr, op->item_ptr, s));
+  CHECK(up(op, &d.atom_noff, op->atom_noff, s));
+  CHECK(up(op, &d.atom_coff, op->atom_coff, s));
+  CHECK(up(op, &d.nproj, op->nproj, s));
+  CHECK(up(op, &d.poff, op->poff, s));
+  CHECK(up(op, &d.poff2, op->poff2, s));
+  CHECK(up(op, &d.dH, op->dH, s));
+  CHECK(up(op, &d.dS, op->dS, s));
+  CHECK(up(op, &d.dSinv, op->dSinv, s));
+  CHECK(up(op, &d.gp_ptr, op->gp_ptr, s));
+  CHECK(up(op, &d.gp_b, op->gp_b, s));
+  CHECK(up(op, &d.gp_off, op->gp_off, s));
+  CHECK(up(op, &d.Gvals, op->Gvals, s));
+  std::vector<int32_t> pa(op->npj_total), pal(op->npj_total), ga, gs, gt;
+  for (int a = 0; a < op->natoms; ++a)
+    for (int t = 0; t < op->nproj[a]; ++t) {
+      pa[op->poff[a] + t] = a;
+      pal[op->poff[a] + t] = t;
+    }
+  for (int a = 0; a < op->natoms; ++a)
+    for (int i = 0; i < op->nproj[a]; ++i)
+      for (int j = 0; j < op->nproj[a]; ++j) {
+        ga.push_back(a);
+        gs.push_back(i);
+        gt.push_back(j);
+      }
+  CHECK(up(op, &op->d_proj_atom, pa, s));
+  CHECK(up(op, &op->d_proj_alpha, pal, s));
+  CHECK(up(op, &op->d_g2_atom, ga, s));
+  CHECK(up(op, &op->d_g2_s, gs, s));
+  CHECK(up(op, &op->d_g2_t, gt, s));
+  return upload_veff(op, s);
+}
+
+void free_device(pawfe_op* op) {
+  for (void* p : op->allocations) (void)hipFree(p);
+  op->allocations.clear();
+  if (op->scratch) (void)hipFree(op->scratch);
+  op->scratch = nullptr;
+  op->scratch_bytes = 0;
+  if (op->blas) rocblas_destroy_handle((rocblas_handle)op->blas);
+  op->blas = nullptr;
+}
+
+}  // namespace pawfe
+
+using namespace pawfe;
+
+extern "C" {
+
+const char* pawfe_last_error(void) { return g_last_error.c_str(); }
+
+pawfe_status pawfe_build_operator(const pawfe_op_desc* desc, void* stream, pawfe_op** out) {
+  if (!out) return fail(PAWFE_EINVAL, "out is NULL");
+  *out = nullptr;
+  pawfe_op* op = new (std::nothrow) pawfe_op();
+  if (!op) return fail(PAWFE_ENOMEM, "host allocation failed");
+  pawfe_status st;
+  try {
+    st = build_host(desc, op);
+  } catch (const std::bad_alloc&) {
+    st = fail(PAWFE_ENOMEM, "host allocation failed while building");
+  } catch (...) {
+    st = fail(PAWFE_EINVAL, "unexpected error while building");
+  }
+  if (st == PAWFE_OK) st = upload(op, S(stream));
+  if (st == PAWFE_OK) {
+    hipError_t e = hipStreamSynchronize(S(stream));
+    if (e != hipSuccess) st = fail(PAWFE_EHIP, std::string("upload: ") + hipGetErrorString(e));
+  }
+  if (st != PAWFE_OK) {
+    free_device(op);
+    delete op;
+    return st;
+  }
+  *out = op;
+  g_last_error.clear();
+  return PAWFE_OK;
+}
+
+pawfe_status pawfe_destroy_operator(pawfe_op* op) {
+  if (!op) return PAWFE_OK;
+  (void)hipDeviceSynchronize();
+  free_device(op);
+  delete op;
+  return PAWFE_OK;
+}
+
+pawfe_status pawfe_query(const pawfe_op* op, int64_t* ndof, int64_t* nquad, int32_t* ncolour, int32_t* nproj_total,
+                         int64_t* nsupp_cells, int64_t* nsupp_nodes) {
+  if (!op) return fail(PAWFE_EINVAL, "op is NULL");
+  if (ndof) *ndof = op->M;
+  if (nquad) *nquad = (int64_t)op->E * op->nq3;
+  if (ncolour) *ncolour = op->ncolour;
+  if (nproj_total) *nproj_total = op->npj_total;
+  if (nsupp_cells) *nsupp_cells = (int64_t)op->supp_cells.size();
+  if (nsupp_nodes) *nsupp_nodes = (int64_t)op->supp_nodes.size();
+  return PAWFE_OK;
+}
+
+pawfe_status pawfe_get_dofmap(const pawfe_op* op, int32_t* cell_dofs, int32_t* cell_colour, int64_t* supp_cell_off,
+                              int64_t* supp_cells, int64_t* supp_node_off, int64_t* supp_nodes) {
+  if (!op) return fail(PAWFE_EINVAL, "op is NULL");
+  if (cell_dofs) {
+    const int np = op->np, p = op->p;
+    const int Gx = op->n[0] * p, Gy = op->n[1] * p, Gz = op->n[2] * p;
+    for (int e = 0; e < op->E; ++e) {
+      const int i = e % op->n[0], j = (e / op->n[0]) % op->n[1], k = e / (op->n[0] * op->n[1]);
+      for (int l = 0; l < op->nloc; ++l) {
+        const int a = l % np, b = (l / np) % np, c = l / (np * np);
+        const int64_t gx = (i * p + a) % Gx, gy = (j * p + b) % Gy, gz = (k * p + c) % Gz;
+        cell_dofs[(int64_t)e * op->nloc + l] = (int32_t)(gx + (int64_t)Gx * (gy + (int64_t)Gy * gz));
+      }
+    }
+  }
+  if (cell_colour) std::copy(op->cell_colour.begin(), op->cell_colour.end(), cell_colour);
+  if (supp_cell_off) std::copy(op->supp_cell_off.begin(), op->supp_cell_off.end(), supp_cell_off);
+  if (supp_cells) std::copy(op->supp_cells.begin(), op->supp_cells.end(), supp_cells);
+  if (supp_node_off) std::copy(op->supp_node_off.begin(), op->supp_node_off.end(), supp_node_off);
+  if (supp_nodes) std::copy(op->supp_nodes.begin(), op->supp_nodes.end(), supp_nodes);
+  return PAWFE_OK;
+}
+
+pawfe_status pawfe_set_veff(pawfe_op* op, const double* veff_q, void* stream) {
+  if (!op || !veff_q) return fail(PAWFE_EINVAL, "op or veff_q is NULL");
+  const size_t n = (size_t)op->E * op->nq3;
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(veff_q[i])) return fail(PAWFE_ENONFINITE, "veff_q has NaN/Inf");
+  op->veff.assign(veff_q, veff_q + n);
+  return upload_veff(op, S(stream));
+}
+
+pawfe_status pawfe_set_dH(pawfe_op* op, const double* dH, void* stream) {
+  if (!op || (!dH && op->npj2_total)) return fail(PAWFE_EINVAL, "op or dH is NULL");
+  for (int i = 0; i < op->npj2_total; ++i)
+    if (!std::isfinite(dH[i])) return fail(PAWFE_ENONFINITE, "dH has NaN/Inf");
+  op->dH.assign(dH, dH + op->npj2_total);
+  if (op->npj2_total)
+    PAWFE_HIP(hipMemcpyAsync(op->d.dH, op->dH.data(), op->dH.size() * 8, hipMemcpyHostToDevice, S(stream)));
+  PAWFE_HIP(hipStreamSynchronize(S(stream)));
+  return PAWFE_OK;
+}
+
+pawfe_status pawfe_apply_H(const pawfe_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy, int64_t nvec,
+                           int32_t prec, void* stream) {
+  return apply_entry(op, 0, X, ldx, Y, ldy, nvec, prec, stream);
+}
+
+pawfe_status pawfe_apply_S(const pawfe_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy, int64_t nvec,
+                           int32_t prec, void* stream) {
+  return apply_entry(op, 1, X, ldx, Y, ldy, nvec, prec, stream);
+}
+
+pawfe_status pawfe_apply_Sinv(const pawfe_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy, int64_t nvec,
+                              int32_t prec, void* stream) {
+  return apply_entry(op, 2, X, ldx, Y, ldy, nvec, prec, stream);
+}
+
+pawfe_status pawfe_apply_local(const pawfe_op* op, int32_t which, const void* X, int64_t ldx, void* Y,
+                               int64_t ldy, int64_t nvec, double alpha, int32_t prec, void* stream) {
+  if (!op) return fail(PAWFE_EINVAL, "op is NULL");
+  if (which != 0 && which != 1) return fail(PAWFE_EINVAL, "which must be 0 (K + V) or 1 (M)");
+  if (nvec < 0) return fail(PAWFE_EINVAL, "nvec < 0");
+  if (nvec == 0) return PAWFE_OK;
+  if (!X || !Y) return fail(PAWFE_EINVAL, "X or Y is NULL");
+  if (ldx < nvec || ldy < nvec) return fail(PAWFE_EINVAL, "leading dimension smaller than nvec");
+  CHECK(check_prec(prec));
+  const int mode = which == 0 ? kModeH : kModeMass;
+  if (nvec > (int64_t)1 << 30) return fail(PAWFE_EINVAL, "nvec too large");
+  if (prec == PAWFE_FP64)
+    return launch_cell<double>(op, mode, (const double*)X, ldx, (double*)Y, ldy, (int)nvec, nullptr, alpha,
+                               S(stream));
+  return launch_cell<float>(op, mode, (const float*)X, ldx, (float*)Y, ldy, (int)nvec, nullptr, alpha, S(stream));
+}
+
+pawfe_status pawfe_cheb_filter_workspace(const pawfe_op* op, int64_t nvec, int32_t block, int32_t prec,
+                                         size_t* bytes) {
+  if (!op || !bytes) return fail(PAWFE_EINVAL, "op or bytes is NULL");
+  if (nvec < 1 || block < 1) return fail(PAWFE_EINVAL, "nvec and block must be >= 1");
+  CHECK(check_prec(prec));
+  *bytes = filter_ws_bytes(op, std::min<int64_t>(block, nvec), prec);
+  return PAWFE_OK;
+}
+
+pawfe_status pawfe_cheb_filter(const pawfe_op* op, const void* Xin, int64_t ldx, void* Xout, int64_t ldo,
+                               int64_t nvec, int32_t block, const double* lambda_in, int32_t degree, double b0,
+                               double bW, double bU, int32_t prec, void* ws, size_t ws_bytes, void* stream) {
+  if (!op) return fail(PAWFE_EINVAL, "op is NULL");
+  if (!Xin || !Xout || !lambda_in || !ws) return fail(PAWFE_EINVAL, "NULL buffer");
+  if (nvec < 1 || block < 1) return fail(PAWFE_EINVAL, "nvec and block must be >= 1");
+  if (ldx < nvec || ldo < nvec) return fail(PAWFE_EINVAL, "leading dimension smaller than nvec");
+  if (degree < 2) return fail(PAWFE_EINVAL, "Chebyshev degree must be >= 2");
+  if (!(std::isfinite(b0) && std::isfinite(bW) && std::isfinite(bU)))
+    return fail(PAWFE_ENONFINITE, "bounds must be finite");
+  if (!(b0 < bW && bW < bU)) return fail(PAWFE_EINVAL, "bounds must satisfy b0 < bW < bU");
+  CHECK(check_prec(prec));
+  if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(PAWFE_EINVAL, "workspace must be 256-byte aligned");
+  const int64_t B = std::min<int64_t>(block, nvec);
+  if (ws_bytes < filter_ws_bytes(op, B, prec)) return fail(PAWFE_EINVAL, "workspace too small");
+  hipStream_t s = S(stream);
+  for (int64_t j0 = 0; j0 < nvec; j0 += B) {
+    const int nc = (int)std::min<int64_t>(B, nvec - j0);
+    Carve cv(ws, ws_bytes);
+    const double* X = (const double*)Xin + j0;
+    double* Xo = (double*)Xout + j0;
+    if (prec == PAWFE_FP64)
+      CHECK(filter_block<double>(op, X, ldx, Xo, ldo, nc, B, lambda_in + j0, degree, b0, bW, bU, cv, s));
+    else
+      CHECK(filter_block<float>(op, X, ldx, Xo, ldo, nc, B, lambda_in + j0, degree, b0, bW, bU, cv, s));
+  }
+  return PAWFE_OK;
+}
+
+// ---- Rayleigh-Ritz ------------------------------------------------------------
+
+static size_t rr_ws_bytes(const pawfe_op* op, int64_t N) {
+  const int64_t B = std::min<int64_t>(256, N);
+  size_t b = align256((size_t)op->M * B * 8);             // HX block
+  b += align256((size_t)op->M * N * 8);                    // rotated copy
+  b += 2 * align256((size_t)N * N * 8);                    // Hp, Sp
+  b += align256((size_t)64 * N * N * 8);                   // split-K partials
+  b += align256((size_t)N * 8) + 256;                      // E work, info
+  b += align256((size_t)((op->M + 4095) / 4096) * B * 8);  // norm partials
+  b += nl_scratch_bytes(op, B);
+  return b + 256;
+}
+
+pawfe_status pawfe_rayleigh_ritz_workspace(const pawfe_op* op, int64_t nvec, size_t* bytes) {
+  if (!op || !bytes) return fail(PAWFE_EINVAL, "op or bytes is NULL");
+  if (nvec < 1) return fail(PAWFE_EINVAL, "nvec must be >= 1");
+  *bytes = rr_ws_bytes(op, nvec);
+  return PAWFE_OK;
+}
+
+pawfe_status pawfe_rayleigh_ritz(const pawfe_op* cop, void* Xv, int64_t ldx, int64_t N, double* lambda,
+                                 double* resnorm, void* ws, size_t ws_bytes, void* stream) {
+  if (!cop) return fail(PAWFE_EINVAL, "op is NULL");
+  if (!Xv || !lambda || !resnorm || !ws) return fail(PAWFE_EINVAL, "NULL buffer");
+  if (N < 1 || ldx < N) return fail(PAWFE_EINVAL, "bad nvec / ldx");
+  if (N > 65536) return fail(PAWFE_EUNSUPPORTED, "nvec too large for the dense projected problem");
+  if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(PAWFE_EINVAL, "workspace must be 256-byte aligned");
+  if (ws_bytes < rr_ws_bytes(cop, N)) return fail(PAWFE_EINVAL, "workspace too small");
+  pawfe_op* op = const_cast<pawfe_op*>(cop);
+  hipStream_t s = S(stream);
+  double* X = (double*)Xv;
+  const int64_t B = std::min<int64_t>(256, N);
+  Carve cv(ws, ws_bytes);
+  double* HXb = cv.take<double>((size_t)op->M * B);
+  double* Xr = cv.take<double>((size_t)op->M * N);
+  double* Hp = cv.take<double>((size_t)N * N);
+  double* Sp = cv.take<double>((size_t)N * N);
+  const size_t npart = (size_t)64 * N * N;
+  double* part = cv.take<double>(npart);
+  double* Ework = cv.take<double>(N);
+  rocblas_int* info = cv.take<rocblas_int>(1);
+  double* npart_buf = cv.take<double>((size_t)((op->M + 4095) / 4096) * B);
+  NlBufs nb = carve_nl(op, cv, B);
+  // projection: H^p = X^T H X, S^p = X^T S X, block by block
+  for (int which = 0; which < 2; ++which) {
+    double* P = which == 0 ? Hp : Sp;
+    for (int64_t j0 = 0; j0 < N; j0 += B) {
+      const int nc = (int)std::min<int64_t>(B, N - j0);
+      CHECK(do_apply<double>(op, which, X + j0, ldx, HXb, nc, nc, nb, s));
+      CHECK(launch_gemm_tn(X, ldx, HXb, nc, op->M, (int)N, nc, P + j0, (int)N, part, npart, false, s));
+    }
+    hipLaunchKernelGGL(k_symmetrize, dim3((unsigned)((N * N + 255) / 256)), dim3(256), 0, s, (int)N, P);
+  }
+  // projected generalized eigenproblem (dense, FP64)
+  if (!op->blas) {
+    rocblas_handle h;
+    if (rocblas_create_handle(&h) != rocblas_status_success) return fail(PAWFE_EHIP, "rocblas_create_handle failed");
+    op->blas = h;
+  }
+  rocblas_handle h = (rocblas_handle)op->blas;
+  rocblas_set_stream(h, s);
+  rocblas_status rs = rocsolver_dsygvd(h, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_upper, (rocblas_int)N,
+                                       Hp, (rocblas_int)N, Sp, (rocblas_int)N, lambda, Ework, info);
+  if (rs != rocblas_status_success) return fail(PAWFE_EHIP, "rocsolver_dsygvd failed");
+  rocblas_int hinfo = 0;
+  PAWFE_HIP(hipMemcpyAsync(&hinfo, info, sizeof(rocblas_int), hipMemcpyDeviceToHost, s));
+  PAWFE_HIP(hipStreamSynchronize(s));
+  if (hinfo > N) return fail(PAWFE_ENOTSPD, "projected overlap S^p is not positive definite");
+  if (hinfo > 0) return fail(PAWFE_ENONFINITE, "projected eigensolver did not converge");
+  // rotation X <- X Q (Q column-major in Hp)
+  CHECK(launch_gemm_nq(X, ldx, Hp, (int)N, op->M, (int)N, Xr, N, s));
+  CHECK(launch_copy_cols(Xr, N, X, ldx, op->M, (int)N, s));
+  // residual norms ||H x - lambda S x||_2
+  for (int64_t j0 = 0; j0 < N; j0 += B) {
+    const int nc = (int)std::min<int64_t>(B, N - j0);
+    CHECK(do_residual(op, X + j0, ldx, lambda + j0, HXb, nc, nc, nb, s));
+    CHECK(launch_coldot(HXb, nc, HXb, nc, op->M, nc, npart_buf, resnorm + j0, nullptr, true, false, s));
+  }
+  return PAWFE_OK;
+}
+
+// ---- band energy gradient ----------------------------------------------------
+
+pawfe_status pawfe_band_energy_grad(const pawfe_op* cop, const void* Xv, int64_t ldx, int64_t N, const double* occ,
+                                    double* E, double* dE_dVq, double* dE_dDH, void* stream) {
+  if (!cop) return fail(PAWFE_EINVAL, "op is NULL");
+  if (!Xv || N < 1 || ldx < N) return fail(PAWFE_EINVAL, "bad X / nvec / ldx");
+  pawfe_op* op = const_cast<pawfe_op*>(cop);
+  hipStream_t s = S(stream);
+  const double* X = (const double*)Xv;
+  const int64_t B = std::min<int64_t>(256, N);
+  const int64_t nchunks = (op->M + 4095) / 4096;
+  size_t need = nl_scratch_bytes(op, std::max<int64_t>(N, B)) + align256((size_t)op->M * B * 8) +
+                align256((size_t)nchunks * B * 8) + 1024;
+  CHECK(ensure_scratch(op, need));
+  Carve cv(op->scratch, op->scratch_bytes);
+  NlBufs nb = carve_nl(op, cv, std::max<int64_t>(N, B));
+  double* HXb = cv.take<double>((size_t)op->M * B);
+  double* pbuf = cv.take<double>((size_t)nchunks * B);
+  if (E) {
+    CHECK(launch_fill<double>(E, 1, 0.0, s));
+    for (int64_t j0 = 0; j0 < N; j0 += B) {
+      const int nc = (int)std::min<int64_t>(B, N - j0);
+      CHECK(do_apply<double>(op, 0, X + j0, ldx, HXb, nc, nc, nb, s));
+      CHECK(launch_coldot(X + j0, ldx, HXb, nc, op->M, nc, pbuf, E, occ ? occ + j0 : nullptr, false, true, s));
+    }
+  }
+  if (dE_dVq) CHECK(launch_density(op, X, ldx, (int)N, occ, dE_dVq, s));
+  if (dE_dDH && op->natoms) {
+    CHECK(launch_nl_reduce<double>(op, X, ldx, (int)N, false, nb.part, nb.c, s));
+    CHECK(launch_grad_dh(op, nb.c, (int)N, occ, dE_dDH, s));
+  }
+  return PAWFE_OK;
+}
+
+// ---- Lanczos bounds ------------------------------------------------------------
+
+pawfe_status pawfe_lanczos_bounds(const pawfe_op* cop, int32_t k, uint64_t seed, double* theta_min,
+                                  double* theta_max, double* beta_k, void* stream) {
+  if (!cop) return fail(PAWFE_EINVAL, "op is NULL");
+  if (k < 2 || k > 200) return fail(PAWFE_EINVAL, "k must be in 2..200");
+  pawfe_op* op = const_cast<pawfe_op*>(cop);
+  hipStream_t s = S(stream);
+  const int64_t M = op->M;
+  const int64_t nchunks = (M + 4095) / 4096;
+  size_t need = nl_scratch_bytes(op, 1) + 5 * align256((size_t)M * 8) + align256((size_t)nchunks * 8) + 1024;
+  CHECK(ensure_scratch(op, need));
+  Carve cv(op->scratch, op->scratch_bytes);
+  NlBufs nb = carve_nl(op, cv, 1);
+  double* v = cv.take<double>(M);
+  double* vp = cv.take<double>(M);
+  double* z = cv.take<double>(M);
+  double* w = cv.take<double>(M);
+  double* u = cv.take<double>(M);
+  double* pbuf = cv.take<double>(nchunks);
+  double* dot = cv.take<double>(2);
+  // seeded start vector (splitmix64 -> uniform(-1, 1)), generated on the host
+  std::vector<double> h(M);
+  uint64_t st = seed;
+  for (int64_t i = 0; i < M; ++i) {
+    st += 0x9E3779B97F4A7C15ull;
+    uint64_t x = st;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    x ^= x >> 31;
+    h[i] = 2.0 * ((x >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
+  }
+  PAWFE_HIP(hipMemcpyAsync(v, h.data(), M * 8, hipMemcpyHostToDevice, s));
+  const dim3 g((unsigned)((M + 255) / 256)), b(256);
+  auto ddot = [&](const double* x, const double* y, double* res) -> pawfe_status {
+    CHECK(launch_fill<double>(dot, 1, 0.0, s));
+    CHECK(launch_coldot(x, 1, y, 1, M, 1, pbuf, dot, nullptr, false, true, s));
+    PAWFE_HIP(hipMemcpyAsync(res, dot, 8, hipMemcpyDeviceToHost, s));
+    PAWFE_HIP(hipStreamSynchronize(s));
+    return PAWFE_OK;
+  };
+  CHECK(do_apply<double>(op, 2, v, 1, z, 1, 1, nb, s));
+  double nrm2 = 0.0;
+  CHECK(ddot(v, z, &nrm2));
+  if (!(nrm2 > 0.0)) return fail(PAWFE_ENOTSPD, "Sinv_hat is not positive on the start vector");
+  const double inv = 1.0 / std::sqrt(nrm2);
+  hipLaunchKernelGGL(k_lincomb, g, b, 0, s, M, v, inv, v, 0.0, nullptr, 0.0);
+  hipLaunchKernelGGL(k_lincomb, g, b, 0, s, M, z, inv, z, 0.0, nullptr, 0.0);
+  CHECK(launch_fill<double>(vp, M, 0.0, s));
+  std::vector<double> al, be;
+  double beta_prev = 0.0;
+  for (int it = 0; it < k; ++it) {
+    CHECK(do_apply<double>(op, 0, z, 1, w, 1, 1, nb, s));
+    double alpha = 0.0;
+    CHECK(ddot(z, w, &alpha));
+    // w = w - alpha v - beta_prev vp
+    hipLaunchKernelGGL(k_lincomb, g, b, 0, s, M, w, -alpha, v, -beta_prev, vp, 1.0);
+    CHECK(do_apply<double>(op, 2, w, 1, u, 1, 1, nb, s));
+    double bb = 0.0;
+    CHECK(ddot(w, u, &bb));
+    const double beta = std::sqrt(std::max(bb, 0.0));
+    al.push_back(alpha);
+    be.push_back(beta);
+    if (beta == 0.0) break;
+    std::swap(vp, v);   // vp <- v
+    hipLaunchKernelGGL(k_lincomb, g, b, 0, s, M, v, 1.0 / beta, w, 0.0, nullptr, 0.0);
+    hipLaunchKernelGGL(k_lincomb, g, b, 0, s, M, z, 1.0 / beta, u, 0.0, nullptr, 0.0);
+    beta_prev = beta;
+  }
+  const int n = (int)al.size();
+  std::vector<double> T(n * n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    T[i * n + i] = al[i];
+    if (i + 1 < n) T[i * n + i + 1] = T[(i + 1) * n + i] = be[i];
+  }
+  std::vector<double> ev = small_sym_eigvals(n, T);
+  if (theta_min) *theta_min = ev.front();
+  if (theta_max) *theta_max = ev.back();
+  if (beta_k) *beta_k = std::fabs(be.back());
+  PAWFE_HIP(hipGetLastError());
+  return PAWFE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,120 @@
+// Kernel launch interface shared by the translation units of libpawfe.
+#pragma once
+
+#include <type_traits>
+
+#include "internal.h"
+
+namespace pawfe {
+
+enum { kModeH = 0, kModeHRes = 1, kModeMass = 2 };
+
+template <typename T>
+struct CellArgs {
+  const T* X;
+  int64_t ldx;
+  T* Y;
+  int64_t ldy;
+  int ncols;
+  const int32_t* cells;
+  const T* Vw;
+  const T* W3;
+  const double* lam;   // per-column lambda (residual mode)
+  T alpha;
+  int n0, n1, n2;
+};
+
+struct DensArgs {
+  const double* X;
+  int64_t ldx;
+  int ncols;
+  const double* occ;
+  double* out;
+  const double* W3;
+  int n0, n1, n2;
+};
+
+// Y += alpha * A_loc X over all cells (colour by colour).
+//  mode kModeH:    A_loc = K + V
+//  mode kModeHRes: A_loc = K + V - lambda_n M (per column n)
+//  mode kModeMass: A_loc = M
+template <typename T>
+pawfe_status launch_cell(const pawfe_op* op, int mode, const T* X, int64_t ldx, T* Y, int64_t ldy,
+                         int ncols, const double* lam, double alpha, hipStream_t s);
+
+// out[e][q] = W_q sum_n occ_n |u_n(x_{e,q})|^2
+pawfe_status launch_density(const pawfe_op* op, const double* X, int64_t ldx, int ncols,
+                            const double* occ, double* out, hipStream_t s);
+
+// ---- non-local / node-wise kernels (kernels_nl.hip) ----
+
+// c[(poff_a + alpha) * ncols + n] = sum_{I in supp(a)} C^a[I][alpha] s_I X[I][n],
+// s_I = M_D^{-1}[I] if scale_minv, else 1.  part: >= item_rows_total*ncols doubles.
+template <typename T>
+pawfe_status launch_nl_reduce(const pawfe_op* op, const T* X, int64_t ldx, int ncols, bool scale_minv,
+                              double* part, double* c, hipStream_t s);
+
+// out = (D1 - lam_n D2) in  (per atom block; D2 may be NULL), scaled by f.
+pawfe_status launch_atom_mul(const pawfe_op* op, const double* D1, const double* D2, const double* lam,
+                             double f, const double* in, double* out, int ncols, hipStream_t s);
+
+// out_a = c_a - sum_b G^{ab} d_b
+pawfe_status launch_atom_gcorr(const pawfe_op* op, const double* c, const double* d, double* out,
+                               int ncols, hipStream_t s);
+
+// Y[I][n] = sum_{a: I in supp(a)} C^a[I] . q_a[n]   (0 outside the supports)
+template <typename T>
+pawfe_status launch_node_nl_init(const pawfe_op* op, const double* q, int ncols, T* Y, int64_t ldy,
+                                 hipStream_t s);
+
+// Y = M_D^{-1} (X - sum_a C^a d_a)
+template <typename T>
+pawfe_status launch_node_sinv(const pawfe_op* op, const T* X, int64_t ldx, const double* d, int ncols,
+                              T* Y, int64_t ldy, hipStream_t s);
+
+// Chebyshev step, node part:  T = M_D^{-1}(RY - C d);
+// RX = -ac RY - zz RX + C q + a Y lamY (q already scaled by a);
+// lamX = a lamY lam_in - ac lamY - zz lamX (row 0 threads).
+template <typename TR>
+pawfe_status launch_node_cheb(const pawfe_op* op, const TR* RY, TR* RX, TR* Tb, int64_t ld,
+                              const double* Y, int64_t ldy, const double* d, const double* q,
+                              const double* lamY, double* lamX, const double* lam_in, double a,
+                              double ac, double zz, int ncols, hipStream_t s);
+
+// Xout = M_D^{-1}(RY - C d) + X lamY
+template <typename TR>
+pawfe_status launch_node_finalize(const pawfe_op* op, const TR* RY, int64_t ld, const double* d,
+                                  const double* X, int64_t ldx, const double* lamY, double* Xout,
+                                  int64_t ldo, int ncols, hipStream_t s);
+
+// RY = f * Y (cast), RX = 0, lamY = f (lam_in - c), lamX = 1
+template <typename TR>
+pawfe_status launch_cheb_init(const pawfe_op* op, const double* Y, int64_t ldy, TR* RY, TR* RX,
+                              int64_t ld, double f, double c, const double* lam_in, double* lamY,
+                              double* lamX, int ncols, hipStream_t s);
+
+// partial[chunk][n] = sum over rows of the chunk of  A[i][n] * B[i][n]  (B == A -> squares)
+pawfe_status launch_coldot(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t nrows,
+                           int ncols, double* partial, double* out, const double* w, bool sqrt_out,
+                           bool accumulate_scalar, hipStream_t s);
+
+// C (N1 x N2) = A^T B, A: [K][lda], B: [K][ldb]; split-K partials in ws
+pawfe_status launch_gemm_tn(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t K,
+                            int N1, int N2, double* C, int ldc, double* ws, size_t ws_doubles,
+                            bool symmetrize, hipStream_t s);
+
+// Out[k][j] = sum_i A[k][i] Q[i][j], Q column-major (Q(i,j) = Qcm[j*ldq + i])
+pawfe_status launch_gemm_nq(const double* A, int64_t lda, const double* Qcm, int ldq, int64_t K, int N,
+                            double* Out, int64_t ldo, hipStream_t s);
+
+// dE/dDelta_H^a = sum_n occ_n P P^T, P = c rows of atom a
+pawfe_status launch_grad_dh(const pawfe_op* op, const double* c, int ncols, const double* occ,
+                            double* out, hipStream_t s);
+
+// elementwise copies / fills
+pawfe_status launch_copy_cols(const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t nrows,
+                              int ncols, hipStream_t s);
+template <typename T>
+pawfe_status launch_fill(T* Y, int64_t n, T v, hipStream_t s);
+
+}  // namespace pawfe

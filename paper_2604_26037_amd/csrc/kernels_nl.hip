@@ -1,0 +1,575 @@
+// Non-local PAW terms, node-wise recurrence kernels, reductions and the FP64
+// GEMMs of the Rayleigh-Ritz step, for gfx950.
+//
+// Non-local action (eq. "FE nonlocal contribution"): the projector
+// coefficients c_a = C^a^T s X (s = 1 or M_D^{-1}) are a long-K skinny
+// reduction over the support nodes of each atom (K <= 19^3 rows, M = nproj,
+// N = columns): one workgroup per (atom, 256-row chunk, 64-column tile),
+// lane <-> column so every row read is one coalesced 512-byte segment and the
+// C^a row is wave-uniform (scalar loads).  Partial sums go to a workspace and
+// a second kernel adds the chunks of each atom in a fixed order (no atomics,
+// deterministic).  The atom-block products (Delta x c, G^{ab} corrections)
+// are tiny and run one thread per (projector, column).  The add-back
+// sum_a C^a q_a is fused into the node-wise kernels that stream the rows.
+
+#include "kernels.h"
+
+namespace pawfe {
+
+namespace {
+
+constexpr int kRowsPerWaveGroup = 4;   // waves per 256-thread block in row-wise kernels
+
+template <typename T, int NPJ>
+__global__ void __launch_bounds__(256) k_nl_reduce(const T* __restrict__ X, int64_t ldx, int ncols,
+                                                   int scale, const T* __restrict__ Minv,
+                                                   const T* __restrict__ Cv, DeviceTables d,
+                                                   double* __restrict__ part) {
+  __shared__ double red[kRowsPerWaveGroup][NPJ][64];
+  const int item = blockIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int n = blockIdx.y * 64 + lane;
+  const bool valid = n < ncols;
+  const int a = d.item_atom[item];
+  const int npj = d.nproj[a];
+  const int r0 = d.item_row0[item], r1 = d.item_row1[item];
+  const int noff = d.atom_noff[a], coff = d.atom_coff[a];
+  T acc[NPJ];
+#pragma unroll
+  for (int al = 0; al < NPJ; ++al) acc[al] = T(0);
+  for (int r = r0 + w; r < r1; r += kRowsPerWaveGroup) {
+    const int I = d.atom_nodes[noff + r];
+    T x = valid ? X[(int64_t)I * ldx + n] : T(0);
+    if (scale) x *= Minv[I];
+    const T* cr = Cv + coff + (int64_t)r * npj;
+#pragma unroll
+    for (int al = 0; al < NPJ; ++al)
+      if (al < npj) acc[al] += cr[al] * x;
+  }
+#pragma unroll
+  for (int al = 0; al < NPJ; ++al) red[w][al][lane] = (double)acc[al];
+  __syncthreads();
+  const int po = d.item_poff[item];
+  for (int al = w; al < npj; al += kRowsPerWaveGroup) {
+    double s = red[0][al][lane] + red[1][al][lane] + red[2][al][lane] + red[3][al][lane];
+    if (valid) part[(int64_t)(po + al) * ncols + n] = s;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_nl_final(const double* __restrict__ part, int ncols,
+                                                  const int32_t* __restrict__ proj_atom,
+                                                  const int32_t* __restrict__ proj_alpha, DeviceTables d,
+                                                  double* __restrict__ c) {
+  const int g = blockIdx.x;
+  const int n = blockIdx.y * 256 + threadIdx.x;
+  if (n >= ncols) return;
+  const int a = proj_atom[g], al = proj_alpha[g];
+  double s = 0.0;
+  for (int it = d.item_ptr[a]; it < d.item_ptr[a + 1]; ++it)
+    s += part[(int64_t)(d.item_poff[it] + al) * ncols + n];
+  c[(int64_t)g * ncols + n] = s;
+}
+
+__global__ void __launch_bounds__(256) k_atom_mul(const double* __restrict__ D1, const double* __restrict__ D2,
+                                                  const double* __restrict__ lam, double f,
+                                                  const double* __restrict__ in, double* __restrict__ out,
+                                                  int ncols, const int32_t* __restrict__ proj_atom,
+                                                  const int32_t* __restrict__ proj_alpha, DeviceTables d) {
+  const int g = blockIdx.x;
+  const int n = blockIdx.y * 256 + threadIdx.x;
+  if (n >= ncols) return;
+  const int a = proj_atom[g], s = proj_alpha[g];
+  const int npj = d.nproj[a], po = d.poff[a];
+  const double* r1 = D1 + d.poff2[a] + s * npj;
+  double acc = 0.0, acc2 = 0.0;
+  for (int t = 0; t < npj; ++t) acc += r1[t] * in[(int64_t)(po + t) * ncols + n];
+  if (D2) {
+    const double* r2 = D2 + d.poff2[a] + s * npj;
+    for (int t = 0; t < npj; ++t) acc2 += r2[t] * in[(int64_t)(po + t) * ncols + n];
+    acc -= lam[n] * acc2;
+  }
+  out[(int64_t)g * ncols + n] = f * acc;
+}
+
+__global__ void __launch_bounds__(256) k_atom_gcorr(const double* __restrict__ c, const double* __restrict__ dv,
+                                                    double* __restrict__ out, int ncols,
+                                                    const int32_t* __restrict__ proj_atom,
+                                                    const int32_t* __restrict__ proj_alpha, DeviceTables d) {
+  const int g = blockIdx.x;
+  const int n = blockIdx.y * 256 + threadIdx.x;
+  if (n >= ncols) return;
+  const int a = proj_atom[g], s = proj_alpha[g];
+  double acc = c[(int64_t)g * ncols + n];
+  for (int k = d.gp_ptr[a]; k < d.gp_ptr[a + 1]; ++k) {
+    const int b = d.gp_b[k], nb = d.nproj[b], pb = d.poff[b];
+    const double* G = d.Gvals + d.gp_off[k] + s * nb;
+    for (int u = 0; u < nb; ++u) acc -= G[u] * dv[(int64_t)(pb + u) * ncols + n];
+  }
+  out[(int64_t)g * ncols + n] = acc;
+}
+
+// sum_{a: I in supp(a)} C^a[I] . v_a[n] for support row sr (wave-uniform)
+template <typename T>
+__device__ __forceinline__ T nl_row(int sr, const DeviceTables& d, const T* __restrict__ Cv,
+                                    const double* __restrict__ v, int ncols, int n) {
+  T acc = T(0);
+  const int k0 = d.srow_ptr[sr], k1 = d.srow_ptr[sr + 1];
+  for (int k = k0; k < k1; ++k) {
+    const int a = d.srow_atom[k], coff = d.srow_coff[k];
+    const int npj = d.nproj[a], po = d.poff[a];
+    for (int al = 0; al < npj; ++al) acc += Cv[coff + al] * (T)v[(int64_t)(po + al) * ncols + n];
+  }
+  return acc;
+}
+
+#define ROW_PROLOGUE                                                       \
+  const int lane = threadIdx.x & 63;                                       \
+  const int64_t I = (int64_t)blockIdx.x * kRowsPerWaveGroup +              \
+                    __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);      \
+  const int n = blockIdx.y * 64 + lane;                                    \
+  if (I >= M || n >= ncols) return;
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_node_nl_init(int64_t M, int ncols, const double* __restrict__ q,
+                                                      T* __restrict__ Y, int64_t ldy, const T* __restrict__ Cv,
+                                                      DeviceTables d) {
+  ROW_PROLOGUE
+  const int sr = d.node2srow[I];
+  Y[I * ldy + n] = sr >= 0 ? nl_row<T>(sr, d, Cv, q, ncols, n) : T(0);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_node_sinv(int64_t M, int ncols, const T* __restrict__ X, int64_t ldx,
+                                                   const double* __restrict__ dv, T* __restrict__ Y, int64_t ldy,
+                                                   const T* __restrict__ Minv, const T* __restrict__ Cv,
+                                                   DeviceTables d) {
+  ROW_PROLOGUE
+  const int sr = d.node2srow[I];
+  T x = X[I * ldx + n];
+  if (sr >= 0) x -= nl_row<T>(sr, d, Cv, dv, ncols, n);
+  Y[I * ldy + n] = Minv[I] * x;
+}
+
+template <typename TR>
+__global__ void __launch_bounds__(256) k_node_cheb(int64_t M, int ncols, const TR* __restrict__ RY,
+                                                   TR* __restrict__ RX, TR* __restrict__ Tb, int64_t ld,
+                                                   const double* __restrict__ Y, int64_t ldy,
+                                                   const double* __restrict__ dv, const double* __restrict__ qv,
+                                                   const double* __restrict__ lamY, double* __restrict__ lamX,
+                                                   const double* __restrict__ lam_in, double a, double ac,
+                                                   double zz, const TR* __restrict__ Minv,
+                                                   const TR* __restrict__ Cv, DeviceTables d) {
+  ROW_PROLOGUE
+  const int sr = d.node2srow[I];
+  const TR ry = RY[I * ld + n];
+  const TR rx = RX[I * ld + n];
+  TR cd = TR(0), cq = TR(0);
+  if (sr >= 0) {
+    const int k0 = d.srow_ptr[sr], k1 = d.srow_ptr[sr + 1];
+    for (int k = k0; k < k1; ++k) {
+      const int at = d.srow_atom[k], coff = d.srow_coff[k];
+      const int npj = d.nproj[at], po = d.poff[at];
+      for (int al = 0; al < npj; ++al) {
+        const TR cv = Cv[coff + al];
+        cd += cv * (TR)dv[(int64_t)(po + al) * ncols + n];
+        cq += cv * (TR)qv[(int64_t)(po + al) * ncols + n];
+      }
+    }
+  }
+  Tb[I * ld + n] = Minv[I] * (ry - cd);
+  // recurrence part in TR arithmetic, residual correction a Y lamY in FP64
+  const TR part = (TR)(-ac) * ry - (TR)zz * rx + cq;
+  RX[I * ld + n] = (TR)((double)part + a * Y[I * ldy + n] * lamY[n]);
+  if (I == 0) lamX[n] = a * lamY[n] * lam_in[n] - ac * lamY[n] - zz * lamX[n];
+}
+
+template <typename TR>
+__global__ void __launch_bounds__(256) k_node_finalize(int64_t M, int ncols, const TR* __restrict__ RY,
+                                                       int64_t ld, const double* __restrict__ dv,
+                                                       const double* __restrict__ X, int64_t ldx,
+                                                       const double* __restrict__ lamY, double* __restrict__ Xo,
+                                                       int64_t ldo, const TR* __restrict__ Minv,
+                                                       const TR* __restrict__ Cv, DeviceTables d) {
+  ROW_PROLOGUE
+  const int sr = d.node2srow[I];
+  TR r = RY[I * ld + n];
+  if (sr >= 0) r -= nl_row<TR>(sr, d, Cv, dv, ncols, n);
+  const TR t = Minv[I] * r;
+  Xo[I * ldo + n] = (double)t + X[I * ldx + n] * lamY[n];
+}
+
+template <typename TR>
+__global__ void __launch_bounds__(256) k_cheb_init(int64_t M, int ncols, const double* __restrict__ Y,
+                                                   int64_t ldy, TR* __restrict__ RY, TR* __restrict__ RX,
+                                                   int64_t ld, double f, double c,
+                                                   const double* __restrict__ lam_in, double* __restrict__ lamY,
+                                                   double* __restrict__ lamX) {
+  ROW_PROLOGUE
+  RY[I * ld + n] = (TR)(f * Y[I * ldy + n]);
+  RX[I * ld + n] = TR(0);
+  if (I == 0) {
+    lamY[n] = f * (lam_in[n] - c);
+    lamX[n] = 1.0;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_copy_cols(int64_t M, int ncols, const double* __restrict__ X, int64_t ldx,
+                                                   double* __restrict__ Y, int64_t ldy) {
+  ROW_PROLOGUE
+  Y[I * ldy + n] = X[I * ldx + n];
+}
+
+template <typename T>
+__global__ void k_fill(T* __restrict__ Y, int64_t n, T v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    Y[i] = v;
+}
+
+// partial[chunk][n] = sum_{i in chunk} A[i][n] B[i][n]
+__global__ void __launch_bounds__(256) k_coldot(const double* __restrict__ A, int64_t lda,
+                                                const double* __restrict__ B, int64_t ldb, int64_t nrows,
+                                                int ncols, int64_t rows_per_chunk, double* __restrict__ partial) {
+  __shared__ double red[kRowsPerWaveGroup][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int n = blockIdx.y * 64 + lane;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_chunk;
+  const int64_t r1 = (r0 + rows_per_chunk < nrows) ? r0 + rows_per_chunk : nrows;
+  double acc = 0.0;
+  if (n < ncols)
+    for (int64_t i = r0 + w; i < r1; i += kRowsPerWaveGroup) acc += A[i * lda + n] * B[i * ldb + n];
+  red[w][lane] = acc;
+  __syncthreads();
+  if (w == 0 && n < ncols)
+    partial[(int64_t)blockIdx.x * ncols + n] = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+}
+
+__global__ void __launch_bounds__(256) k_coldot_final(const double* __restrict__ partial, int nchunks, int ncols,
+                                                      double* __restrict__ out, const double* __restrict__ w,
+                                                      int sqrt_out, int scalar) {
+  __shared__ double red[256];
+  if (!scalar) {
+    const int n = blockIdx.x * 256 + threadIdx.x;
+    if (n >= ncols) return;
+    double s = 0.0;
+    for (int c = 0; c < nchunks; ++c) s += partial[(int64_t)c * ncols + n];
+    out[n] = sqrt_out ? sqrt(s) : s;
+    return;
+  }
+  double s = 0.0;
+  for (int n = threadIdx.x; n < ncols; n += 256) {
+    double t = 0.0;
+    for (int c = 0; c < nchunks; ++c) t += partial[(int64_t)c * ncols + n];
+    s += (w ? w[n] : 1.0) * t;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] += red[0];
+}
+
+// C_part[ks] (N1 x N2) = A[kbeg:kend]^T B[kbeg:kend]; 64x64 tiles, 4x4 per thread
+__global__ void __launch_bounds__(256) k_gemm_tn(const double* __restrict__ A, int64_t lda,
+                                                 const double* __restrict__ B, int64_t ldb, int64_t K, int N1,
+                                                 int N2, int64_t kchunk, double* __restrict__ part) {
+  __shared__ double As[16][64];
+  __shared__ double Bs[16][64];
+  const int tid = threadIdx.x, ti = tid / 16, tj = tid % 16;
+  const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
+  const int64_t kb = (int64_t)blockIdx.z * kchunk, ke = (kb + kchunk < K) ? kb + kchunk : K;
+  double acc[4][4] = {};
+  for (int64_t k = kb; k < ke; k += 16) {
+    for (int idx = tid; idx < 16 * 64; idx += 256) {
+      const int r = idx / 64, c = idx % 64;
+      const int64_t kk = k + r;
+      As[r][c] = (kk < ke && i0 + c < N1) ? A[kk * lda + i0 + c] : 0.0;
+      Bs[r][c] = (kk < ke && j0 + c < N2) ? B[kk * ldb + j0 + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) av[u] = As[r][ti * 4 + u];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) bv[v] = Bs[r][tj * 4 + v];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
+    }
+    __syncthreads();
+  }
+  double* P = part + (int64_t)blockIdx.z * N1 * N2;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = i0 + ti * 4 + u, j = j0 + tj * 4 + v;
+      if (i < N1 && j < N2) P[(int64_t)i * N2 + j] = acc[u][v];
+    }
+}
+
+__global__ void k_gemm_reduce(const double* __restrict__ part, int nsplit, int N1, int N2, double* __restrict__ C,
+                              int ldc, int symmetrize) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)N1 * N2) return;
+  const int i = (int)(idx / N2), j = (int)(idx % N2);
+  double s = 0.0, t = 0.0;
+  for (int k = 0; k < nsplit; ++k) s += part[(int64_t)k * N1 * N2 + (int64_t)i * N2 + j];
+  if (symmetrize) {
+    for (int k = 0; k < nsplit; ++k) t += part[(int64_t)k * N1 * N2 + (int64_t)j * N2 + i];
+    s = 0.5 * (s + t);
+  }
+  C[(int64_t)i * ldc + j] = s;
+}
+
+// Out[k][j] = sum_i A[k][i] Q(i, j), Q column-major with leading dimension ldq
+__global__ void __launch_bounds__(256) k_gemm_nq(const double* __restrict__ A, int64_t lda,
+                                                 const double* __restrict__ Q, int ldq, int64_t K, int N,
+                                                 double* __restrict__ Out, int64_t ldo) {
+  __shared__ double As[64][17];
+  __shared__ double Qs[16][64];
+  const int tid = threadIdx.x, tk = tid / 16, tj = tid % 16;
+  const int64_t k0 = (int64_t)blockIdx.x * 64;
+  const int j0 = blockIdx.y * 64;
+  double acc[4][4] = {};
+  for (int i = 0; i < N; i += 16) {
+    for (int idx = tid; idx < 64 * 16; idx += 256) {
+      const int kk = idx / 16, ii = idx % 16;
+      As[kk][ii] = (k0 + kk < K && i + ii < N) ? A[(k0 + kk) * lda + i + ii] : 0.0;
+      const int jj = idx / 16;
+      Qs[ii][jj] = (j0 + jj < N && i + ii < N) ? Q[(int64_t)(j0 + jj) * ldq + i + ii] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ii = 0; ii < 16; ++ii) {
+      double av[4], qv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) av[u] = As[tk * 4 + u][ii];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) qv[v] = Qs[ii][tj * 4 + v];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * qv[v];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t k = k0 + tk * 4 + u;
+      const int j = j0 + tj * 4 + v;
+      if (k < K && j < N) Out[k * ldo + j] = acc[u][v];
+    }
+}
+
+__global__ void k_grad_dh(const double* __restrict__ c, int ncols, const double* __restrict__ occ,
+                          const int32_t* __restrict__ ent_atom, const int32_t* __restrict__ ent_s,
+                          const int32_t* __restrict__ ent_t, int nent, DeviceTables d, double* __restrict__ out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nent) return;
+  const int a = ent_atom[k], s = ent_s[k], t = ent_t[k];
+  const int po = d.poff[a], npj = d.nproj[a];
+  const double* ps = c + (int64_t)(po + s) * ncols;
+  const double* pt = c + (int64_t)(po + t) * ncols;
+  double acc = 0.0;
+  for (int n = 0; n < ncols; ++n) acc += (occ ? occ[n] : 1.0) * ps[n] * pt[n];
+  out[d.poff2[a] + s * npj + t] = acc;
+}
+
+inline dim3 row_grid(int64_t M, int ncols) {
+  return dim3((unsigned)((M + kRowsPerWaveGroup - 1) / kRowsPerWaveGroup), (unsigned)((ncols + 63) / 64));
+}
+
+template <typename T>
+const T* pick(const double* d64, const float* d32) {
+  if constexpr (std::is_same<T, double>::value) return d64; else return d32;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+
+template <typename T>
+pawfe_status launch_nl_reduce(const pawfe_op* op, const T* X, int64_t ldx, int ncols, bool scale_minv,
+                              double* part, double* c, hipStream_t s) {
+  if (op->natoms == 0 || ncols <= 0) return PAWFE_OK;
+  const T* Cv = pick<T>(op->d.Cvals, op->d.Cvals_f);
+  const T* Minv = pick<T>(op->d.Minv, op->d.Minv_f);
+  const dim3 grid(op->nitems, (ncols + 63) / 64), block(256);
+  if (op->npj_max <= 8)
+    hipLaunchKernelGGL((k_nl_reduce<T, 8>), grid, block, 0, s, X, ldx, ncols, (int)scale_minv, Minv, Cv, op->d, part);
+  else if (op->npj_max <= 18)
+    hipLaunchKernelGGL((k_nl_reduce<T, 18>), grid, block, 0, s, X, ldx, ncols, (int)scale_minv, Minv, Cv, op->d, part);
+  else
+    hipLaunchKernelGGL((k_nl_reduce<T, 32>), grid, block, 0, s, X, ldx, ncols, (int)scale_minv, Minv, Cv, op->d, part);
+  const dim3 g2(op->npj_total, (ncols + 255) / 256);
+  hipLaunchKernelGGL(k_nl_final, g2, block, 0, s, part, ncols, op->d_proj_atom, op->d_proj_alpha, op->d, c);
+  PAWFE_HIP(hipGetLastError());
+  return PAWFE_OK;
+}
+template pawfe_status launch_nl_reduce<double>(const pawfe_op*, const double*, int64_t, int, bool, double*, double*,
+                                               hipStream_t);
+template pawfe_status launch_nl_reduce<float>(const pawfe_op*, const float*, int64_t, int, bool, double*, double*,
+                                              hipStream_t);
+
+pawfe_status launch_atom_mul(const pawfe_op* op, const double* D1, const double* D2, const double* lam, double f,
+                             const double* in, double* out, int ncols, hipStream_t s) {
+  if (op->natoms == 0 || ncols <= 0) return PAWFE_OK;
+  const dim3 grid(op->npj_total, (ncols + 255) / 256), block(256);
+  hipLaunchKernelGGL(k_atom_mul, grid, block, 0, s, D1, D2, lam, f, in, out, ncols, op->d_proj_atom,
+                     op->d_proj_alpha, op->d);
+  PAWFE_HIP(hipGetLastError());
+  return PAWFE_OK;
+}
+
+pawfe_status launch_atom_gcorr(const pawfe_op* op, const double* c, const double* dv, double* out, int ncols,
+                               hipStream_t s) {
+  if (op->natoms == 0 || ncols <= 0) return PAWFE_OK;
+  const dim3 grid(op->npj_total, (ncols + 255) / 256), block(256);
+  hipLaunchKernelGGL(k_atom_gcorr, grid, block, 0, s, c, dv, out, ncols, op->d_proj_atom, op->d_proj_alpha, op->d);
+  PAWFE_HIP(hipGetLastError());
+  return PAWFE_OK;
+}
+
+template <typename T>
+pawfe_status launch_node_nl_init(const pawfe_op* op, const double* q, int ncols, T* Y, int64_t ldy, hipStream_t s) {
+  if (ncols <= 0) return PAWFE_OK;
+  hipLaunchKernelGGL(k_node_nl_init<T>, row_grid(op->M, ncols), dim3(256), 0, s, op->M, ncols, q, Y, ldy,
+                     pick<T>(op->d.Cvals, op->d.Cvals_f), op->d);
+  PAWFE_HIP(hipGetLastError());
+  return PAWFE_OK;
+}
+template pawfe_status launch_node_nl_init<double>(const pawfe_op*, const double*, int, double*, int64_t, hipStream_t);
+template pawfe_status launch_node_nl_init<float>(const pawfe_op*, const double*, int, float*, int64_t, hipStream_t);
+
+template <typename T>
+pawfe_status launch_node_sinv(const pawfe_op* op, const T* X, int64_t ldx, const double* dv, int ncols, T* Y,
+                              int64_t ldy, hipStream_t s) {
+  if (ncols <= 0) return PAWFE_OK;
+  hipLaunchKernelGGL(k_node_sinv<T>, row_grid(op->M, ncols), dim3(256), 0, s, op->M, ncols, X, ldx, dv, Y, ldy,
+                     pick<T>(op->d.Minv, op->d.Minv_f), pick<T>(op->d.Cvals, op->d.Cvals_f), op->d);
+  PAWFE_HIP(hipGetLastError());
+  return PAWFE_OK;
+}
+template pawfe_status launch_node_sinv<double>(const pawfe_op*, const double*, int64_t, const double*, int, double*,
+                                               int64_t, hipStream_t);
+template pawfe_status launch_node_sinv<float>(const pawfe_op*, const float*, int64_t, const double*, int, float*,
+                                              int64_t, hipStream_t);
+
+template <typename TR>
+pawfe_status launch_node_cheb(const pawfe_op* op, const TR* RY, TR* RX, TR* Tb, int64_t ld, const double* Y,
+                              int64_t ldy, const double* dv, const double* qv, const double* lamY, double* lamX,
+                              const double* lam_in, double a, double ac, double zz, int ncols, hipStream_t s) {
+  hipLaunchKernelGGL(k_node_cheb<TR>, row_grid(op->M, ncols), dim3(256), 0, s, op->M, ncols, RY, RX, Tb, ld, Y, ldy,
+                     dv, qv, lamY, lamX, lam_in, a, ac, zz, pick<TR>(op->d.Minv, op->d.Minv_f),
+                     pick<TR>(op->d.Cvals, op->d.Cvals_f), op->d);
+  PAWFE_HIP(hipGetLastError());
+  return PAWFE_OK;
+}
+template pawfe_status launch_node_cheb<double>(const pawfe_op*, const double*, double*, double*, int64_t,
+                                               const double*, int64_t, const double*, const double*, const double*,
+                                               double*, const double*, double, double, double, int, hipStream_t);
+template pawfe_status launch_node_cheb<float>(const pawfe_op*, const float*, float*, float*, int64_t, const double*,
+                                              int64_t, const double*, const double*, const double*, double*,
+                                              const double*, double, double, double, int, hipStream_t);
+
+template <typename TR>
+pawfe_status launch_node_finalize(const pawfe_op* op, const TR* RY, int64_t ld, const double* dv, const double* X,
+                                  int64_t ldx, const double* lamY, double* Xo, int64_t ldo, int ncols, hipStream_t s) {
+  hipLaunchKernelGGL(k_node_finalize<TR>, row_grid(op->M, ncols), dim3(256), 0, s, op->M, ncols, RY, ld, dv, X, ldx,
+                     lamY, Xo, ldo, pick<TR>(op->d.Minv, op->d.Minv_f), pick<TR>(op->d.Cvals, op->d.Cvals_f), op->d);
+  PAWFE_HIP(hipGetLastError());
+  return PAWFE_OK;
+}
+template pawfe_status launch_node_finalize<double>(const pawfe_op*, const double*, int64_t, const double*,
+                                                   const double*, int64_t, const double*, double*, int64_t, int,
+                                                   hipStream_t);
+template pawfe_status launch_node_finalize<float>(const pawfe_op*, const float*, int64_t, const double*, const double*,
+                                                  int64_t, const double*, double*, int64_t, int, hipStream_t);
+
+template <typename TR>
+pawfe_status launch_cheb_init(const pawfe_op* op, const double* Y, int64_t ldy, TR* RY, TR* RX, int64_t ld, double f,
+                              double c, const double* lam_in, double* lamY, double* lamX, int ncols, hipStream_t s) {
+  hipLaunchKernelGGL(k_cheb_init<TR>, row_grid(op->M, ncols), dim3(256), 0, s, op->M, ncols, Y, ldy, RY, RX, ld, f, c,
+                     lam_in, lamY, lamX);
+  PAWFE_HIP(hipGetLastError());
+  return PAWFE_OK;
+}
+template pawfe_status launch_cheb_init<double>(const pawfe_op*, const double*, int64_t, double*, double*, int64_t,
+                                               double, double, const double*, double*, double*, int, hipStream_t);
+template pawfe_status launch_cheb_init<float>(const pawfe_op*, const double*, int64_t, float*, float*, int64_t,
+                                              double, double, const double*, double*, double*, int, hipStream_t);
+
+pawfe_status launch_copy_cols(const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t nrows, int ncols,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_cols, row_grid(nrows, ncols), dim3(256), 0, s, nrows, ncols, X, ldx, Y, ldy);
+  PAWFE_HIP(hipGetLastError());
+  return PAWFE_OK;
+}
+
+template <typename T>
+pawfe_status launch_fill(T* Y, int64_t n, T v, hipStream_t s) {
+  if (n <= 0) return PAWFE_OK;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)blocks), dim3(256), 0, s, Y, n, v);
+  PAWFE_HIP(hipGetLastError());
+  return PAWFE_OK;
+}
+template pawfe_status launch_fill<double>(double*, int64_t, double, hipStream_t);
+template pawfe_status launch_fill<float>(float*, int64_t, float, hipStream_t);
+
+pawfe_status launch_coldot(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t nrows, int ncols,
+                           double* partial, double* out, const double* w, bool sqrt_out, bool scalar, hipStream_t s) {
+  const int64_t rpc = 4096;
+  const int nchunks = (int)((nrows + rpc - 1) / rpc);
+  hipLaunchKernelGGL(k_coldot, dim3(nchunks, (ncols + 63) / 64), dim3(256), 0, s, A, lda, B, ldb, nrows, ncols, rpc,
+                     partial);
+  hipLaunchKernelGGL(k_coldot_final, dim3(scalar ? 1 : (ncols + 255) / 256), dim3(256), 0, s, partial, nchunks, ncols,
+                     out, w, (int)sqrt_out, (int)scalar);
+  PAWFE_HIP(hipGetLastError());
+  return PAWFE_OK;
+}
+
+pawfe_status launch_gemm_tn(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t K, int N1, int N2,
+                            double* C, int ldc, double* ws, size_t ws_doubles, bool symmetrize, hipStream_t s) {
+  const int ti = (N1 + 63) / 64, tj = (N2 + 63) / 64;
+  int nsplit = (int)std::max<int64_t>(1, std::min<int64_t>((K + 4095) / 4096, 4096 / std::max(1, ti * tj) + 1));
+  nsplit = (int)std::min<int64_t>(nsplit, (int64_t)(ws_doubles / ((size_t)N1 * N2)));
+  if (nsplit < 1) return fail(PAWFE_EINVAL, "GEMM workspace too small");
+  int64_t kchunk = (K + nsplit - 1) / nsplit;
+  kchunk = (kchunk + 15) / 16 * 16;
+  nsplit = (int)((K + kchunk - 1) / kchunk);
+  hipLaunchKernelGGL(k_gemm_tn, dim3(ti, tj, nsplit), dim3(256), 0, s, A, lda, B, ldb, K, N1, N2, kchunk, ws);
+  const int64_t tot = (int64_t)N1 * N2;
+  hipLaunchKernelGGL(k_gemm_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, ws, nsplit, N1, N2, C, ldc,
+                     (int)symmetrize);
+  PAWFE_HIP(hipGetLastError());
+  return PAWFE_OK;
+}
+
+pawfe_status launch_gemm_nq(const double* A, int64_t lda, const double* Qcm, int ldq, int64_t K, int N, double* Out,
+                            int64_t ldo, hipStream_t s) {
+  hipLaunchKernelGGL(k_gemm_nq, dim3((unsigned)((K + 63) / 64), (N + 63) / 64), dim3(256), 0, s, A, lda, Qcm, ldq, K,
+                     N, Out, ldo);
+  PAWFE_HIP(hipGetLastError());
+  return PAWFE_OK;
+}
+
+pawfe_status launch_grad_dh(const pawfe_op* op, const double* c, int ncols, const double* occ, double* out,
+                            hipStream_t s) {
+  if (op->natoms == 0) return PAWFE_OK;
+  const int nent = op->npj2_total;
+  hipLaunchKernelGGL(k_grad_dh, dim3((nent + 255) / 256), dim3(256), 0, s, c, ncols, occ, op->d_g2_atom, op->d_g2_s,
+                     op->d_g2_t, nent, op->d, out);
+  PAWFE_HIP(hipGetLastError());
+  return PAWFE_OK;
+}
+
+}  // namespace pawfe

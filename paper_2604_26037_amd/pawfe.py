@@ -1,0 +1,322 @@
+"""ctypes binding of libpawfe (the C ABI in include/pawfe.h).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  PyTorch supplies device memory (tensors) and the stream
+(``torch.cuda.current_stream()``).  There is no fallback: if the shared
+library is missing or fails to load, ``load()`` raises.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpawfe.so")
+
+PAWFE_OK, PAWFE_EINVAL, PAWFE_ENOMEM, PAWFE_EHIP, PAWFE_ENOTSPD, PAWFE_ENONFINITE, PAWFE_EUNSUPPORTED = range(7)
+FP64, FP32, BF16X3 = 0, 1, 2
+SINV_EXACT_G, SINV_PP = 0, 1
+_PREC = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, FP64: FP64, FP32: FP32, BF16X3: BF16X3}
+_STATUS = {1: "EINVAL", 2: "ENOMEM", 3: "EHIP", 4: "ENOTSPD", 5: "ENONFINITE", 6: "EUNSUPPORTED"}
+
+# every symbol include/pawfe.h declares
+EXPORTS = [
+    "pawfe_build_operator", "pawfe_destroy_operator", "pawfe_query", "pawfe_get_dofmap",
+    "pawfe_set_veff", "pawfe_set_dH", "pawfe_apply_H", "pawfe_apply_S", "pawfe_apply_Sinv",
+    "pawfe_apply_local",
+    "pawfe_cheb_filter_workspace", "pawfe_cheb_filter", "pawfe_rayleigh_ritz_workspace",
+    "pawfe_rayleigh_ritz", "pawfe_band_energy_grad", "pawfe_lanczos_bounds", "pawfe_last_error",
+]
+
+
+class PawfeError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"pawfe error {_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Desc(C.Structure):
+    _fields_ = [
+        ("ncell", C.c_int32 * 3), ("box", C.c_double * 3), ("degree", C.c_int32),
+        ("nq1d", C.c_int32), ("kpoint", C.c_double * 3), ("is_complex", C.c_int32),
+        ("veff_q", C.POINTER(C.c_double)), ("natoms", C.c_int32), ("pos", C.POINTER(C.c_double)),
+        ("rcut", C.POINTER(C.c_double)), ("nproj", C.POINTER(C.c_int32)),
+        ("proj_l", C.POINTER(C.c_int32)), ("proj_m", C.POINTER(C.c_int32)),
+        ("proj_sigma", C.POINTER(C.c_double)), ("dH", C.POINTER(C.c_double)),
+        ("dS", C.POINTER(C.c_double)), ("sinv_mode", C.c_int32),
+    ]
+
+
+_lib = None
+
+
+def load(path=LIB_PATH):
+    """Load libpawfe.so (raises if it is missing: there is no other path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing; build it with `python -m paper_2604_26037_amd.build`")
+    lib = C.CDLL(path)
+    vp, i32, i64, dbl, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_size_t
+    P = C.POINTER
+    sig = {
+        "pawfe_build_operator": [P(Desc), vp, P(vp)],
+        "pawfe_destroy_operator": [vp],
+        "pawfe_query": [vp, P(i64), P(i64), P(i32), P(i32), P(i64), P(i64)],
+        "pawfe_get_dofmap": [vp, vp, vp, vp, vp, vp, vp],
+        "pawfe_set_veff": [vp, P(dbl), vp],
+        "pawfe_set_dH": [vp, P(dbl), vp],
+        "pawfe_apply_H": [vp, vp, i64, vp, i64, i64, i32, vp],
+        "pawfe_apply_S": [vp, vp, i64, vp, i64, i64, i32, vp],
+        "pawfe_apply_Sinv": [vp, vp, i64, vp, i64, i64, i32, vp],
+        "pawfe_apply_local": [vp, i32, vp, i64, vp, i64, i64, dbl, i32, vp],
+        "pawfe_cheb_filter_workspace": [vp, i64, i32, i32, P(sz)],
+        "pawfe_cheb_filter": [vp, vp, i64, vp, i64, i64, i32, vp, i32, dbl, dbl, dbl, i32, vp, sz, vp],
+        "pawfe_rayleigh_ritz_workspace": [vp, i64, P(sz)],
+        "pawfe_rayleigh_ritz": [vp, vp, i64, i64, vp, vp, vp, sz, vp],
+        "pawfe_band_energy_grad": [vp, vp, i64, i64, vp, vp, vp, vp, vp],
+        "pawfe_lanczos_bounds": [vp, i32, C.c_uint64, P(dbl), P(dbl), P(dbl), vp],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = i32
+    lib.pawfe_last_error.argtypes = []
+    lib.pawfe_last_error.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(code):
+    if code != PAWFE_OK:
+        msg = _lib.pawfe_last_error().decode(errors="replace")
+        raise PawfeError(code, msg)
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _iptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _tptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Operator:
+    """Device-resident FE-PAW operator (H, S, Sinv_hat) of one system."""
+
+    def __init__(self, system, sinv_mode="exact_g", stream=None):
+        lib = load()
+        s = system
+        self.system = s
+        self._keep = dict(
+            veff=np.ascontiguousarray(s.veff_q, dtype=np.float64).ravel(),
+            pos=np.ascontiguousarray(s.pos, dtype=np.float64).ravel(),
+            rcut=np.ascontiguousarray(s.rcut, dtype=np.float64),
+            nproj=np.ascontiguousarray(s.nproj, dtype=np.int32),
+            l=np.ascontiguousarray(s.proj_l, dtype=np.int32),
+            m=np.ascontiguousarray(s.proj_m, dtype=np.int32),
+            sig=np.ascontiguousarray(s.proj_sigma, dtype=np.float64),
+            dH=np.ascontiguousarray(s.dH, dtype=np.float64),
+            dS=np.ascontiguousarray(s.dS, dtype=np.float64),
+        )
+        k = self._keep
+        d = Desc()
+        d.ncell[:] = [int(n) for n in s.ncell]
+        d.box[:] = [float(b) for b in s.box]
+        d.degree = int(s.degree)
+        d.nq1d = int(s.nq)
+        d.kpoint[:] = [float(x) for x in np.asarray(s.kpoint, dtype=np.float64)]
+        d.is_complex = int(bool(s.is_complex))
+        d.veff_q = _dptr(k["veff"])
+        d.natoms = len(k["rcut"])
+        d.pos = _dptr(k["pos"])
+        d.rcut = _dptr(k["rcut"])
+        d.nproj = _iptr(k["nproj"])
+        d.proj_l = _iptr(k["l"])
+        d.proj_m = _iptr(k["m"])
+        d.proj_sigma = _dptr(k["sig"])
+        d.dH = _dptr(k["dH"])
+        d.dS = _dptr(k["dS"])
+        d.sinv_mode = {"exact_g": SINV_EXACT_G, "pp": SINV_PP}[sinv_mode]
+        self._desc = d
+        h = C.c_void_p()
+        _check(lib.pawfe_build_operator(C.byref(d), _stream(stream), C.byref(h)))
+        self._h = h
+        a = [C.c_int64(), C.c_int64(), C.c_int32(), C.c_int32(), C.c_int64(), C.c_int64()]
+        _check(lib.pawfe_query(h, *[C.byref(x) for x in a]))
+        (self.ndof, self.nquad, self.ncolour, self.nproj_total, self.nsupp_cells,
+         self.nsupp_nodes) = [x.value for x in a]
+        self.ncells = int(np.prod(s.ncell))
+        self.nloc = (int(s.degree) + 1) ** 3
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.pawfe_destroy_operator(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- integer outputs --------------------------------------------------
+    def dofmap(self):
+        na = len(self._keep["rcut"])
+        cd = np.empty((self.ncells, self.nloc), dtype=np.int32)
+        col = np.empty(self.ncells, dtype=np.int32)
+        sco = np.empty(na + 1, dtype=np.int64)
+        sc = np.empty(max(self.nsupp_cells, 1), dtype=np.int64)
+        sno = np.empty(na + 1, dtype=np.int64)
+        sn = np.empty(max(self.nsupp_nodes, 1), dtype=np.int64)
+        _check(_lib.pawfe_get_dofmap(self._h, cd.ctypes.data, col.ctypes.data, sco.ctypes.data,
+                                     sc.ctypes.data, sno.ctypes.data, sn.ctypes.data))
+        return cd, col, sco, sc[:self.nsupp_cells], sno, sn[:self.nsupp_nodes]
+
+    def set_veff(self, veff_q, stream=None):
+        v = np.ascontiguousarray(veff_q, dtype=np.float64).ravel()
+        _check(_lib.pawfe_set_veff(self._h, _dptr(v), _stream(stream)))
+        self._keep["veff"] = v
+
+    def set_dH(self, dH, stream=None):
+        v = np.ascontiguousarray(dH, dtype=np.float64).ravel()
+        _check(_lib.pawfe_set_dH(self._h, _dptr(v), _stream(stream)))
+        self._keep["dH"] = v
+
+    # -- applies ------------------------------------------------------------
+    def _apply(self, fn, X, out, prec, stream):
+        import torch
+        assert X.is_cuda and X.dim() == 2 and X.shape[0] == self.ndof and X.stride(1) == 1
+        dt = torch.float64 if _PREC[prec] == FP64 else torch.float32
+        assert X.dtype == dt, f"X must be {dt}"
+        if out is None:
+            out = torch.empty((X.shape[0], X.shape[1]), dtype=dt, device=X.device)
+        _check(fn(self._h, _tptr(X), X.stride(0), _tptr(out), out.stride(0), X.shape[1],
+                  _PREC[prec], _stream(stream)))
+        return out
+
+    def apply_H(self, X, out=None, prec=FP64, stream=None):
+        return self._apply(_lib.pawfe_apply_H, X, out, prec, stream)
+
+    def apply_S(self, X, out=None, prec=FP64, stream=None):
+        return self._apply(_lib.pawfe_apply_S, X, out, prec, stream)
+
+    def apply_Sinv(self, X, out=None, prec=FP64, stream=None):
+        return self._apply(_lib.pawfe_apply_Sinv, X, out, prec, stream)
+
+    def apply_local(self, X, Y, which=0, alpha=1.0, prec=FP64, stream=None):
+        """Y += alpha * A_loc X (cell part only); Y must be preallocated."""
+        _check(_lib.pawfe_apply_local(self._h, int(which), _tptr(X), X.stride(0), _tptr(Y), Y.stride(0),
+                                      X.shape[1], float(alpha), _PREC[prec], _stream(stream)))
+        return Y
+
+    # -- filter / RR ------------------------------------------------------------
+    def cheb_filter_workspace(self, nvec, block, prec=FP64):
+        b = C.c_size_t()
+        _check(_lib.pawfe_cheb_filter_workspace(self._h, nvec, block, _PREC[prec], C.byref(b)))
+        return b.value
+
+    def workspace(self, nbytes, device="cuda"):
+        import torch
+        return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+    def cheb_filter(self, X, lam, degree, b0, bW, bU, block=None, prec=FP64, out=None, ws=None,
+                    stream=None):
+        import torch
+        assert X.is_cuda and X.dtype == torch.float64 and X.stride(1) == 1
+        n = X.shape[1]
+        block = n if block is None else int(block)
+        if out is None:
+            out = torch.empty_like(X)
+        if ws is None:
+            ws = self.workspace(self.cheb_filter_workspace(n, block, prec), X.device)
+        lam = lam.to(device=X.device, dtype=torch.float64).contiguous()
+        _check(_lib.pawfe_cheb_filter(self._h, _tptr(X), X.stride(0), _tptr(out), out.stride(0), n, block,
+                                      _tptr(lam), int(degree), float(b0), float(bW), float(bU),
+                                      _PREC[prec], _tptr(ws), ws.numel(), _stream(stream)))
+        return out
+
+    def rayleigh_ritz_workspace(self, nvec):
+        b = C.c_size_t()
+        _check(_lib.pawfe_rayleigh_ritz_workspace(self._h, nvec, C.byref(b)))
+        return b.value
+
+    def rayleigh_ritz(self, X, ws=None, stream=None):
+        """In place on X; returns (lambda, resnorm) as device tensors."""
+        import torch
+        assert X.is_cuda and X.dtype == torch.float64 and X.stride(1) == 1
+        n = X.shape[1]
+        lam = torch.empty(n, dtype=torch.float64, device=X.device)
+        res = torch.empty(n, dtype=torch.float64, device=X.device)
+        if ws is None:
+            ws = self.workspace(self.rayleigh_ritz_workspace(n), X.device)
+        _check(_lib.pawfe_rayleigh_ritz(self._h, _tptr(X), X.stride(0), n, _tptr(lam), _tptr(res),
+                                        _tptr(ws), ws.numel(), _stream(stream)))
+        return lam, res
+
+    def band_energy_grad(self, X, occ=None, want_E=True, want_dV=True, want_dH=True, stream=None):
+        import torch
+        assert X.is_cuda and X.dtype == torch.float64 and X.stride(1) == 1
+        dev = X.device
+        E = torch.zeros(1, dtype=torch.float64, device=dev) if want_E else None
+        dV = torch.empty(self.nquad, dtype=torch.float64, device=dev) if want_dV else None
+        ndh = int(len(self._keep["dH"]))
+        dD = torch.empty(max(ndh, 1), dtype=torch.float64, device=dev) if want_dH else None
+        occ_t = None if occ is None else occ.to(device=dev, dtype=torch.float64).contiguous()
+        _check(_lib.pawfe_band_energy_grad(self._h, _tptr(X), X.stride(0), X.shape[1], _tptr(occ_t),
+                                           _tptr(E), _tptr(dV), _tptr(dD), _stream(stream)))
+        return E, dV, (dD[:ndh] if dD is not None else None)
+
+    def lanczos_bounds(self, k=20, seed=1234, stream=None):
+        a, b, c = C.c_double(), C.c_double(), C.c_double()
+        _check(_lib.pawfe_lanczos_bounds(self._h, int(k), C.c_uint64(seed), C.byref(a), C.byref(b),
+                                         C.byref(c), _stream(stream)))
+        return a.value, b.value, c.value
+
+
+def band_energy_function():
+    """torch.autograd.Function for E = sum_n occ_n x_n^T H[V, Delta_H] x_n.
+
+    Forward and backward both call pawfe_band_energy_grad; nothing is cached
+    between them except the inputs themselves.
+    """
+    import torch
+
+    class BandEnergy(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, X, veff_q, dH, op, occ=None):
+            op.set_veff(veff_q.detach().cpu().numpy())
+            op.set_dH(dH.detach().cpu().numpy())
+            E, _, _ = op.band_energy_grad(X, occ, want_E=True, want_dV=False, want_dH=False)
+            ctx.op = op
+            ctx.occ = occ
+            ctx.vshape = tuple(veff_q.shape)
+            ctx.vdev = veff_q.device
+            ctx.ddev = dH.device
+            ctx.save_for_backward(X)
+            return E[0].clone()
+
+        @staticmethod
+        def backward(ctx, g):
+            (X,) = ctx.saved_tensors
+            _, dV, dD = ctx.op.band_energy_grad(X, ctx.occ, want_E=False, want_dV=True, want_dH=True)
+            gv = (g * dV).view(ctx.vshape).to(ctx.vdev)
+            gd = (g * dD).to(ctx.ddev)
+            return None, gv, gd, None, None
+
+    return BandEnergy

@@ -1,0 +1,101 @@
+"""CPU checks of the C ABI library: it loads, exports every symbol that
+include/pawfe.h declares, and rejects bad arguments on the host before any
+device work (no compute call is made here)."""
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2604_26037_amd import pawfe as pw
+from workloads import make_system
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    if not os.path.exists(pw.LIB_PATH):
+        pytest.skip("libpawfe.so not built")
+    return pw.load()
+
+
+def test_exports_match_header():
+    lib = _lib()
+    hdr = open(os.path.join(ROOT, "include", "pawfe.h")).read()
+    declared = sorted(set(re.findall(r"\b(pawfe_[a-zA-Z_]+)\s*\(", hdr)))
+    assert sorted(pw.EXPORTS) == declared
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def _desc(s, **over):
+    keep = dict(veff=np.ascontiguousarray(s.veff_q).ravel(), pos=s.pos.ravel().copy(),
+                rcut=s.rcut.copy(), nproj=s.nproj.astype(np.int32), l=s.proj_l.astype(np.int32),
+                m=s.proj_m.astype(np.int32), sig=s.proj_sigma.copy(), dH=s.dH.copy(), dS=s.dS.copy())
+    for k, v in over.items():
+        if k in keep:
+            keep[k] = v
+    d = pw.Desc()
+    d.ncell[:] = over.get("ncell", list(s.ncell))
+    d.box[:] = list(s.box)
+    d.degree = over.get("degree", s.degree)
+    d.nq1d = over.get("nq", s.nq)
+    d.kpoint[:] = over.get("kpoint", [0.0, 0.0, 0.0])
+    d.is_complex = over.get("is_complex", 0)
+    d.veff_q = pw._dptr(keep["veff"])
+    d.natoms = len(keep["rcut"])
+    d.pos = pw._dptr(keep["pos"])
+    d.rcut = pw._dptr(keep["rcut"])
+    d.nproj = pw._iptr(keep["nproj"])
+    d.proj_l = pw._iptr(keep["l"])
+    d.proj_m = pw._iptr(keep["m"])
+    d.proj_sigma = pw._dptr(keep["sig"])
+    d.dH = pw._dptr(keep["dH"])
+    d.dS = pw._dptr(keep["dS"])
+    d.sinv_mode = over.get("sinv_mode", 0)
+    return d, keep
+
+
+@pytest.mark.parametrize("over,code", [
+    (dict(ncell=[1, 4, 4]), pw.PAWFE_EINVAL),
+    (dict(degree=7, nq=9), pw.PAWFE_EUNSUPPORTED),
+    (dict(degree=4, nq=5), pw.PAWFE_EUNSUPPORTED),
+    (dict(is_complex=1), pw.PAWFE_EUNSUPPORTED),
+    (dict(kpoint=[0.1, 0.0, 0.0]), pw.PAWFE_EINVAL),
+    (dict(sinv_mode=7), pw.PAWFE_EINVAL),
+    (dict(rcut=np.array([6.0, 1.5])), pw.PAWFE_EINVAL),
+    (dict(l=np.full(16, 3, dtype=np.int32)), pw.PAWFE_EINVAL),
+    (dict(sig=np.full(16, -1.0)), pw.PAWFE_EINVAL),
+    (dict(veff=np.full(64 * 216, np.nan)), pw.PAWFE_ENONFINITE),
+    (dict(dH=np.full(128, np.inf)), pw.PAWFE_ENONFINITE),
+])
+def test_build_rejects_bad_descriptor(over, code):
+    lib = _lib()
+    s = make_system("tiny", veff=False)
+    d, keep = _desc(s, **over)
+    h = C.c_void_p()
+    st = lib.pawfe_build_operator(C.byref(d), None, C.byref(h))
+    assert st == code, lib.pawfe_last_error()
+    assert not h.value
+    assert len(lib.pawfe_last_error()) > 0
+
+
+def test_null_operator_rejected():
+    lib = _lib()
+    x = C.c_void_p(1)
+    assert lib.pawfe_apply_H(None, x, 4, x, 4, 4, 0, None) == pw.PAWFE_EINVAL
+    assert lib.pawfe_apply_S(None, x, 4, x, 4, 4, 0, None) == pw.PAWFE_EINVAL
+    assert lib.pawfe_apply_Sinv(None, x, 4, x, 4, 4, 0, None) == pw.PAWFE_EINVAL
+    b = C.c_size_t()
+    assert lib.pawfe_cheb_filter_workspace(None, 4, 4, 0, C.byref(b)) == pw.PAWFE_EINVAL
+    assert lib.pawfe_rayleigh_ritz_workspace(None, 4, C.byref(b)) == pw.PAWFE_EINVAL
+    assert lib.pawfe_cheb_filter(None, x, 4, x, 4, 4, 4, None, 10, 0.0, 1.0, 2.0, 0, x, 1, None) \
+        == pw.PAWFE_EINVAL
+    assert lib.pawfe_rayleigh_ritz(None, x, 4, 4, x, x, x, 1, None) == pw.PAWFE_EINVAL
+    assert lib.pawfe_band_energy_grad(None, x, 4, 4, None, None, None, None, None) == pw.PAWFE_EINVAL
+    a = C.c_double()
+    assert lib.pawfe_lanczos_bounds(None, 10, 1, C.byref(a), C.byref(a), C.byref(a), None) \
+        == pw.PAWFE_EINVAL
+    assert lib.pawfe_destroy_operator(None) == pw.PAWFE_OK
