@@ -79,6 +79,38 @@ def cpu_baseline(system, nstates, degree, ncols=8):
     }
 
 
+def kernels_mode(op, s, gen, dev, args):
+    """Short run for hardware counters: the cell-local operator (FP32 and FP64)
+    on one block, then a plain device copy of known size (counter calibration)."""
+    import torch
+
+    from paper_2604_26037_amd import FP32, FP64
+    B = s.block
+    X = torch.randn((op.ndof, B), generator=gen, dtype=torch.float64, device=dev)
+    res = {}
+    for name, prec, dt in (("fp32", FP32, torch.float32), ("fp64", FP64, torch.float64)):
+        Xs = X.to(dt)
+        Ys = torch.zeros_like(Xs)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        op.apply_local(Xs, Ys, 0, 1.0, prec)
+        e0.record()
+        for _ in range(args.hx_reps):
+            op.apply_local(Xs, Ys, 0, 1.0, prec)
+        e1.record()
+        torch.cuda.synchronize()
+        res[name] = e0.elapsed_time(e1) / args.hx_reps / op.ncolour
+        log(f"cell-local {name}: {res[name]:.3f} ms per colour launch")
+        del Xs, Ys
+    nbytes = 1 << 30
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"calibration copy: {nbytes} bytes read and written per launch, 3 launches")
+    print(json.dumps({"mode": "kernels", "avg_launch_ms": res, "copy_bytes": nbytes}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,6 +120,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-fp64", action="store_true", help="do not time the FP64 filter")
     ap.add_argument("--hx-reps", type=int, default=5)
+    ap.add_argument("--mode", default="full", choices=["full", "kernels"],
+                    help="kernels: only the cell-local operator and a calibration copy (for counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the filter shards "
@@ -109,6 +143,8 @@ def main():
 
     gen = torch.Generator(device=dev)
     gen.manual_seed(int(s.x_seed) % (2 ** 63))
+    if args.mode == "kernels":
+        return kernels_mode(op, s, gen, dev, args)
     X = torch.randn((M, N), generator=gen, dtype=torch.float64, device=dev)
 
     tmin, tmax, beta = op.lanczos_bounds(k=20)
