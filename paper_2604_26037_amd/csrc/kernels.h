@@ -42,6 +42,9 @@ template <typename T>
 pawfe_status launch_cell(const pawfe_op* op, int mode, const T* X, int64_t ldx, T* Y, int64_t ldy,
                          int ncols, const double* lam, double alpha, hipStream_t s);
 
+template <typename T>
+pawfe_status launch_cell_mfma(const pawfe_op* op, int mode, const CellArgs<T>& a, hipStream_t s);
+
 // out[e][q] = W_q sum_n occ_n |u_n(x_{e,q})|^2
 pawfe_status launch_density(const pawfe_op* op, const double* X, int64_t ldx, int ncols,
                             const double* occ, double* out, hipStream_t s);

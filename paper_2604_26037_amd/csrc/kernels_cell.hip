@@ -18,6 +18,9 @@
 // at a time and cells of one colour share no DOF, so no atomics are needed
 // and the result is deterministic.
 
+#include <cstdlib>
+#include <string>
+
 #include "kernels.h"
 
 namespace pawfe {
@@ -391,6 +394,11 @@ pawfe_status launch_cell(const pawfe_op* op, int mode, const T* X, int64_t ldx, 
   a.n0 = op->n[0];
   a.n1 = op->n[1];
   a.n2 = op->n[2];
+  static const bool use_valu = [] {
+    const char* v = std::getenv("PAWFE_CELL_KERNEL");
+    return v && std::string(v) == "valu";
+  }();
+  if (!use_valu) return launch_cell_mfma<T>(op, mode, a, s);
   constexpr int CB = cb_of<T>();
   switch (op->p) {
     case 2: return run_cell<T, 3, 4, CB>(op, mode, a, s);
