@@ -123,36 +123,62 @@ __device__ __forceinline__ T nl_row(int sr, const DeviceTables& d, const T* __re
   return acc;
 }
 
-#define ROW_PROLOGUE                                                       \
-  const int lane = threadIdx.x & 63;                                       \
-  const int64_t I = (int64_t)blockIdx.x * kRowsPerWaveGroup +              \
-                    __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);      \
-  const int n = blockIdx.y * 64 + lane;                                    \
-  if (I >= M || n >= ncols) return;
+// Row-wise kernels: a block of 4 waves covers 4 x kRowsPerWave consecutive
+// DOF rows and 64 columns (lane <-> column, each wave walks its rows, so the
+// row index and its projector entries stay wave-uniform).  Blocks are
+// remapped so that every XCD streams one contiguous slab of rows: the
+// projector coefficients of the atoms in that slab then stay in its L2.
+constexpr int kRowsPerWave = 4;
+constexpr int kRowsPerBlock = kRowsPerWaveGroup * kRowsPerWave;
+
+__device__ __forceinline__ void row_tile(int nblocks, int ncoltiles, int& rowblock, int& coltile) {
+  const int w = blockIdx.x;
+  const int per = nblocks / 8, rem = nblocks % 8;
+  const int xcd = w % 8, idx = w / 8;
+  const int logical = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + idx;
+  rowblock = logical / ncoltiles;
+  coltile = logical % ncoltiles;
+}
+
+#define ROW_LOOP_BEGIN                                                                 \
+  int rb_, ct_;                                                                        \
+  row_tile(nblocks, ncoltiles, rb_, ct_);                                              \
+  const int lane = threadIdx.x & 63;                                                   \
+  const int wv_ = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);                    \
+  const int n = ct_ * 64 + lane;                                                       \
+  if (n >= ncols) return;                                                              \
+  for (int rr_ = 0; rr_ < kRowsPerWave; ++rr_) {                                       \
+    const int64_t I = ((int64_t)rb_ * kRowsPerWaveGroup + wv_) * kRowsPerWave + rr_;   \
+    if (I >= M) break;
+#define ROW_LOOP_END }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_node_nl_init(int64_t M, int ncols, const double* __restrict__ q,
-                                                      T* __restrict__ Y, int64_t ldy, const T* __restrict__ Cv,
-                                                      DeviceTables d) {
-  ROW_PROLOGUE
+__global__ void __launch_bounds__(256) k_node_nl_init(int64_t M, int ncols, int nblocks, int ncoltiles,
+                                                      const double* __restrict__ q, T* __restrict__ Y, int64_t ldy,
+                                                      const T* __restrict__ Cv, DeviceTables d) {
+  ROW_LOOP_BEGIN
   const int sr = d.node2srow[I];
   Y[I * ldy + n] = sr >= 0 ? nl_row<T>(sr, d, Cv, q, ncols, n) : T(0);
+  ROW_LOOP_END
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_node_sinv(int64_t M, int ncols, const T* __restrict__ X, int64_t ldx,
+__global__ void __launch_bounds__(256) k_node_sinv(int64_t M, int ncols, int nblocks, int ncoltiles,
+                                                   const T* __restrict__ X, int64_t ldx,
                                                    const double* __restrict__ dv, T* __restrict__ Y, int64_t ldy,
                                                    const T* __restrict__ Minv, const T* __restrict__ Cv,
                                                    DeviceTables d) {
-  ROW_PROLOGUE
+  ROW_LOOP_BEGIN
   const int sr = d.node2srow[I];
   T x = X[I * ldx + n];
   if (sr >= 0) x -= nl_row<T>(sr, d, Cv, dv, ncols, n);
   Y[I * ldy + n] = Minv[I] * x;
+  ROW_LOOP_END
 }
 
 template <typename TR>
-__global__ void __launch_bounds__(256) k_node_cheb(int64_t M, int ncols, const TR* __restrict__ RY,
+__global__ void __launch_bounds__(256) k_node_cheb(int64_t M, int ncols, int nblocks, int ncoltiles,
+                                                   const TR* __restrict__ RY,
                                                    TR* __restrict__ RX, TR* __restrict__ Tb, int64_t ld,
                                                    const double* __restrict__ Y, int64_t ldy,
                                                    const double* __restrict__ dv, const double* __restrict__ qv,
@@ -160,7 +186,7 @@ __global__ void __launch_bounds__(256) k_node_cheb(int64_t M, int ncols, const T
                                                    const double* __restrict__ lam_in, double a, double ac,
                                                    double zz, const TR* __restrict__ Minv,
                                                    const TR* __restrict__ Cv, DeviceTables d) {
-  ROW_PROLOGUE
+  ROW_LOOP_BEGIN
   const int sr = d.node2srow[I];
   const TR ry = RY[I * ld + n];
   const TR rx = RX[I * ld + n];
@@ -182,42 +208,49 @@ __global__ void __launch_bounds__(256) k_node_cheb(int64_t M, int ncols, const T
   const TR part = (TR)(-ac) * ry - (TR)zz * rx + cq;
   RX[I * ld + n] = (TR)((double)part + a * Y[I * ldy + n] * lamY[n]);
   if (I == 0) lamX[n] = a * lamY[n] * lam_in[n] - ac * lamY[n] - zz * lamX[n];
+  ROW_LOOP_END
 }
 
 template <typename TR>
-__global__ void __launch_bounds__(256) k_node_finalize(int64_t M, int ncols, const TR* __restrict__ RY,
+__global__ void __launch_bounds__(256) k_node_finalize(int64_t M, int ncols, int nblocks, int ncoltiles,
+                                                       const TR* __restrict__ RY,
                                                        int64_t ld, const double* __restrict__ dv,
                                                        const double* __restrict__ X, int64_t ldx,
                                                        const double* __restrict__ lamY, double* __restrict__ Xo,
                                                        int64_t ldo, const TR* __restrict__ Minv,
                                                        const TR* __restrict__ Cv, DeviceTables d) {
-  ROW_PROLOGUE
+  ROW_LOOP_BEGIN
   const int sr = d.node2srow[I];
   TR r = RY[I * ld + n];
   if (sr >= 0) r -= nl_row<TR>(sr, d, Cv, dv, ncols, n);
   const TR t = Minv[I] * r;
   Xo[I * ldo + n] = (double)t + X[I * ldx + n] * lamY[n];
+  ROW_LOOP_END
 }
 
 template <typename TR>
-__global__ void __launch_bounds__(256) k_cheb_init(int64_t M, int ncols, const double* __restrict__ Y,
+__global__ void __launch_bounds__(256) k_cheb_init(int64_t M, int ncols, int nblocks, int ncoltiles,
+                                                   const double* __restrict__ Y,
                                                    int64_t ldy, TR* __restrict__ RY, TR* __restrict__ RX,
                                                    int64_t ld, double f, double c,
                                                    const double* __restrict__ lam_in, double* __restrict__ lamY,
                                                    double* __restrict__ lamX) {
-  ROW_PROLOGUE
+  ROW_LOOP_BEGIN
   RY[I * ld + n] = (TR)(f * Y[I * ldy + n]);
   RX[I * ld + n] = TR(0);
   if (I == 0) {
     lamY[n] = f * (lam_in[n] - c);
     lamX[n] = 1.0;
   }
+  ROW_LOOP_END
 }
 
-__global__ void __launch_bounds__(256) k_copy_cols(int64_t M, int ncols, const double* __restrict__ X, int64_t ldx,
+__global__ void __launch_bounds__(256) k_copy_cols(int64_t M, int ncols, int nblocks, int ncoltiles,
+                                                   const double* __restrict__ X, int64_t ldx,
                                                    double* __restrict__ Y, int64_t ldy) {
-  ROW_PROLOGUE
+  ROW_LOOP_BEGIN
   Y[I * ldy + n] = X[I * ldx + n];
+  ROW_LOOP_END
 }
 
 template <typename T>
@@ -383,8 +416,15 @@ __global__ void k_grad_dh(const double* __restrict__ c, int ncols, const double*
   out[d.poff2[a] + s * npj + t] = acc;
 }
 
-inline dim3 row_grid(int64_t M, int ncols) {
-  return dim3((unsigned)((M + kRowsPerWaveGroup - 1) / kRowsPerWaveGroup), (unsigned)((ncols + 63) / 64));
+struct RowGrid {
+  int nblocks, ncoltiles;
+  dim3 grid() const { return dim3((unsigned)nblocks); }
+};
+inline RowGrid row_grid(int64_t M, int ncols) {
+  RowGrid g;
+  g.ncoltiles = (ncols + 63) / 64;
+  g.nblocks = (int)((M + kRowsPerBlock - 1) / kRowsPerBlock) * g.ncoltiles;
+  return g;
 }
 
 template <typename T>
@@ -441,7 +481,8 @@ pawfe_status launch_atom_gcorr(const pawfe_op* op, const double* c, const double
 template <typename T>
 pawfe_status launch_node_nl_init(const pawfe_op* op, const double* q, int ncols, T* Y, int64_t ldy, hipStream_t s) {
   if (ncols <= 0) return PAWFE_OK;
-  hipLaunchKernelGGL(k_node_nl_init<T>, row_grid(op->M, ncols), dim3(256), 0, s, op->M, ncols, q, Y, ldy,
+  const RowGrid g = row_grid(op->M, ncols);
+  hipLaunchKernelGGL(k_node_nl_init<T>, g.grid(), dim3(256), 0, s, op->M, ncols, g.nblocks, g.ncoltiles, q, Y, ldy,
                      pick<T>(op->d.Cvals, op->d.Cvals_f), op->d);
   PAWFE_HIP(hipGetLastError());
   return PAWFE_OK;
@@ -453,7 +494,9 @@ template <typename T>
 pawfe_status launch_node_sinv(const pawfe_op* op, const T* X, int64_t ldx, const double* dv, int ncols, T* Y,
                               int64_t ldy, hipStream_t s) {
   if (ncols <= 0) return PAWFE_OK;
-  hipLaunchKernelGGL(k_node_sinv<T>, row_grid(op->M, ncols), dim3(256), 0, s, op->M, ncols, X, ldx, dv, Y, ldy,
+  const RowGrid g = row_grid(op->M, ncols);
+  hipLaunchKernelGGL(k_node_sinv<T>, g.grid(), dim3(256), 0, s, op->M, ncols, g.nblocks, g.ncoltiles, X, ldx, dv, Y,
+                     ldy,
                      pick<T>(op->d.Minv, op->d.Minv_f), pick<T>(op->d.Cvals, op->d.Cvals_f), op->d);
   PAWFE_HIP(hipGetLastError());
   return PAWFE_OK;
@@ -467,7 +510,9 @@ template <typename TR>
 pawfe_status launch_node_cheb(const pawfe_op* op, const TR* RY, TR* RX, TR* Tb, int64_t ld, const double* Y,
                               int64_t ldy, const double* dv, const double* qv, const double* lamY, double* lamX,
                               const double* lam_in, double a, double ac, double zz, int ncols, hipStream_t s) {
-  hipLaunchKernelGGL(k_node_cheb<TR>, row_grid(op->M, ncols), dim3(256), 0, s, op->M, ncols, RY, RX, Tb, ld, Y, ldy,
+  const RowGrid g = row_grid(op->M, ncols);
+  hipLaunchKernelGGL(k_node_cheb<TR>, g.grid(), dim3(256), 0, s, op->M, ncols, g.nblocks, g.ncoltiles, RY, RX, Tb,
+                     ld, Y, ldy,
                      dv, qv, lamY, lamX, lam_in, a, ac, zz, pick<TR>(op->d.Minv, op->d.Minv_f),
                      pick<TR>(op->d.Cvals, op->d.Cvals_f), op->d);
   PAWFE_HIP(hipGetLastError());
@@ -483,7 +528,9 @@ template pawfe_status launch_node_cheb<float>(const pawfe_op*, const float*, flo
 template <typename TR>
 pawfe_status launch_node_finalize(const pawfe_op* op, const TR* RY, int64_t ld, const double* dv, const double* X,
                                   int64_t ldx, const double* lamY, double* Xo, int64_t ldo, int ncols, hipStream_t s) {
-  hipLaunchKernelGGL(k_node_finalize<TR>, row_grid(op->M, ncols), dim3(256), 0, s, op->M, ncols, RY, ld, dv, X, ldx,
+  const RowGrid g = row_grid(op->M, ncols);
+  hipLaunchKernelGGL(k_node_finalize<TR>, g.grid(), dim3(256), 0, s, op->M, ncols, g.nblocks, g.ncoltiles, RY, ld, dv,
+                     X, ldx,
                      lamY, Xo, ldo, pick<TR>(op->d.Minv, op->d.Minv_f), pick<TR>(op->d.Cvals, op->d.Cvals_f), op->d);
   PAWFE_HIP(hipGetLastError());
   return PAWFE_OK;
@@ -497,7 +544,9 @@ template pawfe_status launch_node_finalize<float>(const pawfe_op*, const float*,
 template <typename TR>
 pawfe_status launch_cheb_init(const pawfe_op* op, const double* Y, int64_t ldy, TR* RY, TR* RX, int64_t ld, double f,
                               double c, const double* lam_in, double* lamY, double* lamX, int ncols, hipStream_t s) {
-  hipLaunchKernelGGL(k_cheb_init<TR>, row_grid(op->M, ncols), dim3(256), 0, s, op->M, ncols, Y, ldy, RY, RX, ld, f, c,
+  const RowGrid g = row_grid(op->M, ncols);
+  hipLaunchKernelGGL(k_cheb_init<TR>, g.grid(), dim3(256), 0, s, op->M, ncols, g.nblocks, g.ncoltiles, Y, ldy, RY, RX,
+                     ld, f, c,
                      lam_in, lamY, lamX);
   PAWFE_HIP(hipGetLastError());
   return PAWFE_OK;
@@ -509,7 +558,8 @@ template pawfe_status launch_cheb_init<float>(const pawfe_op*, const double*, in
 
 pawfe_status launch_copy_cols(const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t nrows, int ncols,
                               hipStream_t s) {
-  hipLaunchKernelGGL(k_copy_cols, row_grid(nrows, ncols), dim3(256), 0, s, nrows, ncols, X, ldx, Y, ldy);
+  const RowGrid g = row_grid(nrows, ncols);
+  hipLaunchKernelGGL(k_copy_cols, g.grid(), dim3(256), 0, s, nrows, ncols, g.nblocks, g.ncoltiles, X, ldx, Y, ldy);
   PAWFE_HIP(hipGetLastError());
   return PAWFE_OK;
 }
