@@ -10,11 +10,14 @@
 // is the 1-D table, held in registers for the whole pass (one value per
 // lane per k-step), D (16 r x 16 o) is written back to LDS.
 //
-// LDS holds three slabs of 8x8x8 padded slots per column (slot
-// (z*8 + y)*8 + x), so every pass can run in place: a wave owns whole lines
-// and reads all of a tile's inputs before writing its outputs.
+// LDS holds three slabs of 8x8x8 slots per column (slot (z*8 + y)*8 + x),
+// zero-initialized.  Every pass walks all 64 padded lines of the slab with
+// linear addressing and unconditional stores: rows and outputs beyond the
+// true extents only ever meet zero coefficients, so they stay finite and
+// never reach a true slot.  Each wave owns whole lines and reads all of a
+// tile's inputs before writing its outputs, so the passes run in place.
 //
-// Order of the passes (U = gathered cell values, slab A):
+// Passes (U = gathered cell values, slab A):
 //   P1 x: [Bx; Kx; Mx] U  -> slab B (V path), slab C (Kx U), slab A (Mx U)
 //   P2 y: By     (slab B)        P3 z: Bz, times V(q) W_q (slab B)
 //   P4 z: Bz^T   (slab B)        P5 y: By^T (slab B)
@@ -30,6 +33,9 @@ namespace pawfe {
 
 namespace {
 
+// Operand layouts (checked on gfx950): A[i][k] in lane i + 16k, B[k][j] in
+// lane j + 16k; the 16x16 result D[i][j] sits in lane j + 16*g, element e,
+// with i = 4g + e for f32 and i = g + 4e for f64.
 template <typename T>
 struct Mma;
 template <>
@@ -38,6 +44,7 @@ struct Mma<float> {
   static __device__ __forceinline__ V4 op(float a, float b, V4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  static __device__ __forceinline__ int row(int g, int e) { return 4 * g + e; }
 };
 template <>
 struct Mma<double> {
@@ -45,38 +52,39 @@ struct Mma<double> {
   static __device__ __forceinline__ V4 op(double a, double b, V4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  static __device__ __forceinline__ int row(int g, int e) { return g + 4 * e; }
 };
 
 constexpr int kSlots = 512;   // 8 x 8 x 8 padded slots per column
 
 __device__ __forceinline__ int slot(int x, int y, int z) { return (z * 8 + y) * 8 + x; }
 
-// slot of (line, k) for a contraction along `ax`; the line enumerates the two
-// other axes with the lower axis fastest (extent e0 of that lower axis).
+// Slot of padded line L at index 0 for a contraction along AX.  The line
+// enumerates the other two axes (u, v) = (L % 8, L / 8), lower axis first.
 template <int AX>
-__device__ __forceinline__ int line_slot(int line, int e0, int k) {
-  const int u = line % e0, v = line / e0;
-  if constexpr (AX == 0) return slot(k, u, v);
-  else if constexpr (AX == 1) return slot(u, k, v);
-  else return slot(u, v, k);
+__device__ __forceinline__ int line_base(int L) {
+  if constexpr (AX == 0) return L * 8;                         // (y, z)
+  else if constexpr (AX == 1) return (L >> 3) * 64 + (L & 7);  // (x, z)
+  else return L;                                               // (x, y)
 }
+template <int AX>
+constexpr int kstride() { return AX == 0 ? 1 : (AX == 1 ? 8 : 64); }
 
 }  // namespace
 
-// One MFMA contraction pass.  Coefficient callback cf(o, k) gives the stacked
-// matrix; inputs k < K0 come from `in0`, K0 <= k < K0 + K1 from `in1`;
-// outputs o < O0 go to `out0`, then the next O1 to `out1`, the next O2 to
-// `out2` (each indexed from 0).  post(line, o, col, value, old) returns the
-// value to store (pointwise V(q) W_q, or an accumulation in the last pass).
-template <typename T, int AX, int CB, int K0, int K1, int O0, int O1, int O2, int NLINES, int E0, class CF,
-          class POST>
-__device__ __forceinline__ void mfma_pass(const T* in0, const T* in1, T* out0, T* out1, T* out2, CF cf,
-                                          POST post) {
+// One MFMA contraction pass over the 64 padded lines.
+//   inputs:  NIN buffers; input k in [8b, 8b + 8) comes from in[b]
+//   outputs: NG groups of 8; output o in [8g, 8g + 8) goes to out[g]
+//   cf(o, k): stacked coefficient (0 outside the true extents)
+//   post(L, o, col, value, old): the value stored
+template <typename T, int AX, int CB, int NIN, int NG, class CF, class POST>
+__device__ __forceinline__ void mfma_pass(T* const* in, T* const* out, CF cf, POST post) {
   using M = Mma<T>;
-  constexpr int KT = K0 + K1, NKS = (KT + 3) / 4;
-  constexpr int OT = O0 + O1 + O2, NOB = (OT + 15) / 16;
-  constexpr int LPT = 16 / CB;                      // lines per tile
-  constexpr int NTILES = (NLINES + LPT - 1) / LPT;
+  constexpr int NKS = 2 * NIN;                 // k-steps of 4
+  constexpr int NOB = (NG + 1) / 2;            // 16-wide output blocks
+  constexpr int LPT = 16 / CB;                 // lines per tile
+  constexpr int NT = 64 / LPT;                 // tiles per pass
+  constexpr int KS = kstride<AX>() * CB;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int r = lane & 15, kr = lane >> 4;
@@ -84,22 +92,17 @@ __device__ __forceinline__ void mfma_pass(const T* in0, const T* in1, T* out0, T
 #pragma unroll
   for (int ob = 0; ob < NOB; ++ob)
 #pragma unroll
-    for (int ks = 0; ks < NKS; ++ks) {
-      const int o = ob * 16 + r, k = ks * 4 + kr;
-      bco[ob][ks] = (o < OT && k < KT) ? cf(o, k) : T(0);
-    }
-  for (int t = wave; t < NTILES; t += 4) {
-    const int line_a = t * LPT + r / CB, col_a = r % CB;
+    for (int ks = 0; ks < NKS; ++ks) bco[ob][ks] = cf(ob * 16 + r, ks * 4 + kr);
+  const int la = r / CB, ca = r % CB;
+#pragma unroll
+  for (int it = 0; it < NT / 4; ++it) {
+    const int t = wave + 4 * it;
+    const int abase = line_base<AX>(t * LPT + la) * CB + ca;
     T av[NKS];
 #pragma unroll
     for (int ks = 0; ks < NKS; ++ks) {
-      const int k = ks * 4 + kr;
-      T v = T(0);
-      if (line_a < NLINES) {
-        if (k < K0) v = in0[line_slot<AX>(line_a, E0, k) * CB + col_a];
-        else if (k < KT) v = in1[line_slot<AX>(line_a, E0, k - K0) * CB + col_a];
-      }
-      av[ks] = v;
+      const int k = ks * 4 + kr;            // from buffer ks / 2, index k % 8
+      av[ks] = in[ks / 2][abase + (k & 7) * KS];
     }
     typename M::V4 acc[NOB];
 #pragma unroll
@@ -109,19 +112,19 @@ __device__ __forceinline__ void mfma_pass(const T* in0, const T* in1, T* out0, T
       for (int ks = 0; ks < NKS; ++ks) acc[ob] = M::op(av[ks], bco[ob][ks], acc[ob]);
     }
 #pragma unroll
-    for (int ob = 0; ob < NOB; ++ob)
+    for (int ob = 0; ob < NOB; ++ob) {
+      const int o = ob * 16 + r;
+      if (2 * ob + 1 < NG || r < 8) {
+        T* dst = out[o >> 3];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int rr = kr * 4 + j;
-        const int line = t * LPT + rr / CB, col = rr % CB;
-        const int o = ob * 16 + r;
-        if (line < NLINES && o < OT) {
-          T* dst = o < O0 ? out0 : (o < O0 + O1 ? out1 : out2);
-          const int oo = o < O0 ? o : (o < O0 + O1 ? o - O0 : o - O0 - O1);
-          const int s = line_slot<AX>(line, E0, oo) * CB + col;
-          dst[s] = post(line, o, col, acc[ob][j], dst[s]);
+        for (int e = 0; e < 4; ++e) {
+          const int rr = M::row(kr, e);
+          const int L2 = t * LPT + rr / CB, c2 = rr % CB;
+          const int s = line_base<AX>(L2) * CB + c2 + (o & 7) * KS;
+          dst[s] = post(L2, o, c2, acc[ob][e], dst[s]);
         }
       }
+    }
   }
 }
 
@@ -154,7 +157,9 @@ __global__ void __launch_bounds__(256) k_cell_mfma(CellArgs<T> A, const Tab1D<T>
     return (int64_t)gx + (int64_t)Gx * ((int64_t)gy + (int64_t)Gy * gz);
   };
 
-  // extraction: gather the cell's CB columns into slab A
+  // zero the padded slabs, then extraction (gather) of the cell's columns
+  for (int i = threadIdx.x; i < 3 * kSlots * CB; i += 256) smem[i] = T(0);
+  __syncthreads();
   for (int i = threadIdx.x; i < NL * CB; i += 256) {
     const int l = i / CB, col = i % CB;
     const int a = l % NP, b = (l / NP) % NP, c = l / (NP * NP);
@@ -164,37 +169,44 @@ __global__ void __launch_bounds__(256) k_cell_mfma(CellArgs<T> A, const Tab1D<T>
   __syncthreads();
 
   auto store = [](int, int, int, T v, T) { return v; };
+  // padded 1-D tables: zero outside the true extents
+  auto Bm = [&](int q, int a) { return (q < NQ && a < NP) ? tab.B[q * NP + a] : T(0); };
+  auto Km = [&](int a, int b) { return (a < NP && b < NP) ? tab.K1[a * NP + b] : T(0); };
+  auto Mm = [&](int a, int b) { return (a < NP && b < NP) ? tab.M1[a * NP + b] : T(0); };
   T* OUT;
   if constexpr (MODE == kModeMass) {
-    // x: Mx U -> C;  y: My C -> C;  z: detJ Mz C -> C
-    mfma_pass<T, 0, CB, NP, 0, NP, 0, 0, NP * NP, NP>(
-        SA, SA, SC, SC, SC, [&](int o, int k) { return tab.M1[o * NP + k]; }, store);
+    T* inA[1] = {SA};
+    T* inC[1] = {SC};
+    T* oC[1] = {SC};
+    mfma_pass<T, 0, CB, 1, 1>(inA, oC, [&](int o, int k) { return Mm(o, k); }, store);
     __syncthreads();
-    mfma_pass<T, 1, CB, NP, 0, NP, 0, 0, NP * NP, NP>(
-        SC, SC, SC, SC, SC, [&](int o, int k) { return tab.M1[o * NP + k]; }, store);
+    mfma_pass<T, 1, CB, 1, 1>(inC, oC, [&](int o, int k) { return Mm(o, k); }, store);
     __syncthreads();
-    mfma_pass<T, 2, CB, NP, 0, NP, 0, 0, NP * NP, NP>(
-        SC, SC, SC, SC, SC, [&](int o, int k) { return tab.detJ * tab.M1[o * NP + k]; }, store);
+    mfma_pass<T, 2, CB, 1, 1>(inC, oC, [&](int o, int k) { return tab.detJ * Mm(o, k); }, store);
     __syncthreads();
     OUT = SC;
   } else {
-    // P1 x: [Bx; Kx; Mx] U -> B, C, A(in place)
-    mfma_pass<T, 0, CB, NP, 0, NQ, NP, NP, NP * NP, NP>(
-        SA, SA, SB, SC, SA,
-        [&](int o, int k) {
-          return o < NQ ? tab.B[o * NP + k] : (o < NQ + NP ? tab.K1[(o - NQ) * NP + k] : tab.M1[(o - NQ - NP) * NP + k]);
-        },
-        store);
+    T* inA[1] = {SA};
+    T* inB[1] = {SB};
+    T* inCA[2] = {SC, SA};
+    T* oB[1] = {SB};
+    T* oC[1] = {SC};
+    T* oBCA[3] = {SB, SC, SA};
+    T* oCA[2] = {SC, SA};
+    // P1 x: [Bx; Kx; Mx] U
+    mfma_pass<T, 0, CB, 1, 3>(
+        inA, oBCA,
+        [&](int o, int k) { return o < 8 ? Bm(o, k) : (o < 16 ? Km(o - 8, k) : Mm(o - 16, k)); }, store);
     __syncthreads();
-    // P2 y: By on slab B; lines (x in NQ, z in NP)
-    mfma_pass<T, 1, CB, NP, 0, NQ, 0, 0, NQ * NP, NQ>(
-        SB, SB, SB, SB, SB, [&](int o, int k) { return tab.B[o * NP + k]; }, store);
+    // P2 y: By
+    mfma_pass<T, 1, CB, 1, 1>(inB, oB, [&](int o, int k) { return Bm(o, k); }, store);
     __syncthreads();
-    // P3 z: Bz, then V(q) W_q (minus lambda_n W_q); lines (x in NQ, y in NQ)
+    // P3 z: Bz, then V(q) W_q (minus lambda_n W_q); lines are (qa, qb)
     {
       const T* Vw = A.Vw + (int64_t)e * (NQ * NQ * NQ);
-      auto vpost = [&](int line, int o, int col, T v, T) {
-        const int qa = line % NQ, qb = line / NQ;
+      auto vpost = [&](int L, int o, int col, T v, T) {
+        const int qa = L & 7, qb = L >> 3;
+        if (qa >= NQ || qb >= NQ || o >= NQ) return T(0);
         const int q = (o * NQ + qb) * NQ + qa;
         T s = Vw[q];
         if constexpr (MODE == kModeHRes) {
@@ -203,37 +215,30 @@ __global__ void __launch_bounds__(256) k_cell_mfma(CellArgs<T> A, const Tab1D<T>
         }
         return v * s;
       };
-      mfma_pass<T, 2, CB, NP, 0, NQ, 0, 0, NQ * NQ, NQ>(
-          SB, SB, SB, SB, SB, [&](int o, int k) { return tab.B[o * NP + k]; }, vpost);
+      mfma_pass<T, 2, CB, 1, 1>(inB, oB, [&](int o, int k) { return Bm(o, k); }, vpost);
     }
     __syncthreads();
-    // P4 z: Bz^T
-    mfma_pass<T, 2, CB, NQ, 0, NP, 0, 0, NQ * NQ, NQ>(
-        SB, SB, SB, SB, SB, [&](int o, int k) { return tab.B[k * NP + o]; }, store);
+    // P4 z: Bz^T;  P5 y: By^T
+    mfma_pass<T, 2, CB, 1, 1>(inB, oB, [&](int o, int k) { return Bm(k, o); }, store);
     __syncthreads();
-    // P5 y: By^T; lines (x in NQ, z in NP)
-    mfma_pass<T, 1, CB, NQ, 0, NP, 0, 0, NQ * NP, NQ>(
-        SB, SB, SB, SB, SB, [&](int o, int k) { return tab.B[k * NP + o]; }, store);
+    mfma_pass<T, 1, CB, 1, 1>(inB, oB, [&](int o, int k) { return Bm(k, o); }, store);
     __syncthreads();
     // P6 y: P = fx My C + fy Ky A -> C ; Q = My A -> A
-    mfma_pass<T, 1, CB, NP, NP, NP, NP, 0, NP * NP, NP>(
-        SC, SA, SC, SA, SA,
+    mfma_pass<T, 1, CB, 2, 2>(
+        inCA, oCA,
         [&](int o, int k) {
-          if (o < NP) return k < NP ? tab.f[0] * tab.M1[o * NP + k] : tab.f[1] * tab.K1[o * NP + (k - NP)];
-          return k < NP ? T(0) : tab.M1[(o - NP) * NP + (k - NP)];
+          if (o < 8) return k < 8 ? tab.f[0] * Mm(o, k) : tab.f[1] * Km(o, k - 8);
+          return k < 8 ? T(0) : Mm(o - 8, k - 8);
         },
         store);
     __syncthreads();
     // P7 z: kinetic = Mz P + fz Kz Q -> C
-    mfma_pass<T, 2, CB, NP, NP, NP, 0, 0, NP * NP, NP>(
-        SC, SA, SC, SC, SC,
-        [&](int o, int k) { return k < NP ? tab.M1[o * NP + k] : tab.f[2] * tab.K1[o * NP + (k - NP)]; },
-        store);
+    mfma_pass<T, 2, CB, 2, 1>(
+        inCA, oC, [&](int o, int k) { return k < 8 ? Mm(o, k) : tab.f[2] * Km(o, k - 8); }, store);
     __syncthreads();
     // P8 x: Bx^T on slab B, accumulated into C
-    mfma_pass<T, 0, CB, NQ, 0, NP, 0, 0, NP * NP, NP>(
-        SB, SB, SC, SC, SC, [&](int o, int k) { return tab.B[k * NP + o]; },
-        [](int, int, int, T v, T old) { return old + v; });
+    mfma_pass<T, 0, CB, 1, 1>(inB, oC, [&](int o, int k) { return Bm(k, o); },
+                              [](int, int, int, T v, T old) { return old + v; });
     __syncthreads();
     OUT = SC;
   }
@@ -283,7 +288,7 @@ pawfe_status run_cell_mfma(const pawfe_op* op, int mode, CellArgs<T> a, hipStrea
 
 template <typename T>
 pawfe_status launch_cell_mfma(const pawfe_op* op, int mode, const CellArgs<T>& a, hipStream_t s) {
-  constexpr int CB = 8;
+  constexpr int CB = sizeof(T) == 8 ? 4 : 8;
   switch (op->p) {
     case 2: return run_cell_mfma<T, 3, 4, CB>(op, mode, a, s);
     case 3: return run_cell_mfma<T, 4, 5, CB>(op, mode, a, s);

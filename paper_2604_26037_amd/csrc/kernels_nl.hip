@@ -128,7 +128,7 @@ __device__ __forceinline__ T nl_row(int sr, const DeviceTables& d, const T* __re
 // row index and its projector entries stay wave-uniform).  Blocks are
 // remapped so that every XCD streams one contiguous slab of rows: the
 // projector coefficients of the atoms in that slab then stay in its L2.
-constexpr int kRowsPerWave = 4;
+constexpr int kRowsPerWave = 1;
 constexpr int kRowsPerBlock = kRowsPerWaveGroup * kRowsPerWave;
 
 __device__ __forceinline__ void row_tile(int nblocks, int ncoltiles, int& rowblock, int& coltile) {
