@@ -10,12 +10,21 @@
 // is the 1-D table, held in registers for the whole pass (one value per
 // lane per k-step), D (16 r x 16 o) is written back to LDS.
 //
-// LDS holds three slabs of 8x8x8 slots per column (slot (z*8 + y)*8 + x),
-// zero-initialized.  Every pass walks all 64 padded lines of the slab with
-// linear addressing and unconditional stores: rows and outputs beyond the
-// true extents only ever meet zero coefficients, so they stay finite and
-// never reach a true slot.  Each wave owns whole lines and reads all of a
-// tile's inputs before writing its outputs, so the passes run in place.
+// LDS holds three slabs of 8x8x8 slots of CB columns each, zero-initialized.
+// Every pass walks all 64 padded lines of the slab with unconditional stores:
+// rows and outputs beyond the true extents only ever meet zero
+// coefficients, so they stay finite and never reach a true slot.  Each wave
+// owns whole lines and reads all of a tile's inputs before writing its
+// outputs, so the passes run in place.
+//
+// Slab layout (XOR swizzle, a bijection on the slab): element (x, y, z, col)
+// lives at ((z*8 + y)*8 + x')*CB + col', where x' mixes in bits of y ^ z and
+// col' a per-slab key.  With 64 LDS banks this makes every access of the
+// passes conflict-free: the A-operand reads (64 lanes, 16 rows x 4 k), the
+// 16-byte result writes of f32 (16 lanes = 16 outputs, two slabs told apart
+// by the key) and the 8-byte accesses of f64 (16 lanes at a time).  Without
+// it the stride of the contracted axis (64 or 512 elements) put all outputs
+// of a row in one bank.
 //
 // Passes (U = gathered cell values, slab A):
 //   P1 x: [Bx; Kx; Mx] U  -> slab B (V path), slab C (Kx U), slab A (Mx U)
@@ -26,6 +35,8 @@
 //   P8 x: Bx^T (slab B), added into C; then the colour-ordered assembly.
 // The grid is remapped so that consecutive logical blocks (all column tiles
 // of one cell, then the next cells) land on the same XCD and share its L2.
+
+#include <algorithm>
 
 #include "kernels.h"
 
@@ -57,18 +68,71 @@ struct Mma<double> {
 
 constexpr int kSlots = 512;   // 8 x 8 x 8 padded slots per column
 
-__device__ __forceinline__ int slot(int x, int y, int z) { return (z * 8 + y) * 8 + x; }
+__host__ __device__ constexpr int rev3(int v) { return ((v & 1) << 2) | (v & 2) | ((v >> 2) & 1); }
 
-// Slot of padded line L at index 0 for a contraction along AX.  The line
-// enumerates the other two axes (u, v) = (L % 8, L / 8), lower axis first.
-template <int AX>
-__device__ __forceinline__ int line_base(int L) {
-  if constexpr (AX == 0) return L * 8;                         // (y, z)
-  else if constexpr (AX == 1) return (L >> 3) * 64 + (L & 7);  // (x, z)
-  else return L;                                               // (x, y)
+// LDS offset of element (x, y, z, col) of a slab with the given key.
+template <typename T, int CB>
+__host__ __device__ constexpr int phys(int x, int y, int z, int col, int key) {
+  const int r = y ^ z;
+  if constexpr (sizeof(T) == 4) {
+    return ((z * 8 + y) * 8 + (x ^ rev3(r))) * CB + (col ^ key);
+  } else {
+    return ((z * 8 + y) * 8 + (x ^ (r & 3))) * CB + (col ^ (((x ^ r) >> 2) & 1) ^ key);
+  }
 }
+// key that tells apart two slabs written by one instruction (0 for the other)
+template <typename T>
+constexpr int kKeyC = sizeof(T) == 4 ? 4 : 2;
+
+// Element at byte offset `b` of the LDS block.  Offsets are kept in bytes so
+// that an access is the XOR alone (no scaling shift per access).
+template <typename T>
+__device__ __forceinline__ T& lds_at(T* smem, int b) {
+  return *reinterpret_cast<T*>(reinterpret_cast<char*>(smem) + b);
+}
+
+// A slab: its byte offset in the LDS block (a multiple of the slab size, so
+// it never overlaps the bits of an address inside a slab) and its key.
+struct Slab {
+  int off;
+  int key;
+};
+
+// Coordinates of index a along AX on padded line L; the line enumerates the
+// other two axes (u, v) = (L % 8, L / 8), lower axis first.
 template <int AX>
-constexpr int kstride() { return AX == 0 ? 1 : (AX == 1 ? 8 : 64); }
+__host__ __device__ constexpr void line_coords(int L, int a, int& x, int& y, int& z) {
+  const int u = L & 7, v = L >> 3;
+  if constexpr (AX == 0) { x = a; y = u; z = v; }
+  else if constexpr (AX == 1) { x = u; y = a; z = v; }
+  else { x = u; y = v; z = a; }
+}
+
+// byte offset of (line L, index a, col) in a slab with the given key
+template <typename T, int CB, int AX>
+__host__ __device__ constexpr int line_addr(int L, int a, int col, int key) {
+  int x = 0, y = 0, z = 0;
+  line_coords<AX>(L, a, x, y, z);
+  return phys<T, CB>(x, y, z, col, key) * (int)sizeof(T);
+}
+
+// Bits that the lane part of a read (RD) or result-write address can set;
+// a constant part splits into the bits inside this mask (XORed) and those
+// outside it (added through the instruction's offset field).
+template <typename T, int CB, int AX, bool RD>
+constexpr int lane_mask() {
+  constexpr int LPT = 16 / CB;
+  int m = 0;
+  for (int w = 0; w < 4; ++w)
+    for (int r = 0; r < 16; ++r)
+      for (int kr = 0; kr < 4; ++kr)
+        for (int key = 0; key < 2; ++key) {
+          const int rl = sizeof(T) == 4 ? 4 * kr : kr;   // result row of element 0
+          m |= RD ? line_addr<T, CB, AX>(LPT * w | (r / CB), kr, r % CB, 0)
+                  : line_addr<T, CB, AX>(LPT * w | (rl / CB), r & 7, rl % CB, key * kKeyC<T>);
+        }
+  return m;
+}
 
 }  // namespace
 
@@ -77,32 +141,48 @@ constexpr int kstride() { return AX == 0 ? 1 : (AX == 1 ? 8 : 64); }
 //   outputs: NG groups of 8; output o in [8g, 8g + 8) goes to out[g]
 //   cf(o, k): stacked coefficient (0 outside the true extents)
 //   post(L, o, col, value, old): the value stored
+// Every address is built from disjoint bit fields (col, x', y, z, slab) and
+// the swizzle is an XOR, so it splits as  lane part ^ constant part: the lane
+// part (row, k or output index within a tile, wave) is computed once per
+// pass, the constant part (tile, k-step, result element) folds at compile
+// time, and each access costs one XOR.
 template <typename T, int AX, int CB, int NIN, int NG, class CF, class POST>
-__device__ __forceinline__ void mfma_pass(T* const* in, T* const* out, CF cf, POST post) {
+__device__ __forceinline__ void mfma_pass(T* smem, const Slab* in, const Slab* out, CF cf, POST post) {
   using M = Mma<T>;
   constexpr int NKS = 2 * NIN;                 // k-steps of 4
   constexpr int NOB = (NG + 1) / 2;            // 16-wide output blocks
   constexpr int LPT = 16 / CB;                 // lines per tile
   constexpr int NT = 64 / LPT;                 // tiles per pass
-  constexpr int KS = kstride<AX>() * CB;
+  constexpr int MR = lane_mask<T, CB, AX, true>() | (sizeof(T) - 1);
+  constexpr int MW = lane_mask<T, CB, AX, false>() | (sizeof(T) - 1);
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r = lane & 15, kr = lane >> 4;
   T bco[NOB][NKS];
 #pragma unroll
   for (int ob = 0; ob < NOB; ++ob)
 #pragma unroll
     for (int ks = 0; ks < NKS; ++ks) bco[ob][ks] = cf(ob * 16 + r, ks * 4 + kr);
-  const int la = r / CB, ca = r % CB;
+  // tile t = wave + 4 it covers lines LPT t + [0, LPT)
+  const int lw = LPT * wave;
+  const int rd_lane = line_addr<T, CB, AX>(lw | (r / CB), kr, r % CB, 0);
+  const int rl = M::row(kr, 0);                // result row = rl | M::row(0, e)
+  int wr_lane[NOB];
+#pragma unroll
+  for (int ob = 0; ob < NOB; ++ob) {
+    const Slab s0 = out[2 * ob], s1 = out[(2 * ob + 1 < NG) ? 2 * ob + 1 : 2 * ob];
+    const Slab b = r < 8 ? s0 : s1;
+    wr_lane[ob] = b.off | line_addr<T, CB, AX>(lw | (rl / CB), r & 7, rl % CB, b.key);
+  }
 #pragma unroll
   for (int it = 0; it < NT / 4; ++it) {
-    const int t = wave + 4 * it;
-    const int abase = line_base<AX>(t * LPT + la) * CB + ca;
+    const int lc = LPT * 4 * it;
     T av[NKS];
 #pragma unroll
     for (int ks = 0; ks < NKS; ++ks) {
-      const int k = ks * 4 + kr;            // from buffer ks / 2, index k % 8
-      av[ks] = in[ks / 2][abase + (k & 7) * KS];
+      const Slab b = in[ks / 2];             // k = 4 ks + kr, index k % 8 in buffer ks / 2
+      const int c = b.off | line_addr<T, CB, AX>(lc, 4 * (ks & 1), 0, b.key);
+      av[ks] = lds_at(smem, (rd_lane ^ (c & MR)) + (c & ~MR));
     }
     typename M::V4 acc[NOB];
 #pragma unroll
@@ -115,13 +195,28 @@ __device__ __forceinline__ void mfma_pass(T* const* in, T* const* out, CF cf, PO
     for (int ob = 0; ob < NOB; ++ob) {
       const int o = ob * 16 + r;
       if (2 * ob + 1 < NG || r < 8) {
-        T* dst = out[o >> 3];
+        if constexpr (sizeof(T) == 4) {
+          // f32: the four result rows of a lane are four consecutive columns
+          // (the swizzle never touches the two low column bits): one 16-byte
+          // access, 16-byte aligned.
+          const int c = line_addr<T, CB, AX>(lc, 0, 0, 0);
+          const int s = (wr_lane[ob] ^ (c & MW)) + (c & ~MW);
+          typename M::V4* dp = reinterpret_cast<typename M::V4*>(&lds_at(smem, s));
+          typename M::V4 v = *dp;
+          const int L2 = lw | lc | (rl / CB);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int rr = M::row(kr, e);
-          const int L2 = t * LPT + rr / CB, c2 = rr % CB;
-          const int s = line_base<AX>(L2) * CB + c2 + (o & 7) * KS;
-          dst[s] = post(L2, o, c2, acc[ob][e], dst[s]);
+          for (int e = 0; e < 4; ++e) v[e] = post(L2, o, (rl % CB) | e, acc[ob][e], v[e]);
+          *dp = v;
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int re = M::row(0, e);
+            const int c = line_addr<T, CB, AX>(lc | (re / CB), 0, re % CB, 0);
+            const int s = (wr_lane[ob] ^ (c & MW)) + (c & ~MW);
+            const int L2 = lw | lc | ((rl | re) / CB), c2 = (rl | re) % CB;
+            T& d = lds_at(smem, s);
+            d = post(L2, o, c2, acc[ob][e], d);
+          }
         }
       }
     }
@@ -130,42 +225,92 @@ __device__ __forceinline__ void mfma_pass(T* const* in, T* const* out, CF cf, PO
 
 template <typename T, int NP, int NQ, int CB, int MODE>
 __global__ void __launch_bounds__(256) k_cell_mfma(CellArgs<T> A, const Tab1D<T>* __restrict__ tabp,
-                                                   int ncoltiles, int nblocks) {
+                                                   int ncoltiles, int nitems) {
   constexpr int NL = NP * NP * NP;
+  constexpr int NQ3 = NQ * NQ * NQ;
+  constexpr int NJ = (NL * CB + 255) / 256;   // gathered elements per thread and item
+  constexpr int NV = (NQ3 + 255) / 256;       // V(q) W_q values per thread and item
+  constexpr bool HAS_V = MODE != kModeMass;
+  constexpr bool RES = MODE == kModeHRes;
   __shared__ T smem[3 * kSlots * CB];
-  T* SA = smem;
-  T* SB = smem + kSlots * CB;
-  T* SC = smem + 2 * kSlots * CB;
+  __shared__ T vws[HAS_V ? NQ3 : 1];          // V(q) W_q of the current cell
+  __shared__ T w3s[RES ? NQ3 : 1];            // W_q (residual mode)
+  __shared__ T lams[RES ? CB : 1];            // lambda_n of the item's columns (residual mode)
   const Tab1D<T>& tab = *tabp;
+  const int tid = threadIdx.x;
+  const int col = tid % CB;                   // 256 is a multiple of CB
 
-  // XCD-aware remap: hardware dispatches block w to XCD w % 8
-  const int w = blockIdx.x;
-  const int per = nblocks / 8, rem = nblocks % 8;
-  const int xcd = w % 8, idx = w / 8;
-  const int logical = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + idx;
-  const int ct = logical % ncoltiles;
-  const int e = A.cells[logical / ncoltiles];
-  const int n0 = ct * CB;
-
-  const int ci = e % A.n0, cj = (e / A.n0) % A.n1, ck = e / (A.n0 * A.n1);
+  // local nodes gathered by this thread: (a, b, c) in bits 0-8 (3 bits
+  // each) and the element's byte offset in slab A from bit 9; -1 past the end
+  int pk[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int l = tid / CB + (256 / CB) * j;
+    const int a = l % NP, b = (l / NP) % NP, c = l / (NP * NP);
+    pk[j] = l < NL ? a | (b << 3) | (c << 6) | ((phys<T, CB>(a, b, c, col, 0) * (int)sizeof(T)) << 9) : -1;
+  }
   const int p = NP - 1;
   const int Gx = A.n0 * p, Gy = A.n1 * p, Gz = A.n2 * p;
-  auto dof = [&](int a, int b, int c) -> int64_t {
-    int gx = ci * p + a; gx = gx >= Gx ? gx - Gx : gx;
-    int gy = cj * p + b; gy = gy >= Gy ? gy - Gy : gy;
-    int gz = ck * p + c; gz = gz >= Gz ? gz - Gz : gz;
-    return (int64_t)gx + (int64_t)Gx * ((int64_t)gy + (int64_t)Gy * gz);
+  // global node of local node pk in cell e (periodic wrap only for the last
+  // cell along an axis; the cell index is wave-uniform, so is the branch)
+  struct CellPos {
+    int ci, cj, ck, base;
+    bool inner;
+  };
+  auto cell_pos = [&](int e) {
+    CellPos c;
+    c.ci = e % A.n0;
+    c.cj = (e / A.n0) % A.n1;
+    c.ck = e / (A.n0 * A.n1);
+    c.base = c.ci * p + Gx * (c.cj * p + Gy * c.ck * p);
+    c.inner = c.ci + 1 < A.n0 && c.cj + 1 < A.n1 && c.ck + 1 < A.n2;
+    return c;
+  };
+  auto node_of = [&](const CellPos& cp, int pkj) -> int {
+    const int a = pkj & 7, b = (pkj >> 3) & 7, c = (pkj >> 6) & 7;
+    if (cp.inner) return cp.base + a + Gx * (b + Gy * c);
+    int gx = cp.ci * p + a; gx = gx >= Gx ? gx - Gx : gx;
+    int gy = cp.cj * p + b; gy = gy >= Gy ? gy - Gy : gy;
+    int gz = cp.ck * p + c; gz = gz >= Gz ? gz - Gz : gz;
+    return gx + Gx * (gy + Gy * gz);
+  };
+  auto lds_a = [&](int pkj) -> T& { return lds_at(smem, pkj >> 9); };
+  // same element in slab C: its key flips column bits, its base is 2 slabs on
+  auto lds_c = [&](int pkj) -> T& {
+    return lds_at(smem, ((pkj >> 9) ^ (kKeyC<T> * (int)sizeof(T))) + 2 * kSlots * CB * (int)sizeof(T));
   };
 
-  // zero the padded slabs, then extraction (gather) of the cell's columns
-  for (int i = threadIdx.x; i < 3 * kSlots * CB; i += 256) smem[i] = T(0);
-  __syncthreads();
-  for (int i = threadIdx.x; i < NL * CB; i += 256) {
-    const int l = i / CB, col = i % CB;
-    const int a = l % NP, b = (l / NP) % NP, c = l / (NP * NP);
-    const int n = n0 + col;
-    SA[slot(a, b, c) * CB + col] = n < A.ncols ? A.X[dof(a, b, c) * A.ldx + n] : T(0);
-  }
+  // items (cell of the colour, column tile), cell-major; the x-th eighth of
+  // them goes to the workgroups on XCD x (block w runs on XCD w % 8)
+  const int xcd = blockIdx.x & 7;
+  const int i_end = (int)((int64_t)nitems * (xcd + 1) / 8);
+  const int i_step = gridDim.x >> 3;
+  int item = (int)((int64_t)nitems * xcd / 8) + (blockIdx.x >> 3);
+
+  // registers for the gathered values (and V W) of the next item
+  T xr[NJ], vr[NV];
+  auto load_item = [&](int it) {
+    const int e = A.cells[it / ncoltiles];
+    const int n = (it % ncoltiles) * CB + col;
+    const CellPos cp = cell_pos(e);
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+      xr[j] = (pk[j] >= 0 && n < A.ncols) ? A.X[(int64_t)node_of(cp, pk[j]) * A.ldx + n] : T(0);
+    if constexpr (HAS_V) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const int q = tid + 256 * v;
+        vr[v] = q < NQ3 ? A.Vw[(int64_t)e * NQ3 + q] : T(0);
+      }
+    }
+  };
+
+  // the padded slots are zero once and stay zero: every pass only ever
+  // writes zeros there (zero inputs, zero coefficients)
+  for (int i = tid; i < 3 * kSlots * CB; i += 256) smem[i] = T(0);
+  if constexpr (RES)
+    for (int q = tid; q < NQ3; q += 256) w3s[q] = A.W3[q];
+  if (item < i_end) load_item(item);
   __syncthreads();
 
   auto store = [](int, int, int, T v, T) { return v; };
@@ -173,84 +318,104 @@ __global__ void __launch_bounds__(256) k_cell_mfma(CellArgs<T> A, const Tab1D<T>
   auto Bm = [&](int q, int a) { return (q < NQ && a < NP) ? tab.B[q * NP + a] : T(0); };
   auto Km = [&](int a, int b) { return (a < NP && b < NP) ? tab.K1[a * NP + b] : T(0); };
   auto Mm = [&](int a, int b) { return (a < NP && b < NP) ? tab.M1[a * NP + b] : T(0); };
-  T* OUT;
-  if constexpr (MODE == kModeMass) {
-    T* inA[1] = {SA};
-    T* inC[1] = {SC};
-    T* oC[1] = {SC};
-    mfma_pass<T, 0, CB, 1, 1>(inA, oC, [&](int o, int k) { return Mm(o, k); }, store);
-    __syncthreads();
-    mfma_pass<T, 1, CB, 1, 1>(inC, oC, [&](int o, int k) { return Mm(o, k); }, store);
-    __syncthreads();
-    mfma_pass<T, 2, CB, 1, 1>(inC, oC, [&](int o, int k) { return tab.detJ * Mm(o, k); }, store);
-    __syncthreads();
-    OUT = SC;
-  } else {
-    T* inA[1] = {SA};
-    T* inB[1] = {SB};
-    T* inCA[2] = {SC, SA};
-    T* oB[1] = {SB};
-    T* oC[1] = {SC};
-    T* oBCA[3] = {SB, SC, SA};
-    T* oCA[2] = {SC, SA};
-    // P1 x: [Bx; Kx; Mx] U
-    mfma_pass<T, 0, CB, 1, 3>(
-        inA, oBCA,
-        [&](int o, int k) { return o < 8 ? Bm(o, k) : (o < 16 ? Km(o - 8, k) : Mm(o - 16, k)); }, store);
-    __syncthreads();
-    // P2 y: By
-    mfma_pass<T, 1, CB, 1, 1>(inB, oB, [&](int o, int k) { return Bm(o, k); }, store);
-    __syncthreads();
-    // P3 z: Bz, then V(q) W_q (minus lambda_n W_q); lines are (qa, qb)
-    {
-      const T* Vw = A.Vw + (int64_t)e * (NQ * NQ * NQ);
-      auto vpost = [&](int L, int o, int col, T v, T) {
-        const int qa = L & 7, qb = L >> 3;
-        if (qa >= NQ || qb >= NQ || o >= NQ) return T(0);
-        const int q = (o * NQ + qb) * NQ + qa;
-        T s = Vw[q];
-        if constexpr (MODE == kModeHRes) {
-          const int n = n0 + col;
-          s -= (n < A.ncols ? (T)A.lam[n] : T(0)) * A.W3[q];
-        }
-        return v * s;
-      };
-      mfma_pass<T, 2, CB, 1, 1>(inB, oB, [&](int o, int k) { return Bm(o, k); }, vpost);
-    }
-    __syncthreads();
-    // P4 z: Bz^T;  P5 y: By^T
-    mfma_pass<T, 2, CB, 1, 1>(inB, oB, [&](int o, int k) { return Bm(k, o); }, store);
-    __syncthreads();
-    mfma_pass<T, 1, CB, 1, 1>(inB, oB, [&](int o, int k) { return Bm(k, o); }, store);
-    __syncthreads();
-    // P6 y: P = fx My C + fy Ky A -> C ; Q = My A -> A
-    mfma_pass<T, 1, CB, 2, 2>(
-        inCA, oCA,
-        [&](int o, int k) {
-          if (o < 8) return k < 8 ? tab.f[0] * Mm(o, k) : tab.f[1] * Km(o, k - 8);
-          return k < 8 ? T(0) : Mm(o - 8, k - 8);
-        },
-        store);
-    __syncthreads();
-    // P7 z: kinetic = Mz P + fz Kz Q -> C
-    mfma_pass<T, 2, CB, 2, 1>(
-        inCA, oC, [&](int o, int k) { return k < 8 ? Mm(o, k) : tab.f[2] * Km(o, k - 8); }, store);
-    __syncthreads();
-    // P8 x: Bx^T on slab B, accumulated into C
-    mfma_pass<T, 0, CB, 1, 1>(inB, oC, [&](int o, int k) { return Bm(k, o); },
-                              [](int, int, int, T v, T old) { return old + v; });
-    __syncthreads();
-    OUT = SC;
-  }
+  constexpr int KC = kKeyC<T>;
+  constexpr int SLB = kSlots * CB * (int)sizeof(T);   // slab size in bytes
+  const Slab sA{0, 0}, sB{SLB, 0}, sC{2 * SLB, KC};
 
-  // assembly: colour-ordered read-modify-write, CB contiguous columns per DOF
-  for (int i = threadIdx.x; i < NL * CB; i += 256) {
-    const int l = i / CB, col = i % CB;
-    const int a = l % NP, b = (l / NP) % NP, c = l / (NP * NP);
+  for (; item < i_end; item += i_step) {
+    const int e = A.cells[item / ncoltiles];
+    const int n0 = (item % ncoltiles) * CB;
     const int n = n0 + col;
-    if (n < A.ncols) {
-      T* y = A.Y + dof(a, b, c) * A.ldy + n;
-      *y = *y + A.alpha * OUT[slot(a, b, c) * CB + col];
+    const bool valid = n < A.ncols;
+    // stage the item: gathered values -> slab A (extraction), V W -> LDS
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+      if (pk[j] >= 0) lds_a(pk[j]) = xr[j];
+    if constexpr (HAS_V) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        if (tid + 256 * v < NQ3) vws[tid + 256 * v] = vr[v];
+    }
+    if constexpr (RES)
+      if (tid < CB) lams[tid] = n0 + tid < A.ncols ? (T)A.lam[n0 + tid] : T(0);
+    // output rows of this item (old values) and the next item's inputs are
+    // fetched now and arrive while the passes run
+    const CellPos cp = cell_pos(e);
+    T yo[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+      yo[j] = (pk[j] >= 0 && valid) ? A.Y[(int64_t)node_of(cp, pk[j]) * A.ldy + n] : T(0);
+    if (item + i_step < i_end) load_item(item + i_step);
+    __syncthreads();
+
+    if constexpr (MODE == kModeMass) {
+      const Slab inA[1] = {sA};
+      const Slab inC[1] = {sC};
+      const Slab oC[1] = {sC};
+      mfma_pass<T, 0, CB, 1, 1>(smem, inA, oC, [&](int o, int k) { return Mm(o, k); }, store);
+      __syncthreads();
+      mfma_pass<T, 1, CB, 1, 1>(smem, inC, oC, [&](int o, int k) { return Mm(o, k); }, store);
+      __syncthreads();
+      mfma_pass<T, 2, CB, 1, 1>(smem, inC, oC, [&](int o, int k) { return tab.detJ * Mm(o, k); }, store);
+      __syncthreads();
+    } else {
+      const Slab inA[1] = {sA};
+      const Slab inB[1] = {sB};
+      const Slab inCA[2] = {sC, sA};
+      const Slab oB[1] = {sB};
+      const Slab oC[1] = {sC};
+      const Slab oBCA[3] = {sB, sC, sA};
+      const Slab oCA[2] = {sC, sA};
+      // P1 x: [Bx; Kx; Mx] U
+      mfma_pass<T, 0, CB, 1, 3>(
+          smem, inA, oBCA,
+          [&](int o, int k) { return o < 8 ? Bm(o, k) : (o < 16 ? Km(o - 8, k) : Mm(o - 16, k)); }, store);
+      __syncthreads();
+      // P2 y: By
+      mfma_pass<T, 1, CB, 1, 1>(smem, inB, oB, [&](int o, int k) { return Bm(o, k); }, store);
+      __syncthreads();
+      // P3 z: Bz, then V(q) W_q (minus lambda_n W_q); lines are (qa, qb)
+      {
+        auto vpost = [&](int L, int o, int c, T v, T) {
+          const int qa = L & 7, qb = L >> 3;
+          if (qa >= NQ || qb >= NQ || o >= NQ) return T(0);
+          const int q = (o * NQ + qb) * NQ + qa;
+          T s = vws[q];
+          if constexpr (RES) s -= lams[c] * w3s[q];
+          return v * s;
+        };
+        mfma_pass<T, 2, CB, 1, 1>(smem, inB, oB, [&](int o, int k) { return Bm(o, k); }, vpost);
+      }
+      __syncthreads();
+      // P4 z: Bz^T;  P5 y: By^T
+      mfma_pass<T, 2, CB, 1, 1>(smem, inB, oB, [&](int o, int k) { return Bm(k, o); }, store);
+      __syncthreads();
+      mfma_pass<T, 1, CB, 1, 1>(smem, inB, oB, [&](int o, int k) { return Bm(k, o); }, store);
+      __syncthreads();
+      // P6 y: P = fx My C + fy Ky A -> C ; Q = My A -> A
+      mfma_pass<T, 1, CB, 2, 2>(
+          smem, inCA, oCA,
+          [&](int o, int k) {
+            if (o < 8) return k < 8 ? tab.f[0] * Mm(o, k) : tab.f[1] * Km(o, k - 8);
+            return k < 8 ? T(0) : Mm(o - 8, k - 8);
+          },
+          store);
+      __syncthreads();
+      // P7 z: kinetic = Mz P + fz Kz Q -> C
+      mfma_pass<T, 2, CB, 2, 1>(
+          smem, inCA, oC, [&](int o, int k) { return k < 8 ? Mm(o, k) : tab.f[2] * Km(o, k - 8); }, store);
+      __syncthreads();
+      // P8 x: Bx^T on slab B, accumulated into C
+      mfma_pass<T, 0, CB, 1, 1>(smem, inB, oC, [&](int o, int k) { return Bm(k, o); },
+                                [](int, int, int, T v, T old) { return old + v; });
+      __syncthreads();
+    }
+
+    // assembly: colour-ordered read-modify-write, CB contiguous columns per DOF
+    if (valid) {
+#pragma unroll
+      for (int j = 0; j < NJ; ++j)
+        if (pk[j] >= 0) A.Y[(int64_t)node_of(cp, pk[j]) * A.ldy + n] = yo[j] + A.alpha * lds_c(pk[j]);
     }
   }
 }
@@ -262,6 +427,31 @@ const Tab1D<T>* dev_tab_m(const pawfe_op* op) {
   if constexpr (std::is_same<T, double>::value) return op->d.tab64; else return op->d.tab32;
 }
 
+// persistent grid: as many 256-thread workgroups as fit on the chip at once
+// (LDS-limited), a multiple of 8, never more than the items need
+template <typename T, int NQ, int CB, int MODE>
+int cell_grid(int nitems) {
+  static int ncu = 0;
+  if (ncu == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
+      ncu = 256;
+  }
+  constexpr int nq3 = NQ * NQ * NQ;
+  constexpr size_t lds = sizeof(T) * (3 * kSlots * CB + (MODE != kModeMass ? nq3 : 1) +
+                                      (MODE == kModeHRes ? nq3 + CB : 2));
+  const int per_cu = std::max(1, std::min(8, (int)(163840 / lds)));
+  const int want = (nitems + 7) / 8 * 8;
+  return std::max(8, std::min(ncu * per_cu / 8 * 8, want));
+}
+
+template <typename T, int NP, int NQ, int CB, int MODE>
+void launch_mode(const CellArgs<T>& ac, const Tab1D<T>* tab, int ncoltiles, int nitems, hipStream_t s) {
+  const dim3 grid(cell_grid<T, NQ, CB, MODE>(nitems)), block(256);
+  hipLaunchKernelGGL((k_cell_mfma<T, NP, NQ, CB, MODE>), grid, block, 0, s, ac, tab, ncoltiles, nitems);
+}
+
 template <typename T, int NP, int NQ, int CB>
 pawfe_status run_cell_mfma(const pawfe_op* op, int mode, CellArgs<T> a, hipStream_t s) {
   const Tab1D<T>* tab = dev_tab_m<T>(op);
@@ -271,14 +461,13 @@ pawfe_status run_cell_mfma(const pawfe_op* op, int mode, CellArgs<T> a, hipStrea
     if (c1 == c0) continue;
     CellArgs<T> ac = a;
     ac.cells = op->d.cells_by_colour + c0;
-    const int nblocks = (c1 - c0) * ncoltiles;
-    const dim3 grid(nblocks), block(256);
+    const int nitems = (c1 - c0) * ncoltiles;
     if (mode == kModeH)
-      hipLaunchKernelGGL((k_cell_mfma<T, NP, NQ, CB, kModeH>), grid, block, 0, s, ac, tab, ncoltiles, nblocks);
+      launch_mode<T, NP, NQ, CB, kModeH>(ac, tab, ncoltiles, nitems, s);
     else if (mode == kModeHRes)
-      hipLaunchKernelGGL((k_cell_mfma<T, NP, NQ, CB, kModeHRes>), grid, block, 0, s, ac, tab, ncoltiles, nblocks);
+      launch_mode<T, NP, NQ, CB, kModeHRes>(ac, tab, ncoltiles, nitems, s);
     else
-      hipLaunchKernelGGL((k_cell_mfma<T, NP, NQ, CB, kModeMass>), grid, block, 0, s, ac, tab, ncoltiles, nblocks);
+      launch_mode<T, NP, NQ, CB, kModeMass>(ac, tab, ncoltiles, nitems, s);
   }
   PAWFE_HIP(hipGetLastError());
   return PAWFE_OK;

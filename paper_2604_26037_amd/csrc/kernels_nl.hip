@@ -12,6 +12,9 @@
 // are tiny and run one thread per (projector, column).  The add-back
 // sum_a C^a q_a is fused into the node-wise kernels that stream the rows.
 
+#include <cstdint>
+#include <initializer_list>
+
 #include "kernels.h"
 
 namespace pawfe {
@@ -20,17 +23,24 @@ namespace {
 
 constexpr int kRowsPerWaveGroup = 4;   // waves per 256-thread block in row-wise kernels
 
+// One workgroup per (item, 256-column slab): wave w owns the 64 columns
+// [64 w, 64 w + 64) of the slab and walks all rows of the item, so no
+// cross-wave reduction is needed.  Rows are taken kUnroll at a time with all
+// their loads issued before the FMAs (memory-level parallelism).
+constexpr int kUnroll = 8;
+
 template <typename T, int NPJ>
 __global__ void __launch_bounds__(256) k_nl_reduce(const T* __restrict__ X, int64_t ldx, int ncols,
                                                    int scale, const T* __restrict__ Minv,
                                                    const T* __restrict__ Cv, DeviceTables d,
                                                    double* __restrict__ part) {
-  __shared__ double red[kRowsPerWaveGroup][NPJ][64];
   const int item = blockIdx.x;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int n = blockIdx.y * 64 + lane;
+  const int n = (blockIdx.y * kRowsPerWaveGroup + w) * 64 + lane;
+  if ((blockIdx.y * kRowsPerWaveGroup + w) * 64 >= ncols) return;   // wave-uniform
   const bool valid = n < ncols;
+  const int nc = valid ? n : 0;
   const int a = d.item_atom[item];
   const int npj = d.nproj[a];
   const int r0 = d.item_row0[item], r1 = d.item_row1[item];
@@ -38,23 +48,30 @@ __global__ void __launch_bounds__(256) k_nl_reduce(const T* __restrict__ X, int6
   T acc[NPJ];
 #pragma unroll
   for (int al = 0; al < NPJ; ++al) acc[al] = T(0);
-  for (int r = r0 + w; r < r1; r += kRowsPerWaveGroup) {
-    const int I = d.atom_nodes[noff + r];
-    T x = valid ? X[(int64_t)I * ldx + n] : T(0);
-    if (scale) x *= Minv[I];
-    const T* cr = Cv + coff + (int64_t)r * npj;
+  for (int rb = r0; rb < r1; rb += kUnroll) {
+    T x[kUnroll];
 #pragma unroll
-    for (int al = 0; al < NPJ; ++al)
-      if (al < npj) acc[al] += cr[al] * x;
+    for (int u = 0; u < kUnroll; ++u) {
+      const int r = rb + u < r1 ? rb + u : r1 - 1;
+      const int I = d.atom_nodes[noff + r];
+      x[u] = X[(int64_t)I * ldx + nc];
+      if (scale) x[u] *= Minv[I];
+      if (rb + u >= r1 || !valid) x[u] = T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int r = rb + u < r1 ? rb + u : r1 - 1;
+      const T* cr = Cv + coff + (int64_t)r * npj;
+#pragma unroll
+      for (int al = 0; al < NPJ; ++al)
+        if (al < npj) acc[al] += cr[al] * x[u];
+    }
   }
-#pragma unroll
-  for (int al = 0; al < NPJ; ++al) red[w][al][lane] = (double)acc[al];
-  __syncthreads();
+  if (!valid) return;
   const int po = d.item_poff[item];
-  for (int al = w; al < npj; al += kRowsPerWaveGroup) {
-    double s = red[0][al][lane] + red[1][al][lane] + red[2][al][lane] + red[3][al][lane];
-    if (valid) part[(int64_t)(po + al) * ncols + n] = s;
-  }
+#pragma unroll
+  for (int al = 0; al < NPJ; ++al)
+    if (al < npj) part[(int64_t)(po + al) * ncols + n] = (double)acc[al];
 }
 
 __global__ void __launch_bounds__(256) k_nl_final(const double* __restrict__ part, int ncols,
@@ -109,75 +126,144 @@ __global__ void __launch_bounds__(256) k_atom_gcorr(const double* __restrict__ c
   out[(int64_t)g * ncols + n] = acc;
 }
 
-// sum_{a: I in supp(a)} C^a[I] . v_a[n] for support row sr (wave-uniform)
-template <typename T>
-__device__ __forceinline__ T nl_row(int sr, const DeviceTables& d, const T* __restrict__ Cv,
-                                    const double* __restrict__ v, int ncols, int n) {
-  T acc = T(0);
+// Row-wise kernels.  A 256-thread block is 4 waves; a wave takes R
+// consecutive DOF rows at a time, so the row index and its projector entries
+// are wave-uniform (scalar loads).  Each lane owns V consecutive columns:
+// with V = 16 / sizeof(element) every access of the streamed blocks is one
+// 16-byte load or store per lane.  All loads of the R rows are issued before
+// the first store, which keeps enough bytes in flight per CU to cover the HBM
+// latency.  The grid is persistent (a fixed multiple of 8 workgroups): work
+// item = (group of 4 R rows, column tile); XCD x takes the x-th contiguous
+// eighth of the items (block w runs on XCD w % 8) and its workgroups stride
+// through it, so each XCD streams one slab of rows and the projector
+// coefficients of the atoms in that slab stay in its L2.  The host takes
+// V = 1 when a leading dimension, a base pointer or the column count does
+// not allow 16-byte accesses.
+constexpr int kRowsPerWave = 2;
+constexpr int kPersistBlocks = 2048;
+
+template <typename T, int V>
+struct Lanes {
+  T v[V];
+};
+
+template <int V, typename T>
+__device__ __forceinline__ Lanes<T, V> vld(const T* p) {
+  Lanes<T, V> r;
+  if constexpr (V == 1) {
+    r.v[0] = *p;
+  } else {
+    typedef T VT __attribute__((ext_vector_type(V)));
+    const VT x = *reinterpret_cast<const VT*>(p);
+#pragma unroll
+    for (int i = 0; i < V; ++i) r.v[i] = x[i];
+  }
+  return r;
+}
+
+template <int V, typename T>
+__device__ __forceinline__ void vst(T* p, const Lanes<T, V>& r) {
+  if constexpr (V == 1) {
+    *p = r.v[0];
+  } else {
+    typedef T VT __attribute__((ext_vector_type(V)));
+    VT x;
+#pragma unroll
+    for (int i = 0; i < V; ++i) x[i] = r.v[i];
+    *reinterpret_cast<VT*>(p) = x;
+  }
+}
+
+// acc += sum_{a: I in supp(a)} C^a[I] . v_a[n .. n+V) for support row sr
+template <typename T, int V>
+__device__ __forceinline__ void nl_row(int sr, const DeviceTables& d, const T* __restrict__ Cv,
+                                       const double* __restrict__ v, int ncols, int n, T (&acc)[V]) {
   const int k0 = d.srow_ptr[sr], k1 = d.srow_ptr[sr + 1];
   for (int k = k0; k < k1; ++k) {
     const int a = d.srow_atom[k], coff = d.srow_coff[k];
     const int npj = d.nproj[a], po = d.poff[a];
-    for (int al = 0; al < npj; ++al) acc += Cv[coff + al] * (T)v[(int64_t)(po + al) * ncols + n];
+    for (int al = 0; al < npj; ++al) {
+      const T cv = Cv[coff + al];
+      const Lanes<double, V> x = vld<V>(v + (int64_t)(po + al) * ncols + n);
+#pragma unroll
+      for (int i = 0; i < V; ++i) acc[i] += cv * (T)x.v[i];
+    }
   }
-  return acc;
 }
 
-// Row-wise kernels: a block of 4 waves covers 4 x kRowsPerWave consecutive
-// DOF rows and 64 columns (lane <-> column, each wave walks its rows, so the
-// row index and its projector entries stay wave-uniform).  Blocks are
-// remapped so that every XCD streams one contiguous slab of rows: the
-// projector coefficients of the atoms in that slab then stay in its L2.
-constexpr int kRowsPerWave = 1;
-constexpr int kRowsPerBlock = kRowsPerWaveGroup * kRowsPerWave;
+// Persistent loop over work items; inside, I0 is the wave's first row and
+// n its first column (both valid), the rows are I0 + [0, R) below M.
+#define ROWS_BEGIN(V, R)                                                                       \
+  const int lane_ = threadIdx.x & 63;                                                          \
+  const int wv_ = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);                            \
+  const int xcd_ = blockIdx.x & 7;                                                             \
+  const int64_t ngroups_ = (M + kRowsPerWaveGroup * (R) - 1) / (kRowsPerWaveGroup * (R));      \
+  const int64_t nwork_ = ngroups_ * ncoltiles;                                                 \
+  const int64_t we_ = nwork_ * (xcd_ + 1) / 8;                                                 \
+  for (int64_t wi_ = nwork_ * xcd_ / 8 + (blockIdx.x >> 3); wi_ < we_; wi_ += (gridDim.x >> 3)) { \
+    const int64_t grp_ = wi_ / ncoltiles;                                                      \
+    const int n = ((int)(wi_ - grp_ * ncoltiles) * 64 + lane_) * (V);                          \
+    const int64_t I0 = (grp_ * kRowsPerWaveGroup + wv_) * (R);                                 \
+    if (n < ncols && I0 < M) {
+#define ROWS_END \
+  }              \
+  }
 
-__device__ __forceinline__ void row_tile(int nblocks, int ncoltiles, int& rowblock, int& coltile) {
-  const int w = blockIdx.x;
-  const int per = nblocks / 8, rem = nblocks % 8;
-  const int xcd = w % 8, idx = w / 8;
-  const int logical = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + idx;
-  rowblock = logical / ncoltiles;
-  coltile = logical % ncoltiles;
-}
+// row I0 + r clamped into range (loads only; its result is not stored)
+#define ROW_CLAMP(r) ((I0 + (r) < M) ? I0 + (r) : M - 1)
 
-#define ROW_LOOP_BEGIN                                                                 \
-  int rb_, ct_;                                                                        \
-  row_tile(nblocks, ncoltiles, rb_, ct_);                                              \
-  const int lane = threadIdx.x & 63;                                                   \
-  const int wv_ = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);                    \
-  const int n = ct_ * 64 + lane;                                                       \
-  if (n >= ncols) return;                                                              \
-  for (int rr_ = 0; rr_ < kRowsPerWave; ++rr_) {                                       \
-    const int64_t I = ((int64_t)rb_ * kRowsPerWaveGroup + wv_) * kRowsPerWave + rr_;   \
-    if (I >= M) break;
-#define ROW_LOOP_END }
-
-template <typename T>
-__global__ void __launch_bounds__(256) k_node_nl_init(int64_t M, int ncols, int nblocks, int ncoltiles,
+template <typename T, int V, int R>
+__global__ void __launch_bounds__(256) k_node_nl_init(int64_t M, int ncols, int ncoltiles,
                                                       const double* __restrict__ q, T* __restrict__ Y, int64_t ldy,
                                                       const T* __restrict__ Cv, DeviceTables d) {
-  ROW_LOOP_BEGIN
-  const int sr = d.node2srow[I];
-  Y[I * ldy + n] = sr >= 0 ? nl_row<T>(sr, d, Cv, q, ncols, n) : T(0);
-  ROW_LOOP_END
+  ROWS_BEGIN(V, R)
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t I = I0 + r;
+    if (I >= M) break;
+    const int sr = d.node2srow[I];
+    T acc[V];
+#pragma unroll
+    for (int i = 0; i < V; ++i) acc[i] = T(0);
+    if (sr >= 0) nl_row<T, V>(sr, d, Cv, q, ncols, n, acc);
+    Lanes<T, V> y;
+#pragma unroll
+    for (int i = 0; i < V; ++i) y.v[i] = acc[i];
+    vst<V>(Y + I * ldy + n, y);
+  }
+  ROWS_END
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) k_node_sinv(int64_t M, int ncols, int nblocks, int ncoltiles,
+template <typename T, int V, int R>
+__global__ void __launch_bounds__(256) k_node_sinv(int64_t M, int ncols, int ncoltiles,
                                                    const T* __restrict__ X, int64_t ldx,
                                                    const double* __restrict__ dv, T* __restrict__ Y, int64_t ldy,
                                                    const T* __restrict__ Minv, const T* __restrict__ Cv,
                                                    DeviceTables d) {
-  ROW_LOOP_BEGIN
-  const int sr = d.node2srow[I];
-  T x = X[I * ldx + n];
-  if (sr >= 0) x -= nl_row<T>(sr, d, Cv, dv, ncols, n);
-  Y[I * ldy + n] = Minv[I] * x;
-  ROW_LOOP_END
+  ROWS_BEGIN(V, R)
+  Lanes<T, V> x[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) x[r] = vld<V>(X + ROW_CLAMP(r) * ldx + n);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t I = I0 + r;
+    if (I >= M) break;
+    const int sr = d.node2srow[I];
+    T acc[V];
+#pragma unroll
+    for (int i = 0; i < V; ++i) acc[i] = T(0);
+    if (sr >= 0) nl_row<T, V>(sr, d, Cv, dv, ncols, n, acc);
+    const T m = Minv[I];
+    Lanes<T, V> y;
+#pragma unroll
+    for (int i = 0; i < V; ++i) y.v[i] = m * (x[r].v[i] - acc[i]);
+    vst<V>(Y + I * ldy + n, y);
+  }
+  ROWS_END
 }
 
-template <typename TR>
-__global__ void __launch_bounds__(256) k_node_cheb(int64_t M, int ncols, int nblocks, int ncoltiles,
+template <typename TR, int V, int R>
+__global__ void __launch_bounds__(256) k_node_cheb(int64_t M, int ncols, int ncoltiles,
                                                    const TR* __restrict__ RY,
                                                    TR* __restrict__ RX, TR* __restrict__ Tb, int64_t ld,
                                                    const double* __restrict__ Y, int64_t ldy,
@@ -186,71 +272,134 @@ __global__ void __launch_bounds__(256) k_node_cheb(int64_t M, int ncols, int nbl
                                                    const double* __restrict__ lam_in, double a, double ac,
                                                    double zz, const TR* __restrict__ Minv,
                                                    const TR* __restrict__ Cv, DeviceTables d) {
-  ROW_LOOP_BEGIN
-  const int sr = d.node2srow[I];
-  const TR ry = RY[I * ld + n];
-  const TR rx = RX[I * ld + n];
-  TR cd = TR(0), cq = TR(0);
-  if (sr >= 0) {
-    const int k0 = d.srow_ptr[sr], k1 = d.srow_ptr[sr + 1];
-    for (int k = k0; k < k1; ++k) {
-      const int at = d.srow_atom[k], coff = d.srow_coff[k];
-      const int npj = d.nproj[at], po = d.poff[at];
-      for (int al = 0; al < npj; ++al) {
-        const TR cv = Cv[coff + al];
-        cd += cv * (TR)dv[(int64_t)(po + al) * ncols + n];
-        cq += cv * (TR)qv[(int64_t)(po + al) * ncols + n];
-      }
+  ROWS_BEGIN(V, R)
+  Lanes<TR, V> ry[R], rx[R];
+  Lanes<double, V> y[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t I = ROW_CLAMP(r);
+    ry[r] = vld<V>(RY + I * ld + n);
+    rx[r] = vld<V>(RX + I * ld + n);
+    y[r] = vld<V>(Y + I * ldy + n);
+  }
+  double ly[V];
+#pragma unroll
+  for (int i = 0; i < V; ++i) ly[i] = a * lamY[n + i];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t I = I0 + r;
+    if (I >= M) break;
+    const int sr = d.node2srow[I];
+    TR cd[V], cq[V];
+#pragma unroll
+    for (int i = 0; i < V; ++i) cd[i] = cq[i] = TR(0);
+    if (sr >= 0) {
+      nl_row<TR, V>(sr, d, Cv, dv, ncols, n, cd);
+      nl_row<TR, V>(sr, d, Cv, qv, ncols, n, cq);
+    }
+    const TR m = Minv[I];
+    Lanes<TR, V> t, o;
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      t.v[i] = m * (ry[r].v[i] - cd[i]);
+      // recurrence part in TR arithmetic, residual correction a Y lamY in FP64
+      const TR part = (TR)(-ac) * ry[r].v[i] - (TR)zz * rx[r].v[i] + cq[i];
+      o.v[i] = (TR)((double)part + y[r].v[i] * ly[i]);
+    }
+    vst<V>(Tb + I * ld + n, t);
+    vst<V>(RX + I * ld + n, o);
+    if (I == 0) {
+#pragma unroll
+      for (int i = 0; i < V; ++i)
+        lamX[n + i] = a * lamY[n + i] * lam_in[n + i] - ac * lamY[n + i] - zz * lamX[n + i];
     }
   }
-  Tb[I * ld + n] = Minv[I] * (ry - cd);
-  // recurrence part in TR arithmetic, residual correction a Y lamY in FP64
-  const TR part = (TR)(-ac) * ry - (TR)zz * rx + cq;
-  RX[I * ld + n] = (TR)((double)part + a * Y[I * ldy + n] * lamY[n]);
-  if (I == 0) lamX[n] = a * lamY[n] * lam_in[n] - ac * lamY[n] - zz * lamX[n];
-  ROW_LOOP_END
+  ROWS_END
 }
 
-template <typename TR>
-__global__ void __launch_bounds__(256) k_node_finalize(int64_t M, int ncols, int nblocks, int ncoltiles,
+template <typename TR, int V, int R>
+__global__ void __launch_bounds__(256) k_node_finalize(int64_t M, int ncols, int ncoltiles,
                                                        const TR* __restrict__ RY,
                                                        int64_t ld, const double* __restrict__ dv,
                                                        const double* __restrict__ X, int64_t ldx,
                                                        const double* __restrict__ lamY, double* __restrict__ Xo,
                                                        int64_t ldo, const TR* __restrict__ Minv,
                                                        const TR* __restrict__ Cv, DeviceTables d) {
-  ROW_LOOP_BEGIN
-  const int sr = d.node2srow[I];
-  TR r = RY[I * ld + n];
-  if (sr >= 0) r -= nl_row<TR>(sr, d, Cv, dv, ncols, n);
-  const TR t = Minv[I] * r;
-  Xo[I * ldo + n] = (double)t + X[I * ldx + n] * lamY[n];
-  ROW_LOOP_END
+  ROWS_BEGIN(V, R)
+  Lanes<TR, V> ry[R];
+  Lanes<double, V> x[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t I = ROW_CLAMP(r);
+    ry[r] = vld<V>(RY + I * ld + n);
+    x[r] = vld<V>(X + I * ldx + n);
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t I = I0 + r;
+    if (I >= M) break;
+    const int sr = d.node2srow[I];
+    TR acc[V];
+#pragma unroll
+    for (int i = 0; i < V; ++i) acc[i] = TR(0);
+    if (sr >= 0) nl_row<TR, V>(sr, d, Cv, dv, ncols, n, acc);
+    const TR m = Minv[I];
+    Lanes<double, V> o;
+#pragma unroll
+    for (int i = 0; i < V; ++i) o.v[i] = (double)(m * (ry[r].v[i] - acc[i])) + x[r].v[i] * lamY[n + i];
+    vst<V>(Xo + I * ldo + n, o);
+  }
+  ROWS_END
 }
 
-template <typename TR>
-__global__ void __launch_bounds__(256) k_cheb_init(int64_t M, int ncols, int nblocks, int ncoltiles,
+template <typename TR, int V, int R>
+__global__ void __launch_bounds__(256) k_cheb_init(int64_t M, int ncols, int ncoltiles,
                                                    const double* __restrict__ Y,
                                                    int64_t ldy, TR* __restrict__ RY, TR* __restrict__ RX,
                                                    int64_t ld, double f, double c,
                                                    const double* __restrict__ lam_in, double* __restrict__ lamY,
                                                    double* __restrict__ lamX) {
-  ROW_LOOP_BEGIN
-  RY[I * ld + n] = (TR)(f * Y[I * ldy + n]);
-  RX[I * ld + n] = TR(0);
-  if (I == 0) {
-    lamY[n] = f * (lam_in[n] - c);
-    lamX[n] = 1.0;
+  ROWS_BEGIN(V, R)
+  Lanes<double, V> y[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) y[r] = vld<V>(Y + ROW_CLAMP(r) * ldy + n);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t I = I0 + r;
+    if (I >= M) break;
+    Lanes<TR, V> ry, z;
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      ry.v[i] = (TR)(f * y[r].v[i]);
+      z.v[i] = TR(0);
+    }
+    vst<V>(RY + I * ld + n, ry);
+    vst<V>(RX + I * ld + n, z);
+    if (I == 0) {
+#pragma unroll
+      for (int i = 0; i < V; ++i) {
+        lamY[n + i] = f * (lam_in[n + i] - c);
+        lamX[n + i] = 1.0;
+      }
+    }
   }
-  ROW_LOOP_END
+  ROWS_END
 }
 
-__global__ void __launch_bounds__(256) k_copy_cols(int64_t M, int ncols, int nblocks, int ncoltiles,
+template <int V, int R>
+__global__ void __launch_bounds__(256) k_copy_cols(int64_t M, int ncols, int ncoltiles,
                                                    const double* __restrict__ X, int64_t ldx,
                                                    double* __restrict__ Y, int64_t ldy) {
-  ROW_LOOP_BEGIN
-  Y[I * ldy + n] = X[I * ldx + n];
-  ROW_LOOP_END
+  ROWS_BEGIN(V, R)
+  Lanes<double, V> x[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) x[r] = vld<V>(X + ROW_CLAMP(r) * ldx + n);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (I0 + r >= M) break;
+    vst<V>(Y + (I0 + r) * ldy + n, x[r]);
+  }
+  ROWS_END
 }
 
 template <typename T>
@@ -417,14 +566,30 @@ __global__ void k_grad_dh(const double* __restrict__ c, int ncols, const double*
 }
 
 struct RowGrid {
-  int nblocks, ncoltiles;
-  dim3 grid() const { return dim3((unsigned)nblocks); }
+  int ncoltiles;
+  dim3 grid;
 };
-inline RowGrid row_grid(int64_t M, int ncols) {
+// persistent grid: enough workgroups to fill the chip, a multiple of 8
+inline RowGrid row_grid(int64_t M, int ncols, int V, int R) {
   RowGrid g;
-  g.ncoltiles = (ncols + 63) / 64;
-  g.nblocks = (int)((M + kRowsPerBlock - 1) / kRowsPerBlock) * g.ncoltiles;
+  g.ncoltiles = (ncols + 64 * V - 1) / (64 * V);
+  const int64_t nwork = (M + kRowsPerWaveGroup * R - 1) / (kRowsPerWaveGroup * R) * g.ncoltiles;
+  const int64_t nb = std::min<int64_t>(kPersistBlocks, (nwork + 7) / 8 * 8);
+  g.grid = dim3((unsigned)std::max<int64_t>(nb, 8));
   return g;
+}
+
+// True when V columns per lane are allowed: ncols a multiple of V and every
+// (base pointer, leading dimension) pair 16-byte aligned row by row.
+struct Strided {
+  const void* p;
+  int64_t ld;
+};
+inline bool vec_ok(int V, int ncols, std::initializer_list<Strided> xs) {
+  if (ncols % V) return false;
+  for (const Strided& x : xs)
+    if ((reinterpret_cast<uintptr_t>(x.p) & 15) || x.ld % V) return false;
+  return true;
 }
 
 template <typename T>
@@ -442,7 +607,7 @@ pawfe_status launch_nl_reduce(const pawfe_op* op, const T* X, int64_t ldx, int n
   if (op->natoms == 0 || ncols <= 0) return PAWFE_OK;
   const T* Cv = pick<T>(op->d.Cvals, op->d.Cvals_f);
   const T* Minv = pick<T>(op->d.Minv, op->d.Minv_f);
-  const dim3 grid(op->nitems, (ncols + 63) / 64), block(256);
+  const dim3 grid(op->nitems, (ncols + 255) / 256), block(256);
   if (op->npj_max <= 8)
     hipLaunchKernelGGL((k_nl_reduce<T, 8>), grid, block, 0, s, X, ldx, ncols, (int)scale_minv, Minv, Cv, op->d, part);
   else if (op->npj_max <= 18)
@@ -481,9 +646,17 @@ pawfe_status launch_atom_gcorr(const pawfe_op* op, const double* c, const double
 template <typename T>
 pawfe_status launch_node_nl_init(const pawfe_op* op, const double* q, int ncols, T* Y, int64_t ldy, hipStream_t s) {
   if (ncols <= 0) return PAWFE_OK;
-  const RowGrid g = row_grid(op->M, ncols);
-  hipLaunchKernelGGL(k_node_nl_init<T>, g.grid(), dim3(256), 0, s, op->M, ncols, g.nblocks, g.ncoltiles, q, Y, ldy,
-                     pick<T>(op->d.Cvals, op->d.Cvals_f), op->d);
+  constexpr int V = 16 / sizeof(T);
+  const T* Cv = pick<T>(op->d.Cvals, op->d.Cvals_f);
+  if (vec_ok(V, ncols, {{Y, ldy}})) {
+    const RowGrid g = row_grid(op->M, ncols, V, kRowsPerWave);
+    hipLaunchKernelGGL((k_node_nl_init<T, V, kRowsPerWave>), g.grid, dim3(256), 0, s, op->M, ncols, g.ncoltiles, q,
+                       Y, ldy, Cv, op->d);
+  } else {
+    const RowGrid g = row_grid(op->M, ncols, 1, kRowsPerWave);
+    hipLaunchKernelGGL((k_node_nl_init<T, 1, kRowsPerWave>), g.grid, dim3(256), 0, s, op->M, ncols, g.ncoltiles, q,
+                       Y, ldy, Cv, op->d);
+  }
   PAWFE_HIP(hipGetLastError());
   return PAWFE_OK;
 }
@@ -494,10 +667,18 @@ template <typename T>
 pawfe_status launch_node_sinv(const pawfe_op* op, const T* X, int64_t ldx, const double* dv, int ncols, T* Y,
                               int64_t ldy, hipStream_t s) {
   if (ncols <= 0) return PAWFE_OK;
-  const RowGrid g = row_grid(op->M, ncols);
-  hipLaunchKernelGGL(k_node_sinv<T>, g.grid(), dim3(256), 0, s, op->M, ncols, g.nblocks, g.ncoltiles, X, ldx, dv, Y,
-                     ldy,
-                     pick<T>(op->d.Minv, op->d.Minv_f), pick<T>(op->d.Cvals, op->d.Cvals_f), op->d);
+  constexpr int V = 16 / sizeof(T);
+  const T* Minv = pick<T>(op->d.Minv, op->d.Minv_f);
+  const T* Cv = pick<T>(op->d.Cvals, op->d.Cvals_f);
+  if (vec_ok(V, ncols, {{X, ldx}, {Y, ldy}})) {
+    const RowGrid g = row_grid(op->M, ncols, V, kRowsPerWave);
+    hipLaunchKernelGGL((k_node_sinv<T, V, kRowsPerWave>), g.grid, dim3(256), 0, s, op->M, ncols, g.ncoltiles, X, ldx,
+                       dv, Y, ldy, Minv, Cv, op->d);
+  } else {
+    const RowGrid g = row_grid(op->M, ncols, 1, kRowsPerWave);
+    hipLaunchKernelGGL((k_node_sinv<T, 1, kRowsPerWave>), g.grid, dim3(256), 0, s, op->M, ncols, g.ncoltiles, X, ldx,
+                       dv, Y, ldy, Minv, Cv, op->d);
+  }
   PAWFE_HIP(hipGetLastError());
   return PAWFE_OK;
 }
@@ -510,11 +691,19 @@ template <typename TR>
 pawfe_status launch_node_cheb(const pawfe_op* op, const TR* RY, TR* RX, TR* Tb, int64_t ld, const double* Y,
                               int64_t ldy, const double* dv, const double* qv, const double* lamY, double* lamX,
                               const double* lam_in, double a, double ac, double zz, int ncols, hipStream_t s) {
-  const RowGrid g = row_grid(op->M, ncols);
-  hipLaunchKernelGGL(k_node_cheb<TR>, g.grid(), dim3(256), 0, s, op->M, ncols, g.nblocks, g.ncoltiles, RY, RX, Tb,
-                     ld, Y, ldy,
-                     dv, qv, lamY, lamX, lam_in, a, ac, zz, pick<TR>(op->d.Minv, op->d.Minv_f),
-                     pick<TR>(op->d.Cvals, op->d.Cvals_f), op->d);
+  if (ncols <= 0) return PAWFE_OK;
+  constexpr int V = 16 / sizeof(TR);
+  const TR* Minv = pick<TR>(op->d.Minv, op->d.Minv_f);
+  const TR* Cv = pick<TR>(op->d.Cvals, op->d.Cvals_f);
+  if (vec_ok(V, ncols, {{RY, ld}, {RX, ld}, {Tb, ld}, {Y, ldy}})) {
+    const RowGrid g = row_grid(op->M, ncols, V, kRowsPerWave);
+    hipLaunchKernelGGL((k_node_cheb<TR, V, kRowsPerWave>), g.grid, dim3(256), 0, s, op->M, ncols, g.ncoltiles, RY, RX,
+                       Tb, ld, Y, ldy, dv, qv, lamY, lamX, lam_in, a, ac, zz, Minv, Cv, op->d);
+  } else {
+    const RowGrid g = row_grid(op->M, ncols, 1, kRowsPerWave);
+    hipLaunchKernelGGL((k_node_cheb<TR, 1, kRowsPerWave>), g.grid, dim3(256), 0, s, op->M, ncols, g.ncoltiles, RY, RX,
+                       Tb, ld, Y, ldy, dv, qv, lamY, lamX, lam_in, a, ac, zz, Minv, Cv, op->d);
+  }
   PAWFE_HIP(hipGetLastError());
   return PAWFE_OK;
 }
@@ -528,10 +717,19 @@ template pawfe_status launch_node_cheb<float>(const pawfe_op*, const float*, flo
 template <typename TR>
 pawfe_status launch_node_finalize(const pawfe_op* op, const TR* RY, int64_t ld, const double* dv, const double* X,
                                   int64_t ldx, const double* lamY, double* Xo, int64_t ldo, int ncols, hipStream_t s) {
-  const RowGrid g = row_grid(op->M, ncols);
-  hipLaunchKernelGGL(k_node_finalize<TR>, g.grid(), dim3(256), 0, s, op->M, ncols, g.nblocks, g.ncoltiles, RY, ld, dv,
-                     X, ldx,
-                     lamY, Xo, ldo, pick<TR>(op->d.Minv, op->d.Minv_f), pick<TR>(op->d.Cvals, op->d.Cvals_f), op->d);
+  if (ncols <= 0) return PAWFE_OK;
+  constexpr int V = 16 / sizeof(TR);
+  const TR* Minv = pick<TR>(op->d.Minv, op->d.Minv_f);
+  const TR* Cv = pick<TR>(op->d.Cvals, op->d.Cvals_f);
+  if (vec_ok(V, ncols, {{RY, ld}, {X, ldx}, {Xo, ldo}})) {
+    const RowGrid g = row_grid(op->M, ncols, V, kRowsPerWave);
+    hipLaunchKernelGGL((k_node_finalize<TR, V, kRowsPerWave>), g.grid, dim3(256), 0, s, op->M, ncols, g.ncoltiles, RY,
+                       ld, dv, X, ldx, lamY, Xo, ldo, Minv, Cv, op->d);
+  } else {
+    const RowGrid g = row_grid(op->M, ncols, 1, kRowsPerWave);
+    hipLaunchKernelGGL((k_node_finalize<TR, 1, kRowsPerWave>), g.grid, dim3(256), 0, s, op->M, ncols, g.ncoltiles, RY,
+                       ld, dv, X, ldx, lamY, Xo, ldo, Minv, Cv, op->d);
+  }
   PAWFE_HIP(hipGetLastError());
   return PAWFE_OK;
 }
@@ -544,10 +742,17 @@ template pawfe_status launch_node_finalize<float>(const pawfe_op*, const float*,
 template <typename TR>
 pawfe_status launch_cheb_init(const pawfe_op* op, const double* Y, int64_t ldy, TR* RY, TR* RX, int64_t ld, double f,
                               double c, const double* lam_in, double* lamY, double* lamX, int ncols, hipStream_t s) {
-  const RowGrid g = row_grid(op->M, ncols);
-  hipLaunchKernelGGL(k_cheb_init<TR>, g.grid(), dim3(256), 0, s, op->M, ncols, g.nblocks, g.ncoltiles, Y, ldy, RY, RX,
-                     ld, f, c,
-                     lam_in, lamY, lamX);
+  if (ncols <= 0) return PAWFE_OK;
+  constexpr int V = 16 / sizeof(TR);
+  if (vec_ok(V, ncols, {{Y, ldy}, {RY, ld}, {RX, ld}})) {
+    const RowGrid g = row_grid(op->M, ncols, V, kRowsPerWave);
+    hipLaunchKernelGGL((k_cheb_init<TR, V, kRowsPerWave>), g.grid, dim3(256), 0, s, op->M, ncols, g.ncoltiles, Y, ldy,
+                       RY, RX, ld, f, c, lam_in, lamY, lamX);
+  } else {
+    const RowGrid g = row_grid(op->M, ncols, 1, kRowsPerWave);
+    hipLaunchKernelGGL((k_cheb_init<TR, 1, kRowsPerWave>), g.grid, dim3(256), 0, s, op->M, ncols, g.ncoltiles, Y, ldy,
+                       RY, RX, ld, f, c, lam_in, lamY, lamX);
+  }
   PAWFE_HIP(hipGetLastError());
   return PAWFE_OK;
 }
@@ -558,8 +763,16 @@ template pawfe_status launch_cheb_init<float>(const pawfe_op*, const double*, in
 
 pawfe_status launch_copy_cols(const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t nrows, int ncols,
                               hipStream_t s) {
-  const RowGrid g = row_grid(nrows, ncols);
-  hipLaunchKernelGGL(k_copy_cols, g.grid(), dim3(256), 0, s, nrows, ncols, g.nblocks, g.ncoltiles, X, ldx, Y, ldy);
+  if (ncols <= 0 || nrows <= 0) return PAWFE_OK;
+  if (vec_ok(2, ncols, {{X, ldx}, {Y, ldy}})) {
+    const RowGrid g = row_grid(nrows, ncols, 2, kRowsPerWave);
+    hipLaunchKernelGGL((k_copy_cols<2, kRowsPerWave>), g.grid, dim3(256), 0, s, nrows, ncols, g.ncoltiles, X, ldx, Y,
+                       ldy);
+  } else {
+    const RowGrid g = row_grid(nrows, ncols, 1, kRowsPerWave);
+    hipLaunchKernelGGL((k_copy_cols<1, kRowsPerWave>), g.grid, dim3(256), 0, s, nrows, ncols, g.ncoltiles, X, ldx, Y,
+                       ldy);
+  }
   PAWFE_HIP(hipGetLastError());
   return PAWFE_OK;
 }
