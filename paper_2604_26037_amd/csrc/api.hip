@@ -331,12 +331,20 @@ pawfe_status upload(pawfe_op* op, hipStream_t s) {
   std::vector<float> cf = to_f32(op->Cvals);
   CHECK(up(op, &d.Cvals_f, cf, s));
   std::vector<int32_t> an(op->atom_nodes.begin(), op->atom_nodes.end());
-  CHECK(up(op, &d.atom_nodes, an, s));
+  {
+    // padded so that batched reads of consecutive rows never leave the list
+    std::vector<int32_t> an(op->atom_nodes);
+    an.resize(an.size() + 16, an.empty() ? 0 : an.back());
+    CHECK(up(op, &d.atom_nodes, an, s));
+  }
   CHECK(up(op, &d.item_atom, op->item_atom, s));
   CHECK(up(op, &d.item_row0, op->item_row0, s));
   CHECK(up(op, &d.item_row1, op->item_row1, s));
   CHECK(up(op, &d.item_poff, op->item_poff, s));
   CHECK(up(op, &d.item_ptr, op->item_ptr, s));
+  CHECK(up(op, &d.fix_atom, op->fix_atom, s));
+  CHECK(up(op, &d.fix_row0, op->fix_row0, s));
+  CHECK(up(op, &d.fix_row1, op->fix_row1, s));
   CHECK(up(op, &d.atom_noff, op->atom_noff, s));
   CHECK(up(op, &d.atom_coff, op->atom_coff, s));
   CHECK(up(op, &d.nproj, op->nproj, s));

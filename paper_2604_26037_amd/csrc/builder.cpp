@@ -534,6 +534,44 @@ pawfe_status build_host(const pawfe_op_desc* d, pawfe_op* op) {
   }
   op->nitems = (int)op->item_atom.size();
   op->item_rows_total = prow;
+
+  // greedy colouring of the atom overlap graph (atoms sharing a support node)
+  std::vector<std::vector<int>> nbr(na);
+  for (int64_t sr = 0; sr < op->nsrow; ++sr)
+    for (int32_t k = op->srow_ptr[sr]; k < op->srow_ptr[sr + 1]; ++k)
+      for (int32_t k2 = k + 1; k2 < op->srow_ptr[sr + 1]; ++k2) {
+        nbr[op->srow_atom[k]].push_back(op->srow_atom[k2]);
+        nbr[op->srow_atom[k2]].push_back(op->srow_atom[k]);
+      }
+  std::vector<int> acol(na, -1);
+  int ncol = 0;
+  for (int a = 0; a < na; ++a) {
+    std::vector<char> used(ncol + 1, 0);
+    for (int b : nbr[a])
+      if (acol[b] >= 0) used[acol[b]] = 1;
+    int c = 0;
+    while (used[c]) ++c;
+    acol[a] = c;
+    ncol = std::max(ncol, c + 1);
+  }
+  op->natom_colours = ncol;
+  const int kFixRows = 16;   // rows per add-back work item
+  op->fix_atom.clear();
+  op->fix_row0.clear();
+  op->fix_row1.clear();
+  op->fix_colour_off.assign(1, 0);
+  for (int c = 0; c < ncol; ++c) {
+    for (int a = 0; a < na; ++a) {
+      if (acol[a] != c) continue;
+      const int64_t nrow = op->supp_node_off[a + 1] - op->supp_node_off[a];
+      for (int64_t r0 = 0; r0 < nrow; r0 += kFixRows) {
+        op->fix_atom.push_back(a);
+        op->fix_row0.push_back((int32_t)r0);
+        op->fix_row1.push_back((int32_t)std::min<int64_t>(nrow, r0 + kFixRows));
+      }
+    }
+    op->fix_colour_off.push_back((int32_t)op->fix_atom.size());
+  }
   op->atom_noff.assign(na + 1, 0);
   for (int a = 0; a <= na; ++a) op->atom_noff[a] = (int32_t)op->supp_node_off[a];
   op->atom_nodes.assign(op->supp_nodes.begin(), op->supp_nodes.end());

@@ -63,6 +63,9 @@ struct DeviceTables {
   int32_t* item_row1 = nullptr;
   int32_t* item_poff = nullptr;   // offset of the item's partial block (in units of ncols)
   int32_t* item_ptr = nullptr;    // [natoms+1] items of each atom
+  int32_t* fix_atom = nullptr;    // add-back work items (atom, row range), ordered by atom colour
+  int32_t* fix_row0 = nullptr;
+  int32_t* fix_row1 = nullptr;
   int32_t* atom_noff = nullptr;   // [natoms+1] offsets into atom_nodes
   int32_t* atom_coff = nullptr;   // [natoms]   offsets into Cvals
   int32_t* nproj = nullptr;       // [natoms]
@@ -110,6 +113,10 @@ struct pawfe_op {
   std::vector<int32_t> node2srow, srow_ptr, srow_atom, srow_coff;
   std::vector<int32_t> item_atom, item_row0, item_row1, item_poff, item_ptr, atom_noff, atom_nodes;
   int nitems = 0;
+  // atoms coloured so that atoms of one colour share no support node; the
+  // add-back of C^a q_a runs one colour at a time without write conflicts
+  int natom_colours = 0;
+  std::vector<int32_t> fix_atom, fix_row0, fix_row1, fix_colour_off;
   int64_t item_rows_total = 0;         // sum over items of nproj (partial rows per column)
   int sinv_mode;
   pawfe::DeviceTables d;

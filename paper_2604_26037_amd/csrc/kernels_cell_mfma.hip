@@ -18,13 +18,16 @@
 // outputs, so the passes run in place.
 //
 // Slab layout (XOR swizzle, a bijection on the slab): element (x, y, z, col)
-// lives at ((z*8 + y)*8 + x')*CB + col', where x' mixes in bits of y ^ z and
-// col' a per-slab key.  With 64 LDS banks this makes every access of the
-// passes conflict-free: the A-operand reads (64 lanes, 16 rows x 4 k), the
-// 16-byte result writes of f32 (16 lanes = 16 outputs, two slabs told apart
-// by the key) and the 8-byte accesses of f64 (16 lanes at a time).  Without
-// it the stride of the contracted axis (64 or 512 elements) put all outputs
-// of a row in one bank.
+// lives at ((z*8 + y)*8 + x')*CB + col', where x' and col' mix in bits of the
+// other coordinates and of a per-slab key.  The masks are chosen (GF(2) rank
+// conditions, one per contraction axis) so that the A-operand reads (16 rows
+// x 4 k) hit distinct banks whether the LDS serves 32 or 64 lanes per cycle,
+// and the 16-byte f32 result writes (one output per lane, two slabs told
+// apart by the key) and the 8-byte f64 accesses hit distinct bank groups
+// whether 8 or 16 lanes are served per cycle.  Without it the stride of the
+// contracted axis (64 or 512 elements) put all outputs of a row in one bank.
+// The two low column bits are never swizzled, so the four f32 results of a
+// lane stay one aligned 16-byte chunk.
 //
 // Passes (U = gathered cell values, slab A):
 //   P1 x: [Bx; Kx; Mx] U  -> slab B (V path), slab C (Kx U), slab A (Mx U)
@@ -75,7 +78,10 @@ template <typename T, int CB>
 __host__ __device__ constexpr int phys(int x, int y, int z, int col, int key) {
   const int r = y ^ z;
   if constexpr (sizeof(T) == 4) {
-    return ((z * 8 + y) * 8 + (x ^ rev3(r))) * CB + (col ^ key);
+    // x'0 = x0^y2^z2, x'1 = x1^y0^z0, x'2 = x2^y0^y1^z1, col'2 = c2^x2^y1^z1^key
+    const int xs = x ^ ((r >> 2) & 1) ^ ((r & 1) << 1) ^ (((y ^ (y >> 1) ^ (z >> 1)) & 1) << 2);
+    const int cs = col ^ ((((x >> 2) ^ (y >> 1) ^ (z >> 1)) & 1) << 2) ^ key;
+    return ((z * 8 + y) * 8 + xs) * CB + cs;
   } else {
     return ((z * 8 + y) * 8 + (x ^ (r & 3))) * CB + (col ^ (((x ^ r) >> 2) & 1) ^ key);
   }
@@ -233,8 +239,11 @@ __global__ void __launch_bounds__(256) k_cell_mfma(CellArgs<T> A, const Tab1D<T>
   constexpr bool HAS_V = MODE != kModeMass;
   constexpr bool RES = MODE == kModeHRes;
   __shared__ T smem[3 * kSlots * CB];
-  __shared__ T vws[HAS_V ? NQ3 : 1];          // V(q) W_q of the current cell
-  __shared__ T w3s[RES ? NQ3 : 1];            // W_q (residual mode)
+  // V(q) W_q of the current cell and W_q (residual mode); entry q at
+  // q + q / 64, so the 8 outputs of a result write (stride 64) differ in bank
+  constexpr int NQP = NQ3 + NQ3 / 64;
+  __shared__ T vws[HAS_V ? NQP : 1];
+  __shared__ T w3s[RES ? NQP : 1];
   __shared__ T lams[RES ? CB : 1];            // lambda_n of the item's columns (residual mode)
   const Tab1D<T>& tab = *tabp;
   const int tid = threadIdx.x;
@@ -309,7 +318,7 @@ __global__ void __launch_bounds__(256) k_cell_mfma(CellArgs<T> A, const Tab1D<T>
   // writes zeros there (zero inputs, zero coefficients)
   for (int i = tid; i < 3 * kSlots * CB; i += 256) smem[i] = T(0);
   if constexpr (RES)
-    for (int q = tid; q < NQ3; q += 256) w3s[q] = A.W3[q];
+    for (int q = tid; q < NQ3; q += 256) w3s[q + q / 64] = A.W3[q];
   if (item < i_end) load_item(item);
   __syncthreads();
 
@@ -334,7 +343,7 @@ __global__ void __launch_bounds__(256) k_cell_mfma(CellArgs<T> A, const Tab1D<T>
     if constexpr (HAS_V) {
 #pragma unroll
       for (int v = 0; v < NV; ++v)
-        if (tid + 256 * v < NQ3) vws[tid + 256 * v] = vr[v];
+        if (tid + 256 * v < NQ3) vws[tid + 256 * v + (tid + 256 * v) / 64] = vr[v];
     }
     if constexpr (RES)
       if (tid < CB) lams[tid] = n0 + tid < A.ncols ? (T)A.lam[n0 + tid] : T(0);
@@ -380,8 +389,8 @@ __global__ void __launch_bounds__(256) k_cell_mfma(CellArgs<T> A, const Tab1D<T>
           const int qa = L & 7, qb = L >> 3;
           if (qa >= NQ || qb >= NQ || o >= NQ) return T(0);
           const int q = (o * NQ + qb) * NQ + qa;
-          T s = vws[q];
-          if constexpr (RES) s -= lams[c] * w3s[q];
+          T s = vws[q + q / 64];
+          if constexpr (RES) s -= lams[c] * w3s[q + q / 64];
           return v * s;
         };
         mfma_pass<T, 2, CB, 1, 1>(smem, inB, oB, [&](int o, int k) { return Bm(o, k); }, vpost);
@@ -427,28 +436,25 @@ const Tab1D<T>* dev_tab_m(const pawfe_op* op) {
   if constexpr (std::is_same<T, double>::value) return op->d.tab64; else return op->d.tab32;
 }
 
-// persistent grid: as many 256-thread workgroups as fit on the chip at once
-// (LDS-limited), a multiple of 8, never more than the items need
-template <typename T, int NQ, int CB, int MODE>
+// persistent grid: as many 256-thread workgroups as are resident on the
+// chip at once (LDS- and register-limited), a multiple of 8, never more than
+// the items need
+template <auto K>
 int cell_grid(int nitems) {
-  static int ncu = 0;
-  if (ncu == 0) {
-    int dev = 0;
+  static const int resident = [] {
+    int dev = 0, ncu = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
       ncu = 256;
-  }
-  constexpr int nq3 = NQ * NQ * NQ;
-  constexpr size_t lds = sizeof(T) * (3 * kSlots * CB + (MODE != kModeMass ? nq3 : 1) +
-                                      (MODE == kModeHRes ? nq3 + CB : 2));
-  const int per_cu = std::max(1, std::min(8, (int)(163840 / lds)));
-  const int want = (nitems + 7) / 8 * 8;
-  return std::max(8, std::min(ncu * per_cu / 8 * 8, want));
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, K, 256, 0) != hipSuccess || per_cu <= 0) per_cu = 1;
+    return std::max(8, ncu * per_cu / 8 * 8);
+  }();
+  return std::max(8, std::min(resident, (nitems + 7) / 8 * 8));
 }
 
 template <typename T, int NP, int NQ, int CB, int MODE>
 void launch_mode(const CellArgs<T>& ac, const Tab1D<T>* tab, int ncoltiles, int nitems, hipStream_t s) {
-  const dim3 grid(cell_grid<T, NQ, CB, MODE>(nitems)), block(256);
+  const dim3 grid(cell_grid<k_cell_mfma<T, NP, NQ, CB, MODE>>(nitems)), block(256);
   hipLaunchKernelGGL((k_cell_mfma<T, NP, NQ, CB, MODE>), grid, block, 0, s, ac, tab, ncoltiles, nitems);
 }
 

@@ -14,6 +14,7 @@
 
 #include <cstdint>
 #include <initializer_list>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -29,9 +30,9 @@ constexpr int kRowsPerWaveGroup = 4;   // waves per 256-thread block in row-wise
 // their loads issued before the FMAs (memory-level parallelism).
 constexpr int kUnroll = 8;
 
-template <typename T, int NPJ>
+template <typename T, int NPJ, bool SCALE>
 __global__ void __launch_bounds__(256) k_nl_reduce(const T* __restrict__ X, int64_t ldx, int ncols,
-                                                   int scale, const T* __restrict__ Minv,
+                                                   const T* __restrict__ Minv,
                                                    const T* __restrict__ Cv, DeviceTables d,
                                                    double* __restrict__ part) {
   const int item = blockIdx.x;
@@ -48,25 +49,38 @@ __global__ void __launch_bounds__(256) k_nl_reduce(const T* __restrict__ X, int6
   T acc[NPJ];
 #pragma unroll
   for (int al = 0; al < NPJ; ++al) acc[al] = T(0);
-  for (int rb = r0; rb < r1; rb += kUnroll) {
-    T x[kUnroll];
+  // every load is unconditional (indices clamped into range, padded entries
+  // multiply zeros or land in accumulators that are never stored), so the
+  // loads of a batch are all in flight together
+  auto rows = [&](auto full) {
+    constexpr bool FULL = decltype(full)::value;
+    for (int rb = r0; rb < r1; rb += kUnroll) {
+      // the node list is padded by kUnroll entries, so the batch of indices
+      // is one contiguous read; rows past r1 are masked below
+      int I[kUnroll];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      const int r = rb + u < r1 ? rb + u : r1 - 1;
-      const int I = d.atom_nodes[noff + r];
-      x[u] = X[(int64_t)I * ldx + nc];
-      if (scale) x[u] *= Minv[I];
-      if (rb + u >= r1 || !valid) x[u] = T(0);
+      for (int u = 0; u < kUnroll; ++u) I[u] = d.atom_nodes[noff + rb + u];
+      T x[kUnroll], m[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        x[u] = X[(int64_t)I[u] * ldx + nc];
+        if constexpr (SCALE) m[u] = Minv[I[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        if constexpr (SCALE) x[u] *= m[u];
+        if (rb + u >= r1 || !valid) x[u] = T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int r = rb + u < r1 ? rb + u : r1 - 1;
+        const T* cr = Cv + coff + (int64_t)r * npj;
+#pragma unroll
+        for (int al = 0; al < NPJ; ++al) acc[al] += cr[FULL ? al : (al < npj ? al : npj - 1)] * x[u];
+      }
     }
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      const int r = rb + u < r1 ? rb + u : r1 - 1;
-      const T* cr = Cv + coff + (int64_t)r * npj;
-#pragma unroll
-      for (int al = 0; al < NPJ; ++al)
-        if (al < npj) acc[al] += cr[al] * x[u];
-    }
-  }
+  };
+  if (npj == NPJ) rows(std::true_type{}); else rows(std::false_type{});
   if (!valid) return;
   const int po = d.item_poff[item];
 #pragma unroll
@@ -174,72 +188,54 @@ __device__ __forceinline__ void vst(T* p, const Lanes<T, V>& r) {
   }
 }
 
-// acc += sum_{a: I in supp(a)} C^a[I] . v_a[n .. n+V) for support row sr
-template <typename T, int V>
-__device__ __forceinline__ void nl_row(int sr, const DeviceTables& d, const T* __restrict__ Cv,
-                                       const double* __restrict__ v, int ncols, int n, T (&acc)[V]) {
-  const int k0 = d.srow_ptr[sr], k1 = d.srow_ptr[sr + 1];
-  for (int k = k0; k < k1; ++k) {
-    const int a = d.srow_atom[k], coff = d.srow_coff[k];
-    const int npj = d.nproj[a], po = d.poff[a];
-    for (int al = 0; al < npj; ++al) {
-      const T cv = Cv[coff + al];
-      const Lanes<double, V> x = vld<V>(v + (int64_t)(po + al) * ncols + n);
-#pragma unroll
-      for (int i = 0; i < V; ++i) acc[i] += cv * (T)x.v[i];
-    }
-  }
-}
-
-// Persistent loop over work items; inside, I0 is the wave's first row and
-// n its first column (both valid), the rows are I0 + [0, R) below M.
-#define ROWS_BEGIN(V, R)                                                                       \
-  const int lane_ = threadIdx.x & 63;                                                          \
-  const int wv_ = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);                            \
-  const int xcd_ = blockIdx.x & 7;                                                             \
-  const int64_t ngroups_ = (M + kRowsPerWaveGroup * (R) - 1) / (kRowsPerWaveGroup * (R));      \
-  const int64_t nwork_ = ngroups_ * ncoltiles;                                                 \
-  const int64_t we_ = nwork_ * (xcd_ + 1) / 8;                                                 \
-  for (int64_t wi_ = nwork_ * xcd_ / 8 + (blockIdx.x >> 3); wi_ < we_; wi_ += (gridDim.x >> 3)) { \
-    const int64_t grp_ = wi_ / ncoltiles;                                                      \
-    const int n = ((int)(wi_ - grp_ * ncoltiles) * 64 + lane_) * (V);                          \
-    const int64_t I0 = (grp_ * kRowsPerWaveGroup + wv_) * (R);                                 \
-    if (n < ncols && I0 < M) {
+// Persistent loop; inside, I0 is the wave's first row and n its first
+// column (both valid), the rows are I0 + [0, R) below M.  Row groups of 4 R
+// rows are split into 8 contiguous ranges, one per XCD; the workgroups of an
+// XCD stride through its range and sweep the column tiles of each group.
+#define ROWS_BEGIN(V, R)                                                                         \
+  const int lane_ = threadIdx.x & 63;                                                            \
+  const int wv_ = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);                              \
+  const int xcd_ = blockIdx.x & 7;                                                               \
+  const int ngroups_ = (int)((M + kRowsPerWaveGroup * (R) - 1) / (kRowsPerWaveGroup * (R)));     \
+  const int ge_ = (int)((int64_t)ngroups_ * (xcd_ + 1) / 8);                                     \
+  for (int grp_ = (int)((int64_t)ngroups_ * xcd_ / 8) + (blockIdx.x >> 3); grp_ < ge_;           \
+       grp_ += (gridDim.x >> 3)) {                                                               \
+    const int64_t I0 = ((int64_t)grp_ * kRowsPerWaveGroup + wv_) * (R);                          \
+    for (int ct_ = 0; ct_ < ncoltiles; ++ct_) {                                                  \
+      const int n = (ct_ * 64 + lane_) * (V);                                                    \
+      if (n < ncols && I0 < M) {
 #define ROWS_END \
+  }              \
   }              \
   }
 
 // row I0 + r clamped into range (loads only; its result is not stored)
 #define ROW_CLAMP(r) ((I0 + (r) < M) ? I0 + (r) : M - 1)
 
+// Streaming parts of the node-wise operations (local terms only); the
+// projector terms sum_a C^a v_a at the support nodes are added afterwards by
+// k_nl_fixup, atom colour by atom colour.
+
 template <typename T, int V, int R>
-__global__ void __launch_bounds__(256) k_node_nl_init(int64_t M, int ncols, int ncoltiles,
-                                                      const double* __restrict__ q, T* __restrict__ Y, int64_t ldy,
-                                                      const T* __restrict__ Cv, DeviceTables d) {
+__global__ void __launch_bounds__(256) k_node_zero(int64_t M, int ncols, int ncoltiles, T* __restrict__ Y,
+                                                   int64_t ldy) {
   ROWS_BEGIN(V, R)
+  Lanes<T, V> z;
+#pragma unroll
+  for (int i = 0; i < V; ++i) z.v[i] = T(0);
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int64_t I = I0 + r;
-    if (I >= M) break;
-    const int sr = d.node2srow[I];
-    T acc[V];
-#pragma unroll
-    for (int i = 0; i < V; ++i) acc[i] = T(0);
-    if (sr >= 0) nl_row<T, V>(sr, d, Cv, q, ncols, n, acc);
-    Lanes<T, V> y;
-#pragma unroll
-    for (int i = 0; i < V; ++i) y.v[i] = acc[i];
-    vst<V>(Y + I * ldy + n, y);
+    if (I0 + r >= M) break;
+    vst<V>(Y + (I0 + r) * ldy + n, z);
   }
   ROWS_END
 }
 
+// Y = M_D^{-1} X
 template <typename T, int V, int R>
 __global__ void __launch_bounds__(256) k_node_sinv(int64_t M, int ncols, int ncoltiles,
-                                                   const T* __restrict__ X, int64_t ldx,
-                                                   const double* __restrict__ dv, T* __restrict__ Y, int64_t ldy,
-                                                   const T* __restrict__ Minv, const T* __restrict__ Cv,
-                                                   DeviceTables d) {
+                                                   const T* __restrict__ X, int64_t ldx, T* __restrict__ Y,
+                                                   int64_t ldy, const T* __restrict__ Minv) {
   ROWS_BEGIN(V, R)
   Lanes<T, V> x[R];
 #pragma unroll
@@ -248,39 +244,35 @@ __global__ void __launch_bounds__(256) k_node_sinv(int64_t M, int ncols, int nco
   for (int r = 0; r < R; ++r) {
     const int64_t I = I0 + r;
     if (I >= M) break;
-    const int sr = d.node2srow[I];
-    T acc[V];
-#pragma unroll
-    for (int i = 0; i < V; ++i) acc[i] = T(0);
-    if (sr >= 0) nl_row<T, V>(sr, d, Cv, dv, ncols, n, acc);
     const T m = Minv[I];
     Lanes<T, V> y;
 #pragma unroll
-    for (int i = 0; i < V; ++i) y.v[i] = m * (x[r].v[i] - acc[i]);
+    for (int i = 0; i < V; ++i) y.v[i] = m * x[r].v[i];
     vst<V>(Y + I * ldy + n, y);
   }
   ROWS_END
 }
 
+// T = M_D^{-1} R_Y;  R_X <- -a c R_Y - zeta zeta' R_X + a Y Lambda_Y
 template <typename TR, int V, int R>
 __global__ void __launch_bounds__(256) k_node_cheb(int64_t M, int ncols, int ncoltiles,
                                                    const TR* __restrict__ RY,
                                                    TR* __restrict__ RX, TR* __restrict__ Tb, int64_t ld,
                                                    const double* __restrict__ Y, int64_t ldy,
-                                                   const double* __restrict__ dv, const double* __restrict__ qv,
                                                    const double* __restrict__ lamY, double* __restrict__ lamX,
                                                    const double* __restrict__ lam_in, double a, double ac,
-                                                   double zz, const TR* __restrict__ Minv,
-                                                   const TR* __restrict__ Cv, DeviceTables d) {
+                                                   double zz, const TR* __restrict__ Minv) {
   ROWS_BEGIN(V, R)
   Lanes<TR, V> ry[R], rx[R];
   Lanes<double, V> y[R];
+  TR m[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int64_t I = ROW_CLAMP(r);
     ry[r] = vld<V>(RY + I * ld + n);
     rx[r] = vld<V>(RX + I * ld + n);
     y[r] = vld<V>(Y + I * ldy + n);
+    m[r] = Minv[I];
   }
   double ly[V];
 #pragma unroll
@@ -289,21 +281,12 @@ __global__ void __launch_bounds__(256) k_node_cheb(int64_t M, int ncols, int nco
   for (int r = 0; r < R; ++r) {
     const int64_t I = I0 + r;
     if (I >= M) break;
-    const int sr = d.node2srow[I];
-    TR cd[V], cq[V];
-#pragma unroll
-    for (int i = 0; i < V; ++i) cd[i] = cq[i] = TR(0);
-    if (sr >= 0) {
-      nl_row<TR, V>(sr, d, Cv, dv, ncols, n, cd);
-      nl_row<TR, V>(sr, d, Cv, qv, ncols, n, cq);
-    }
-    const TR m = Minv[I];
     Lanes<TR, V> t, o;
 #pragma unroll
     for (int i = 0; i < V; ++i) {
-      t.v[i] = m * (ry[r].v[i] - cd[i]);
+      t.v[i] = m[r] * ry[r].v[i];
       // recurrence part in TR arithmetic, residual correction a Y lamY in FP64
-      const TR part = (TR)(-ac) * ry[r].v[i] - (TR)zz * rx[r].v[i] + cq[i];
+      const TR part = (TR)(-ac) * ry[r].v[i] - (TR)zz * rx[r].v[i];
       o.v[i] = (TR)((double)part + y[r].v[i] * ly[i]);
     }
     vst<V>(Tb + I * ld + n, t);
@@ -317,14 +300,13 @@ __global__ void __launch_bounds__(256) k_node_cheb(int64_t M, int ncols, int nco
   ROWS_END
 }
 
+// Xout = M_D^{-1} R_Y + X Lambda_Y
 template <typename TR, int V, int R>
 __global__ void __launch_bounds__(256) k_node_finalize(int64_t M, int ncols, int ncoltiles,
-                                                       const TR* __restrict__ RY,
-                                                       int64_t ld, const double* __restrict__ dv,
+                                                       const TR* __restrict__ RY, int64_t ld,
                                                        const double* __restrict__ X, int64_t ldx,
                                                        const double* __restrict__ lamY, double* __restrict__ Xo,
-                                                       int64_t ldo, const TR* __restrict__ Minv,
-                                                       const TR* __restrict__ Cv, DeviceTables d) {
+                                                       int64_t ldo, const TR* __restrict__ Minv) {
   ROWS_BEGIN(V, R)
   Lanes<TR, V> ry[R];
   Lanes<double, V> x[R];
@@ -338,19 +320,92 @@ __global__ void __launch_bounds__(256) k_node_finalize(int64_t M, int ncols, int
   for (int r = 0; r < R; ++r) {
     const int64_t I = I0 + r;
     if (I >= M) break;
-    const int sr = d.node2srow[I];
-    TR acc[V];
-#pragma unroll
-    for (int i = 0; i < V; ++i) acc[i] = TR(0);
-    if (sr >= 0) nl_row<TR, V>(sr, d, Cv, dv, ncols, n, acc);
     const TR m = Minv[I];
     Lanes<double, V> o;
 #pragma unroll
-    for (int i = 0; i < V; ++i) o.v[i] = (double)(m * (ry[r].v[i] - acc[i])) + x[r].v[i] * lamY[n + i];
+    for (int i = 0; i < V; ++i) o.v[i] = (double)(m * ry[r].v[i]) + x[r].v[i] * lamY[n + i];
     vst<V>(Xo + I * ldo + n, o);
   }
   ROWS_END
 }
+
+// Projector add-back on the support nodes, for the items of one atom colour
+// (atoms of a colour share no node, so the read-modify-writes never meet):
+//   out1[I] += s1 * w_I * sum_alpha C^a[I][alpha] v1_a[alpha][n]
+//   out2[I] +=              sum_alpha C^a[I][alpha] v2_a[alpha][n]   (if out2)
+// with w_I = M_D^{-1}[I] if minv, else 1.  One workgroup per (item, 256
+// columns): thread <-> column, the atom's coefficient vectors for that column
+// sit in registers, the item's rows (<= 64) are walked kFixUnroll at a time
+// with all loads issued first.
+constexpr int kFixUnroll = 8;
+
+template <typename TR, typename TO1, int NPJ, bool MINV, bool HAS2>
+__global__ void __launch_bounds__(256) k_nl_fixup(const int32_t* __restrict__ fatom,
+                                                  const int32_t* __restrict__ frow0,
+                                                  const int32_t* __restrict__ frow1, int ncols,
+                                                  const double* __restrict__ v1, double s1,
+                                                  TO1* __restrict__ out1, int64_t ld1,
+                                                  const double* __restrict__ v2, TR* __restrict__ out2,
+                                                  int64_t ld2, const TR* __restrict__ Minv,
+                                                  const TR* __restrict__ Cv, DeviceTables d) {
+  const int n = blockIdx.y * 256 + threadIdx.x;
+  if (n >= ncols) return;
+  const int a = fatom[blockIdx.x];
+  const int r0 = frow0[blockIdx.x], r1 = frow1[blockIdx.x];
+  const int npj = d.nproj[a], po = d.poff[a];
+  const int noff = d.atom_noff[a], coff = d.atom_coff[a];
+  // All loads are unconditional (indices clamped into range), so they are in
+  // flight together; an atom with exactly NPJ projectors takes the path with
+  // plain indices (wide scalar loads of its C rows).
+  auto body = [&](auto full) {
+    constexpr bool FULL = decltype(full)::value;
+    auto idx = [&](int al) { return FULL ? al : (al < npj ? al : npj - 1); };
+    TR w1[NPJ], w2[NPJ];
+#pragma unroll
+    for (int al = 0; al < NPJ; ++al) {
+      const double x1 = v1[(int64_t)(po + idx(al)) * ncols + n];
+      w1[al] = (FULL || al < npj) ? (TR)(s1 * x1) : TR(0);
+      if constexpr (HAS2) {
+        const double x2 = v2[(int64_t)(po + idx(al)) * ncols + n];
+        w2[al] = (FULL || al < npj) ? (TR)x2 : TR(0);
+      }
+    }
+    for (int rb = r0; rb < r1; rb += kFixUnroll) {
+      int I[kFixUnroll];
+      TO1 o1[kFixUnroll];
+      TR o2[kFixUnroll], c1[kFixUnroll], c2[kFixUnroll];
+#pragma unroll
+      for (int u = 0; u < kFixUnroll; ++u) I[u] = d.atom_nodes[noff + rb + u];   // list padded
+#pragma unroll
+      for (int u = 0; u < kFixUnroll; ++u) {
+        o1[u] = out1[(int64_t)I[u] * ld1 + n];
+        if constexpr (HAS2) o2[u] = out2[(int64_t)I[u] * ld2 + n];
+      }
+#pragma unroll
+      for (int u = 0; u < kFixUnroll; ++u) {
+        const int r = rb + u < r1 ? rb + u : r1 - 1;
+        const TR* cr = Cv + coff + (int64_t)r * npj;
+        c1[u] = c2[u] = TR(0);
+#pragma unroll
+        for (int al = 0; al < NPJ; ++al) {
+          const TR cv = cr[idx(al)];
+          c1[u] += cv * w1[al];
+          if constexpr (HAS2) c2[u] += cv * w2[al];
+        }
+        if constexpr (MINV) c1[u] *= Minv[I[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < kFixUnroll; ++u) {
+        if (rb + u >= r1) break;
+        out1[(int64_t)I[u] * ld1 + n] = o1[u] + (TO1)c1[u];
+        if constexpr (HAS2) out2[(int64_t)I[u] * ld2 + n] = o2[u] + c2[u];
+      }
+    }
+  };
+  if (npj == NPJ) body(std::true_type{}); else body(std::false_type{});
+}
+
+
 
 template <typename TR, int V, int R>
 __global__ void __launch_bounds__(256) k_cheb_init(int64_t M, int ncols, int ncoltiles,
@@ -569,13 +624,25 @@ struct RowGrid {
   int ncoltiles;
   dim3 grid;
 };
-// persistent grid: enough workgroups to fill the chip, a multiple of 8
+// Persistent grid: the workgroups of kernel K that are resident at once
+// (so none waits for a second round), a multiple of 8, capped by the work.
+template <typename K>
+inline int resident_blocks(K kernel) {
+  int dev = 0, ncu = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
+    ncu = 256;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess || per_cu <= 0)
+    per_cu = 1;
+  return std::max(8, ncu * per_cu / 8 * 8);
+}
+template <auto K>
 inline RowGrid row_grid(int64_t M, int ncols, int V, int R) {
+  static const int resident = resident_blocks(K);
   RowGrid g;
   g.ncoltiles = (ncols + 64 * V - 1) / (64 * V);
-  const int64_t nwork = (M + kRowsPerWaveGroup * R - 1) / (kRowsPerWaveGroup * R) * g.ncoltiles;
-  const int64_t nb = std::min<int64_t>(kPersistBlocks, (nwork + 7) / 8 * 8);
-  g.grid = dim3((unsigned)std::max<int64_t>(nb, 8));
+  const int64_t ngroups = (M + kRowsPerWaveGroup * R - 1) / (kRowsPerWaveGroup * R);
+  g.grid = dim3((unsigned)std::max<int64_t>(8, std::min<int64_t>(resident, (ngroups + 7) / 8 * 8)));
   return g;
 }
 
@@ -608,12 +675,16 @@ pawfe_status launch_nl_reduce(const pawfe_op* op, const T* X, int64_t ldx, int n
   const T* Cv = pick<T>(op->d.Cvals, op->d.Cvals_f);
   const T* Minv = pick<T>(op->d.Minv, op->d.Minv_f);
   const dim3 grid(op->nitems, (ncols + 255) / 256), block(256);
-  if (op->npj_max <= 8)
-    hipLaunchKernelGGL((k_nl_reduce<T, 8>), grid, block, 0, s, X, ldx, ncols, (int)scale_minv, Minv, Cv, op->d, part);
-  else if (op->npj_max <= 18)
-    hipLaunchKernelGGL((k_nl_reduce<T, 18>), grid, block, 0, s, X, ldx, ncols, (int)scale_minv, Minv, Cv, op->d, part);
-  else
-    hipLaunchKernelGGL((k_nl_reduce<T, 32>), grid, block, 0, s, X, ldx, ncols, (int)scale_minv, Minv, Cv, op->d, part);
+  auto go = [&](auto scale) {
+    constexpr bool SC = decltype(scale)::value;
+    if (op->npj_max <= 8)
+      hipLaunchKernelGGL((k_nl_reduce<T, 8, SC>), grid, block, 0, s, X, ldx, ncols, Minv, Cv, op->d, part);
+    else if (op->npj_max <= 18)
+      hipLaunchKernelGGL((k_nl_reduce<T, 18, SC>), grid, block, 0, s, X, ldx, ncols, Minv, Cv, op->d, part);
+    else
+      hipLaunchKernelGGL((k_nl_reduce<T, 32, SC>), grid, block, 0, s, X, ldx, ncols, Minv, Cv, op->d, part);
+  };
+  if (scale_minv) go(std::true_type{}); else go(std::false_type{});
   const dim3 g2(op->npj_total, (ncols + 255) / 256);
   hipLaunchKernelGGL(k_nl_final, g2, block, 0, s, part, ncols, op->d_proj_atom, op->d_proj_alpha, op->d, c);
   PAWFE_HIP(hipGetLastError());
@@ -643,22 +714,45 @@ pawfe_status launch_atom_gcorr(const pawfe_op* op, const double* c, const double
   return PAWFE_OK;
 }
 
+// out1 += s1 w C v1 (w = M_D^{-1} if MINV), out2 += C v2 (if HAS2), atom colour by colour
+template <typename TR, typename TO1, bool MINV, bool HAS2>
+pawfe_status nl_fixup(const pawfe_op* op, int ncols, const double* v1, double s1, TO1* out1, int64_t ld1,
+                      const double* v2, TR* out2, int64_t ld2, hipStream_t s) {
+  if (op->natoms == 0 || ncols <= 0) return PAWFE_OK;
+  const TR* Cv = pick<TR>(op->d.Cvals, op->d.Cvals_f);
+  const TR* Minv = pick<TR>(op->d.Minv, op->d.Minv_f);
+  for (int c = 0; c < op->natom_colours; ++c) {
+    const int i0 = op->fix_colour_off[c], i1 = op->fix_colour_off[c + 1];
+    if (i1 == i0) continue;
+    const dim3 grid(i1 - i0, (ncols + 255) / 256), block(256);
+    const int32_t *fa = op->d.fix_atom + i0, *f0 = op->d.fix_row0 + i0, *f1 = op->d.fix_row1 + i0;
+    if (op->npj_max <= 8)
+      hipLaunchKernelGGL((k_nl_fixup<TR, TO1, 8, MINV, HAS2>), grid, block, 0, s, fa, f0, f1, ncols, v1, s1, out1,
+                         ld1, v2, out2, ld2, Minv, Cv, op->d);
+    else if (op->npj_max <= 18)
+      hipLaunchKernelGGL((k_nl_fixup<TR, TO1, 18, MINV, HAS2>), grid, block, 0, s, fa, f0, f1, ncols, v1, s1, out1,
+                         ld1, v2, out2, ld2, Minv, Cv, op->d);
+    else
+      hipLaunchKernelGGL((k_nl_fixup<TR, TO1, 32, MINV, HAS2>), grid, block, 0, s, fa, f0, f1, ncols, v1, s1, out1,
+                         ld1, v2, out2, ld2, Minv, Cv, op->d);
+  }
+  PAWFE_HIP(hipGetLastError());
+  return PAWFE_OK;
+}
+
 template <typename T>
 pawfe_status launch_node_nl_init(const pawfe_op* op, const double* q, int ncols, T* Y, int64_t ldy, hipStream_t s) {
   if (ncols <= 0) return PAWFE_OK;
   constexpr int V = 16 / sizeof(T);
-  const T* Cv = pick<T>(op->d.Cvals, op->d.Cvals_f);
   if (vec_ok(V, ncols, {{Y, ldy}})) {
-    const RowGrid g = row_grid(op->M, ncols, V, kRowsPerWave);
-    hipLaunchKernelGGL((k_node_nl_init<T, V, kRowsPerWave>), g.grid, dim3(256), 0, s, op->M, ncols, g.ncoltiles, q,
-                       Y, ldy, Cv, op->d);
+    const RowGrid g = row_grid<k_node_zero<T, V, kRowsPerWave>>(op->M, ncols, V, kRowsPerWave);
+    hipLaunchKernelGGL((k_node_zero<T, V, kRowsPerWave>), g.grid, dim3(256), 0, s, op->M, ncols, g.ncoltiles, Y, ldy);
   } else {
-    const RowGrid g = row_grid(op->M, ncols, 1, kRowsPerWave);
-    hipLaunchKernelGGL((k_node_nl_init<T, 1, kRowsPerWave>), g.grid, dim3(256), 0, s, op->M, ncols, g.ncoltiles, q,
-                       Y, ldy, Cv, op->d);
+    const RowGrid g = row_grid<k_node_zero<T, 1, kRowsPerWave>>(op->M, ncols, 1, kRowsPerWave);
+    hipLaunchKernelGGL((k_node_zero<T, 1, kRowsPerWave>), g.grid, dim3(256), 0, s, op->M, ncols, g.ncoltiles, Y, ldy);
   }
   PAWFE_HIP(hipGetLastError());
-  return PAWFE_OK;
+  return nl_fixup<T, T, false, false>(op, ncols, q, 1.0, Y, ldy, nullptr, (T*)nullptr, 0, s);
 }
 template pawfe_status launch_node_nl_init<double>(const pawfe_op*, const double*, int, double*, int64_t, hipStream_t);
 template pawfe_status launch_node_nl_init<float>(const pawfe_op*, const double*, int, float*, int64_t, hipStream_t);
@@ -669,18 +763,17 @@ pawfe_status launch_node_sinv(const pawfe_op* op, const T* X, int64_t ldx, const
   if (ncols <= 0) return PAWFE_OK;
   constexpr int V = 16 / sizeof(T);
   const T* Minv = pick<T>(op->d.Minv, op->d.Minv_f);
-  const T* Cv = pick<T>(op->d.Cvals, op->d.Cvals_f);
   if (vec_ok(V, ncols, {{X, ldx}, {Y, ldy}})) {
-    const RowGrid g = row_grid(op->M, ncols, V, kRowsPerWave);
+    const RowGrid g = row_grid<k_node_sinv<T, V, kRowsPerWave>>(op->M, ncols, V, kRowsPerWave);
     hipLaunchKernelGGL((k_node_sinv<T, V, kRowsPerWave>), g.grid, dim3(256), 0, s, op->M, ncols, g.ncoltiles, X, ldx,
-                       dv, Y, ldy, Minv, Cv, op->d);
+                       Y, ldy, Minv);
   } else {
-    const RowGrid g = row_grid(op->M, ncols, 1, kRowsPerWave);
+    const RowGrid g = row_grid<k_node_sinv<T, 1, kRowsPerWave>>(op->M, ncols, 1, kRowsPerWave);
     hipLaunchKernelGGL((k_node_sinv<T, 1, kRowsPerWave>), g.grid, dim3(256), 0, s, op->M, ncols, g.ncoltiles, X, ldx,
-                       dv, Y, ldy, Minv, Cv, op->d);
+                       Y, ldy, Minv);
   }
   PAWFE_HIP(hipGetLastError());
-  return PAWFE_OK;
+  return nl_fixup<T, T, true, false>(op, ncols, dv, -1.0, Y, ldy, nullptr, (T*)nullptr, 0, s);
 }
 template pawfe_status launch_node_sinv<double>(const pawfe_op*, const double*, int64_t, const double*, int, double*,
                                                int64_t, hipStream_t);
@@ -694,18 +787,18 @@ pawfe_status launch_node_cheb(const pawfe_op* op, const TR* RY, TR* RX, TR* Tb, 
   if (ncols <= 0) return PAWFE_OK;
   constexpr int V = 16 / sizeof(TR);
   const TR* Minv = pick<TR>(op->d.Minv, op->d.Minv_f);
-  const TR* Cv = pick<TR>(op->d.Cvals, op->d.Cvals_f);
   if (vec_ok(V, ncols, {{RY, ld}, {RX, ld}, {Tb, ld}, {Y, ldy}})) {
-    const RowGrid g = row_grid(op->M, ncols, V, kRowsPerWave);
-    hipLaunchKernelGGL((k_node_cheb<TR, V, kRowsPerWave>), g.grid, dim3(256), 0, s, op->M, ncols, g.ncoltiles, RY, RX,
-                       Tb, ld, Y, ldy, dv, qv, lamY, lamX, lam_in, a, ac, zz, Minv, Cv, op->d);
+    const RowGrid g = row_grid<k_node_cheb<TR, V, kRowsPerWave>>(op->M, ncols, V, kRowsPerWave);
+    hipLaunchKernelGGL((k_node_cheb<TR, V, kRowsPerWave>), g.grid, dim3(256), 0, s, op->M, ncols, g.ncoltiles, RY,
+                       RX, Tb, ld, Y, ldy, lamY, lamX, lam_in, a, ac, zz, Minv);
   } else {
-    const RowGrid g = row_grid(op->M, ncols, 1, kRowsPerWave);
-    hipLaunchKernelGGL((k_node_cheb<TR, 1, kRowsPerWave>), g.grid, dim3(256), 0, s, op->M, ncols, g.ncoltiles, RY, RX,
-                       Tb, ld, Y, ldy, dv, qv, lamY, lamX, lam_in, a, ac, zz, Minv, Cv, op->d);
+    const RowGrid g = row_grid<k_node_cheb<TR, 1, kRowsPerWave>>(op->M, ncols, 1, kRowsPerWave);
+    hipLaunchKernelGGL((k_node_cheb<TR, 1, kRowsPerWave>), g.grid, dim3(256), 0, s, op->M, ncols, g.ncoltiles, RY,
+                       RX, Tb, ld, Y, ldy, lamY, lamX, lam_in, a, ac, zz, Minv);
   }
   PAWFE_HIP(hipGetLastError());
-  return PAWFE_OK;
+  // T -= M_D^{-1} C d ; R_X += C q  (q already scaled by a)
+  return nl_fixup<TR, TR, true, true>(op, ncols, dv, -1.0, Tb, ld, qv, RX, ld, s);
 }
 template pawfe_status launch_node_cheb<double>(const pawfe_op*, const double*, double*, double*, int64_t,
                                                const double*, int64_t, const double*, const double*, const double*,
@@ -720,18 +813,17 @@ pawfe_status launch_node_finalize(const pawfe_op* op, const TR* RY, int64_t ld, 
   if (ncols <= 0) return PAWFE_OK;
   constexpr int V = 16 / sizeof(TR);
   const TR* Minv = pick<TR>(op->d.Minv, op->d.Minv_f);
-  const TR* Cv = pick<TR>(op->d.Cvals, op->d.Cvals_f);
   if (vec_ok(V, ncols, {{RY, ld}, {X, ldx}, {Xo, ldo}})) {
-    const RowGrid g = row_grid(op->M, ncols, V, kRowsPerWave);
-    hipLaunchKernelGGL((k_node_finalize<TR, V, kRowsPerWave>), g.grid, dim3(256), 0, s, op->M, ncols, g.ncoltiles, RY,
-                       ld, dv, X, ldx, lamY, Xo, ldo, Minv, Cv, op->d);
+    const RowGrid g = row_grid<k_node_finalize<TR, V, kRowsPerWave>>(op->M, ncols, V, kRowsPerWave);
+    hipLaunchKernelGGL((k_node_finalize<TR, V, kRowsPerWave>), g.grid, dim3(256), 0, s, op->M, ncols, g.ncoltiles,
+                       RY, ld, X, ldx, lamY, Xo, ldo, Minv);
   } else {
-    const RowGrid g = row_grid(op->M, ncols, 1, kRowsPerWave);
-    hipLaunchKernelGGL((k_node_finalize<TR, 1, kRowsPerWave>), g.grid, dim3(256), 0, s, op->M, ncols, g.ncoltiles, RY,
-                       ld, dv, X, ldx, lamY, Xo, ldo, Minv, Cv, op->d);
+    const RowGrid g = row_grid<k_node_finalize<TR, 1, kRowsPerWave>>(op->M, ncols, 1, kRowsPerWave);
+    hipLaunchKernelGGL((k_node_finalize<TR, 1, kRowsPerWave>), g.grid, dim3(256), 0, s, op->M, ncols, g.ncoltiles,
+                       RY, ld, X, ldx, lamY, Xo, ldo, Minv);
   }
   PAWFE_HIP(hipGetLastError());
-  return PAWFE_OK;
+  return nl_fixup<TR, double, true, false>(op, ncols, dv, -1.0, Xo, ldo, nullptr, (TR*)nullptr, 0, s);
 }
 template pawfe_status launch_node_finalize<double>(const pawfe_op*, const double*, int64_t, const double*,
                                                    const double*, int64_t, const double*, double*, int64_t, int,
@@ -745,11 +837,11 @@ pawfe_status launch_cheb_init(const pawfe_op* op, const double* Y, int64_t ldy, 
   if (ncols <= 0) return PAWFE_OK;
   constexpr int V = 16 / sizeof(TR);
   if (vec_ok(V, ncols, {{Y, ldy}, {RY, ld}, {RX, ld}})) {
-    const RowGrid g = row_grid(op->M, ncols, V, kRowsPerWave);
+    const RowGrid g = row_grid<k_cheb_init<TR, V, kRowsPerWave>>(op->M, ncols, V, kRowsPerWave);
     hipLaunchKernelGGL((k_cheb_init<TR, V, kRowsPerWave>), g.grid, dim3(256), 0, s, op->M, ncols, g.ncoltiles, Y, ldy,
                        RY, RX, ld, f, c, lam_in, lamY, lamX);
   } else {
-    const RowGrid g = row_grid(op->M, ncols, 1, kRowsPerWave);
+    const RowGrid g = row_grid<k_cheb_init<TR, 1, kRowsPerWave>>(op->M, ncols, 1, kRowsPerWave);
     hipLaunchKernelGGL((k_cheb_init<TR, 1, kRowsPerWave>), g.grid, dim3(256), 0, s, op->M, ncols, g.ncoltiles, Y, ldy,
                        RY, RX, ld, f, c, lam_in, lamY, lamX);
   }
@@ -765,11 +857,11 @@ pawfe_status launch_copy_cols(const double* X, int64_t ldx, double* Y, int64_t l
                               hipStream_t s) {
   if (ncols <= 0 || nrows <= 0) return PAWFE_OK;
   if (vec_ok(2, ncols, {{X, ldx}, {Y, ldy}})) {
-    const RowGrid g = row_grid(nrows, ncols, 2, kRowsPerWave);
+    const RowGrid g = row_grid<k_copy_cols<2, kRowsPerWave>>(nrows, ncols, 2, kRowsPerWave);
     hipLaunchKernelGGL((k_copy_cols<2, kRowsPerWave>), g.grid, dim3(256), 0, s, nrows, ncols, g.ncoltiles, X, ldx, Y,
                        ldy);
   } else {
-    const RowGrid g = row_grid(nrows, ncols, 1, kRowsPerWave);
+    const RowGrid g = row_grid<k_copy_cols<1, kRowsPerWave>>(nrows, ncols, 1, kRowsPerWave);
     hipLaunchKernelGGL((k_copy_cols<1, kRowsPerWave>), g.grid, dim3(256), 0, s, nrows, ncols, g.ncoltiles, X, ldx, Y,
                        ldy);
   }
