@@ -31,6 +31,9 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 PEAK_VALU_TFLOPS = 78.6     # FP64 vector; also FP32 vector without packed-FP32 instructions
+PEAK_MFMA_F32_TFLOPS = 157.3  # dense FP32 matrix cores (the dominant kernel's contractions)
+CELL_KERNEL_SRC = os.path.join(ROOT, "paper_2604_26037_amd", "csrc", "kernels_cell_mfma.hip")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "cell_mfma_f32_paper_counters.md")
 METRIC = "ChFSI filter s/SCF pass & HX GFLOP/s, mixed vs FP64 at ≤1e-6 Ha eig err"
 
 
@@ -39,6 +42,30 @@ def local_flops_per_cell_col(np1, nq):
     kin = 14 * np1 ** 4 + 2 * np1 ** 3
     pot = 4 * nq * np1 * (np1 * np1 + np1 * nq + nq * nq) + nq ** 3
     return kin + pot
+
+
+def measured_traffic():
+    """HBM bytes per launch of the cell kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the
+    kernel source changed since the counters were taken."""
+    import hashlib
+    try:
+        text = open(COUNTERS_FILE).read()
+        src = hashlib.sha256(open(CELL_KERNEL_SRC, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    fields = {}
+    for line in text.splitlines():
+        line = line.strip().lstrip("-* ")
+        if ":" in line:
+            k, v = line.split(":", 1)
+            fields[k.strip().strip("`")] = v.strip().strip("`")
+    if fields.get("source_sha256") != src:
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def nonlocal_flops_per_col(op_sys, supp_nodes_per_atom):
@@ -243,16 +270,20 @@ def main():
             f"local {t_loc * 1e3:.2f} ms ({hx[name]['local_tflops']:.2f} TFLOP/s)")
         del Xs, Ys
 
+    # roofline of the dominant kernel: the cell-local operator on the matrix
+    # cores (FP32 MFMA), one colour (1/8 of the cells) x 256 columns per launch;
+    # algorithmic flops = 72,668 per cell-column (sum-factorized K + V)
     per_launch_flops = nloc_flops * B / op.ncolour
     t_launch = hx["fp32"]["t_local"] / op.ncolour
+    achieved = per_launch_flops / t_launch / 1e12
     roof = {
-        "kernel": "k_cell<float,7,8,16,H> (cell-local K + V, one colour per launch)",
-        "bound": "alu",
-        "achieved": per_launch_flops / t_launch / 1e12,
-        "peak": PEAK_VALU_TFLOPS,
+        "kernel": "k_cell_mfma<float,7,8,8,H> (cell-local K + V, one colour per launch)",
+        "bound": "mfma",
+        "achieved": achieved,
+        "peak": PEAK_MFMA_F32_TFLOPS,
         "unit": "TFLOP/s",
-        "frac": per_launch_flops / t_launch / 1e12 / PEAK_VALU_TFLOPS,
-        "traffic": None,
+        "frac": achieved / PEAK_MFMA_F32_TFLOPS,
+        "traffic": measured_traffic(),
         "per_launch_flops": per_launch_flops,
         "avg_launch_ms": t_launch * 1e3,
     }
