@@ -221,6 +221,64 @@ pawfe_status pawfe_band_energy_grad(const pawfe_op* op, const void* X, int64_t l
 pawfe_status pawfe_lanczos_bounds(const pawfe_op* op, int32_t k, uint64_t seed, double* theta_min,
                                   double* theta_max, double* beta_k, void* stream);
 
+/* ---- Batched filter over independent problems (HIP graph) ----------------
+ *
+ * Several independent problems of uneven size (different operators, column
+ * counts, polynomial degrees and bounds; the sum over k-points or small
+ * cells of the band-energy expression, FE governing equations section)
+ * are filtered together: each job is one pawfe_cheb_filter call.  The batch
+ * sorts the jobs by estimated cost (largest first), assigns them to
+ * nstreams streams by longest-processing-time-first, captures the whole
+ * multi-stream schedule once into a HIP graph and replays it.  Every
+ * pointer of every job is baked into the graph: a replay re-reads the
+ * current CONTENTS of Xin and lambda_in and overwrites Xout.
+ *
+ * Column block sizes: a job with block <= 0 gets its block size from the
+ * autotuner, which times the candidates {64, 128, 256} (those <= nvec, and
+ * nvec itself when smaller) with a short degree-3 filter of that job on a
+ * private stream and keeps the fastest.  nstreams <= 0 lets the autotuner
+ * time the whole batch eagerly for 1, 2 and 4 streams and keep the fastest.
+ * The autotuning runs (eager filters on the jobs' own buffers) happen
+ * inside pawfe_batch_create; their outputs are overwritten by any replay.
+ *
+ * Real (Gamma-point) operators only: this build rejects complex operators
+ * at pawfe_build_operator.
+ */
+typedef struct pawfe_batch pawfe_batch;
+
+typedef struct {
+  const pawfe_op* op;        /* operator of this problem (not owned) */
+  const void* Xin;           /* device FP64 [ndof][ldx] */
+  int64_t ldx;
+  void* Xout;                /* device FP64 [ndof][ldo]; may equal Xin */
+  int64_t ldo;
+  int64_t nvec;              /* columns */
+  int32_t block;             /* columns per filter block; <= 0: autotuned */
+  const double* lambda_in;   /* device FP64 [nvec] */
+  int32_t degree;            /* Chebyshev degree m >= 2 */
+  double b0, bW, bU;         /* filter bounds, b0 < bW < bU */
+} pawfe_filter_job;
+
+/* Builds the batch: validates every job (as pawfe_cheb_filter), allocates
+ * one workspace per job (device memory owned by the batch), autotunes,
+ * captures and instantiates the graph.  `stream` is used for the tuning
+ * runs and is synchronized before return.  prec: PAWFE_FP64 or PAWFE_FP32
+ * (the recurrence precision of every job).  The operators must outlive the
+ * batch and must not be used by other calls while the batch runs. */
+pawfe_status pawfe_batch_create(const pawfe_filter_job* jobs, int32_t njobs, int32_t prec, int32_t nstreams,
+                                void* stream, pawfe_batch** out);
+
+/* Enqueues one replay of the captured graph on `stream` (asynchronous). */
+pawfe_status pawfe_batch_run(pawfe_batch* batch, void* stream);
+
+/* Chosen schedule: number of streams, per-job block size and stream index
+ * (host arrays of njobs entries, may be NULL). */
+pawfe_status pawfe_batch_query(const pawfe_batch* batch, int32_t* nstreams, int32_t* blocks,
+                               int32_t* stream_of_job);
+
+/* Frees the graph, the streams and the workspaces (synchronizes first). */
+void pawfe_batch_destroy(pawfe_batch* batch);
+
 /* Message for the last non-OK status on the calling thread ("" if none). */
 const char* pawfe_last_error(void);
 

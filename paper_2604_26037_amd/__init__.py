@@ -6,6 +6,6 @@ binding.
 """
 
 from .pawfe import (  # noqa: F401
-    Operator, PawfeError, load, band_energy_function, EXPORTS, LIB_PATH,
+    Operator, Batch, PawfeError, load, band_energy_function, EXPORTS, LIB_PATH,
     FP64, FP32, BF16X3,
 )

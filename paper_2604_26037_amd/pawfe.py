@@ -29,7 +29,17 @@ EXPORTS = [
     "pawfe_apply_local",
     "pawfe_cheb_filter_workspace", "pawfe_cheb_filter", "pawfe_rayleigh_ritz_workspace",
     "pawfe_rayleigh_ritz", "pawfe_band_energy_grad", "pawfe_lanczos_bounds", "pawfe_last_error",
+    "pawfe_batch_create", "pawfe_batch_run", "pawfe_batch_query", "pawfe_batch_destroy",
 ]
+
+
+class FilterJob(C.Structure):
+    """One problem of a batch (pawfe_filter_job)."""
+    _fields_ = [
+        ("op", C.c_void_p), ("Xin", C.c_void_p), ("ldx", C.c_int64), ("Xout", C.c_void_p),
+        ("ldo", C.c_int64), ("nvec", C.c_int64), ("block", C.c_int32), ("lambda_in", C.c_void_p),
+        ("degree", C.c_int32), ("b0", C.c_double), ("bW", C.c_double), ("bU", C.c_double),
+    ]
 
 
 class PawfeError(RuntimeError):
@@ -80,11 +90,16 @@ def load(path=LIB_PATH):
         "pawfe_rayleigh_ritz": [vp, vp, i64, i64, vp, vp, vp, sz, vp],
         "pawfe_band_energy_grad": [vp, vp, i64, i64, vp, vp, vp, vp, vp],
         "pawfe_lanczos_bounds": [vp, i32, C.c_uint64, P(dbl), P(dbl), P(dbl), vp],
+        "pawfe_batch_create": [P(FilterJob), i32, i32, i32, vp, P(vp)],
+        "pawfe_batch_run": [vp, vp],
+        "pawfe_batch_query": [vp, P(i32), P(i32), P(i32)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
         f.argtypes = args
         f.restype = i32
+    lib.pawfe_batch_destroy.argtypes = [vp]
+    lib.pawfe_batch_destroy.restype = None
     lib.pawfe_last_error.argtypes = []
     lib.pawfe_last_error.restype = C.c_char_p
     _lib = lib
@@ -320,3 +335,53 @@ def band_energy_function():
             return None, gv, gd, None, None
 
     return BandEnergy
+
+
+class Batch:
+    """Filters of several independent problems captured into one HIP graph.
+
+    jobs: list of dicts with keys op (Operator), X (device FP64 [ndof][n]),
+    out (same shape, may be X), lam (device FP64 [n]), degree, b0, bW, bU and
+    optionally block (default: autotuned).  nstreams=None lets the library
+    pick 1, 2 or 4 streams by timing.  The tensors are kept alive by the
+    batch; run() replays the graph on the current stream.
+    """
+
+    def __init__(self, jobs, prec=FP64, nstreams=None, stream=None):
+        import torch
+        lib = load()
+        self._jobs = []
+        arr = (FilterJob * len(jobs))()
+        for i, j in enumerate(jobs):
+            X, out, lam = j["X"], j.get("out", j["X"]), j["lam"]
+            for t in (X, out, lam):
+                assert t.is_cuda and t.dtype == torch.float64
+            assert X.stride(1) == 1 and out.stride(1) == 1 and lam.is_contiguous()
+            self._jobs.append((j["op"], X, out, lam))
+            arr[i] = FilterJob(j["op"]._h.value,
+                               X.data_ptr(), X.stride(0), out.data_ptr(), out.stride(0), X.shape[1],
+                               int(j.get("block", 0) or 0), lam.data_ptr(), int(j["degree"]),
+                               float(j["b0"]), float(j["bW"]), float(j["bU"]))
+        h = C.c_void_p()
+        _check(lib.pawfe_batch_create(arr, len(jobs), _PREC[prec], 0 if nstreams is None else int(nstreams),
+                                      _stream(stream), C.byref(h)))
+        self._h = h
+        self.njobs = len(jobs)
+
+    def run(self, stream=None):
+        _check(_lib.pawfe_batch_run(self._h, _stream(stream)))
+
+    def schedule(self):
+        ns = C.c_int32()
+        blocks = np.zeros(self.njobs, dtype=np.int32)
+        sof = np.zeros(self.njobs, dtype=np.int32)
+        _check(_lib.pawfe_batch_query(self._h, C.byref(ns), _iptr(blocks), _iptr(sof)))
+        return ns.value, blocks, sof
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.pawfe_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()

@@ -1,0 +1,108 @@
+"""Batched filter over independent problems of uneven size, captured into a
+HIP graph (pawfe_batch_*): every replay against the oracle's filter of each
+problem, replays against each other with eager work and synchronization in
+between, explicit and autotuned schedules, in place."""
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def problems():
+    from oracle import chfsi
+    from oracle.paw import PAWOperator
+    from paper_2604_26037_amd import Operator
+    from workloads.configs import batch_systems
+    out = []
+    for i, s in enumerate(batch_systems(4, small=True)):
+        ref = PAWOperator(s)
+        op = Operator(s)
+        X = s.trial(s.nstates)
+        Psi, lam, _ = chfsi.rayleigh_ritz(ref, X)
+        t0, t1, beta = chfsi.lanczos_bounds(ref, k=20)
+        bU = 1.02 * max(t1 + abs(beta), float(lam[-1])) + 1.0
+        m = 5 + 2 * i                                   # uneven degrees
+        b0, bW = float(lam[0]), float(lam[-1])
+        want = chfsi.rchfsi_filter(ref, Psi, lam, m, b0, bW, bU, block=s.nstates)
+        out.append(dict(s=s, ref=ref, op=op, Psi=Psi, lam=lam, m=m, b0=b0, bW=bW, bU=bU, want=want))
+    return out
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _jobs(problems, block=None, inplace=False):
+    jobs, keep = [], []
+    for p in problems:
+        X = _dev(p["Psi"])
+        out = X if inplace else torch.empty_like(X)
+        lam = _dev(p["lam"])
+        j = dict(op=p["op"], X=X, out=out, lam=lam, degree=p["m"], b0=p["b0"], bW=p["bW"], bU=p["bU"])
+        if block is not None:
+            j["block"] = block
+        jobs.append(j)
+        keep.append((X, out, lam))
+    return jobs, keep
+
+
+def test_batch_graph_autotuned_vs_oracle_and_replays(problems):
+    from paper_2604_26037_amd import Batch
+    jobs, keep = _jobs(problems)
+    b = Batch(jobs)                                     # block sizes and streams autotuned
+    ns, blocks, sof = b.schedule()
+    assert ns in (1, 2, 4)
+    for j, p in enumerate(problems):
+        n = p["s"].nstates
+        assert 1 <= blocks[j] <= n and 0 <= sof[j] < ns
+    b.run()
+    torch.cuda.synchronize()
+    first = [j["out"].cpu().numpy() for j in jobs]
+    for got, p in zip(first, problems):
+        assert _rel(got, p["want"]) < 1e-9
+    for rep in range(3):
+        # eager work and a synchronization between replays
+        p0 = problems[0]
+        p0["op"].apply_H(_dev(p0["Psi"]))
+        torch.cuda.synchronize()
+        for j in jobs:
+            j["out"].zero_()
+        b.run()
+        torch.cuda.synchronize()
+        for got, j in zip(first, jobs):
+            np.testing.assert_array_equal(j["out"].cpu().numpy(), got)
+    b.close()
+
+
+def test_batch_graph_fixed_schedule_fp32(problems):
+    from paper_2604_26037_amd import FP32, Batch
+    jobs, keep = _jobs(problems, block=5)             # ragged blocks
+    b = Batch(jobs, prec=FP32, nstreams=2)
+    ns, blocks, _ = b.schedule()
+    assert ns == 2 and all(int(x) == 5 for x in blocks)
+    b.run()
+    torch.cuda.synchronize()
+    for j, p in zip(jobs, problems):
+        assert _rel(j["out"].cpu().numpy(), p["want"]) < 1e-4
+    b.close()
+
+
+def test_batch_graph_in_place(problems):
+    from paper_2604_26037_amd import Batch
+    jobs, keep = _jobs(problems, inplace=True)
+    b = Batch(jobs, nstreams=1)
+    for j, p in zip(jobs, problems):                   # tuning runs never touch the jobs' buffers
+        np.testing.assert_array_equal(j["X"].cpu().numpy(), p["Psi"])
+    b.run()
+    torch.cuda.synchronize()
+    for j, p in zip(jobs, problems):
+        assert _rel(j["X"].cpu().numpy(), p["want"]) < 1e-9
+    b.close()

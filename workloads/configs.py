@@ -363,3 +363,43 @@ def custom_system(ncell, box, degree, nq, pos=(), rcut=1.5, channels="spd8",
         nstates=nstates, block=nstates, cheb_degree=10, iterations=1,
         x_seed=int(rng.integers(1, 2 ** 62)), spec=None,
     )
+
+
+def batch_systems(count=24, seed=26037 + 4000, small=False):
+    """Independent problems of uneven size for the batched filter: cubes of
+    6-14 cells of degree-5 elements (7 Gauss points), 8-64 PAW atoms of 18
+    projectors on a jittered lattice, 64-384 states (small=True: 2-4 cells
+    of degree 2-4, 0-2 atoms, 8-24 states, for parity tests).  Real
+    (Gamma-point) operators.  Seeded; no arithmetic of the method here."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed)))
+    out = []
+    for i in range(count):
+        if small:
+            n = tuple(int(v) for v in rng.integers(2, 5, size=3))
+            degree = int(rng.integers(2, 5))
+            nq = degree + 2
+            h = 1.25
+            box = tuple(h * v for v in n)
+            na = int(rng.integers(0, 3))
+            pos = rng.uniform(0.0, 1.0, size=(na, 3)) * np.asarray(box)
+            nst = int(rng.choice([8, 16, 24]))
+            s = custom_system(n, box, degree, nq, pos=pos, rcut=1.0, channels="spd8",
+                              wells=rng.uniform(0.0, 1.0, size=(2, 3)) * np.asarray(box),
+                              s_H=0.5, s_S=0.4, seed=int(rng.integers(1, 2 ** 31)), nstates=nst)
+        else:
+            c = int(rng.integers(6, 15))
+            n = (c, c, c)
+            degree, nq = 5, 7
+            h = 2.0
+            box = tuple(h * v for v in n)
+            na = int(rng.integers(8, 65))
+            a = (np.prod(box) / na) ** (1.0 / 3.0)
+            g = int(np.ceil(na ** (1.0 / 3.0)))
+            grid = np.array([(x, y, z) for z in range(g) for y in range(g) for x in range(g)], dtype=np.float64)
+            pos = (grid[:na] + 0.5) * (np.asarray(box) / g) + rng.normal(0.0, 0.1 * a, size=(na, 3))
+            nst = int(rng.choice([64, 128, 192, 256, 384]))
+            s = custom_system(n, box, degree, nq, pos=pos, rcut=1.8, channels="spd18",
+                              wells=rng.uniform(0.0, 1.0, size=(4, 3)) * np.asarray(box),
+                              s_H=0.9, s_S=0.45, seed=int(rng.integers(1, 2 ** 31)), nstates=nst)
+        out.append(s)
+    return out
