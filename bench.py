@@ -138,6 +138,61 @@ def kernels_mode(op, s, gen, dev, args):
     print(json.dumps({"mode": "kernels", "avg_launch_ms": res, "copy_bytes": nbytes}), flush=True)
 
 
+def batch_mode(dev, args):
+    """Uneven real problems (6^3-14^3 cells of degree 5, 8-64 atoms x 18
+    projectors, 64-384 states, Chebyshev degree 25, FP32 recurrence) filtered
+    as one graph-captured, autotuned multi-stream batch, against the same
+    filters issued one after another on one stream."""
+    import torch
+
+    from paper_2604_26037_amd import FP32, Batch, Operator
+    from workloads.configs import batch_systems
+    t0 = time.time()
+    systems = batch_systems(args.batch_count)
+    jobs, ops = [], []
+    gen = torch.Generator(device=dev)
+    for i, s in enumerate(systems):
+        op = Operator(s)
+        gen.manual_seed(int(s.x_seed) % (2 ** 63))
+        X = torch.randn((op.ndof, s.nstates), generator=gen, dtype=torch.float64, device=dev)
+        lam, _ = op.rayleigh_ritz(X)
+        tmin, tmax, beta = op.lanczos_bounds(k=20)
+        lam_h = lam.cpu().numpy()
+        jobs.append(dict(op=op, X=X, out=torch.empty_like(X), lam=lam, degree=25, b0=float(lam_h[0]),
+                         bW=float(lam_h[-1]), bU=float(max(tmax + beta, lam_h[-1] + 1.0))))
+        ops.append(op)
+    ndof = [o.ndof for o in ops]
+    log(f"{len(jobs)} problems built in {time.time() - t0:.1f} s: DOFs {min(ndof)}-{max(ndof)}, "
+        f"states {min(s.nstates for s in systems)}-{max(s.nstates for s in systems)}")
+    t0 = time.time()
+    b = Batch(jobs, prec=FP32)
+    ns, blocks, sof = b.schedule()
+    log(f"batch created (autotune + capture) in {time.time() - t0:.1f} s: {ns} streams, blocks {sorted(set(blocks.tolist()))}")
+    reps = max(1, args.steps)
+    b.run()
+    torch.cuda.synchronize()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record()
+    for _ in range(reps):
+        b.run()
+    e1.record()
+    for _ in range(reps):
+        for j, blk in zip(jobs, blocks):
+            j["op"].cheb_filter(j["X"], j["lam"], j["degree"], j["b0"], j["bW"], j["bU"], block=int(blk),
+                                prec=FP32, out=j["out"], ws=j.setdefault("ws", j["op"].workspace(
+                                    j["op"].cheb_filter_workspace(j["X"].shape[1], int(blk), FP32))))
+    e2.record()
+    torch.cuda.synchronize()
+    t_graph = e0.elapsed_time(e1) / reps / 1e3
+    t_eager = e1.elapsed_time(e2) / reps / 1e3
+    work = sum(o.ndof * s.nstates for o, s in zip(ops, systems))
+    log(f"graph replay {t_graph:.3f} s, one stream eager {t_eager:.3f} s")
+    print(json.dumps({"mode": "batch", "problems": len(jobs), "streams": ns, "blocks": blocks.tolist(),
+                      "stream_of_job": sof.tolist(), "t_graph_s": t_graph, "t_eager_one_stream_s": t_eager,
+                      "dof_columns_per_s_graph": work * 25 / t_graph}), flush=True)
+    b.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,8 +202,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-fp64", action="store_true", help="do not time the FP64 filter")
     ap.add_argument("--hx-reps", type=int, default=5)
-    ap.add_argument("--mode", default="full", choices=["full", "kernels"],
-                    help="kernels: only the cell-local operator and a calibration copy (for counters)")
+    ap.add_argument("--mode", default="full", choices=["full", "kernels", "batch"],
+                    help="kernels: only the cell-local operator and a calibration copy (for counters); "
+                         "batch: the graph-captured filter of 24 uneven problems")
+    ap.add_argument("--batch-count", type=int, default=24)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the filter shards "
@@ -162,6 +219,8 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.mode == "batch":
+        return batch_mode(dev, args)
     t0 = time.time()
     s = make_system(args.config)
     op = Operator(s)
