@@ -266,6 +266,18 @@ __global__ void k_symmetrize(int N, double* __restrict__ A) {
   A[(int64_t)j * N + i] = v;
 }
 
+// P[i*ldp + j0 + j] = sum_b part[b][j + i*nc] (split-K partials of a block column)
+__global__ void k_part_reduce(const double* __restrict__ part, int nb, int nc, int N, double* __restrict__ P,
+                              int64_t ldp, int64_t j0) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)nc * N) return;
+  const int64_t pstride = (int64_t)nc * N;
+  double acc = 0.0;
+  for (int b = 0; b < nb; ++b) acc += part[b * pstride + idx];
+  const int64_t i = idx / nc, j = idx % nc;
+  P[i * ldp + j0 + j] = acc;
+}
+
 }  // namespace
 
 // ---- upload / free ------------------------------------------------------------
@@ -601,24 +613,50 @@ pawfe_status pawfe_rayleigh_ritz(const pawfe_op* cop, void* Xv, int64_t ldx, int
   rocblas_int* info = cv.take<rocblas_int>(1);
   double* npart_buf = cv.take<double>((size_t)((op->M + 4095) / 4096) * B);
   NlBufs nb = carve_nl(op, cv, B);
-  // projection: H^p = X^T H X, S^p = X^T S X, block by block
-  for (int which = 0; which < 2; ++which) {
-    double* P = which == 0 ? Hp : Sp;
-    for (int64_t j0 = 0; j0 < N; j0 += B) {
-      const int nc = (int)std::min<int64_t>(B, N - j0);
-      CHECK(do_apply<double>(op, which, X + j0, ldx, HXb, nc, nc, nb, s));
-      CHECK(launch_gemm_tn(X, ldx, HXb, nc, op->M, (int)N, nc, P + j0, (int)N, part, npart, false, s));
-    }
-    hipLaunchKernelGGL(k_symmetrize, dim3((unsigned)((N * N + 255) / 256)), dim3(256), 0, s, (int)N, P);
-  }
-  // projected generalized eigenproblem (dense, FP64)
   if (!op->blas) {
     rocblas_handle h;
     if (rocblas_create_handle(&h) != rocblas_status_success) return fail(PAWFE_EHIP, "rocblas_create_handle failed");
     op->blas = h;
   }
   rocblas_handle h = (rocblas_handle)op->blas;
-  rocblas_set_stream(h, s);
+  if (rocblas_set_stream(h, s) != rocblas_status_success) return fail(PAWFE_EHIP, "rocblas_set_stream failed");
+  // projection: H^p = X^T H X, S^p = X^T S X, block column by block column.
+  // Each block is a plain FP64 GEMM with K = ndof: rocBLAS on the matrix
+  // cores, split over K into `nsk` strided-batched pieces (the output is only
+  // N x nc, so K is where the parallelism is), then a fixed-order sum.
+  // Row-major X [K][ldx] is the column-major matrix X^T, so the block
+  // P[:, j0:j0+nc] (row-major) is the column-major product HXb^T-block
+  // (nc x K) times X (K x N).
+  const int64_t K = op->M;
+  for (int which = 0; which < 2; ++which) {
+    double* P = which == 0 ? Hp : Sp;
+    for (int64_t j0 = 0; j0 < N; j0 += B) {
+      const int nc = (int)std::min<int64_t>(B, N - j0);
+      CHECK(do_apply<double>(op, which, X + j0, ldx, HXb, nc, nc, nb, s));
+      const int64_t pbytes = (int64_t)nc * N;
+      int64_t nsk = std::min<int64_t>(32, std::max<int64_t>(1, (int64_t)(npart / (size_t)pbytes) - 1));
+      nsk = std::max<int64_t>(1, std::min<int64_t>(nsk, K / 1024));
+      const int64_t kc = K / nsk, krem = K - nsk * kc;
+      const double one = 1.0, zero = 0.0;
+      if (rocblas_dgemm_strided_batched(h, rocblas_operation_none, rocblas_operation_transpose, nc, (rocblas_int)N,
+                                        (rocblas_int)kc, &one, HXb, nc, kc * nc, X, (rocblas_int)ldx, kc * ldx, &zero,
+                                        part, nc, pbytes, (rocblas_int)nsk) != rocblas_status_success)
+        return fail(PAWFE_EHIP, "rocblas_dgemm_strided_batched failed");
+      int64_t nparts = nsk;
+      if (krem > 0) {
+        if (rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, nc, (rocblas_int)N,
+                          (rocblas_int)krem, &one, HXb + nsk * kc * nc, nc, X + nsk * kc * ldx, (rocblas_int)ldx,
+                          &zero, part + nsk * pbytes, nc) != rocblas_status_success)
+          return fail(PAWFE_EHIP, "rocblas_dgemm failed");
+        ++nparts;
+      }
+      hipLaunchKernelGGL(k_part_reduce, dim3((unsigned)((pbytes + 255) / 256)), dim3(256), 0, s, part, (int)nparts,
+                         nc, (int)N, P, (int64_t)N, j0);
+    }
+    hipLaunchKernelGGL(k_symmetrize, dim3((unsigned)((N * N + 255) / 256)), dim3(256), 0, s, (int)N, P);
+  }
+  PAWFE_HIP(hipGetLastError());
+  // projected generalized eigenproblem (dense, FP64)
   rocblas_status rs = rocsolver_dsygvd(h, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_upper, (rocblas_int)N,
                                        Hp, (rocblas_int)N, Sp, (rocblas_int)N, lambda, Ework, info);
   if (rs != rocblas_status_success) return fail(PAWFE_EHIP, "rocsolver_dsygvd failed");
@@ -628,7 +666,14 @@ pawfe_status pawfe_rayleigh_ritz(const pawfe_op* cop, void* Xv, int64_t ldx, int
   if (hinfo > N) return fail(PAWFE_ENOTSPD, "projected overlap S^p is not positive definite");
   if (hinfo > 0) return fail(PAWFE_ENONFINITE, "projected eigensolver did not converge");
   // rotation X <- X Q (Q column-major in Hp)
-  CHECK(launch_gemm_nq(X, ldx, Hp, (int)N, op->M, (int)N, Xr, N, s));
+  {
+    // Xr = X Q: column-major, Xr^T (N x K) = Q^T (N x N) X^T (N x K)
+    const double one = 1.0, zero = 0.0;
+    if (rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)N, (rocblas_int)K,
+                      (rocblas_int)N, &one, Hp, (rocblas_int)N, X, (rocblas_int)ldx, &zero, Xr,
+                      (rocblas_int)N) != rocblas_status_success)
+      return fail(PAWFE_EHIP, "rocblas_dgemm (rotation) failed");
+  }
   CHECK(launch_copy_cols(Xr, N, X, ldx, op->M, (int)N, s));
   // residual norms ||H x - lambda S x||_2
   for (int64_t j0 = 0; j0 < N; j0 += B) {
