@@ -180,16 +180,25 @@ __device__ __forceinline__ void mfma_pass(T* smem, const Slab* in, const Slab* o
     const Slab b = r < 8 ? s0 : s1;
     wr_lane[ob] = b.off | line_addr<T, CB, AX>(lw | (rl / CB), r & 7, rl % CB, b.key);
   }
+  // A operands of tile `it` (k = 4 ks + kr, index k % 8 in buffer ks / 2)
+  auto load_a = [&](int it, T (&av)[NKS]) {
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks) {
+      const Slab b = in[ks / 2];
+      const int c = b.off | line_addr<T, CB, AX>(LPT * 4 * it, 4 * (ks & 1), 0, b.key);
+      av[ks] = lds_at(smem, (rd_lane ^ (c & MR)) + (c & ~MR));
+    }
+  };
+  // software pipeline: the next tile's operands are read before this tile's
+  // results are written (in program order), so the LDS latency overlaps the
+  // MFMAs instead of waiting behind the in-place stores
+  T av[NKS];
+  load_a(0, av);
 #pragma unroll
   for (int it = 0; it < NT / 4; ++it) {
     const int lc = LPT * 4 * it;
-    T av[NKS];
-#pragma unroll
-    for (int ks = 0; ks < NKS; ++ks) {
-      const Slab b = in[ks / 2];             // k = 4 ks + kr, index k % 8 in buffer ks / 2
-      const int c = b.off | line_addr<T, CB, AX>(lc, 4 * (ks & 1), 0, b.key);
-      av[ks] = lds_at(smem, (rd_lane ^ (c & MR)) + (c & ~MR));
-    }
+    T an[NKS];
+    if (it + 1 < NT / 4) load_a(it + 1, an);
     typename M::V4 acc[NOB];
 #pragma unroll
     for (int ob = 0; ob < NOB; ++ob) {
@@ -225,6 +234,10 @@ __device__ __forceinline__ void mfma_pass(T* smem, const Slab* in, const Slab* o
           }
         }
       }
+    }
+    if (it + 1 < NT / 4) {
+#pragma unroll
+      for (int ks = 0; ks < NKS; ++ks) av[ks] = an[ks];
     }
   }
 }
