@@ -214,7 +214,7 @@ def main():
 
     import torch
 
-    from paper_2604_26037_amd import FP32, FP64, Operator
+    from paper_2604_26037_amd import BF16X3, FP32, FP64, Operator
     from workloads import make_system
 
     dev = torch.device("cuda:0")
@@ -296,6 +296,15 @@ def main():
         t_filter64 = float(np.mean(times))
         log(f"FP64 filter pass {t_filter64:.3f} s, mixed {t_filter:.3f} s")
 
+    # --- bf16x3 filter pass timing (cell contractions as bf16x3 split products) ---
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    filt(X, lam, BF16X3)
+    e1.record()
+    torch.cuda.synchronize()
+    t_filter_bf3 = e0.elapsed_time(e1) / 1e3
+    log(f"bf16x3 filter pass {t_filter_bf3:.3f} s")
+
     # --- dominant kernel: cell-local operator (K + V) on one 256-column block ---
     cd, col, sco, sc, sno, sn = op.dofmap()
     supp_nodes = np.diff(sno)
@@ -367,6 +376,7 @@ def main():
             "step": "mixed filter pass over all states + FP64 Rayleigh-Ritz + residual norms",
         },
         "filter_fp64_s_per_pass": t_filter64,
+        "filter_bf16x3_s_per_pass": t_filter_bf3,
         "speedup_mixed_vs_fp64": (t_filter64 / t_filter) if t_filter64 else None,
         "rayleigh_ritz_s": t_rr,
         "eig_err_mixed_vs_fp64_ha": eig_err,

@@ -64,7 +64,14 @@ enum {
  * the subspace-construction section).  PAWFE_FP64: everything FP64.
  * PAWFE_FP32: the residual recurrence R and the operator applies inside the
  * loop in FP32 with R stored in FP32, the Y*Lambda correction added in FP64
- * (Y kept in FP64), the final Sinv_hat R in FP32 promoted before + X Lambda. */
+ * (Y kept in FP64), the final Sinv_hat R in FP32 promoted before + X Lambda.
+ * PAWFE_BF16X3: as PAWFE_FP32 (FP32 data), but the cell contractions of the
+ * local operator run as bf16x3 split products on the bf16 matrix cores
+ * (x = hi + lo, two bf16 parts; a*b ~ lo_a hi_b + hi_a lo_b + hi_a hi_b with
+ * FP32 accumulation; relative error ~2^-16 per product, the FP32 (TF32-like)
+ * stand-in of the precision paragraph).  The projector contractions stay
+ * FP32.  Accepted by the apply entry points, pawfe_apply_local,
+ * pawfe_cheb_filter and its workspace query; data must be finite. */
 enum { PAWFE_FP64 = 0, PAWFE_FP32 = 1, PAWFE_BF16X3 = 2 };
 
 /* How G^a inside Delta_Sinv^a = (Delta_S^{a,-1} + G^a)^{-1} is formed

@@ -105,7 +105,7 @@ NlBufs carve_nl(const pawfe_op* op, Carve& cv, int64_t ncols) {
 
 template <typename T>
 pawfe_status do_apply(const pawfe_op* op, int which, const T* X, int64_t ldx, T* Y, int64_t ldy, int ncols,
-                      const NlBufs& b, hipStream_t s) {
+                      const NlBufs& b, hipStream_t s, bool bf3 = false) {
   if (which == 0 || which == 1) {   // H or S
     CHECK(launch_nl_reduce<T>(op, X, ldx, ncols, false, b.part, b.c, s));
     CHECK(launch_atom_mul(op, which == 0 ? op->d.dH : op->d.dS, nullptr, nullptr, 1.0, b.c, b.d, ncols, s));
@@ -113,7 +113,7 @@ pawfe_status do_apply(const pawfe_op* op, int which, const T* X, int64_t ldx, T*
       CHECK(launch_node_nl_init<T>(op, b.d, ncols, Y, ldy, s));
     else
       CHECK(launch_node_nl_init<T>(op, nullptr, ncols, Y, ldy, s));
-    return launch_cell<T>(op, which == 0 ? kModeH : kModeMass, X, ldx, Y, ldy, ncols, nullptr, 1.0, s);
+    return launch_cell<T>(op, which == 0 ? kModeH : kModeMass, X, ldx, Y, ldy, ncols, nullptr, 1.0, s, bf3);
   }
   // Sinv_hat
   CHECK(launch_nl_reduce<T>(op, X, ldx, ncols, true, b.part, b.c, s));
@@ -130,9 +130,10 @@ pawfe_status do_residual(const pawfe_op* op, const double* X, int64_t ldx, const
   return launch_cell<double>(op, kModeHRes, X, ldx, Y, ldy, ncols, lam, 1.0, s);
 }
 
+// PAWFE_BF16X3: FP32 data, the cell contractions as bf16x3 split products
+// (everything else as PAWFE_FP32).
 pawfe_status check_prec(int32_t prec) {
-  if (prec == PAWFE_FP64 || prec == PAWFE_FP32) return PAWFE_OK;
-  if (prec == PAWFE_BF16X3) return fail(PAWFE_EUNSUPPORTED, "BF16X3 is not implemented for this entry point");
+  if (prec == PAWFE_FP64 || prec == PAWFE_FP32 || prec == PAWFE_BF16X3) return PAWFE_OK;
   return fail(PAWFE_EINVAL, "unknown precision");
 }
 
@@ -156,7 +157,8 @@ pawfe_status apply_entry(const pawfe_op* cop, int which, const void* X, int64_t 
     if (prec == PAWFE_FP64)
       CHECK(do_apply<double>(op, which, (const double*)X + j0, ldx, (double*)Y + j0, ldy, nc, b, s));
     else
-      CHECK(do_apply<float>(op, which, (const float*)X + j0, ldx, (float*)Y + j0, ldy, nc, b, s));
+      CHECK(do_apply<float>(op, which, (const float*)X + j0, ldx, (float*)Y + j0, ldy, nc, b, s,
+                            prec == PAWFE_BF16X3));
   }
   return PAWFE_OK;
 }
@@ -175,7 +177,7 @@ size_t filter_ws_bytes(const pawfe_op* op, int64_t B, int32_t prec) {
 template <typename TR>
 pawfe_status filter_block(const pawfe_op* op, const double* X, int64_t ldx, double* Xo, int64_t ldo, int nc,
                           int64_t B, const double* lam_in, int m, double b0, double bW, double bU, Carve cv,
-                          hipStream_t s) {
+                          hipStream_t s, bool bf3 = false) {
   double* Y = cv.take<double>((size_t)op->M * B);
   TR* RX = cv.take<TR>((size_t)op->M * B);
   TR* RY = cv.take<TR>((size_t)op->M * B);
@@ -205,7 +207,7 @@ pawfe_status filter_block(const pawfe_op* op, const double* X, int64_t ldx, doub
     CHECK(launch_node_cheb<TR>(op, RY, RX, Tb, ld, Y, ld, nb.d, nb.c, lamY, lamX, lam_in, a, a * c, zeta * znew,
                                nc, s));
     // R_X += a H_loc T
-    CHECK(launch_cell<TR>(op, kModeH, Tb, ld, RX, ld, nc, nullptr, a, s));
+    CHECK(launch_cell<TR>(op, kModeH, Tb, ld, RX, ld, nc, nullptr, a, s, bf3));
     std::swap(RX, RY);
     std::swap(lamX, lamY);
     zeta = znew;
@@ -528,7 +530,8 @@ pawfe_status pawfe_apply_local(const pawfe_op* op, int32_t which, const void* X,
   if (prec == PAWFE_FP64)
     return launch_cell<double>(op, mode, (const double*)X, ldx, (double*)Y, ldy, (int)nvec, nullptr, alpha,
                                S(stream));
-  return launch_cell<float>(op, mode, (const float*)X, ldx, (float*)Y, ldy, (int)nvec, nullptr, alpha, S(stream));
+  return launch_cell<float>(op, mode, (const float*)X, ldx, (float*)Y, ldy, (int)nvec, nullptr, alpha, S(stream),
+                            prec == PAWFE_BF16X3);
 }
 
 pawfe_status pawfe_cheb_filter_workspace(const pawfe_op* op, int64_t nvec, int32_t block, int32_t prec,
@@ -564,7 +567,8 @@ pawfe_status pawfe_cheb_filter(const pawfe_op* op, const void* Xin, int64_t ldx,
     if (prec == PAWFE_FP64)
       CHECK(filter_block<double>(op, X, ldx, Xo, ldo, nc, B, lambda_in + j0, degree, b0, bW, bU, cv, s));
     else
-      CHECK(filter_block<float>(op, X, ldx, Xo, ldo, nc, B, lambda_in + j0, degree, b0, bW, bU, cv, s));
+      CHECK(filter_block<float>(op, X, ldx, Xo, ldo, nc, B, lambda_in + j0, degree, b0, bW, bU, cv, s,
+                                prec == PAWFE_BF16X3));
   }
   return PAWFE_OK;
 }

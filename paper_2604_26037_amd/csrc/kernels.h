@@ -22,6 +22,7 @@ struct CellArgs {
   const double* lam;   // per-column lambda (residual mode)
   T alpha;
   int n0, n1, n2;
+  int bf3;             // FP32 data, contractions as bf16x3 split products
 };
 
 struct DensArgs {
@@ -38,9 +39,11 @@ struct DensArgs {
 //  mode kModeH:    A_loc = K + V
 //  mode kModeHRes: A_loc = K + V - lambda_n M (per column n)
 //  mode kModeMass: A_loc = M
+//  bf3: (FP32 only) the cell contractions as bf16x3 split products on the
+//  bf16 matrix cores, FP32 accumulation.
 template <typename T>
 pawfe_status launch_cell(const pawfe_op* op, int mode, const T* X, int64_t ldx, T* Y, int64_t ldy,
-                         int ncols, const double* lam, double alpha, hipStream_t s);
+                         int ncols, const double* lam, double alpha, hipStream_t s, bool bf3 = false);
 
 template <typename T>
 pawfe_status launch_cell_mfma(const pawfe_op* op, int mode, const CellArgs<T>& a, hipStream_t s);

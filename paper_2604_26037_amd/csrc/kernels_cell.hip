@@ -379,9 +379,11 @@ pawfe_status run_cell(const pawfe_op* op, int mode, CellArgs<T> a, hipStream_t s
 
 template <typename T>
 pawfe_status launch_cell(const pawfe_op* op, int mode, const T* X, int64_t ldx, T* Y, int64_t ldy,
-                         int ncols, const double* lam, double alpha, hipStream_t s) {
+                         int ncols, const double* lam, double alpha, hipStream_t s, bool bf3) {
   if (ncols <= 0) return PAWFE_OK;
+  if (bf3 && sizeof(T) != 4) return fail(PAWFE_EINVAL, "bf16x3 needs FP32 data");
   CellArgs<T> a{};
+  a.bf3 = bf3 ? 1 : 0;
   a.X = X;
   a.ldx = ldx;
   a.Y = Y;
@@ -398,7 +400,7 @@ pawfe_status launch_cell(const pawfe_op* op, int mode, const T* X, int64_t ldx, 
     const char* v = std::getenv("PAWFE_CELL_KERNEL");
     return v && std::string(v) == "valu";
   }();
-  if (!use_valu) return launch_cell_mfma<T>(op, mode, a, s);
+  if (!use_valu || bf3) return launch_cell_mfma<T>(op, mode, a, s);
   constexpr int CB = cb_of<T>();
   switch (op->p) {
     case 2: return run_cell<T, 3, 4, CB>(op, mode, a, s);
@@ -411,9 +413,9 @@ pawfe_status launch_cell(const pawfe_op* op, int mode, const T* X, int64_t ldx, 
 }
 
 template pawfe_status launch_cell<double>(const pawfe_op*, int, const double*, int64_t, double*, int64_t,
-                                          int, const double*, double, hipStream_t);
+                                          int, const double*, double, hipStream_t, bool);
 template pawfe_status launch_cell<float>(const pawfe_op*, int, const float*, int64_t, float*, int64_t,
-                                         int, const double*, double, hipStream_t);
+                                         int, const double*, double, hipStream_t, bool);
 
 pawfe_status launch_density(const pawfe_op* op, const double* X, int64_t ldx, int ncols,
                             const double* occ, double* out, hipStream_t s) {

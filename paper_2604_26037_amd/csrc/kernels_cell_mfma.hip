@@ -69,6 +69,37 @@ struct Mma<double> {
   static __device__ __forceinline__ int row(int g, int e) { return g + 4 * e; }
 };
 
+// bf16x3 split products (FP32 data on the bf16 matrix cores): x = hi + lo with
+// hi = bf16(x), lo = bf16(x - hi) (round to nearest even; finite inputs), and
+// a*b ~ lo_a hi_b + hi_a lo_b + hi_a hi_b accumulated in FP32 (the lo*lo
+// term, ~2^-16 relative, is dropped).  v_mfma_f32_16x16x16_bf16 operand
+// layout (checked on gfx950): A[i][k] in lane i + 16 (k/4), element k % 4;
+// B[k][j] in lane j + 16 (k/4), element k % 4; D as for f32.
+typedef short BfV4 __attribute__((ext_vector_type(4)));
+typedef float F4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short bf16_rne(float x, float& back) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  back = __uint_as_float(u & 0xFFFF0000u);
+  return (short)(u >> 16);
+}
+
+__device__ __forceinline__ void bf16_split(const float (&x)[4], BfV4& hi, BfV4& lo) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    float h, dummy;
+    hi[v] = bf16_rne(x[v], h);
+    lo[v] = bf16_rne(x[v] - h, dummy);
+  }
+}
+
+__device__ __forceinline__ F4 mfma_bf3(const BfV4& ahi, const BfV4& alo, const BfV4& bhi, const BfV4& blo, F4 acc) {
+  acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo, bhi, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, blo, acc, 0, 0, 0);
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, bhi, acc, 0, 0, 0);
+}
+
 constexpr int kSlots = 512;   // 8 x 8 x 8 padded slots per column
 
 __host__ __device__ constexpr int rev3(int v) { return ((v & 1) << 2) | (v & 2) | ((v >> 2) & 1); }
@@ -140,6 +171,23 @@ constexpr int lane_mask() {
   return m;
 }
 
+// Same for the A-operand reads of the bf16x3 variant: lane (row r, group g)
+// reads axis index 4 (g & 1) + v of input buffer g >> 1 (buffer 0 when the
+// pass has one input), v = 0..3 in the constant part.
+template <int CB, int AX>
+constexpr int lane_mask_bf3(int nin, int keyc) {
+  constexpr int LPT = 16 / CB;
+  int m = 0;
+  for (int w = 0; w < 4; ++w)
+    for (int r = 0; r < 16; ++r)
+      for (int g = 0; g < 4; ++g) {
+        const int key = (nin == 2 && (g >> 1)) ? 0 : keyc;
+        m |= line_addr<float, CB, AX>(LPT * w | (r / CB), 4 * (g & 1), r % CB, key);
+        m |= line_addr<float, CB, AX>(LPT * w | (r / CB), 4 * (g & 1), r % CB, 0);
+      }
+  return m;
+}
+
 }  // namespace
 
 // One MFMA contraction pass over the 64 padded lines.
@@ -152,7 +200,7 @@ constexpr int lane_mask() {
 // part (row, k or output index within a tile, wave) is computed once per
 // pass, the constant part (tile, k-step, result element) folds at compile
 // time, and each access costs one XOR.
-template <typename T, int AX, int CB, int NIN, int NG, class CF, class POST>
+template <typename T, int AX, int CB, int NIN, int NG, bool BF3, class CF, class POST>
 __device__ __forceinline__ void mfma_pass(T* smem, const Slab* in, const Slab* out, CF cf, POST post) {
   using M = Mma<T>;
   constexpr int NKS = 2 * NIN;                 // k-steps of 4
@@ -164,11 +212,23 @@ __device__ __forceinline__ void mfma_pass(T* smem, const Slab* in, const Slab* o
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r = lane & 15, kr = lane >> 4;
+  static_assert(!BF3 || sizeof(T) == 4, "bf16x3 runs on FP32 data");
   T bco[NOB][NKS];
+  BfV4 bhi[NOB], blo[NOB];
+  if constexpr (BF3) {
 #pragma unroll
-  for (int ob = 0; ob < NOB; ++ob)
+    for (int ob = 0; ob < NOB; ++ob) {
+      float c[4];
 #pragma unroll
-    for (int ks = 0; ks < NKS; ++ks) bco[ob][ks] = cf(ob * 16 + r, ks * 4 + kr);
+      for (int v = 0; v < 4; ++v) c[v] = (float)cf(ob * 16 + r, 4 * kr + v);
+      bf16_split(c, bhi[ob], blo[ob]);
+    }
+  } else {
+#pragma unroll
+    for (int ob = 0; ob < NOB; ++ob)
+#pragma unroll
+      for (int ks = 0; ks < NKS; ++ks) bco[ob][ks] = cf(ob * 16 + r, ks * 4 + kr);
+  }
   // tile t = wave + 4 it covers lines LPT t + [0, LPT)
   const int lw = LPT * wave;
   const int rd_lane = line_addr<T, CB, AX>(lw | (r / CB), kr, r % CB, 0);
@@ -180,31 +240,61 @@ __device__ __forceinline__ void mfma_pass(T* smem, const Slab* in, const Slab* o
     const Slab b = r < 8 ? s0 : s1;
     wr_lane[ob] = b.off | line_addr<T, CB, AX>(lw | (rl / CB), r & 7, rl % CB, b.key);
   }
-  // A operands of tile `it` (k = 4 ks + kr, index k % 8 in buffer ks / 2)
-  auto load_a = [&](int it, T (&av)[NKS]) {
+  // A operands of tile `it`.  FP32/FP64: k = 4 ks + kr, index k % 8 in
+  // buffer ks / 2.  bf16x3: the lane's four k = 4 kr + v (v = 0..3), buffer
+  // kr / 2 when there are two inputs (else buffer 0, duplicates that meet
+  // zero coefficients), index 4 (kr & 1) + v.
+  constexpr int NA = BF3 ? 4 : NKS;
+  constexpr int MR3 = BF3 ? (lane_mask_bf3<CB, AX>(NIN, kKeyC<float>) | 3) : 0;
+  int rd3_lane = 0;
+  if constexpr (BF3) {
+    const Slab b = in[(NIN == 2 && (kr >> 1)) ? NIN - 1 : 0];
+    rd3_lane = b.off | line_addr<T, CB, AX>(lw | (r / CB), 4 * (kr & 1), r % CB, b.key);
+  }
+  auto load_a = [&](int it, T (&av)[NA]) {
+    if constexpr (BF3) {
 #pragma unroll
-    for (int ks = 0; ks < NKS; ++ks) {
-      const Slab b = in[ks / 2];
-      const int c = b.off | line_addr<T, CB, AX>(LPT * 4 * it, 4 * (ks & 1), 0, b.key);
-      av[ks] = lds_at(smem, (rd_lane ^ (c & MR)) + (c & ~MR));
+      for (int v = 0; v < 4; ++v) {
+        const int c = line_addr<T, CB, AX>(LPT * 4 * it, v, 0, 0);
+        av[v] = lds_at(smem, (rd3_lane ^ (c & MR3)) + (c & ~MR3));
+      }
+    } else {
+#pragma unroll
+      for (int ks = 0; ks < NKS; ++ks) {
+        const Slab b = in[ks / 2];
+        const int c = b.off | line_addr<T, CB, AX>(LPT * 4 * it, 4 * (ks & 1), 0, b.key);
+        av[ks] = lds_at(smem, (rd_lane ^ (c & MR)) + (c & ~MR));
+      }
     }
   };
   // software pipeline: the next tile's operands are read before this tile's
   // results are written (in program order), so the LDS latency overlaps the
   // MFMAs instead of waiting behind the in-place stores
-  T av[NKS];
+  T av[NA];
   load_a(0, av);
 #pragma unroll
   for (int it = 0; it < NT / 4; ++it) {
     const int lc = LPT * 4 * it;
-    T an[NKS];
+    T an[NA];
     if (it + 1 < NT / 4) load_a(it + 1, an);
     typename M::V4 acc[NOB];
+    if constexpr (BF3) {
+      BfV4 ahi, alo;
+      float a4[4] = {(float)av[0], (float)av[1], (float)av[2], (float)av[3]};
+      bf16_split(a4, ahi, alo);
 #pragma unroll
-    for (int ob = 0; ob < NOB; ++ob) {
-      acc[ob] = typename M::V4{T(0), T(0), T(0), T(0)};
+      for (int ob = 0; ob < NOB; ++ob) {
+        F4 z = {0.f, 0.f, 0.f, 0.f};
+        const F4 d = mfma_bf3(ahi, alo, bhi[ob], blo[ob], z);
+        acc[ob] = typename M::V4{(T)d[0], (T)d[1], (T)d[2], (T)d[3]};
+      }
+    } else {
 #pragma unroll
-      for (int ks = 0; ks < NKS; ++ks) acc[ob] = M::op(av[ks], bco[ob][ks], acc[ob]);
+      for (int ob = 0; ob < NOB; ++ob) {
+        acc[ob] = typename M::V4{T(0), T(0), T(0), T(0)};
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks) acc[ob] = M::op(av[ks], bco[ob][ks], acc[ob]);
+      }
     }
 #pragma unroll
     for (int ob = 0; ob < NOB; ++ob) {
@@ -237,12 +327,12 @@ __device__ __forceinline__ void mfma_pass(T* smem, const Slab* in, const Slab* o
     }
     if (it + 1 < NT / 4) {
 #pragma unroll
-      for (int ks = 0; ks < NKS; ++ks) av[ks] = an[ks];
+      for (int ks = 0; ks < NA; ++ks) av[ks] = an[ks];
     }
   }
 }
 
-template <typename T, int NP, int NQ, int CB, int MODE>
+template <typename T, int NP, int NQ, int CB, int MODE, bool BF3>
 __global__ void __launch_bounds__(256) k_cell_mfma(CellArgs<T> A, const Tab1D<T>* __restrict__ tabp,
                                                    int ncoltiles, int nitems) {
   constexpr int NL = NP * NP * NP;
@@ -374,11 +464,11 @@ __global__ void __launch_bounds__(256) k_cell_mfma(CellArgs<T> A, const Tab1D<T>
       const Slab inA[1] = {sA};
       const Slab inC[1] = {sC};
       const Slab oC[1] = {sC};
-      mfma_pass<T, 0, CB, 1, 1>(smem, inA, oC, [&](int o, int k) { return Mm(o, k); }, store);
+      mfma_pass<T, 0, CB, 1, 1, BF3>(smem, inA, oC, [&](int o, int k) { return Mm(o, k); }, store);
       __syncthreads();
-      mfma_pass<T, 1, CB, 1, 1>(smem, inC, oC, [&](int o, int k) { return Mm(o, k); }, store);
+      mfma_pass<T, 1, CB, 1, 1, BF3>(smem, inC, oC, [&](int o, int k) { return Mm(o, k); }, store);
       __syncthreads();
-      mfma_pass<T, 2, CB, 1, 1>(smem, inC, oC, [&](int o, int k) { return tab.detJ * Mm(o, k); }, store);
+      mfma_pass<T, 2, CB, 1, 1, BF3>(smem, inC, oC, [&](int o, int k) { return tab.detJ * Mm(o, k); }, store);
       __syncthreads();
     } else {
       const Slab inA[1] = {sA};
@@ -389,12 +479,12 @@ __global__ void __launch_bounds__(256) k_cell_mfma(CellArgs<T> A, const Tab1D<T>
       const Slab oBCA[3] = {sB, sC, sA};
       const Slab oCA[2] = {sC, sA};
       // P1 x: [Bx; Kx; Mx] U
-      mfma_pass<T, 0, CB, 1, 3>(
+      mfma_pass<T, 0, CB, 1, 3, BF3>(
           smem, inA, oBCA,
           [&](int o, int k) { return o < 8 ? Bm(o, k) : (o < 16 ? Km(o - 8, k) : Mm(o - 16, k)); }, store);
       __syncthreads();
       // P2 y: By
-      mfma_pass<T, 1, CB, 1, 1>(smem, inB, oB, [&](int o, int k) { return Bm(o, k); }, store);
+      mfma_pass<T, 1, CB, 1, 1, BF3>(smem, inB, oB, [&](int o, int k) { return Bm(o, k); }, store);
       __syncthreads();
       // P3 z: Bz, then V(q) W_q (minus lambda_n W_q); lines are (qa, qb)
       {
@@ -406,16 +496,16 @@ __global__ void __launch_bounds__(256) k_cell_mfma(CellArgs<T> A, const Tab1D<T>
           if constexpr (RES) s -= lams[c] * w3s[q + q / 64];
           return v * s;
         };
-        mfma_pass<T, 2, CB, 1, 1>(smem, inB, oB, [&](int o, int k) { return Bm(o, k); }, vpost);
+        mfma_pass<T, 2, CB, 1, 1, BF3>(smem, inB, oB, [&](int o, int k) { return Bm(o, k); }, vpost);
       }
       __syncthreads();
       // P4 z: Bz^T;  P5 y: By^T
-      mfma_pass<T, 2, CB, 1, 1>(smem, inB, oB, [&](int o, int k) { return Bm(k, o); }, store);
+      mfma_pass<T, 2, CB, 1, 1, BF3>(smem, inB, oB, [&](int o, int k) { return Bm(k, o); }, store);
       __syncthreads();
-      mfma_pass<T, 1, CB, 1, 1>(smem, inB, oB, [&](int o, int k) { return Bm(k, o); }, store);
+      mfma_pass<T, 1, CB, 1, 1, BF3>(smem, inB, oB, [&](int o, int k) { return Bm(k, o); }, store);
       __syncthreads();
       // P6 y: P = fx My C + fy Ky A -> C ; Q = My A -> A
-      mfma_pass<T, 1, CB, 2, 2>(
+      mfma_pass<T, 1, CB, 2, 2, BF3>(
           smem, inCA, oCA,
           [&](int o, int k) {
             if (o < 8) return k < 8 ? tab.f[0] * Mm(o, k) : tab.f[1] * Km(o, k - 8);
@@ -424,11 +514,11 @@ __global__ void __launch_bounds__(256) k_cell_mfma(CellArgs<T> A, const Tab1D<T>
           store);
       __syncthreads();
       // P7 z: kinetic = Mz P + fz Kz Q -> C
-      mfma_pass<T, 2, CB, 2, 1>(
+      mfma_pass<T, 2, CB, 2, 1, BF3>(
           smem, inCA, oC, [&](int o, int k) { return k < 8 ? Mm(o, k) : tab.f[2] * Km(o, k - 8); }, store);
       __syncthreads();
       // P8 x: Bx^T on slab B, accumulated into C
-      mfma_pass<T, 0, CB, 1, 1>(smem, inB, oC, [&](int o, int k) { return Bm(k, o); },
+      mfma_pass<T, 0, CB, 1, 1, BF3>(smem, inB, oC, [&](int o, int k) { return Bm(k, o); },
                                 [](int, int, int, T v, T old) { return old + v; });
       __syncthreads();
     }
@@ -467,8 +557,15 @@ int cell_grid(int nitems) {
 
 template <typename T, int NP, int NQ, int CB, int MODE>
 void launch_mode(const CellArgs<T>& ac, const Tab1D<T>* tab, int ncoltiles, int nitems, hipStream_t s) {
-  const dim3 grid(cell_grid<k_cell_mfma<T, NP, NQ, CB, MODE>>(nitems)), block(256);
-  hipLaunchKernelGGL((k_cell_mfma<T, NP, NQ, CB, MODE>), grid, block, 0, s, ac, tab, ncoltiles, nitems);
+  if constexpr (sizeof(T) == 4) {
+    if (ac.bf3) {
+      const dim3 grid(cell_grid<k_cell_mfma<T, NP, NQ, CB, MODE, true>>(nitems)), block(256);
+      hipLaunchKernelGGL((k_cell_mfma<T, NP, NQ, CB, MODE, true>), grid, block, 0, s, ac, tab, ncoltiles, nitems);
+      return;
+    }
+  }
+  const dim3 grid(cell_grid<k_cell_mfma<T, NP, NQ, CB, MODE, false>>(nitems)), block(256);
+  hipLaunchKernelGGL((k_cell_mfma<T, NP, NQ, CB, MODE, false>), grid, block, 0, s, ac, tab, ncoltiles, nitems);
 }
 
 template <typename T, int NP, int NQ, int CB>
