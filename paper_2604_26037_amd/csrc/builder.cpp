@@ -514,7 +514,7 @@ pawfe_status build_host(const pawfe_op_desc* d, pawfe_op* op) {
   }
 
   // reduction work items: chunks of at most kItemRows support rows per atom
-  const int kItemRows = 64;
+  const int kItemRows = 128;
   op->item_atom.clear();
   op->item_row0.clear();
   op->item_row1.clear();

@@ -96,9 +96,21 @@ __global__ void __launch_bounds__(256) k_nl_final(const double* __restrict__ par
   const int n = blockIdx.y * 256 + threadIdx.x;
   if (n >= ncols) return;
   const int a = proj_atom[g], al = proj_alpha[g];
+  const int i0 = d.item_ptr[a], i1 = d.item_ptr[a + 1];
+  // the partials of all items are independent loads: eight in flight at a
+  // time, summed in item order
   double s = 0.0;
-  for (int it = d.item_ptr[a]; it < d.item_ptr[a + 1]; ++it)
-    s += part[(int64_t)(d.item_poff[it] + al) * ncols + n];
+  for (int it = i0; it < i1; it += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int k = it + u < i1 ? it + u : i1 - 1;
+      v[u] = part[(int64_t)(d.item_poff[k] + al) * ncols + n];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (it + u < i1) s += v[u];
+  }
   c[(int64_t)g * ncols + n] = s;
 }
 
@@ -135,6 +147,7 @@ __global__ void __launch_bounds__(256) k_atom_gcorr(const double* __restrict__ c
   for (int k = d.gp_ptr[a]; k < d.gp_ptr[a + 1]; ++k) {
     const int b = d.gp_b[k], nb = d.nproj[b], pb = d.poff[b];
     const double* G = d.Gvals + d.gp_off[k] + s * nb;
+#pragma unroll 6
     for (int u = 0; u < nb; ++u) acc -= G[u] * dv[(int64_t)(pb + u) * ncols + n];
   }
   out[(int64_t)g * ncols + n] = acc;
