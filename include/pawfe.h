@@ -175,7 +175,10 @@ pawfe_status pawfe_apply_Sinv(const pawfe_op* op, const void* X, int64_t ldx, vo
 pawfe_status pawfe_apply_local(const pawfe_op* op, int32_t which, const void* X, int64_t ldx, void* Y,
                                int64_t ldy, int64_t nvec, double alpha, int32_t prec, void* stream);
 
-/* Bytes of workspace pawfe_cheb_filter needs for blocks of `block` columns. */
+/* Bytes of workspace pawfe_cheb_filter needs for blocks of `block` columns:
+ * room for two block states when nvec > block (two blocks in flight), else
+ * one.  A workspace of one block state (the query with nvec = block) is
+ * also accepted by pawfe_cheb_filter; blocks then run one after another. */
 pawfe_status pawfe_cheb_filter_workspace(const pawfe_op* op, int64_t nvec, int32_t block,
                                          int32_t prec, size_t* bytes);
 
@@ -189,7 +192,12 @@ pawfe_status pawfe_cheb_filter_workspace(const pawfe_op* op, int64_t nvec, int32
  * Xin, Xout: device FP64 [ndof][ld]; Xout may equal Xin (in place).
  * lambda_in: device FP64 [nvec] (estimates of the eigenvalues).
  * Requires b0 < bW < bU, degree >= 2, 1 <= block.  ws: device workspace of
- * at least pawfe_cheb_filter_workspace bytes, 256-byte aligned. */
+ * at least one block state (pawfe_cheb_filter_workspace with nvec = block),
+ * 256-byte aligned.  With room for two block states and more than one block,
+ * even and odd blocks run on two internal streams of the operator (default
+ * priority), forked from and joined back into `stream`, so that one block's
+ * memory-bound node kernels overlap the other block's cell kernel; the
+ * results are identical to the one-stream order. */
 pawfe_status pawfe_cheb_filter(const pawfe_op* op, const void* Xin, int64_t ldx, void* Xout,
                                int64_t ldo, int64_t nvec, int32_t block, const double* lambda_in,
                                int32_t degree, double b0, double bW, double bU, int32_t prec,

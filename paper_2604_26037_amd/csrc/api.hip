@@ -400,6 +400,14 @@ void free_device(pawfe_op* op) {
   op->scratch_bytes = 0;
   if (op->blas) rocblas_destroy_handle((rocblas_handle)op->blas);
   op->blas = nullptr;
+  for (hipEvent_t& e : op->fevent) {
+    if (e) (void)hipEventDestroy(e);
+    e = nullptr;
+  }
+  for (hipStream_t& st : op->fstream) {
+    if (st) (void)hipStreamDestroy(st);
+    st = nullptr;
+  }
 }
 
 }  // namespace pawfe
@@ -539,7 +547,9 @@ pawfe_status pawfe_cheb_filter_workspace(const pawfe_op* op, int64_t nvec, int32
   if (!op || !bytes) return fail(PAWFE_EINVAL, "op or bytes is NULL");
   if (nvec < 1 || block < 1) return fail(PAWFE_EINVAL, "nvec and block must be >= 1");
   CHECK(check_prec(prec));
-  *bytes = filter_ws_bytes(op, std::min<int64_t>(block, nvec), prec);
+  const int64_t B = std::min<int64_t>(block, nvec);
+  // room for two blocks in flight when there is more than one block
+  *bytes = filter_ws_bytes(op, B, prec) * (nvec > B ? 2 : 1);
   return PAWFE_OK;
 }
 
@@ -557,19 +567,50 @@ pawfe_status pawfe_cheb_filter(const pawfe_op* op, const void* Xin, int64_t ldx,
   CHECK(check_prec(prec));
   if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(PAWFE_EINVAL, "workspace must be 256-byte aligned");
   const int64_t B = std::min<int64_t>(block, nvec);
-  if (ws_bytes < filter_ws_bytes(op, B, prec)) return fail(PAWFE_EINVAL, "workspace too small");
+  const size_t one = filter_ws_bytes(op, B, prec);
+  if (ws_bytes < one) return fail(PAWFE_EINVAL, "workspace too small");
   hipStream_t s = S(stream);
-  for (int64_t j0 = 0; j0 < nvec; j0 += B) {
+  // Blocks are uncoupled.  With room for two block states (and more than one
+  // block), even blocks run on one internal stream and odd blocks on the
+  // other, forked from and joined back into `s`: one block's HBM-bound node
+  // kernels then overlap the other's latency-bound cell kernel.
+  const int nconc = (nvec > B && ws_bytes >= 2 * one) ? 2 : 1;
+  pawfe_op* mop = const_cast<pawfe_op*>(op);
+  if (nconc == 2) {
+    for (hipStream_t& st : mop->fstream)
+      if (!st) PAWFE_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    for (hipEvent_t& e : mop->fevent)
+      if (!e) PAWFE_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    PAWFE_HIP(hipEventRecord(mop->fevent[0], s));
+    for (hipStream_t st : mop->fstream) PAWFE_HIP(hipStreamWaitEvent(st, mop->fevent[0], 0));
+  }
+  for (int64_t j0 = 0, blk = 0; j0 < nvec; j0 += B, ++blk) {
     const int nc = (int)std::min<int64_t>(B, nvec - j0);
-    Carve cv(ws, ws_bytes);
+    const int k = nconc == 2 ? (int)(blk & 1) : 0;
+    hipStream_t sb = nconc == 2 ? mop->fstream[k] : s;
+    Carve cv((char*)ws + (size_t)k * one, one);
     const double* X = (const double*)Xin + j0;
     double* Xo = (double*)Xout + j0;
+    pawfe_status st;
     if (prec == PAWFE_FP64)
-      CHECK(filter_block<double>(op, X, ldx, Xo, ldo, nc, B, lambda_in + j0, degree, b0, bW, bU, cv, s));
+      st = filter_block<double>(op, X, ldx, Xo, ldo, nc, B, lambda_in + j0, degree, b0, bW, bU, cv, sb);
     else
-      CHECK(filter_block<float>(op, X, ldx, Xo, ldo, nc, B, lambda_in + j0, degree, b0, bW, bU, cv, s,
-                                prec == PAWFE_BF16X3));
+      st = filter_block<float>(op, X, ldx, Xo, ldo, nc, B, lambda_in + j0, degree, b0, bW, bU, cv, sb,
+                               prec == PAWFE_BF16X3);
+    if (st != PAWFE_OK) {
+      if (nconc == 2)   // still join, so `s` never runs ahead of work already enqueued
+        for (int q = 0; q < 2; ++q) {
+          (void)hipEventRecord(mop->fevent[1 + q], mop->fstream[q]);
+          (void)hipStreamWaitEvent(s, mop->fevent[1 + q], 0);
+        }
+      return st;
+    }
   }
+  if (nconc == 2)
+    for (int q = 0; q < 2; ++q) {
+      PAWFE_HIP(hipEventRecord(mop->fevent[1 + q], mop->fstream[q]));
+      PAWFE_HIP(hipStreamWaitEvent(s, mop->fevent[1 + q], 0));
+    }
   return PAWFE_OK;
 }
 

@@ -185,7 +185,9 @@ pawfe_status build(pawfe_batch* b, const pawfe_filter_job* jobs, int32_t njobs, 
     size_t wmax = 0;
     for (int32_t c : cand) {
       size_t w = 0;
-      CHECK(pawfe_cheb_filter_workspace(J.op, J.nvec, c, b->prec, &w));
+      // one block state: the batch's own streams provide the overlap, the
+      // filter then keeps every block of a job on the job's stream
+      CHECK(pawfe_cheb_filter_workspace(J.op, std::min<int64_t>(J.nvec, c), c, b->prec, &w));
       wmax = std::max(wmax, w);
     }
     if (hipMalloc(&b->ws[j], wmax) != hipSuccess) return fail(PAWFE_ENOMEM, "batch workspace allocation failed");

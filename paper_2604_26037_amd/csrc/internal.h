@@ -131,6 +131,10 @@ struct pawfe_op {
   size_t scratch_bytes = 0;
   // dense solver handle (rocBLAS handle, opaque here)
   void* blas = nullptr;
+  // two streams (default priority) and fork/join events of the filter's
+  // two-block overlap, created on first use
+  hipStream_t fstream[2] = {nullptr, nullptr};
+  hipEvent_t fevent[3] = {nullptr, nullptr, nullptr};
 };
 
 namespace pawfe {

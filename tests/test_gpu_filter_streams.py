@@ -1,0 +1,38 @@
+"""The filter with room for two block states runs even and odd blocks on two
+internal streams; every column must come out bit-identical to the
+one-stream order (blocks are uncoupled and every kernel is deterministic),
+also for a ragged last block, in FP64 and FP32."""
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_two_stream_blocks_bit_identical(prec):
+    from oracle import chfsi
+    from oracle.paw import PAWOperator
+    from paper_2604_26037_amd import Operator
+    from workloads import make_system
+    s = make_system("mid")
+    ref = PAWOperator(s)
+    op = Operator(s)
+    N, B, m = 70, 16, 9                      # 5 blocks, the last one ragged (6 columns)
+    X = torch.from_numpy(s.trial(N)).to("cuda:0")
+    lam, _ = op.rayleigh_ritz(X)
+    a = lam.cpu().numpy()
+    bU = 1.02 * chfsi.lanczos_bounds(ref, k=25)[1] + 1.0
+    one = op.workspace(op.cheb_filter_workspace(B, B, prec))
+    two = op.workspace(op.cheb_filter_workspace(N, B, prec))
+    assert two.numel() == 2 * one.numel()
+    y1 = op.cheb_filter(X, lam, m, float(a[0]), float(a[-1]), bU, block=B, prec=prec, ws=one)
+    y2 = op.cheb_filter(X, lam, m, float(a[0]), float(a[-1]), bU, block=B, prec=prec, ws=two)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(y1.cpu().numpy(), y2.cpu().numpy())
+    if prec == 0:
+        want = chfsi.rchfsi_filter(ref, X.cpu().numpy(), a, m, float(a[0]), float(a[-1]), bU, block=B)
+        err = np.linalg.norm(y2.cpu().numpy() - want) / np.linalg.norm(want)
+        assert err < 1e-9, err
