@@ -104,15 +104,6 @@ pawfe_status launch_coldot(const double* A, int64_t lda, const double* B, int64_
                            int ncols, double* partial, double* out, const double* w, bool sqrt_out,
                            bool accumulate_scalar, hipStream_t s);
 
-// C (N1 x N2) = A^T B, A: [K][lda], B: [K][ldb]; split-K partials in ws
-pawfe_status launch_gemm_tn(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t K,
-                            int N1, int N2, double* C, int ldc, double* ws, size_t ws_doubles,
-                            bool symmetrize, hipStream_t s);
-
-// Out[k][j] = sum_i A[k][i] Q[i][j], Q column-major (Q(i,j) = Qcm[j*ldq + i])
-pawfe_status launch_gemm_nq(const double* A, int64_t lda, const double* Qcm, int ldq, int64_t K, int N,
-                            double* Out, int64_t ldo, hipStream_t s);
-
 // dE/dDelta_H^a = sum_n occ_n P P^T, P = c rows of atom a
 pawfe_status launch_grad_dh(const pawfe_op* op, const double* c, int ncols, const double* occ,
                             double* out, hipStream_t s);

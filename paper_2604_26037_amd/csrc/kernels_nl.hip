@@ -1,5 +1,5 @@
-// Non-local PAW terms, node-wise recurrence kernels, reductions and the FP64
-// GEMMs of the Rayleigh-Ritz step, for gfx950.
+// Non-local PAW terms, node-wise recurrence kernels and column reductions,
+// for gfx950.
 //
 // Non-local action (eq. "FE nonlocal contribution"): the projector
 // coefficients c_a = C^a^T s X (s = 1 or M_D^{-1}) are a long-K skinny
@@ -10,7 +10,8 @@
 // a second kernel adds the chunks of each atom in a fixed order (no atomics,
 // deterministic).  The atom-block products (Delta x c, G^{ab} corrections)
 // are tiny and run one thread per (projector, column).  The add-back
-// sum_a C^a q_a is fused into the node-wise kernels that stream the rows.
+// sum_a C^a q_a on the support rows is a separate pass per atom colour
+// (k_nl_fixup) after the node-wise kernels that stream the rows.
 
 #include <cstdint>
 #include <initializer_list>
@@ -521,104 +522,6 @@ __global__ void __launch_bounds__(256) k_coldot_final(const double* __restrict__
   if (threadIdx.x == 0) out[0] += red[0];
 }
 
-// C_part[ks] (N1 x N2) = A[kbeg:kend]^T B[kbeg:kend]; 64x64 tiles, 4x4 per thread
-__global__ void __launch_bounds__(256) k_gemm_tn(const double* __restrict__ A, int64_t lda,
-                                                 const double* __restrict__ B, int64_t ldb, int64_t K, int N1,
-                                                 int N2, int64_t kchunk, double* __restrict__ part) {
-  __shared__ double As[16][64];
-  __shared__ double Bs[16][64];
-  const int tid = threadIdx.x, ti = tid / 16, tj = tid % 16;
-  const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
-  const int64_t kb = (int64_t)blockIdx.z * kchunk, ke = (kb + kchunk < K) ? kb + kchunk : K;
-  double acc[4][4] = {};
-  for (int64_t k = kb; k < ke; k += 16) {
-    for (int idx = tid; idx < 16 * 64; idx += 256) {
-      const int r = idx / 64, c = idx % 64;
-      const int64_t kk = k + r;
-      As[r][c] = (kk < ke && i0 + c < N1) ? A[kk * lda + i0 + c] : 0.0;
-      Bs[r][c] = (kk < ke && j0 + c < N2) ? B[kk * ldb + j0 + c] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      double av[4], bv[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) av[u] = As[r][ti * 4 + u];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) bv[v] = Bs[r][tj * 4 + v];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
-    }
-    __syncthreads();
-  }
-  double* P = part + (int64_t)blockIdx.z * N1 * N2;
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = i0 + ti * 4 + u, j = j0 + tj * 4 + v;
-      if (i < N1 && j < N2) P[(int64_t)i * N2 + j] = acc[u][v];
-    }
-}
-
-__global__ void k_gemm_reduce(const double* __restrict__ part, int nsplit, int N1, int N2, double* __restrict__ C,
-                              int ldc, int symmetrize) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)N1 * N2) return;
-  const int i = (int)(idx / N2), j = (int)(idx % N2);
-  double s = 0.0, t = 0.0;
-  for (int k = 0; k < nsplit; ++k) s += part[(int64_t)k * N1 * N2 + (int64_t)i * N2 + j];
-  if (symmetrize) {
-    for (int k = 0; k < nsplit; ++k) t += part[(int64_t)k * N1 * N2 + (int64_t)j * N2 + i];
-    s = 0.5 * (s + t);
-  }
-  C[(int64_t)i * ldc + j] = s;
-}
-
-// Out[k][j] = sum_i A[k][i] Q(i, j), Q column-major with leading dimension ldq
-__global__ void __launch_bounds__(256) k_gemm_nq(const double* __restrict__ A, int64_t lda,
-                                                 const double* __restrict__ Q, int ldq, int64_t K, int N,
-                                                 double* __restrict__ Out, int64_t ldo) {
-  __shared__ double As[64][17];
-  __shared__ double Qs[16][64];
-  const int tid = threadIdx.x, tk = tid / 16, tj = tid % 16;
-  const int64_t k0 = (int64_t)blockIdx.x * 64;
-  const int j0 = blockIdx.y * 64;
-  double acc[4][4] = {};
-  for (int i = 0; i < N; i += 16) {
-    for (int idx = tid; idx < 64 * 16; idx += 256) {
-      const int kk = idx / 16, ii = idx % 16;
-      As[kk][ii] = (k0 + kk < K && i + ii < N) ? A[(k0 + kk) * lda + i + ii] : 0.0;
-      const int jj = idx / 16;
-      Qs[ii][jj] = (j0 + jj < N && i + ii < N) ? Q[(int64_t)(j0 + jj) * ldq + i + ii] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int ii = 0; ii < 16; ++ii) {
-      double av[4], qv[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) av[u] = As[tk * 4 + u][ii];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) qv[v] = Qs[ii][tj * 4 + v];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * qv[v];
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t k = k0 + tk * 4 + u;
-      const int j = j0 + tj * 4 + v;
-      if (k < K && j < N) Out[k * ldo + j] = acc[u][v];
-    }
-}
-
 __global__ void k_grad_dh(const double* __restrict__ c, int ncols, const double* __restrict__ occ,
                           const int32_t* __restrict__ ent_atom, const int32_t* __restrict__ ent_s,
                           const int32_t* __restrict__ ent_t, int nent, DeviceTables d, double* __restrict__ out) {
@@ -901,31 +804,6 @@ pawfe_status launch_coldot(const double* A, int64_t lda, const double* B, int64_
                      partial);
   hipLaunchKernelGGL(k_coldot_final, dim3(scalar ? 1 : (ncols + 255) / 256), dim3(256), 0, s, partial, nchunks, ncols,
                      out, w, (int)sqrt_out, (int)scalar);
-  PAWFE_HIP(hipGetLastError());
-  return PAWFE_OK;
-}
-
-pawfe_status launch_gemm_tn(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t K, int N1, int N2,
-                            double* C, int ldc, double* ws, size_t ws_doubles, bool symmetrize, hipStream_t s) {
-  const int ti = (N1 + 63) / 64, tj = (N2 + 63) / 64;
-  int nsplit = (int)std::max<int64_t>(1, std::min<int64_t>((K + 4095) / 4096, 4096 / std::max(1, ti * tj) + 1));
-  nsplit = (int)std::min<int64_t>(nsplit, (int64_t)(ws_doubles / ((size_t)N1 * N2)));
-  if (nsplit < 1) return fail(PAWFE_EINVAL, "GEMM workspace too small");
-  int64_t kchunk = (K + nsplit - 1) / nsplit;
-  kchunk = (kchunk + 15) / 16 * 16;
-  nsplit = (int)((K + kchunk - 1) / kchunk);
-  hipLaunchKernelGGL(k_gemm_tn, dim3(ti, tj, nsplit), dim3(256), 0, s, A, lda, B, ldb, K, N1, N2, kchunk, ws);
-  const int64_t tot = (int64_t)N1 * N2;
-  hipLaunchKernelGGL(k_gemm_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, ws, nsplit, N1, N2, C, ldc,
-                     (int)symmetrize);
-  PAWFE_HIP(hipGetLastError());
-  return PAWFE_OK;
-}
-
-pawfe_status launch_gemm_nq(const double* A, int64_t lda, const double* Qcm, int ldq, int64_t K, int N, double* Out,
-                            int64_t ldo, hipStream_t s) {
-  hipLaunchKernelGGL(k_gemm_nq, dim3((unsigned)((K + 63) / 64), (N + 63) / 64), dim3(256), 0, s, A, lda, Qcm, ldq, K,
-                     N, Out, ldo);
   PAWFE_HIP(hipGetLastError());
   return PAWFE_OK;
 }
