@@ -332,8 +332,11 @@ __device__ __forceinline__ void mfma_pass(T* smem, const Slab* in, const Slab* o
   }
 }
 
+// FP32: registers held to three waves per SIMD (the LDS of three
+// workgroups fits in a CU).
 template <typename T, int NP, int NQ, int CB, int MODE, bool BF3>
-__global__ void __launch_bounds__(256) k_cell_mfma(CellArgs<T> A, const Tab1D<T>* __restrict__ tabp,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1)))
+k_cell_mfma(CellArgs<T> A, const Tab1D<T>* __restrict__ tabp,
                                                    int ncoltiles, int nitems) {
   constexpr int NL = NP * NP * NP;
   constexpr int NQ3 = NQ * NQ * NQ;
@@ -351,15 +354,39 @@ __global__ void __launch_bounds__(256) k_cell_mfma(CellArgs<T> A, const Tab1D<T>
   const Tab1D<T>& tab = *tabp;
   const int tid = threadIdx.x;
   const int col = tid % CB;                   // 256 is a multiple of CB
+  // FP32: the 1-D tables as zero-padded 8x8 blocks in LDS (B[q][a], K1, M1,
+  // zeros) and the scale factors f_x, f_y, f_z, detJ, so that no global load
+  // sits between the passes (a vector-memory wait there would also wait for
+  // the next item's prefetch).  FP64 has no LDS left at three workgroups per
+  // CU and reads the tables from global memory.
+  constexpr bool CT = sizeof(T) == 4;
+  constexpr int kBlkB = 0, kBlkK = 64, kBlkM = 128, kBlkZ = 192, kScal = 256;
+  __shared__ T ctab[CT ? 260 : 1];
+  if constexpr (CT) {
+    for (int i = tid; i < 260; i += 256) {
+      const int blk = i >> 6, o = (i >> 3) & 7, k = i & 7;
+      T v = T(0);
+      if (i >= kScal) v = i - kScal < 3 ? tab.f[i - kScal] : tab.detJ;
+      else if (blk == 0) v = (o < NQ && k < NP) ? tab.B[o * NP + k] : T(0);
+      else if (blk == 1) v = (o < NP && k < NP) ? tab.K1[o * NP + k] : T(0);
+      else if (blk == 2) v = (o < NP && k < NP) ? tab.M1[o * NP + k] : T(0);
+      ctab[i] = v;
+    }
+  }
 
   // local nodes gathered by this thread: (a, b, c) in bits 0-8 (3 bits
-  // each) and the element's byte offset in slab A from bit 9; -1 past the end
+  // each) and the element's byte offset in slab A from bit 9.  Threads past
+  // the last node (only in the last group) carry node (0, 0, 0), a padding
+  // slot (7, 7, 7) and the sign bit: they load a valid row, stage a zero
+  // into padding and store nothing.
+  constexpr int kLast = (NL * CB) % 256 == 0 ? NJ : NJ - 1;   // groups before kLast are all real
   int pk[NJ];
 #pragma unroll
   for (int j = 0; j < NJ; ++j) {
     const int l = tid / CB + (256 / CB) * j;
     const int a = l % NP, b = (l / NP) % NP, c = l / (NP * NP);
-    pk[j] = l < NL ? a | (b << 3) | (c << 6) | ((phys<T, CB>(a, b, c, col, 0) * (int)sizeof(T)) << 9) : -1;
+    pk[j] = l < NL ? a | (b << 3) | (c << 6) | ((phys<T, CB>(a, b, c, col, 0) * (int)sizeof(T)) << 9)
+                   : (int)(0x80000000u | (unsigned)((phys<T, CB>(7, 7, 7, col, 0) * (int)sizeof(T)) << 9));
   }
   const int p = NP - 1;
   const int Gx = A.n0 * p, Gy = A.n1 * p, Gz = A.n2 * p;
@@ -378,43 +405,91 @@ __global__ void __launch_bounds__(256) k_cell_mfma(CellArgs<T> A, const Tab1D<T>
     c.inner = c.ci + 1 < A.n0 && c.cj + 1 < A.n1 && c.ck + 1 < A.n2;
     return c;
   };
-  auto node_of = [&](const CellPos& cp, int pkj) -> int {
+  auto node_inner = [&](const CellPos& cp, int pkj) -> int {
+    return cp.base + (pkj & 7) + Gx * (((pkj >> 3) & 7) + Gy * ((pkj >> 6) & 7));
+  };
+  auto node_wrap = [&](const CellPos& cp, int pkj) -> int {
     const int a = pkj & 7, b = (pkj >> 3) & 7, c = (pkj >> 6) & 7;
-    if (cp.inner) return cp.base + a + Gx * (b + Gy * c);
     int gx = cp.ci * p + a; gx = gx >= Gx ? gx - Gx : gx;
     int gy = cp.cj * p + b; gy = gy >= Gy ? gy - Gy : gy;
     int gz = cp.ck * p + c; gz = gz >= Gz ? gz - Gz : gz;
     return gx + Gx * (gy + Gy * gz);
   };
-  auto lds_a = [&](int pkj) -> T& { return lds_at(smem, pkj >> 9); };
+  // global nodes of the thread's local nodes (one wave-uniform branch)
+  auto nodes_of = [&](const CellPos& cp, int (&node)[NJ]) {
+    if (cp.inner) {
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) node[j] = node_inner(cp, pk[j]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) node[j] = node_wrap(cp, pk[j]);
+    }
+  };
+  // rows of those nodes, column n: the loads are issued after the branch
+  // joins, so no copy of a loaded value waits for its load
+  auto gather = [&](const T* __restrict__ src, int64_t ld, const CellPos& cp, int n, T (&dst)[NJ]) {
+    int node[NJ];
+    nodes_of(cp, node);
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) dst[j] = src[(int64_t)node[j] * ld + n];
+  };
+  auto lds_a = [&](int pkj) -> T& { return lds_at(smem, (pkj >> 9) & 0xFFFFF); };
   // same element in slab C: its key flips column bits, its base is 2 slabs on
   auto lds_c = [&](int pkj) -> T& {
-    return lds_at(smem, ((pkj >> 9) ^ (kKeyC<T> * (int)sizeof(T))) + 2 * kSlots * CB * (int)sizeof(T));
+    return lds_at(smem, (((pkj >> 9) & 0xFFFFF) ^ (kKeyC<T> * (int)sizeof(T))) + 2 * kSlots * CB * (int)sizeof(T));
   };
 
   // items (cell of the colour, column tile), cell-major; the x-th eighth of
-  // them goes to the workgroups on XCD x (block w runs on XCD w % 8)
+  // them goes to the workgroups on XCD x (block w runs on XCD w % 8).  The
+  // cell list is read through the scalar cache (it is not written here), so
+  // reading it never waits for the vector loads in flight.
+  typedef const __attribute__((address_space(4))) int* ConstIntP;
+  const ConstIntP cells = (ConstIntP)A.cells;
   const int xcd = blockIdx.x & 7;
   const int i_end = (int)((int64_t)nitems * (xcd + 1) / 8);
   const int i_step = gridDim.x >> 3;
   int item = (int)((int64_t)nitems * xcd / 8) + (blockIdx.x >> 3);
 
   // registers for the gathered values (and V W) of the next item
+  // (xok: the column exists; values are zeroed only when staged, so that
+  // nothing waits for these loads before the passes run)
   T xr[NJ], vr[NV];
+  bool xok = false;
+  int xn0 = 0;
+  double xlam = 0.0;
   auto load_item = [&](int it) {
-    const int e = A.cells[it / ncoltiles];
-    const int n = (it % ncoltiles) * CB + col;
-    const CellPos cp = cell_pos(e);
-#pragma unroll
-    for (int j = 0; j < NJ; ++j)
-      xr[j] = (pk[j] >= 0 && n < A.ncols) ? A.X[(int64_t)node_of(cp, pk[j]) * A.ldx + n] : T(0);
+    const int e = cells[it / ncoltiles];
+    xn0 = (it % ncoltiles) * CB;
+    const int n = xn0 + col;
+    xok = n < A.ncols;
+    gather(A.X, A.ldx, cell_pos(e), xok ? n : 0, xr);
+    if constexpr (RES) xlam = A.lam[min(xn0 + col, A.ncols - 1)];
     if constexpr (HAS_V) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         const int q = tid + 256 * v;
-        vr[v] = q < NQ3 ? A.Vw[(int64_t)e * NQ3 + q] : T(0);
+        if (NQ3 % 256 == 0 || q < NQ3) vr[v] = A.Vw[(int64_t)e * NQ3 + q];
       }
     }
+  };
+
+  // stage the loaded item: gathered values -> slab A (extraction), V W and
+  // the columns' lambdas -> LDS.  It runs at the end of the previous item
+  // (slab A and these tables are no longer read once the last pass has
+  // started), where the loads it waits for are the most recent vector-memory
+  // operations and have had a whole item to arrive.
+  auto stage = [&]() {
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) lds_a(pk[j]) = (xok && (j < kLast || pk[j] >= 0)) ? xr[j] : T(0);
+    // (writes without branches, so that the wait for every load happens on
+    // every path and nothing is left in doubt at the top of the loop)
+    if constexpr (HAS_V) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        if (NQ3 % 256 == 0 || tid + 256 * v < NQ3) vws[tid + 256 * v + (tid + 256 * v) / 64] = vr[v];
+    }
+    // every thread of a column writes the same value
+    if constexpr (RES) lams[col] = xn0 + col < A.ncols ? (T)xlam : T(0);
   };
 
   // the padded slots are zero once and stay zero: every pass only ever
@@ -424,41 +499,43 @@ __global__ void __launch_bounds__(256) k_cell_mfma(CellArgs<T> A, const Tab1D<T>
     for (int q = tid; q < NQ3; q += 256) w3s[q + q / 64] = A.W3[q];
   if (item < i_end) load_item(item);
   __syncthreads();
+  if (item < i_end) stage();
+  __syncthreads();
 
   auto store = [](int, int, int, T v, T) { return v; };
   // padded 1-D tables: zero outside the true extents
-  auto Bm = [&](int q, int a) { return (q < NQ && a < NP) ? tab.B[q * NP + a] : T(0); };
-  auto Km = [&](int a, int b) { return (a < NP && b < NP) ? tab.K1[a * NP + b] : T(0); };
-  auto Mm = [&](int a, int b) { return (a < NP && b < NP) ? tab.M1[a * NP + b] : T(0); };
+  auto Bm = [&](int q, int a) -> T {
+    if constexpr (CT) return ctab[(q < 8 && a < 8) ? kBlkB + q * 8 + a : kBlkZ];
+    else return (q < NQ && a < NP) ? tab.B[q * NP + a] : T(0);
+  };
+  auto Km = [&](int a, int b) -> T {
+    if constexpr (CT) return ctab[(a < 8 && b < 8) ? kBlkK + a * 8 + b : kBlkZ];
+    else return (a < NP && b < NP) ? tab.K1[a * NP + b] : T(0);
+  };
+  auto Mm = [&](int a, int b) -> T {
+    if constexpr (CT) return ctab[(a < 8 && b < 8) ? kBlkM + a * 8 + b : kBlkZ];
+    else return (a < NP && b < NP) ? tab.M1[a * NP + b] : T(0);
+  };
+  auto fsc = [&](int i) -> T {
+    if constexpr (CT) return ctab[kScal + i];
+    else return i < 3 ? tab.f[i] : tab.detJ;
+  };
   constexpr int KC = kKeyC<T>;
   constexpr int SLB = kSlots * CB * (int)sizeof(T);   // slab size in bytes
   const Slab sA{0, 0}, sB{SLB, 0}, sC{2 * SLB, KC};
 
   for (; item < i_end; item += i_step) {
-    const int e = A.cells[item / ncoltiles];
+    const int e = cells[item / ncoltiles];
     const int n0 = (item % ncoltiles) * CB;
     const int n = n0 + col;
     const bool valid = n < A.ncols;
-    // stage the item: gathered values -> slab A (extraction), V W -> LDS
-#pragma unroll
-    for (int j = 0; j < NJ; ++j)
-      if (pk[j] >= 0) lds_a(pk[j]) = xr[j];
-    if constexpr (HAS_V) {
-#pragma unroll
-      for (int v = 0; v < NV; ++v)
-        if (tid + 256 * v < NQ3) vws[tid + 256 * v + (tid + 256 * v) / 64] = vr[v];
-    }
-    if constexpr (RES)
-      if (tid < CB) lams[tid] = n0 + tid < A.ncols ? (T)A.lam[n0 + tid] : T(0);
     // output rows of this item (old values) and the next item's inputs are
-    // fetched now and arrive while the passes run
+    // fetched now and arrive while the passes run (the item itself is staged)
     const CellPos cp = cell_pos(e);
     T yo[NJ];
-#pragma unroll
-    for (int j = 0; j < NJ; ++j)
-      yo[j] = (pk[j] >= 0 && valid) ? A.Y[(int64_t)node_of(cp, pk[j]) * A.ldy + n] : T(0);
-    if (item + i_step < i_end) load_item(item + i_step);
-    __syncthreads();
+    gather(A.Y, A.ldy, cp, valid ? n : 0, yo);
+    // (the last item loads itself again: unconditional loads, no join)
+    load_item(item + i_step < i_end ? item + i_step : item);
 
     if constexpr (MODE == kModeMass) {
       const Slab inA[1] = {sA};
@@ -468,7 +545,7 @@ __global__ void __launch_bounds__(256) k_cell_mfma(CellArgs<T> A, const Tab1D<T>
       __syncthreads();
       mfma_pass<T, 1, CB, 1, 1, BF3>(smem, inC, oC, [&](int o, int k) { return Mm(o, k); }, store);
       __syncthreads();
-      mfma_pass<T, 2, CB, 1, 1, BF3>(smem, inC, oC, [&](int o, int k) { return tab.detJ * Mm(o, k); }, store);
+      mfma_pass<T, 2, CB, 1, 1, BF3>(smem, inC, oC, [&](int o, int k) { return fsc(3) * Mm(o, k); }, store);
       __syncthreads();
     } else {
       const Slab inA[1] = {sA};
@@ -508,27 +585,31 @@ __global__ void __launch_bounds__(256) k_cell_mfma(CellArgs<T> A, const Tab1D<T>
       mfma_pass<T, 1, CB, 2, 2, BF3>(
           smem, inCA, oCA,
           [&](int o, int k) {
-            if (o < 8) return k < 8 ? tab.f[0] * Mm(o, k) : tab.f[1] * Km(o, k - 8);
+            if (o < 8) return k < 8 ? fsc(0) * Mm(o, k) : fsc(1) * Km(o, k - 8);
             return k < 8 ? T(0) : Mm(o - 8, k - 8);
           },
           store);
       __syncthreads();
       // P7 z: kinetic = Mz P + fz Kz Q -> C
       mfma_pass<T, 2, CB, 2, 1, BF3>(
-          smem, inCA, oC, [&](int o, int k) { return k < 8 ? Mm(o, k) : tab.f[2] * Km(o, k - 8); }, store);
+          smem, inCA, oC, [&](int o, int k) { return k < 8 ? Mm(o, k) : fsc(2) * Km(o, k - 8); }, store);
       __syncthreads();
       // P8 x: Bx^T on slab B, accumulated into C
       mfma_pass<T, 0, CB, 1, 1, BF3>(smem, inB, oC, [&](int o, int k) { return Bm(k, o); },
                                 [](int, int, int, T v, T old) { return old + v; });
       __syncthreads();
     }
+    stage();
 
     // assembly: colour-ordered read-modify-write, CB contiguous columns per DOF
     if (valid) {
+      int node[NJ];
+      nodes_of(cp, node);
 #pragma unroll
       for (int j = 0; j < NJ; ++j)
-        if (pk[j] >= 0) A.Y[(int64_t)node_of(cp, pk[j]) * A.ldy + n] = yo[j] + A.alpha * lds_c(pk[j]);
+        if (j < kLast || pk[j] >= 0) A.Y[(int64_t)node[j] * A.ldy + n] = yo[j] + A.alpha * lds_c(pk[j]);
     }
+    __syncthreads();
   }
 }
 
