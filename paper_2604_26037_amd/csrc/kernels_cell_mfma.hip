@@ -354,24 +354,36 @@ k_cell_mfma(CellArgs<T> A, const Tab1D<T>* __restrict__ tabp,
   const Tab1D<T>& tab = *tabp;
   const int tid = threadIdx.x;
   const int col = tid % CB;                   // 256 is a multiple of CB
-  // FP32: the 1-D tables as zero-padded 8x8 blocks in LDS (B[q][a], K1, M1,
-  // zeros) and the scale factors f_x, f_y, f_z, detJ, so that no global load
-  // sits between the passes (a vector-memory wait there would also wait for
-  // the next item's prefetch).  FP64 has no LDS left at three workgroups per
-  // CU and reads the tables from global memory.
-  constexpr bool CT = sizeof(T) == 4;
-  constexpr int kBlkB = 0, kBlkK = 64, kBlkM = 128, kBlkZ = 192, kScal = 256;
-  __shared__ T ctab[CT ? 260 : 1];
-  if constexpr (CT) {
-    for (int i = tid; i < 260; i += 256) {
+  // The 1-D tables and the scale factors f_x, f_y, f_z, detJ live in LDS,
+  // so that no global load sits between the passes (a vector-memory wait
+  // there would also wait for the next item's prefetch).  FP32: zero-padded
+  // 8x8 blocks B[q][a], K1, M1 and a zero block (no bounds test on a read).
+  // FP64 (no LDS to spare at three workgroups per CU): B unpadded, the
+  // symmetric K1 and M1 as lower triangles, one zero.
+  constexpr bool PADT = sizeof(T) == 4;
+  constexpr int NB = NQ * NP, NS = NP * (NP + 1) / 2;
+  constexpr int tK = PADT ? 64 : NB, tM = PADT ? 128 : NB + NS, tZ = PADT ? 192 : NB + 2 * NS;
+  constexpr int tF = PADT ? 256 : tZ + 1, NCT = tF + 4;
+  __shared__ T ctab[NCT];
+  for (int i = tid; i < NCT; i += 256) {
+    T v = T(0);
+    if (i >= tF) {
+      v = i - tF < 3 ? tab.f[i - tF] : tab.detJ;
+    } else if constexpr (PADT) {
       const int blk = i >> 6, o = (i >> 3) & 7, k = i & 7;
-      T v = T(0);
-      if (i >= kScal) v = i - kScal < 3 ? tab.f[i - kScal] : tab.detJ;
-      else if (blk == 0) v = (o < NQ && k < NP) ? tab.B[o * NP + k] : T(0);
+      if (blk == 0) v = (o < NQ && k < NP) ? tab.B[o * NP + k] : T(0);
       else if (blk == 1) v = (o < NP && k < NP) ? tab.K1[o * NP + k] : T(0);
       else if (blk == 2) v = (o < NP && k < NP) ? tab.M1[o * NP + k] : T(0);
-      ctab[i] = v;
+    } else {
+      if (i < tK) {
+        v = tab.B[i];
+      } else if (i < tZ) {
+        int t = i < tM ? i - tK : i - tM, h = 0;   // packed (h, l), l <= h
+        while ((h + 1) * (h + 2) / 2 <= t) ++h;
+        v = (i < tM ? tab.K1 : tab.M1)[h * NP + (t - h * (h + 1) / 2)];
+      }
     }
+    ctab[i] = v;
   }
 
   // local nodes gathered by this thread: (a, b, c) in bits 0-8 (3 bits
@@ -503,23 +515,21 @@ k_cell_mfma(CellArgs<T> A, const Tab1D<T>* __restrict__ tabp,
   __syncthreads();
 
   auto store = [](int, int, int, T v, T) { return v; };
-  // padded 1-D tables: zero outside the true extents
+  // 1-D tables, zero outside the true extents
+  auto sym = [](int a, int b) { const int h = a > b ? a : b, l = a > b ? b : a; return h * (h + 1) / 2 + l; };
   auto Bm = [&](int q, int a) -> T {
-    if constexpr (CT) return ctab[(q < 8 && a < 8) ? kBlkB + q * 8 + a : kBlkZ];
-    else return (q < NQ && a < NP) ? tab.B[q * NP + a] : T(0);
+    if constexpr (PADT) return ctab[(q < 8 && a < 8) ? q * 8 + a : tZ];
+    else return ctab[(q < NQ && a < NP) ? q * NP + a : tZ];
   };
   auto Km = [&](int a, int b) -> T {
-    if constexpr (CT) return ctab[(a < 8 && b < 8) ? kBlkK + a * 8 + b : kBlkZ];
-    else return (a < NP && b < NP) ? tab.K1[a * NP + b] : T(0);
+    if constexpr (PADT) return ctab[(a < 8 && b < 8) ? tK + a * 8 + b : tZ];
+    else return ctab[(a < NP && b < NP) ? tK + sym(a, b) : tZ];
   };
   auto Mm = [&](int a, int b) -> T {
-    if constexpr (CT) return ctab[(a < 8 && b < 8) ? kBlkM + a * 8 + b : kBlkZ];
-    else return (a < NP && b < NP) ? tab.M1[a * NP + b] : T(0);
+    if constexpr (PADT) return ctab[(a < 8 && b < 8) ? tM + a * 8 + b : tZ];
+    else return ctab[(a < NP && b < NP) ? tM + sym(a, b) : tZ];
   };
-  auto fsc = [&](int i) -> T {
-    if constexpr (CT) return ctab[kScal + i];
-    else return i < 3 ? tab.f[i] : tab.detJ;
-  };
+  auto fsc = [&](int i) -> T { return ctab[tF + i]; };
   constexpr int KC = kKeyC<T>;
   constexpr int SLB = kSlots * CB * (int)sizeof(T);   // slab size in bytes
   const Slab sA{0, 0}, sB{SLB, 0}, sC{2 * SLB, KC};
