@@ -40,6 +40,7 @@
 // of one cell, then the next cells) land on the same XCD and share its L2.
 
 #include <algorithm>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -194,14 +195,20 @@ constexpr int lane_mask_bf3(int nin, int keyc) {
 //   inputs:  NIN buffers; input k in [8b, 8b + 8) comes from in[b]
 //   outputs: NG groups of 8; output o in [8g, 8g + 8) goes to out[g]
 //   cf(o, k): stacked coefficient (0 outside the true extents)
-//   post(L, o, col, value, old): the value stored
+//   pre(L, o): a value the store of (line L, output o) needs, read one tile
+//     ahead with the A operands (NoPre: none)
+//   post(L, o, col, value, old, pre value): the value stored
 // Every address is built from disjoint bit fields (col, x', y, z, slab) and
 // the swizzle is an XOR, so it splits as  lane part ^ constant part: the lane
 // part (row, k or output index within a tile, wave) is computed once per
 // pass, the constant part (tile, k-step, result element) folds at compile
 // time, and each access costs one XOR.
-template <typename T, int AX, int CB, int NIN, int NG, bool BF3, class CF, class POST>
-__device__ __forceinline__ void mfma_pass(T* smem, const Slab* in, const Slab* out, CF cf, POST post) {
+struct NoPre {};
+
+template <typename T, int AX, int CB, int NIN, int NG, bool BF3, class CF, class POST, class PRE = NoPre>
+__device__ __forceinline__ void mfma_pass(T* smem, const Slab* in, const Slab* out, CF cf, POST post,
+                                          PRE pre = PRE()) {
+  constexpr bool HAS_PRE = !std::is_same<PRE, NoPre>::value;
   using M = Mma<T>;
   constexpr int NKS = 2 * NIN;                 // k-steps of 4
   constexpr int NOB = (NG + 1) / 2;            // 16-wide output blocks
@@ -267,16 +274,39 @@ __device__ __forceinline__ void mfma_pass(T* smem, const Slab* in, const Slab* o
       }
     }
   };
+  // the pre values of tile `it`, one per output block and result element
+  // (f32: the four results of a lane lie on one line, one value serves them)
+  auto load_pre = [&](int it, T (&pv)[NOB][4]) {
+    if constexpr (HAS_PRE) {
+#pragma unroll
+      for (int ob = 0; ob < NOB; ++ob) {
+        if constexpr (sizeof(T) == 4) {
+          const T v = pre(lw | (LPT * 4 * it) | (rl / CB), ob * 16 + r);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) pv[ob][e] = v;
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) pv[ob][e] = pre(lw | (LPT * 4 * it) | ((rl | M::row(0, e)) / CB), ob * 16 + r);
+        }
+      }
+    }
+  };
   // software pipeline: the next tile's operands are read before this tile's
   // results are written (in program order), so the LDS latency overlaps the
   // MFMAs instead of waiting behind the in-place stores
   T av[NA];
+  T pv[NOB][4];
   load_a(0, av);
+  load_pre(0, pv);
 #pragma unroll
   for (int it = 0; it < NT / 4; ++it) {
     const int lc = LPT * 4 * it;
     T an[NA];
-    if (it + 1 < NT / 4) load_a(it + 1, an);
+    T pvn[NOB][4];
+    if (it + 1 < NT / 4) {
+      load_a(it + 1, an);
+      load_pre(it + 1, pvn);
+    }
     typename M::V4 acc[NOB];
     if constexpr (BF3) {
       BfV4 ahi, alo;
@@ -310,7 +340,7 @@ __device__ __forceinline__ void mfma_pass(T* smem, const Slab* in, const Slab* o
           typename M::V4 v = *dp;
           const int L2 = lw | lc | (rl / CB);
 #pragma unroll
-          for (int e = 0; e < 4; ++e) v[e] = post(L2, o, (rl % CB) | e, acc[ob][e], v[e]);
+          for (int e = 0; e < 4; ++e) v[e] = post(L2, o, (rl % CB) | e, acc[ob][e], v[e], pv[ob][e]);
           *dp = v;
         } else {
 #pragma unroll
@@ -320,7 +350,7 @@ __device__ __forceinline__ void mfma_pass(T* smem, const Slab* in, const Slab* o
             const int s = (wr_lane[ob] ^ (c & MW)) + (c & ~MW);
             const int L2 = lw | lc | ((rl | re) / CB), c2 = (rl | re) % CB;
             T& d = lds_at(smem, s);
-            d = post(L2, o, c2, acc[ob][e], d);
+            d = post(L2, o, c2, acc[ob][e], d, pv[ob][e]);
           }
         }
       }
@@ -328,6 +358,12 @@ __device__ __forceinline__ void mfma_pass(T* smem, const Slab* in, const Slab* o
     if (it + 1 < NT / 4) {
 #pragma unroll
       for (int ks = 0; ks < NA; ++ks) av[ks] = an[ks];
+      if constexpr (HAS_PRE) {
+#pragma unroll
+        for (int ob = 0; ob < NOB; ++ob)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) pv[ob][e] = pvn[ob][e];
+      }
     }
   }
 }
@@ -514,7 +550,7 @@ k_cell_mfma(CellArgs<T> A, const Tab1D<T>* __restrict__ tabp,
   if (item < i_end) stage();
   __syncthreads();
 
-  auto store = [](int, int, int, T v, T) { return v; };
+  auto store = [](int, int, int, T v, T, T) { return v; };
   // 1-D tables, zero outside the true extents
   auto sym = [](int a, int b) { const int h = a > b ? a : b, l = a > b ? b : a; return h * (h + 1) / 2 + l; };
   auto Bm = [&](int q, int a) -> T {
@@ -575,15 +611,23 @@ k_cell_mfma(CellArgs<T> A, const Tab1D<T>* __restrict__ tabp,
       __syncthreads();
       // P3 z: Bz, then V(q) W_q (minus lambda_n W_q); lines are (qa, qb)
       {
-        auto vpost = [&](int L, int o, int c, T v, T) {
+        // point index (clamped, so that a read never leaves the table) and
+        // whether the point is real; the weight is read one tile ahead
+        auto qidx = [](int L, int o) {
           const int qa = L & 7, qb = L >> 3;
-          if (qa >= NQ || qb >= NQ || o >= NQ) return T(0);
-          const int q = (o * NQ + qb) * NQ + qa;
-          T s = vws[q + q / 64];
-          if constexpr (RES) s -= lams[c] * w3s[q + q / 64];
-          return v * s;
+          const int q = ((o < NQ ? o : 0) * NQ + (qb < NQ ? qb : 0)) * NQ + (qa < NQ ? qa : 0);
+          return q + q / 64;
         };
-        mfma_pass<T, 2, CB, 1, 1, BF3>(smem, inB, oB, [&](int o, int k) { return Bm(o, k); }, vpost);
+        auto qin = [](int L, int o) { return (L & 7) < NQ && (L >> 3) < NQ && o < NQ; };
+        auto vpre = [&](int L, int o) {
+          const T w = vws[qidx(L, o)];   // unconditional read, then select
+          return qin(L, o) ? w : T(0);
+        };
+        auto vpost = [&](int L, int o, int c, T v, T, T w) {
+          if constexpr (RES) return qin(L, o) ? v * (w - lams[c] * w3s[qidx(L, o)]) : T(0);
+          else return v * w;
+        };
+        mfma_pass<T, 2, CB, 1, 1, BF3>(smem, inB, oB, [&](int o, int k) { return Bm(o, k); }, vpost, vpre);
       }
       __syncthreads();
       // P4 z: Bz^T;  P5 y: By^T
@@ -606,7 +650,7 @@ k_cell_mfma(CellArgs<T> A, const Tab1D<T>* __restrict__ tabp,
       __syncthreads();
       // P8 x: Bx^T on slab B, accumulated into C
       mfma_pass<T, 0, CB, 1, 1, BF3>(smem, inB, oC, [&](int o, int k) { return Bm(k, o); },
-                                [](int, int, int, T v, T old) { return old + v; });
+                                [](int, int, int, T v, T old, T) { return old + v; });
       __syncthreads();
     }
     stage();
