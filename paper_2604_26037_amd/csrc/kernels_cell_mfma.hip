@@ -205,6 +205,14 @@ constexpr int lane_mask_bf3(int nin, int keyc) {
 // time, and each access costs one XOR.
 struct NoPre {};
 
+// element (row, column n) of a row-major block with a row stride of ldb
+// bytes: the address is one 32 x 32 + 64-bit multiply-add
+template <typename P>
+__device__ __forceinline__ P* elem_ptr(P* base, uint32_t ldb, int n, int row) {
+  using C = typename std::conditional<std::is_const<P>::value, const char, char>::type;
+  return reinterpret_cast<P*>(reinterpret_cast<C*>(base + n) + (uint64_t)(uint32_t)row * ldb);
+}
+
 template <typename T, int AX, int CB, int NIN, int NG, bool BF3, class CF, class POST, class PRE = NoPre>
 __device__ __forceinline__ void mfma_pass(T* smem, const Slab* in, const Slab* out, CF cf, POST post,
                                           PRE pre = PRE()) {
@@ -422,23 +430,32 @@ k_cell_mfma(CellArgs<T> A, const Tab1D<T>* __restrict__ tabp,
     ctab[i] = v;
   }
 
-  // local nodes gathered by this thread: (a, b, c) in bits 0-8 (3 bits
-  // each) and the element's byte offset in slab A from bit 9.  Threads past
-  // the last node (only in the last group) carry node (0, 0, 0), a padding
-  // slot (7, 7, 7) and the sign bit: they load a valid row, stage a zero
-  // into padding and store nothing.
+  // local nodes gathered by this thread: local node l = tid / CB +
+  // (256 / CB) j = (a, b, c).  pk[j] = (off << 14) | (byte offset of the
+  // element in slab A), off = a + Gx (b + Gy c) the node's row offset from
+  // the cell's first node when no index wraps.  Threads past the last node
+  // (only in the last group) carry off 0 and a padding slot (7, 7, 7): they
+  // load a valid row, stage a zero into padding and store nothing.  The
+  // offset field holds 18 bits; larger meshes send every cell down the wrap
+  // path, which recomputes (a, b, c).
   constexpr int kLast = (NL * CB) % 256 == 0 ? NJ : NJ - 1;   // groups before kLast are all real
-  int pk[NJ];
-#pragma unroll
-  for (int j = 0; j < NJ; ++j) {
-    const int l = tid / CB + (256 / CB) * j;
-    const int a = l % NP, b = (l / NP) % NP, c = l / (NP * NP);
-    pk[j] = l < NL ? a | (b << 3) | (c << 6) | ((phys<T, CB>(a, b, c, col, 0) * (int)sizeof(T)) << 9)
-                   : (int)(0x80000000u | (unsigned)((phys<T, CB>(7, 7, 7, col, 0) * (int)sizeof(T)) << 9));
-  }
+  constexpr int kLdsBits = 14;
+  static_assert(kSlots * CB * sizeof(T) <= (1u << kLdsBits), "slab A offsets must fit the field");
   const int p = NP - 1;
   const int Gx = A.n0 * p, Gy = A.n1 * p, Gz = A.n2 * p;
-  // global node of local node pk in cell e (periodic wrap only for the last
+  const bool off_fits = (int64_t)p + (int64_t)Gx * (p + (int64_t)Gy * p) < (1 << (32 - kLdsBits));
+  auto lnode = [&](int j) { return tid / CB + (256 / CB) * j; };
+  auto lreal = [&](int j) { return j < kLast || lnode(j) < NL; };
+  unsigned pk[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int l = lnode(j);
+    const int a = l % NP, b = (l / NP) % NP, c = l / (NP * NP);
+    pk[j] = l < NL ? ((off_fits ? (unsigned)(a + Gx * (b + Gy * c)) : 0u) << kLdsBits) |
+                         (unsigned)(phys<T, CB>(a, b, c, col, 0) * (int)sizeof(T))
+                   : (unsigned)(phys<T, CB>(7, 7, 7, col, 0) * (int)sizeof(T));
+  }
+  // global node of local node j in cell e (periodic wrap only for the last
   // cell along an axis; the cell index is wave-uniform, so is the branch)
   struct CellPos {
     int ci, cj, ck, base;
@@ -450,14 +467,13 @@ k_cell_mfma(CellArgs<T> A, const Tab1D<T>* __restrict__ tabp,
     c.cj = (e / A.n0) % A.n1;
     c.ck = e / (A.n0 * A.n1);
     c.base = c.ci * p + Gx * (c.cj * p + Gy * c.ck * p);
-    c.inner = c.ci + 1 < A.n0 && c.cj + 1 < A.n1 && c.ck + 1 < A.n2;
+    c.inner = off_fits && c.ci + 1 < A.n0 && c.cj + 1 < A.n1 && c.ck + 1 < A.n2;
     return c;
   };
-  auto node_inner = [&](const CellPos& cp, int pkj) -> int {
-    return cp.base + (pkj & 7) + Gx * (((pkj >> 3) & 7) + Gy * ((pkj >> 6) & 7));
-  };
-  auto node_wrap = [&](const CellPos& cp, int pkj) -> int {
-    const int a = pkj & 7, b = (pkj >> 3) & 7, c = (pkj >> 6) & 7;
+  auto node_inner = [&](const CellPos& cp, int j) -> int { return cp.base + (int)(pk[j] >> kLdsBits); };
+  auto node_wrap = [&](const CellPos& cp, int j) -> int {
+    const int l = lreal(j) ? lnode(j) : 0;
+    const int a = l % NP, b = (l / NP) % NP, c = l / (NP * NP);
     int gx = cp.ci * p + a; gx = gx >= Gx ? gx - Gx : gx;
     int gy = cp.cj * p + b; gy = gy >= Gy ? gy - Gy : gy;
     int gz = cp.ck * p + c; gz = gz >= Gz ? gz - Gz : gz;
@@ -467,24 +483,27 @@ k_cell_mfma(CellArgs<T> A, const Tab1D<T>* __restrict__ tabp,
   auto nodes_of = [&](const CellPos& cp, int (&node)[NJ]) {
     if (cp.inner) {
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) node[j] = node_inner(cp, pk[j]);
+      for (int j = 0; j < NJ; ++j) node[j] = node_inner(cp, j);
     } else {
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) node[j] = node_wrap(cp, pk[j]);
+      for (int j = 0; j < NJ; ++j) node[j] = node_wrap(cp, j);
     }
   };
+  // row strides in bytes (below 4 GiB, checked on launch)
+  const uint32_t ldxb = (uint32_t)(A.ldx * (int64_t)sizeof(T)), ldyb = (uint32_t)(A.ldy * (int64_t)sizeof(T));
   // rows of those nodes, column n: the loads are issued after the branch
   // joins, so no copy of a loaded value waits for its load
-  auto gather = [&](const T* __restrict__ src, int64_t ld, const CellPos& cp, int n, T (&dst)[NJ]) {
+  auto gather = [&](const T* __restrict__ src, uint32_t ldb, const CellPos& cp, int n, T (&dst)[NJ]) {
     int node[NJ];
     nodes_of(cp, node);
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) dst[j] = src[(int64_t)node[j] * ld + n];
+    for (int j = 0; j < NJ; ++j) dst[j] = *elem_ptr(src, ldb, n, node[j]);
   };
-  auto lds_a = [&](int pkj) -> T& { return lds_at(smem, (pkj >> 9) & 0xFFFFF); };
+  auto lds_a = [&](unsigned pkj) -> T& { return lds_at(smem, (int)(pkj & ((1u << kLdsBits) - 1))); };
   // same element in slab C: its key flips column bits, its base is 2 slabs on
-  auto lds_c = [&](int pkj) -> T& {
-    return lds_at(smem, (((pkj >> 9) & 0xFFFFF) ^ (kKeyC<T> * (int)sizeof(T))) + 2 * kSlots * CB * (int)sizeof(T));
+  auto lds_c = [&](unsigned pkj) -> T& {
+    return lds_at(smem, ((int)(pkj & ((1u << kLdsBits) - 1)) ^ (kKeyC<T> * (int)sizeof(T))) +
+                            2 * kSlots * CB * (int)sizeof(T));
   };
 
   // items (cell of the colour, column tile), cell-major; the x-th eighth of
@@ -510,7 +529,7 @@ k_cell_mfma(CellArgs<T> A, const Tab1D<T>* __restrict__ tabp,
     xn0 = (it % ncoltiles) * CB;
     const int n = xn0 + col;
     xok = n < A.ncols;
-    gather(A.X, A.ldx, cell_pos(e), xok ? n : 0, xr);
+    gather(A.X, ldxb, cell_pos(e), xok ? n : 0, xr);
     if constexpr (RES) xlam = A.lam[min(xn0 + col, A.ncols - 1)];
     if constexpr (HAS_V) {
 #pragma unroll
@@ -528,7 +547,7 @@ k_cell_mfma(CellArgs<T> A, const Tab1D<T>* __restrict__ tabp,
   // operations and have had a whole item to arrive.
   auto stage = [&]() {
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) lds_a(pk[j]) = (xok && (j < kLast || pk[j] >= 0)) ? xr[j] : T(0);
+    for (int j = 0; j < NJ; ++j) lds_a(pk[j]) = (xok && lreal(j)) ? xr[j] : T(0);
     // (writes without branches, so that the wait for every load happens on
     // every path and nothing is left in doubt at the top of the loop)
     if constexpr (HAS_V) {
@@ -579,7 +598,7 @@ k_cell_mfma(CellArgs<T> A, const Tab1D<T>* __restrict__ tabp,
     // fetched now and arrive while the passes run (the item itself is staged)
     const CellPos cp = cell_pos(e);
     T yo[NJ];
-    gather(A.Y, A.ldy, cp, valid ? n : 0, yo);
+    gather(A.Y, ldyb, cp, valid ? n : 0, yo);
     // (the last item loads itself again: unconditional loads, no join)
     load_item(item + i_step < i_end ? item + i_step : item);
 
@@ -661,7 +680,7 @@ k_cell_mfma(CellArgs<T> A, const Tab1D<T>* __restrict__ tabp,
       nodes_of(cp, node);
 #pragma unroll
       for (int j = 0; j < NJ; ++j)
-        if (j < kLast || pk[j] >= 0) A.Y[(int64_t)node[j] * A.ldy + n] = yo[j] + A.alpha * lds_c(pk[j]);
+        if (lreal(j)) *elem_ptr(A.Y, ldyb, n, node[j]) = yo[j] + A.alpha * lds_c(pk[j]);
     }
     __syncthreads();
   }
@@ -729,6 +748,9 @@ pawfe_status run_cell_mfma(const pawfe_op* op, int mode, CellArgs<T> a, hipStrea
 template <typename T>
 pawfe_status launch_cell_mfma(const pawfe_op* op, int mode, const CellArgs<T>& a, hipStream_t s) {
   constexpr int CB = sizeof(T) == 8 ? 4 : 8;
+  if (a.ldx < 0 || a.ldy < 0 || a.ldx * (int64_t)sizeof(T) >= (int64_t(1) << 32) ||
+      a.ldy * (int64_t)sizeof(T) >= (int64_t(1) << 32))
+    return fail(PAWFE_EINVAL, "row stride of 4 GiB or more");
   switch (op->p) {
     case 2: return run_cell_mfma<T, 3, 4, CB>(op, mode, a, s);
     case 3: return run_cell_mfma<T, 4, 5, CB>(op, mode, a, s);
