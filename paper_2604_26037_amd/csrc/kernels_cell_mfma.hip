@@ -633,9 +633,15 @@ k_cell_mfma(CellArgs<T> A, const Tab1D<T>* __restrict__ tabp,
         // point index (clamped, so that a read never leaves the table) and
         // whether the point is real; the weight is read one tile ahead
         auto qidx = [](int L, int o) {
-          const int qa = L & 7, qb = L >> 3;
-          const int q = ((o < NQ ? o : 0) * NQ + (qb < NQ ? qb : 0)) * NQ + (qa < NQ ? qa : 0);
-          return q + q / 64;
+          if constexpr (NQ == 8) {
+            // q = 64 o + L, stored at q + o: the lane part plus a constant
+            // (o >= 8 lanes read in range and are discarded)
+            return 65 * (o & 7) + L;
+          } else {
+            const int qa = L & 7, qb = L >> 3;
+            const int q = ((o < NQ ? o : 0) * NQ + (qb < NQ ? qb : 0)) * NQ + (qa < NQ ? qa : 0);
+            return q + q / 64;
+          }
         };
         auto qin = [](int L, int o) { return (L & 7) < NQ && (L >> 3) < NQ && o < NQ; };
         auto vpre = [&](int L, int o) {
