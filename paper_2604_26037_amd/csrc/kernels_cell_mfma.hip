@@ -11,9 +11,12 @@
 // lane per k-step), D (16 r x 16 o) is written back to LDS.
 //
 // LDS holds three slabs of 8x8x8 slots of CB columns each, zero-initialized.
-// Every pass walks all 64 padded lines of the slab with unconditional stores:
+// Every pass walks the padded lines of the slab with unconditional stores:
 // rows and outputs beyond the true extents only ever meet zero
-// coefficients, so they stay finite and never reach a true slot.  Each wave
+// coefficients, so they stay finite and never reach a true slot.  Lines
+// whose outer coordinate lies beyond its axis' extent hold zeros on input
+// and output alike (the zero fill, then every pass that wrote them) and are
+// skipped where a tile holds nothing else (FP32, two lines per tile).  Each wave
 // owns whole lines and reads all of a tile's inputs before writing its
 // outputs, so the passes run in place.
 //
@@ -213,7 +216,7 @@ __device__ __forceinline__ P* elem_ptr(P* base, uint32_t ldb, int n, int row) {
   return reinterpret_cast<P*>(reinterpret_cast<C*>(base + n) + (uint64_t)(uint32_t)row * ldb);
 }
 
-template <typename T, int AX, int CB, int NIN, int NG, bool BF3, class CF, class POST, class PRE = NoPre>
+template <typename T, int AX, int CB, int NIN, int NG, bool BF3, int VEXT = 8, class CF, class POST, class PRE = NoPre>
 __device__ __forceinline__ void mfma_pass(T* smem, const Slab* in, const Slab* out, CF cf, POST post,
                                           PRE pre = PRE()) {
   constexpr bool HAS_PRE = !std::is_same<PRE, NoPre>::value;
@@ -222,6 +225,11 @@ __device__ __forceinline__ void mfma_pass(T* smem, const Slab* in, const Slab* o
   constexpr int NOB = (NG + 1) / 2;            // 16-wide output blocks
   constexpr int LPT = 16 / CB;                 // lines per tile
   constexpr int NT = 64 / LPT;                 // tiles per pass
+  // With two lines per tile, iteration it covers exactly the lines whose
+  // outer coordinate v (line / 8) is it.  Lines with v >= VEXT (the extent of
+  // that axis in this pass's input and output) read only zeros and their
+  // output slots already hold zeros, so those iterations are skipped.
+  constexpr int NIT = (LPT == 2 && VEXT < NT / 4) ? VEXT : NT / 4;
   constexpr int MR = lane_mask<T, CB, AX, true>() | (sizeof(T) - 1);
   constexpr int MW = lane_mask<T, CB, AX, false>() | (sizeof(T) - 1);
   const int lane = threadIdx.x & 63;
@@ -307,11 +315,11 @@ __device__ __forceinline__ void mfma_pass(T* smem, const Slab* in, const Slab* o
   load_a(0, av);
   load_pre(0, pv);
 #pragma unroll
-  for (int it = 0; it < NT / 4; ++it) {
+  for (int it = 0; it < NIT; ++it) {
     const int lc = LPT * 4 * it;
     T an[NA];
     T pvn[NOB][4];
-    if (it + 1 < NT / 4) {
+    if (it + 1 < NIT) {
       load_a(it + 1, an);
       load_pre(it + 1, pvn);
     }
@@ -363,7 +371,7 @@ __device__ __forceinline__ void mfma_pass(T* smem, const Slab* in, const Slab* o
         }
       }
     }
-    if (it + 1 < NT / 4) {
+    if (it + 1 < NIT) {
 #pragma unroll
       for (int ks = 0; ks < NA; ++ks) av[ks] = an[ks];
       if constexpr (HAS_PRE) {
@@ -606,11 +614,11 @@ k_cell_mfma(CellArgs<T> A, const Tab1D<T>* __restrict__ tabp,
       const Slab inA[1] = {sA};
       const Slab inC[1] = {sC};
       const Slab oC[1] = {sC};
-      mfma_pass<T, 0, CB, 1, 1, BF3>(smem, inA, oC, [&](int o, int k) { return Mm(o, k); }, store);
+      mfma_pass<T, 0, CB, 1, 1, BF3, NP>(smem, inA, oC, [&](int o, int k) { return Mm(o, k); }, store);
       __syncthreads();
-      mfma_pass<T, 1, CB, 1, 1, BF3>(smem, inC, oC, [&](int o, int k) { return Mm(o, k); }, store);
+      mfma_pass<T, 1, CB, 1, 1, BF3, NP>(smem, inC, oC, [&](int o, int k) { return Mm(o, k); }, store);
       __syncthreads();
-      mfma_pass<T, 2, CB, 1, 1, BF3>(smem, inC, oC, [&](int o, int k) { return fsc(3) * Mm(o, k); }, store);
+      mfma_pass<T, 2, CB, 1, 1, BF3, NP>(smem, inC, oC, [&](int o, int k) { return fsc(3) * Mm(o, k); }, store);
       __syncthreads();
     } else {
       const Slab inA[1] = {sA};
@@ -621,12 +629,12 @@ k_cell_mfma(CellArgs<T> A, const Tab1D<T>* __restrict__ tabp,
       const Slab oBCA[3] = {sB, sC, sA};
       const Slab oCA[2] = {sC, sA};
       // P1 x: [Bx; Kx; Mx] U
-      mfma_pass<T, 0, CB, 1, 3, BF3>(
+      mfma_pass<T, 0, CB, 1, 3, BF3, NP>(
           smem, inA, oBCA,
           [&](int o, int k) { return o < 8 ? Bm(o, k) : (o < 16 ? Km(o - 8, k) : Mm(o - 16, k)); }, store);
       __syncthreads();
       // P2 y: By
-      mfma_pass<T, 1, CB, 1, 1, BF3>(smem, inB, oB, [&](int o, int k) { return Bm(o, k); }, store);
+      mfma_pass<T, 1, CB, 1, 1, BF3, NP>(smem, inB, oB, [&](int o, int k) { return Bm(o, k); }, store);
       __syncthreads();
       // P3 z: Bz, then V(q) W_q (minus lambda_n W_q); lines are (qa, qb)
       {
@@ -652,16 +660,16 @@ k_cell_mfma(CellArgs<T> A, const Tab1D<T>* __restrict__ tabp,
           if constexpr (RES) return qin(L, o) ? v * (w - lams[c] * w3s[qidx(L, o)]) : T(0);
           else return v * w;
         };
-        mfma_pass<T, 2, CB, 1, 1, BF3>(smem, inB, oB, [&](int o, int k) { return Bm(o, k); }, vpost, vpre);
+        mfma_pass<T, 2, CB, 1, 1, BF3, NQ>(smem, inB, oB, [&](int o, int k) { return Bm(o, k); }, vpost, vpre);
       }
       __syncthreads();
       // P4 z: Bz^T;  P5 y: By^T
-      mfma_pass<T, 2, CB, 1, 1, BF3>(smem, inB, oB, [&](int o, int k) { return Bm(k, o); }, store);
+      mfma_pass<T, 2, CB, 1, 1, BF3, NQ>(smem, inB, oB, [&](int o, int k) { return Bm(k, o); }, store);
       __syncthreads();
-      mfma_pass<T, 1, CB, 1, 1, BF3>(smem, inB, oB, [&](int o, int k) { return Bm(k, o); }, store);
+      mfma_pass<T, 1, CB, 1, 1, BF3, NP>(smem, inB, oB, [&](int o, int k) { return Bm(k, o); }, store);
       __syncthreads();
       // P6 y: P = fx My C + fy Ky A -> C ; Q = My A -> A
-      mfma_pass<T, 1, CB, 2, 2, BF3>(
+      mfma_pass<T, 1, CB, 2, 2, BF3, NP>(
           smem, inCA, oCA,
           [&](int o, int k) {
             if (o < 8) return k < 8 ? fsc(0) * Mm(o, k) : fsc(1) * Km(o, k - 8);
@@ -670,11 +678,11 @@ k_cell_mfma(CellArgs<T> A, const Tab1D<T>* __restrict__ tabp,
           store);
       __syncthreads();
       // P7 z: kinetic = Mz P + fz Kz Q -> C
-      mfma_pass<T, 2, CB, 2, 1, BF3>(
+      mfma_pass<T, 2, CB, 2, 1, BF3, NP>(
           smem, inCA, oC, [&](int o, int k) { return k < 8 ? Mm(o, k) : fsc(2) * Km(o, k - 8); }, store);
       __syncthreads();
       // P8 x: Bx^T on slab B, accumulated into C
-      mfma_pass<T, 0, CB, 1, 1, BF3>(smem, inB, oC, [&](int o, int k) { return Bm(k, o); },
+      mfma_pass<T, 0, CB, 1, 1, BF3, NP>(smem, inB, oC, [&](int o, int k) { return Bm(k, o); },
                                 [](int, int, int, T v, T old, T) { return old + v; });
       __syncthreads();
     }
