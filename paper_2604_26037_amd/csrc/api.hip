@@ -337,6 +337,13 @@ pawfe_status upload(pawfe_op* op, hipStream_t s) {
   std::vector<float> minvf = to_f32(minv);
   CHECK(up(op, &d.Minv_f, minvf, s));
   CHECK(up(op, &d.cells_by_colour, op->cells_by_colour, s));
+  if (op->n[0] > 1024 || op->n[1] > 1024 || op->n[2] > 1024) return fail(PAWFE_EINVAL, "more than 1024 cells along an axis");
+  std::vector<int32_t> cpk(op->cells_by_colour.size());
+  for (size_t t = 0; t < cpk.size(); ++t) {
+    const int e = op->cells_by_colour[t];
+    cpk[t] = (e % op->n[0]) | ((e / op->n[0]) % op->n[1]) << 10 | (e / (op->n[0] * op->n[1])) << 20;
+  }
+  CHECK(up(op, &d.cell_pack, cpk, s));
   CHECK(up(op, &d.node2srow, op->node2srow, s));
   CHECK(up(op, &d.srow_ptr, op->srow_ptr, s));
   CHECK(up(op, &d.srow_atom, op->srow_atom, s));

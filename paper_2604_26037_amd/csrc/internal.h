@@ -50,6 +50,7 @@ struct DeviceTables {
   double* Minv = nullptr;    // [M]        1 / M_D
   float* Minv_f = nullptr;
   int32_t* cells_by_colour = nullptr;  // [E]
+  int32_t* cell_pack = nullptr;        // [E] the same cells as i | j << 10 | k << 20
   // projector structure
   int32_t* node2srow = nullptr;   // [M]  support row of a DOF, -1 if none
   int32_t* srow_ptr = nullptr;    // [nsrow+1]

@@ -16,7 +16,7 @@ struct CellArgs {
   T* Y;
   int64_t ldy;
   int ncols;
-  const int32_t* cells;
+  const int32_t* cells;   // the colour's cells as i | j << 10 | k << 20
   const T* Vw;
   const T* W3;
   const double* lam;   // per-column lambda (residual mode)

@@ -466,14 +466,15 @@ k_cell_mfma(CellArgs<T> A, const Tab1D<T>* __restrict__ tabp,
   // global node of local node j in cell e (periodic wrap only for the last
   // cell along an axis; the cell index is wave-uniform, so is the branch)
   struct CellPos {
-    int ci, cj, ck, base;
+    int ci, cj, ck, e, base;
     bool inner;
   };
-  auto cell_pos = [&](int e) {
+  auto cell_pos = [&](int packed) {
     CellPos c;
-    c.ci = e % A.n0;
-    c.cj = (e / A.n0) % A.n1;
-    c.ck = e / (A.n0 * A.n1);
+    c.ci = packed & 1023;
+    c.cj = (packed >> 10) & 1023;
+    c.ck = packed >> 20;
+    c.e = c.ci + A.n0 * (c.cj + A.n1 * c.ck);
     c.base = c.ci * p + Gx * (c.cj * p + Gy * c.ck * p);
     c.inner = off_fits && c.ci + 1 < A.n0 && c.cj + 1 < A.n1 && c.ck + 1 < A.n2;
     return c;
@@ -516,28 +517,36 @@ k_cell_mfma(CellArgs<T> A, const Tab1D<T>* __restrict__ tabp,
 
   // items (cell of the colour, column tile), cell-major; the x-th eighth of
   // them goes to the workgroups on XCD x (block w runs on XCD w % 8).  The
-  // cell list is read through the scalar cache (it is not written here), so
-  // reading it never waits for the vector loads in flight.
+  // cell list (packed cell coordinates) is read through the scalar cache (it
+  // is not written here), so reading it never waits for the vector loads in
+  // flight; (cell, tile) advance by a fixed step without divisions.
   typedef const __attribute__((address_space(4))) int* ConstIntP;
   const ConstIntP cells = (ConstIntP)A.cells;
   const int xcd = blockIdx.x & 7;
   const int i_end = (int)((int64_t)nitems * (xcd + 1) / 8);
   const int i_step = gridDim.x >> 3;
   int item = (int)((int64_t)nitems * xcd / 8) + (blockIdx.x >> 3);
+  const int st_c = i_step / ncoltiles, st_t = i_step % ncoltiles;
+  int cur_c = item / ncoltiles, cur_t = item % ncoltiles;
+  auto advance = [&](int& c, int& t) {
+    c += st_c;
+    t += st_t;
+    if (t >= ncoltiles) {
+      t -= ncoltiles;
+      ++c;
+    }
+  };
 
   // registers for the gathered values (and V W) of the next item
-  // (xok: the column exists; values are zeroed only when staged, so that
-  // nothing waits for these loads before the passes run)
   T xr[NJ], vr[NV];
-  bool xok = false;
   int xn0 = 0;
   double xlam = 0.0;
-  auto load_item = [&](int it) {
-    const int e = cells[it / ncoltiles];
-    xn0 = (it % ncoltiles) * CB;
+  auto load_item = [&](int c, int t) {
+    const CellPos cp = cell_pos(cells[c]);
+    const int e = cp.e;
+    xn0 = t * CB;
     const int n = xn0 + col;
-    xok = n < A.ncols;
-    gather(A.X, ldxb, cell_pos(e), xok ? n : 0, xr);
+    gather(A.X, ldxb, cp, n < A.ncols ? n : 0, xr);
     if constexpr (RES) xlam = A.lam[min(xn0 + col, A.ncols - 1)];
     if constexpr (HAS_V) {
 #pragma unroll
@@ -548,14 +557,23 @@ k_cell_mfma(CellArgs<T> A, const Tab1D<T>* __restrict__ tabp,
     }
   };
 
+  // value v, or +0 where `keep` is false, through a bit mask (a select the
+  // compiler cannot turn into a branch around the wait for v's load)
+  auto zero_unless = [](bool keep, T v) -> T {
+    if constexpr (sizeof(T) == 4) return __uint_as_float(__float_as_uint(v) & (keep ? ~0u : 0u));
+    else return __longlong_as_double(__double_as_longlong(v) & (keep ? ~0ll : 0ll));
+  };
   // stage the loaded item: gathered values -> slab A (extraction), V W and
-  // the columns' lambdas -> LDS.  It runs at the end of the previous item
+  // the columns' lambdas -> LDS.  Columns past the last one carry the values
+  // of column 0 (a valid load): columns never mix in the passes and those
+  // are never stored.  Threads past the last node stage a zero into padding.
+  // It runs at the end of the previous item
   // (slab A and these tables are no longer read once the last pass has
   // started), where the loads it waits for are the most recent vector-memory
   // operations and have had a whole item to arrive.
   auto stage = [&]() {
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) lds_a(pk[j]) = (xok && lreal(j)) ? xr[j] : T(0);
+    for (int j = 0; j < NJ; ++j) lds_a(pk[j]) = j < kLast ? xr[j] : zero_unless(lreal(j), xr[j]);
     // (writes without branches, so that the wait for every load happens on
     // every path and nothing is left in doubt at the top of the loop)
     if constexpr (HAS_V) {
@@ -572,7 +590,7 @@ k_cell_mfma(CellArgs<T> A, const Tab1D<T>* __restrict__ tabp,
   for (int i = tid; i < 3 * kSlots * CB; i += 256) smem[i] = T(0);
   if constexpr (RES)
     for (int q = tid; q < NQ3; q += 256) w3s[q + q / 64] = A.W3[q];
-  if (item < i_end) load_item(item);
+  if (item < i_end) load_item(cur_c, cur_t);
   __syncthreads();
   if (item < i_end) stage();
   __syncthreads();
@@ -598,17 +616,19 @@ k_cell_mfma(CellArgs<T> A, const Tab1D<T>* __restrict__ tabp,
   const Slab sA{0, 0}, sB{SLB, 0}, sC{2 * SLB, KC};
 
   for (; item < i_end; item += i_step) {
-    const int e = cells[item / ncoltiles];
-    const int n0 = (item % ncoltiles) * CB;
+    const int n0 = cur_t * CB;
     const int n = n0 + col;
     const bool valid = n < A.ncols;
     // output rows of this item (old values) and the next item's inputs are
     // fetched now and arrive while the passes run (the item itself is staged)
-    const CellPos cp = cell_pos(e);
+    const CellPos cp = cell_pos(cells[cur_c]);
     T yo[NJ];
     gather(A.Y, ldyb, cp, valid ? n : 0, yo);
+    int nxt_c = cur_c, nxt_t = cur_t;
+    advance(nxt_c, nxt_t);
     // (the last item loads itself again: unconditional loads, no join)
-    load_item(item + i_step < i_end ? item + i_step : item);
+    const bool more = item + i_step < i_end;
+    load_item(more ? nxt_c : cur_c, more ? nxt_t : cur_t);
 
     if constexpr (MODE == kModeMass) {
       const Slab inA[1] = {sA};
@@ -697,6 +717,8 @@ k_cell_mfma(CellArgs<T> A, const Tab1D<T>* __restrict__ tabp,
         if (lreal(j)) *elem_ptr(A.Y, ldyb, n, node[j]) = yo[j] + A.alpha * lds_c(pk[j]);
     }
     __syncthreads();
+    cur_c = nxt_c;
+    cur_t = nxt_t;
   }
 }
 
@@ -744,7 +766,7 @@ pawfe_status run_cell_mfma(const pawfe_op* op, int mode, CellArgs<T> a, hipStrea
     const int c0 = op->colour_off[c], c1 = op->colour_off[c + 1];
     if (c1 == c0) continue;
     CellArgs<T> ac = a;
-    ac.cells = op->d.cells_by_colour + c0;
+    ac.cells = op->d.cell_pack + c0;
     const int nitems = (c1 - c0) * ncoltiles;
     if (mode == kModeH)
       launch_mode<T, NP, NQ, CB, kModeH>(ac, tab, ncoltiles, nitems, s);
