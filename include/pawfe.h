@@ -94,9 +94,17 @@ enum { PAWFE_SINV_EXACT_G = 0, PAWFE_SINV_PP = 1 };
  *            3z^2-r^2, xz, x^2-y^2.
  * dH, dS     Delta_H^a and Delta_S^a (eq. "FE nonlocal contribution"),
  *            nproj[a]^2 row-major blocks, atom after atom.
- * kpoint     Cartesian Bloch vector (bohr^-1); must be 0 unless is_complex.
- * is_complex 1 for the complex (k-point) operator.  Not implemented in this
- *            build: returns PAWFE_EUNSUPPORTED.
+ * kpoint     Cartesian Bloch vector k (bohr^-1); must be 0 unless is_complex;
+ *            NaN/Inf gives PAWFE_ENONFINITE.
+ * is_complex 1 for the complex (k-point) operator of the Bloch-periodic part
+ *            u of psi = e^{i k.x} u: H_loc gains 1/2 |k|^2 M and the
+ *            imaginary term -i sum_d k_d <N_I | d/dx_d N_J>, and C^a carries
+ *            the phase e^{-i k.x} at every quadrature point x (x taken at the
+ *            image next to the atom as given in pos, unwrapped), so G^{ab}
+ *            and Delta_Sinv^a become complex Hermitian.  Every column
+ *            argument of a complex operator is complex: (re, im) pairs of
+ *            doubles (or floats at PAWFE_FP32), and ld and nvec count
+ *            complex entries.  Any other value: PAWFE_EINVAL.
  * Supported (degree, nq): (2,4) (3,5) (4,6) (5,7) (6,8); each n_d >= 2. */
 typedef struct {
   int32_t ncell[3];
@@ -158,7 +166,8 @@ pawfe_status pawfe_set_dH(pawfe_op* op, const double* dH, void* stream);
  *   apply_S:    S X = M X + sum_a C^a Delta_S^a C^a^H X   (consistent M)
  *   apply_Sinv: Sinv_hat X = M_D^{-1} X - sum_a M_D^{-1} C^a Delta_Sinv^a
  *               C^a^H M_D^{-1} X
- * X, Y device, [ndof][ld]; FP64 (prec = PAWFE_FP64) or FP32 (PAWFE_FP32).
+ * X, Y device, [ndof][ld]; FP64 (prec = PAWFE_FP64) or FP32 (PAWFE_FP32);
+ * complex operators: complex entries, (re, im) interleaved.
  * X and Y must not overlap. */
 pawfe_status pawfe_apply_H(const pawfe_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy,
                            int64_t nvec, int32_t prec, void* stream);
@@ -212,7 +221,10 @@ pawfe_status pawfe_rayleigh_ritz_workspace(const pawfe_op* op, int64_t nvec, siz
  * X <- X Q (in place), and resnorm[i] = ||H x_i - lambda_i S x_i||_2 (the
  * eigen-residual check).  X device FP64 [ndof][ldx]; lambda (ascending)
  * and resnorm: device FP64 [nvec].  Returns PAWFE_ENOTSPD if S^p is not
- * positive definite. Synchronizes the stream (it reads the solver status). */
+ * positive definite. Synchronizes the stream (it reads the solver status).
+ * Complex operators: X holds nvec complex columns; the projected problem is
+ * complex Hermitian (H^p, S^p and Q complex), lambda and resnorm stay real,
+ * one entry per complex column. */
 pawfe_status pawfe_rayleigh_ritz(const pawfe_op* op, void* X, int64_t ldx, int64_t nvec,
                                  double* lambda, double* resnorm, void* ws, size_t ws_bytes,
                                  void* stream);
@@ -224,7 +236,8 @@ pawfe_status pawfe_rayleigh_ritz(const pawfe_op* op, void* X, int64_t ldx, int64
  *                  packed like desc.dH (full-matrix gradient).
  * X device FP64; occ device FP64 [nvec] or NULL (all ones); E device FP64
  * scalar; dE_dVq device [E*nq^3]; dE_dDH device [sum nproj^2].  Any output
- * may be NULL.  Nothing cell-local is stored between cell batches. */
+ * may be NULL.  Nothing cell-local is stored between cell batches.
+ * Real operators only: a complex operator gives PAWFE_EUNSUPPORTED. */
 pawfe_status pawfe_band_energy_grad(const pawfe_op* op, const void* X, int64_t ldx, int64_t nvec,
                                     const double* occ, double* E, double* dE_dVq, double* dE_dDH,
                                     void* stream);
@@ -256,8 +269,8 @@ pawfe_status pawfe_lanczos_bounds(const pawfe_op* op, int32_t k, uint64_t seed, 
  * The autotuning runs (eager filters on the jobs' own buffers) happen
  * inside pawfe_batch_create; their outputs are overwritten by any replay.
  *
- * Real (Gamma-point) operators only: this build rejects complex operators
- * at pawfe_build_operator.
+ * Real and complex (k-point) operators may be mixed in one batch; the
+ * columns of a complex job are complex (as for pawfe_cheb_filter).
  */
 typedef struct pawfe_batch pawfe_batch;
 

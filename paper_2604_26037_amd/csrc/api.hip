@@ -117,7 +117,7 @@ pawfe_status do_apply(const pawfe_op* op, int which, const T* X, int64_t ldx, T*
   }
   // Sinv_hat
   CHECK(launch_nl_reduce<T>(op, X, ldx, ncols, true, b.part, b.c, s));
-  CHECK(launch_atom_mul(op, op->d.dSinv, nullptr, nullptr, 1.0, b.c, b.d, ncols, s));
+  CHECK(launch_atom_mul(op, op->d.dSinv, nullptr, nullptr, 1.0, b.c, b.d, ncols, s, op->d.dSinv_im));
   return launch_node_sinv<T>(op, X, ldx, b.d, ncols, Y, ldy, s);
 }
 
@@ -146,6 +146,11 @@ pawfe_status apply_entry(const pawfe_op* cop, int which, const void* X, int64_t 
   if (ldx < nvec || ldy < nvec) return fail(PAWFE_EINVAL, "leading dimension smaller than nvec");
   CHECK(check_prec(prec));
   pawfe_op* op = const_cast<pawfe_op*>(cop);
+  if (op->cplx) {   // complex columns as (re, im) pairs of real columns
+    nvec *= 2;
+    ldx *= 2;
+    ldy *= 2;
+  }
   const int64_t chunk = 512;
   const int64_t cmax = std::min<int64_t>(chunk, nvec);
   CHECK(ensure_scratch(op, nl_scratch_bytes(op, cmax)));
@@ -165,12 +170,14 @@ pawfe_status apply_entry(const pawfe_op* cop, int which, const void* X, int64_t 
 
 // ---- filter ------------------------------------------------------------------
 
+// B: real columns of one block (two per complex column)
 size_t filter_ws_bytes(const pawfe_op* op, int64_t B, int32_t prec) {
   const size_t tr = prec == PAWFE_FP64 ? 8 : 4;
   size_t b = align256((size_t)op->M * B * 8);            // Y
   b += 3 * align256((size_t)op->M * B * tr);            // RX, RY, T
   b += nl_scratch_bytes(op, B);
   b += 2 * align256((size_t)B * 8);                      // lamX, lamY
+  if (op->cplx) b += align256((size_t)B * 8);             // lambda per real column
   return b + 256;
 }
 
@@ -200,7 +207,7 @@ pawfe_status filter_block(const pawfe_op* op, const double* X, int64_t ldx, doub
     const double a = 2.0 * znew / e;
     // projector coefficients of Sinv_hat R_Y and of H's non-local term on T
     CHECK(launch_nl_reduce<TR>(op, RY, ld, nc, true, nb.part, nb.c, s));
-    CHECK(launch_atom_mul(op, op->d.dSinv, nullptr, nullptr, 1.0, nb.c, nb.d, nc, s));
+    CHECK(launch_atom_mul(op, op->d.dSinv, nullptr, nullptr, 1.0, nb.c, nb.d, nc, s, op->d.dSinv_im));
     CHECK(launch_atom_gcorr(op, nb.c, nb.d, nb.t, nc, s));
     CHECK(launch_atom_mul(op, op->d.dH, nullptr, nullptr, a, nb.t, nb.c, nc, s));   // q = a Dh t (into c)
     // T = Sinv_hat R_Y; R_X <- -a c R_Y - zeta zeta' R_X + a C q + a Y Lambda_Y
@@ -214,7 +221,7 @@ pawfe_status filter_block(const pawfe_op* op, const double* X, int64_t ldx, doub
   }
   // step 5: Xout = Sinv_hat R_Y + X Lambda_Y
   CHECK(launch_nl_reduce<TR>(op, RY, ld, nc, true, nb.part, nb.c, s));
-  CHECK(launch_atom_mul(op, op->d.dSinv, nullptr, nullptr, 1.0, nb.c, nb.d, nc, s));
+  CHECK(launch_atom_mul(op, op->d.dSinv, nullptr, nullptr, 1.0, nb.c, nb.d, nc, s, op->d.dSinv_im));
   return launch_node_finalize<TR>(op, RY, ld, nb.d, X, ldx, lamY, Xo, ldo, nc, s);
 }
 
@@ -268,6 +275,40 @@ __global__ void k_symmetrize(int N, double* __restrict__ A) {
   A[(int64_t)j * N + i] = v;
 }
 
+// Complex operators: the realified projection P (2N x 2N, row-major, real
+// view of (re, im) column pairs) -> the N x N complex Hermitian matrix
+// A_ij = x_i^H (A x)_j, column-major (i + j N), interleaved (re, im)
+__global__ void k_form_herm(int N, const double* __restrict__ P, double* __restrict__ A) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)N * N) return;
+  const int i = (int)(idx % N), j = (int)(idx / N);
+  const int64_t n2 = 2 * (int64_t)N;
+  const double rr = P[(2 * i) * n2 + 2 * j], ii = P[(2 * i + 1) * n2 + 2 * j + 1];
+  const double ri = P[(2 * i) * n2 + 2 * j + 1], ir = P[(2 * i + 1) * n2 + 2 * j];
+  A[2 * idx] = rr + ii;
+  A[2 * idx + 1] = ri - ir;
+}
+
+// the complex N x N matrix Q (column-major, interleaved) -> its real 2N x 2N
+// form R (column-major) acting on (re, im) column pairs: X_new = X R
+__global__ void k_realify_rot(int N, const double* __restrict__ Q, double* __restrict__ R) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)N * N) return;
+  const int i = (int)(idx % N), j = (int)(idx / N);
+  const double qr = Q[2 * idx], qi = Q[2 * idx + 1];
+  const int64_t n2 = 2 * (int64_t)N;
+  R[(2 * i) + (2 * j) * n2] = qr;
+  R[(2 * i + 1) + (2 * j) * n2] = -qi;
+  R[(2 * i) + (2 * j + 1) * n2] = qi;
+  R[(2 * i + 1) + (2 * j + 1) * n2] = qr;
+}
+
+// out[j] = sqrt(sq[2 j] + sq[2 j + 1])
+__global__ void k_pair_norm(int N, const double* __restrict__ sq, double* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < N) out[j] = sqrt(sq[2 * j] + sq[2 * j + 1]);
+}
+
 // P[i*ldp + j0 + j] = sum_b part[b][j + i*nc] (split-K partials of a block column)
 __global__ void k_part_reduce(const double* __restrict__ part, int nb, int nc, int N, double* __restrict__ P,
                               int64_t ldp, int64_t j0) {
@@ -285,9 +326,13 @@ __global__ void k_part_reduce(const double* __restrict__ part, int nb, int nc, i
 // ---- upload / free ------------------------------------------------------------
 
 pawfe_status upload_veff(pawfe_op* op, hipStream_t s) {
+  // complex operators: the 1/2 |k|^2 M term of the Bloch Hamiltonian joins
+  // the potential at the Gauss points (same quadrature)
+  const double k2 = 0.5 * (op->kpt[0] * op->kpt[0] + op->kpt[1] * op->kpt[1] + op->kpt[2] * op->kpt[2]);
   std::vector<double> vw(op->veff.size());
   for (int e = 0; e < op->E; ++e)
-    for (int q = 0; q < op->nq3; ++q) vw[(size_t)e * op->nq3 + q] = op->veff[(size_t)e * op->nq3 + q] * op->W3[q];
+    for (int q = 0; q < op->nq3; ++q)
+      vw[(size_t)e * op->nq3 + q] = (op->veff[(size_t)e * op->nq3 + q] + k2) * op->W3[q];
   std::vector<float> vwf(vw.begin(), vw.end());
   PAWFE_HIP(hipMemcpyAsync(op->d.Vw, vw.data(), vw.size() * 8, hipMemcpyHostToDevice, s));
   PAWFE_HIP(hipMemcpyAsync(op->d.Vw_f, vwf.data(), vwf.size() * 4, hipMemcpyHostToDevice, s));
@@ -316,14 +361,18 @@ pawfe_status upload(pawfe_op* op, hipStream_t s) {
       t64.K1[i] = op->K1[i];
       t64.M1[i] = op->M1[i];
     }
+    for (int i = 0; i < np * np; ++i) t64.G1[i] = op->G1[i];
     for (int k = 0; k < 3; ++k) t64.f[k] = 0.5 * op->detJ * (2.0 / op->h[k]) * (2.0 / op->h[k]);
+    for (int k = 0; k < 3; ++k) t64.g[k] = -op->kpt[k] * op->detJ * (2.0 / op->h[k]);
     t64.detJ = op->detJ;
     for (int i = 0; i < kNqMax * kNpMax; ++i) t32.B[i] = (float)t64.B[i];
     for (int i = 0; i < kNpMax * kNpMax; ++i) {
       t32.K1[i] = (float)t64.K1[i];
       t32.M1[i] = (float)t64.M1[i];
+      t32.G1[i] = (float)t64.G1[i];
     }
     for (int k = 0; k < 3; ++k) t32.f[k] = (float)t64.f[k];
+    for (int k = 0; k < 3; ++k) t32.g[k] = (float)t64.g[k];
     t32.detJ = (float)t64.detJ;
     CHECK(up(op, &d.tab64, &t64, 1, s));
     CHECK(up(op, &d.tab32, &t32, 1, s));
@@ -351,6 +400,14 @@ pawfe_status upload(pawfe_op* op, hipStream_t s) {
   CHECK(up(op, &d.Cvals, op->Cvals, s));
   std::vector<float> cf = to_f32(op->Cvals);
   CHECK(up(op, &d.Cvals_f, cf, s));
+  std::vector<float> cfi;
+  if (op->cplx) {
+    CHECK(up(op, &d.Cvals_im, op->Cvals_im, s));
+    cfi = to_f32(op->Cvals_im);
+    CHECK(up(op, &d.Cvals_im_f, cfi, s));
+    CHECK(up(op, &d.Gvals_im, op->Gvals_im, s));
+    if (!op->dSinv_im.empty()) CHECK(up(op, &d.dSinv_im, op->dSinv_im, s));
+  }
   std::vector<int32_t> an(op->atom_nodes.begin(), op->atom_nodes.end());
   {
     // padded so that batched reads of consecutive rows never leave the list
@@ -541,7 +598,12 @@ pawfe_status pawfe_apply_local(const pawfe_op* op, int32_t which, const void* X,
   if (ldx < nvec || ldy < nvec) return fail(PAWFE_EINVAL, "leading dimension smaller than nvec");
   CHECK(check_prec(prec));
   const int mode = which == 0 ? kModeH : kModeMass;
-  if (nvec > (int64_t)1 << 30) return fail(PAWFE_EINVAL, "nvec too large");
+  if (nvec > (int64_t)1 << 29) return fail(PAWFE_EINVAL, "nvec too large");
+  if (op->cplx) {   // complex columns as (re, im) pairs of real columns
+    nvec *= 2;
+    ldx *= 2;
+    ldy *= 2;
+  }
   if (prec == PAWFE_FP64)
     return launch_cell<double>(op, mode, (const double*)X, ldx, (double*)Y, ldy, (int)nvec, nullptr, alpha,
                                S(stream));
@@ -556,7 +618,7 @@ pawfe_status pawfe_cheb_filter_workspace(const pawfe_op* op, int64_t nvec, int32
   CHECK(check_prec(prec));
   const int64_t B = std::min<int64_t>(block, nvec);
   // room for two blocks in flight when there is more than one block
-  *bytes = filter_ws_bytes(op, B, prec) * (nvec > B ? 2 : 1);
+  *bytes = filter_ws_bytes(op, B * (op->cplx ? 2 : 1), prec) * (nvec > B ? 2 : 1);
   return PAWFE_OK;
 }
 
@@ -573,8 +635,9 @@ pawfe_status pawfe_cheb_filter(const pawfe_op* op, const void* Xin, int64_t ldx,
   if (!(b0 < bW && bW < bU)) return fail(PAWFE_EINVAL, "bounds must satisfy b0 < bW < bU");
   CHECK(check_prec(prec));
   if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(PAWFE_EINVAL, "workspace must be 256-byte aligned");
+  const int64_t cf = op->cplx ? 2 : 1;   // real columns per column
   const int64_t B = std::min<int64_t>(block, nvec);
-  const size_t one = filter_ws_bytes(op, B, prec);
+  const size_t one = filter_ws_bytes(op, B * cf, prec);
   if (ws_bytes < one) return fail(PAWFE_EINVAL, "workspace too small");
   hipStream_t s = S(stream);
   // Blocks are uncoupled.  With room for two block states (and more than one
@@ -596,14 +659,23 @@ pawfe_status pawfe_cheb_filter(const pawfe_op* op, const void* Xin, int64_t ldx,
     const int k = nconc == 2 ? (int)(blk & 1) : 0;
     hipStream_t sb = nconc == 2 ? mop->fstream[k] : s;
     Carve cv((char*)ws + (size_t)k * one, one);
-    const double* X = (const double*)Xin + j0;
-    double* Xo = (double*)Xout + j0;
-    pawfe_status st;
-    if (prec == PAWFE_FP64)
-      st = filter_block<double>(op, X, ldx, Xo, ldo, nc, B, lambda_in + j0, degree, b0, bW, bU, cv, sb);
-    else
-      st = filter_block<float>(op, X, ldx, Xo, ldo, nc, B, lambda_in + j0, degree, b0, bW, bU, cv, sb,
-                               prec == PAWFE_BF16X3);
+    const double* X = (const double*)Xin + j0 * cf;
+    double* Xo = (double*)Xout + j0 * cf;
+    const double* lam = lambda_in + j0;
+    pawfe_status st = PAWFE_OK;
+    if (op->cplx) {   // lambda per real column of the (re, im) pairs
+      double* lam2 = cv.take<double>((size_t)B * cf);
+      st = launch_dup_pairs(lambda_in + j0, lam2, nc, sb);
+      lam = lam2;
+    }
+    if (st != PAWFE_OK) {
+    } else if (prec == PAWFE_FP64) {
+      st = filter_block<double>(op, X, ldx * cf, Xo, ldo * cf, (int)(nc * cf), B * cf, lam, degree, b0, bW, bU, cv,
+                                sb);
+    } else {
+      st = filter_block<float>(op, X, ldx * cf, Xo, ldo * cf, (int)(nc * cf), B * cf, lam, degree, b0, bW, bU, cv,
+                               sb, prec == PAWFE_BF16X3);
+    }
     if (st != PAWFE_OK) {
       if (nconc == 2)   // still join, so `s` never runs ahead of work already enqueued
         for (int q = 0; q < 2; ++q) {
@@ -624,6 +696,7 @@ pawfe_status pawfe_cheb_filter(const pawfe_op* op, const void* Xin, int64_t ldx,
 // ---- Rayleigh-Ritz ------------------------------------------------------------
 
 static size_t rr_ws_bytes(const pawfe_op* op, int64_t N) {
+  N *= op->cplx ? 2 : 1;   // real columns
   const int64_t B = std::min<int64_t>(256, N);
   size_t b = align256((size_t)op->M * B * 8);             // HX block
   b += align256((size_t)op->M * N * 8);                    // rotated copy
@@ -653,6 +726,12 @@ pawfe_status pawfe_rayleigh_ritz(const pawfe_op* cop, void* Xv, int64_t ldx, int
   pawfe_op* op = const_cast<pawfe_op*>(cop);
   hipStream_t s = S(stream);
   double* X = (double*)Xv;
+  // complex operators: the (re, im) real view, Nc complex columns
+  const int64_t Nc = N;
+  if (op->cplx) {
+    N *= 2;
+    ldx *= 2;
+  }
   const int64_t B = std::min<int64_t>(256, N);
   Carve cv(ws, ws_bytes);
   double* HXb = cv.take<double>((size_t)op->M * B);
@@ -708,16 +787,37 @@ pawfe_status pawfe_rayleigh_ritz(const pawfe_op* cop, void* Xv, int64_t ldx, int
     hipLaunchKernelGGL(k_symmetrize, dim3((unsigned)((N * N + 255) / 256)), dim3(256), 0, s, (int)N, P);
   }
   PAWFE_HIP(hipGetLastError());
-  // projected generalized eigenproblem (dense, FP64)
-  rocblas_status rs = rocsolver_dsygvd(h, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_upper, (rocblas_int)N,
-                                       Hp, (rocblas_int)N, Sp, (rocblas_int)N, lambda, Ework, info);
-  if (rs != rocblas_status_success) return fail(PAWFE_EHIP, "rocsolver_dsygvd failed");
+  // projected generalized eigenproblem (dense, FP64); complex operators: the
+  // Hermitian N x N problem formed from the realified projections (in the
+  // split-K buffer, free by now), solved complex, and its eigenvectors
+  // turned into the real rotation of the (re, im) pairs (into Hp)
+  rocblas_status rs;
+  double* lam2 = nullptr;
+  if (!op->cplx) {
+    rs = rocsolver_dsygvd(h, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_upper, (rocblas_int)N, Hp,
+                          (rocblas_int)N, Sp, (rocblas_int)N, lambda, Ework, info);
+  } else {
+    double* Hc = part;
+    double* Sc = part + 2 * Nc * Nc;
+    lam2 = part + 4 * Nc * Nc;
+    const dim3 gq((unsigned)((Nc * Nc + 255) / 256));
+    hipLaunchKernelGGL(k_form_herm, gq, dim3(256), 0, s, (int)Nc, Hp, Hc);
+    hipLaunchKernelGGL(k_form_herm, gq, dim3(256), 0, s, (int)Nc, Sp, Sc);
+    rs = rocsolver_zhegvd(h, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_upper, (rocblas_int)Nc,
+                          (rocblas_double_complex*)Hc, (rocblas_int)Nc, (rocblas_double_complex*)Sc, (rocblas_int)Nc,
+                          lambda, Ework, info);
+    if (rs == rocblas_status_success) {
+      hipLaunchKernelGGL(k_realify_rot, gq, dim3(256), 0, s, (int)Nc, Hc, Hp);
+      CHECK(launch_dup_pairs(lambda, lam2, (int)Nc, s));
+    }
+  }
+  if (rs != rocblas_status_success) return fail(PAWFE_EHIP, "rocsolver generalized eigensolver failed");
   rocblas_int hinfo = 0;
   PAWFE_HIP(hipMemcpyAsync(&hinfo, info, sizeof(rocblas_int), hipMemcpyDeviceToHost, s));
   PAWFE_HIP(hipStreamSynchronize(s));
-  if (hinfo > N) return fail(PAWFE_ENOTSPD, "projected overlap S^p is not positive definite");
+  if (hinfo > Nc) return fail(PAWFE_ENOTSPD, "projected overlap S^p is not positive definite");
   if (hinfo > 0) return fail(PAWFE_ENONFINITE, "projected eigensolver did not converge");
-  // rotation X <- X Q (Q column-major in Hp)
+  // rotation X <- X Q (Q column-major in Hp; real form for complex operators)
   {
     // Xr = X Q: column-major, Xr^T (N x K) = Q^T (N x N) X^T (N x K)
     const double one = 1.0, zero = 0.0;
@@ -727,11 +827,17 @@ pawfe_status pawfe_rayleigh_ritz(const pawfe_op* cop, void* Xv, int64_t ldx, int
       return fail(PAWFE_EHIP, "rocblas_dgemm (rotation) failed");
   }
   CHECK(launch_copy_cols(Xr, N, X, ldx, op->M, (int)N, s));
-  // residual norms ||H x - lambda S x||_2
+  // residual norms ||H x - lambda S x||_2 (complex: over both parts)
+  double* sq = op->cplx ? lam2 + N : nullptr;
   for (int64_t j0 = 0; j0 < N; j0 += B) {
     const int nc = (int)std::min<int64_t>(B, N - j0);
-    CHECK(do_residual(op, X + j0, ldx, lambda + j0, HXb, nc, nc, nb, s));
-    CHECK(launch_coldot(HXb, nc, HXb, nc, op->M, nc, npart_buf, resnorm + j0, nullptr, true, false, s));
+    CHECK(do_residual(op, X + j0, ldx, (op->cplx ? lam2 : lambda) + j0, HXb, nc, nc, nb, s));
+    CHECK(launch_coldot(HXb, nc, HXb, nc, op->M, nc, npart_buf, (op->cplx ? sq : resnorm) + j0, nullptr,
+                        !op->cplx, false, s));
+  }
+  if (op->cplx) {
+    hipLaunchKernelGGL(k_pair_norm, dim3((unsigned)((Nc + 255) / 256)), dim3(256), 0, s, (int)Nc, sq, resnorm);
+    PAWFE_HIP(hipGetLastError());
   }
   return PAWFE_OK;
 }
@@ -742,6 +848,7 @@ pawfe_status pawfe_band_energy_grad(const pawfe_op* cop, const void* Xv, int64_t
                                     double* E, double* dE_dVq, double* dE_dDH, void* stream) {
   if (!cop) return fail(PAWFE_EINVAL, "op is NULL");
   if (!Xv || N < 1 || ldx < N) return fail(PAWFE_EINVAL, "bad X / nvec / ldx");
+  if (cop->cplx) return fail(PAWFE_EUNSUPPORTED, "band_energy_grad: real (Gamma-point) operators only");
   pawfe_op* op = const_cast<pawfe_op*>(cop);
   hipStream_t s = S(stream);
   const double* X = (const double*)Xv;
@@ -778,12 +885,15 @@ pawfe_status pawfe_lanczos_bounds(const pawfe_op* cop, int32_t k, uint64_t seed,
   if (k < 2 || k > 200) return fail(PAWFE_EINVAL, "k must be in 2..200");
   pawfe_op* op = const_cast<pawfe_op*>(cop);
   hipStream_t s = S(stream);
-  const int64_t M = op->M;
+  // complex operators: vectors of M complex entries as (re, im) pairs; the
+  // real inner product of that view is Re x^H y, the Hermitian form
+  const int cf = op->cplx ? 2 : 1;
+  const int64_t M = op->M * cf;
   const int64_t nchunks = (M + 4095) / 4096;
-  size_t need = nl_scratch_bytes(op, 1) + 5 * align256((size_t)M * 8) + align256((size_t)nchunks * 8) + 1024;
+  size_t need = nl_scratch_bytes(op, cf) + 5 * align256((size_t)M * 8) + align256((size_t)nchunks * 8) + 1024;
   CHECK(ensure_scratch(op, need));
   Carve cv(op->scratch, op->scratch_bytes);
-  NlBufs nb = carve_nl(op, cv, 1);
+  NlBufs nb = carve_nl(op, cv, cf);
   double* v = cv.take<double>(M);
   double* vp = cv.take<double>(M);
   double* z = cv.take<double>(M);
@@ -811,7 +921,7 @@ pawfe_status pawfe_lanczos_bounds(const pawfe_op* cop, int32_t k, uint64_t seed,
     PAWFE_HIP(hipStreamSynchronize(s));
     return PAWFE_OK;
   };
-  CHECK(do_apply<double>(op, 2, v, 1, z, 1, 1, nb, s));
+  CHECK(do_apply<double>(op, 2, v, cf, z, cf, cf, nb, s));
   double nrm2 = 0.0;
   CHECK(ddot(v, z, &nrm2));
   if (!(nrm2 > 0.0)) return fail(PAWFE_ENOTSPD, "Sinv_hat is not positive on the start vector");
@@ -822,12 +932,12 @@ pawfe_status pawfe_lanczos_bounds(const pawfe_op* cop, int32_t k, uint64_t seed,
   std::vector<double> al, be;
   double beta_prev = 0.0;
   for (int it = 0; it < k; ++it) {
-    CHECK(do_apply<double>(op, 0, z, 1, w, 1, 1, nb, s));
+    CHECK(do_apply<double>(op, 0, z, cf, w, cf, cf, nb, s));
     double alpha = 0.0;
     CHECK(ddot(z, w, &alpha));
     // w = w - alpha v - beta_prev vp
     hipLaunchKernelGGL(k_lincomb, g, b, 0, s, M, w, -alpha, v, -beta_prev, vp, 1.0);
-    CHECK(do_apply<double>(op, 2, w, 1, u, 1, 1, nb, s));
+    CHECK(do_apply<double>(op, 2, w, cf, u, cf, cf, nb, s));
     double bb = 0.0;
     CHECK(ddot(w, u, &bb));
     const double beta = std::sqrt(std::max(bb, 0.0));

@@ -172,7 +172,8 @@ pawfe_status build(pawfe_batch* b, const pawfe_filter_job* jobs, int32_t njobs, 
     int64_t ndof = 0;
     if (pawfe_query(J.op, &ndof, nullptr, nullptr, nullptr, nullptr, nullptr) != PAWFE_OK)
       return fail(PAWFE_EINVAL, "job " + std::to_string(j) + ": bad operator");
-    if (tune_any && hipMalloc(&tmp[j], (size_t)ndof * J.nvec * 8) != hipSuccess)
+    const size_t esz = J.op->cplx ? 16 : 8;   // complex (k-point) operators: complex128 columns
+    if (tune_any && hipMalloc(&tmp[j], (size_t)ndof * J.nvec * esz) != hipSuccess)
       return fail(PAWFE_ENOMEM, "tuning output allocation failed");
     std::vector<int32_t> cand;
     if (J.block > 0) {

@@ -16,6 +16,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstring>
 #include <map>
 #include <numeric>
@@ -130,6 +131,48 @@ bool dsinv_block(int n, const double* G, const double* S, double* Z) {
   return true;
 }
 
+// Complex version: Z (I + G S) = S with G = Gr + i Gi and S real; Z = Zr + i Zi.
+bool dsinv_block_c(int n, const double* Gr, const double* Gi, const double* S, double* Zr, double* Zi) {
+  typedef std::complex<double> C;
+  std::vector<C> A(n * n), R(n * n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      C gs = (i == j) ? C(1.0, 0.0) : C(0.0, 0.0);
+      for (int k = 0; k < n; ++k) gs += C(Gr[i * n + k], Gi[i * n + k]) * S[k * n + j];
+      A[j * n + i] = gs;
+      R[j * n + i] = C(S[i * n + j], 0.0);
+    }
+  double scale = 0.0;
+  for (const C& v : A) scale = std::max(scale, std::abs(v));
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::abs(A[r * n + c]) > std::abs(A[piv * n + c])) piv = r;
+    if (std::abs(A[piv * n + c]) <= 1e-13 * scale) return false;
+    if (piv != c)
+      for (int k = 0; k < n; ++k) {
+        std::swap(A[c * n + k], A[piv * n + k]);
+        std::swap(R[c * n + k], R[piv * n + k]);
+      }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const C f = A[r * n + c] / A[c * n + c];
+      if (f == C(0.0, 0.0)) continue;
+      for (int k = 0; k < n; ++k) {
+        A[r * n + k] -= f * A[c * n + k];
+        R[r * n + k] -= f * R[c * n + k];
+      }
+    }
+  }
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) {
+      const C z = R[j * n + i] / A[j * n + j];
+      Zr[i * n + j] = z.real();
+      Zi[i * n + j] = z.imag();
+    }
+  return true;
+}
+
 }  // namespace
 
 void gll_rule(int p, std::vector<double>& x, std::vector<double>& w) {
@@ -194,9 +237,11 @@ pawfe_status build_host(const pawfe_op_desc* d, pawfe_op* op) {
   const bool ok_pair = (p == 2 && nq == 4) || (p == 3 && nq == 5) || (p == 4 && nq == 6) ||
                        (p == 5 && nq == 7) || (p == 6 && nq == 8);
   if (!ok_pair) return fail(PAWFE_EUNSUPPORTED, "supported (degree, nq): (2,4) (3,5) (4,6) (5,7) (6,8)");
-  if (d->is_complex) return fail(PAWFE_EUNSUPPORTED, "complex (k-point) operators are not implemented");
-  if (d->kpoint[0] != 0.0 || d->kpoint[1] != 0.0 || d->kpoint[2] != 0.0)
+  if (d->is_complex != 0 && d->is_complex != 1) return fail(PAWFE_EINVAL, "is_complex must be 0 or 1");
+  if (!d->is_complex && (d->kpoint[0] != 0.0 || d->kpoint[1] != 0.0 || d->kpoint[2] != 0.0))
     return fail(PAWFE_EINVAL, "non-zero kpoint requires is_complex");
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(d->kpoint[k])) return fail(PAWFE_ENONFINITE, "kpoint has NaN/Inf");
   if (d->sinv_mode != PAWFE_SINV_EXACT_G && d->sinv_mode != PAWFE_SINV_PP)
     return fail(PAWFE_EINVAL, "unknown sinv_mode");
   if (d->natoms < 0) return fail(PAWFE_EINVAL, "natoms < 0");
@@ -216,6 +261,8 @@ pawfe_status build_host(const pawfe_op_desc* d, pawfe_op* op) {
   op->M = (int64_t)op->E * p * p * p;
   op->detJ = op->h[0] * op->h[1] * op->h[2] / 8.0;
   op->sinv_mode = d->sinv_mode;
+  op->cplx = d->is_complex != 0;
+  for (int k = 0; k < 3; ++k) op->kpt[k] = op->cplx ? d->kpoint[k] : 0.0;
   const int np = op->np, E = op->E;
   const int64_t nquad = (int64_t)E * op->nq3;
   if (!finite_all(d->veff_q, nquad)) return fail(PAWFE_ENONFINITE, "veff_q has NaN/Inf");
@@ -229,15 +276,18 @@ pawfe_status build_host(const pawfe_op_desc* d, pawfe_op* op) {
     lagrange_at(op->gll_x, op->gauss_x[q], &op->B[q * np], &op->D[q * np]);
   op->K1.assign(np * np, 0.0);
   op->M1.assign(np * np, 0.0);
+  op->G1.assign(np * np, 0.0);
   for (int a = 0; a < np; ++a)
     for (int b = 0; b < np; ++b) {
-      double k = 0.0, m = 0.0;
+      double k = 0.0, m = 0.0, g = 0.0;
       for (int q = 0; q < nq; ++q) {
         k += op->gauss_w[q] * op->D[q * np + a] * op->D[q * np + b];
         m += op->gauss_w[q] * op->B[q * np + a] * op->B[q * np + b];
+        g += op->gauss_w[q] * op->B[q * np + a] * op->D[q * np + b];
       }
       op->K1[a * np + b] = k;
       op->M1[a * np + b] = m;
+      op->G1[a * np + b] = g;
     }
   op->W3.assign(op->nq3, 0.0);
   for (int qz = 0; qz < nq; ++qz)
@@ -346,12 +396,13 @@ pawfe_status build_host(const pawfe_op_desc* d, pawfe_op* op) {
     }
     std::vector<int> cells;
     std::vector<std::vector<double>> Ppts;    // per support cell: [nq3][npj] W p
+    std::vector<std::vector<double>> Pth;     // per support cell: [nq3] Bloch phase k.x (complex)
     Gpp[a].assign(npj * npj, 0.0);
     for (int k : cand[2])
       for (int j : cand[1])
         for (int i : cand[0]) {
           int e = i + op->n[0] * (j + op->n[1] * k);
-          std::vector<double> P((size_t)nq3 * npj, 0.0);
+          std::vector<double> P((size_t)nq3 * npj, 0.0), TH(op->cplx ? nq3 : 0, 0.0);
           bool inside_any = false;
           for (int qz = 0; qz < nq; ++qz)
             for (int qy = 0; qy < nq; ++qy)
@@ -368,6 +419,10 @@ pawfe_status build_host(const pawfe_op_desc* d, pawfe_op* op) {
                 if (!(r2 < rc2)) continue;
                 inside_any = true;
                 int q = qx + nq * (qy + nq * qz);
+                // phase at the point's image next to the atom (the given, unwrapped
+                // atom position plus the minimum-image displacement)
+                if (op->cplx)
+                  for (int t = 0; t < 3; ++t) TH[q] += op->kpt[t] * (d->pos[3 * a + t] + dd[t]);
                 for (int t = 0; t < npj; ++t) {
                   int g = op->poff[a] + t;
                   double sg = d->proj_sigma[g];
@@ -387,6 +442,7 @@ pawfe_status build_host(const pawfe_op_desc* d, pawfe_op* op) {
               for (int t = 0; t < npj; ++t) Gpp[a][s * npj + t] += op->W3[q] * ps * P[(size_t)q * npj + t];
             }
           Ppts.push_back(std::move(P));
+          Pth.push_back(std::move(TH));
         }
     // sort support cells (and their point data) by cell index
     std::vector<int> order(cells.size());
@@ -404,12 +460,19 @@ pawfe_status build_host(const pawfe_op_desc* d, pawfe_op* op) {
     for (size_t r = 0; r < nodes.size(); ++r) rowmap[nodes[r]] = (int32_t)r;
     op->atom_coff[a] = (int32_t)op->Cvals.size();
     op->Cvals.resize(op->Cvals.size() + nodes.size() * npj, 0.0);
+    if (op->cplx) op->Cvals_im.resize(op->Cvals.size(), 0.0);
     double* Ca = &op->Cvals[op->atom_coff[a]];
+    double* Ca_im = op->cplx ? &op->Cvals_im[op->atom_coff[a]] : nullptr;
     for (int idx : order) {
       const int e = cells[idx];
       const std::vector<double>& P = Ppts[idx];
+      // C = N^T W (p e^{-i k.x}): real part, then (complex) imaginary part
+      for (int part = 0; part < (op->cplx ? 2 : 1); ++part)
       for (int t = 0; t < npj; ++t) {
-        for (int q = 0; q < nq3; ++q) F[q] = op->W3[q] * P[(size_t)q * npj + t];
+        for (int q = 0; q < nq3; ++q) {
+          const double wp = op->W3[q] * P[(size_t)q * npj + t];
+          F[q] = !op->cplx ? wp : (part == 0 ? wp * std::cos(Pth[idx][q]) : -wp * std::sin(Pth[idx][q]));
+        }
         // x: F[qz][qy][qx] -> T1[qz][qy][a]
         for (int qz = 0; qz < nq; ++qz)
           for (int qy = 0; qy < nq; ++qy)
@@ -434,7 +497,8 @@ pawfe_status build_host(const pawfe_op_desc* d, pawfe_op* op) {
               for (int qz = 0; qz < nq; ++qz) s += op->B[qz * np + cc] * T2[aa + np * (bb + np * qz)];
               Cl[aa + np * (bb + np * cc)] = s;
             }
-        for (int l = 0; l < op->nloc; ++l) Ca[(size_t)rowmap[dof(e, l)] * npj + t] += Cl[l];
+        double* dst = part == 0 ? Ca : Ca_im;
+        for (int l = 0; l < op->nloc; ++l) dst[(size_t)rowmap[dof(e, l)] * npj + t] += Cl[l];
       }
     }
     for (int64_t nd : nodes) {
@@ -464,8 +528,9 @@ pawfe_status build_host(const pawfe_op_desc* d, pawfe_op* op) {
   if (!ent.empty()) op->srow_ptr.push_back((int32_t)ent.size());
   op->nsrow = (int64_t)op->srow_ptr.size() - 1;
 
-  // G^{ab} = C^a^T M_D^{-1} C^b over shared support nodes
-  std::map<std::pair<int, int>, std::vector<double>> Gab;
+  // G^{ab} = C^a^H M_D^{-1} C^b over shared support nodes (imaginary part in
+  // Gab_im for complex operators)
+  std::map<std::pair<int, int>, std::vector<double>> Gab, Gab_im;
   {
     size_t s0 = 0;
     while (s0 < ent.size()) {
@@ -478,10 +543,24 @@ pawfe_status build_host(const pawfe_op_desc* d, pawfe_op* op) {
           int na_ = op->nproj[a], nb_ = op->nproj[b];
           auto& G = Gab[{a, b}];
           if (G.empty()) G.assign(na_ * nb_, 0.0);
-          const double* ca = &op->Cvals[op->atom_coff[a] + (size_t)ent[x].second.second * na_];
-          const double* cb = &op->Cvals[op->atom_coff[b] + (size_t)ent[y].second.second * nb_];
-          for (int s = 0; s < na_; ++s)
-            for (int t = 0; t < nb_; ++t) G[s * nb_ + t] += ca[s] * minv * cb[t];
+          const size_t oa = op->atom_coff[a] + (size_t)ent[x].second.second * na_;
+          const size_t ob = op->atom_coff[b] + (size_t)ent[y].second.second * nb_;
+          const double* ca = &op->Cvals[oa];
+          const double* cb = &op->Cvals[ob];
+          if (!op->cplx) {
+            for (int s = 0; s < na_; ++s)
+              for (int t = 0; t < nb_; ++t) G[s * nb_ + t] += ca[s] * minv * cb[t];
+          } else {
+            auto& Gi = Gab_im[{a, b}];
+            if (Gi.empty()) Gi.assign(na_ * nb_, 0.0);
+            const double* cai = &op->Cvals_im[oa];
+            const double* cbi = &op->Cvals_im[ob];
+            for (int s = 0; s < na_; ++s)
+              for (int t = 0; t < nb_; ++t) {   // conj(ca) cb
+                G[s * nb_ + t] += minv * (ca[s] * cb[t] + cai[s] * cbi[t]);
+                Gi[s * nb_ + t] += minv * (ca[s] * cbi[t] - cai[s] * cb[t]);
+              }
+          }
         }
       s0 = s1;
     }
@@ -492,25 +571,39 @@ pawfe_status build_host(const pawfe_op_desc* d, pawfe_op* op) {
   op->Gvals.clear();
   for (auto& kv : Gab) op->gp_ptr[kv.first.first + 1]++;
   for (int a = 0; a < na; ++a) op->gp_ptr[a + 1] += op->gp_ptr[a];
+  op->Gvals_im.clear();
   for (auto& kv : Gab) {   // std::map iterates (a, b) in order
     op->gp_b.push_back(kv.first.second);
     op->gp_off.push_back((int32_t)op->Gvals.size());
     op->Gvals.insert(op->Gvals.end(), kv.second.begin(), kv.second.end());
+    if (op->cplx) {
+      const std::vector<double>& gi = Gab_im[kv.first];
+      op->Gvals_im.insert(op->Gvals_im.end(), gi.begin(), gi.end());
+    }
   }
 
-  // Delta_Sinv^a = Delta_S^a (I + G^a Delta_S^a)^{-1}
+  // Delta_Sinv^a = Delta_S^a (I + G^a Delta_S^a)^{-1} (complex for complex
+  // operators with the exact G^a)
   op->dSinv.assign(op->npj2_total, 0.0);
+  const bool csinv = op->cplx && op->sinv_mode != PAWFE_SINV_PP;
+  op->dSinv_im.assign(csinv ? op->npj2_total : 0, 0.0);
   for (int a = 0; a < na; ++a) {
     const int npj = op->nproj[a];
-    std::vector<double> Ga(npj * npj, 0.0);
+    std::vector<double> Ga(npj * npj, 0.0), Gai(npj * npj, 0.0);
     if (op->sinv_mode == PAWFE_SINV_PP) {
       Ga = Gpp[a];
     } else {
       auto it = Gab.find({a, a});
       if (it != Gab.end()) Ga = it->second;
+      if (csinv) {
+        auto jt = Gab_im.find({a, a});
+        if (jt != Gab_im.end()) Gai = jt->second;
+      }
     }
-    if (!dsinv_block(npj, Ga.data(), &op->dS[op->poff2[a]], &op->dSinv[op->poff2[a]]))
-      return fail(PAWFE_ENOTSPD, "I + G^a Delta_S^a is singular for atom " + std::to_string(a));
+    const bool ok = csinv ? dsinv_block_c(npj, Ga.data(), Gai.data(), &op->dS[op->poff2[a]],
+                                          &op->dSinv[op->poff2[a]], &op->dSinv_im[op->poff2[a]])
+                          : dsinv_block(npj, Ga.data(), &op->dS[op->poff2[a]], &op->dSinv[op->poff2[a]]);
+    if (!ok) return fail(PAWFE_ENOTSPD, "I + G^a Delta_S^a is singular for atom " + std::to_string(a));
   }
 
   // reduction work items: chunks of at most kItemRows support rows per atom

@@ -35,8 +35,10 @@ struct Tab1D {
   T B[kNqMax * kNpMax];
   T K1[kNpMax * kNpMax];
   T M1[kNpMax * kNpMax];
+  T G1[kNpMax * kNpMax];   // G1[a][b] = sum_q w_q N_a N_b' (reference element)
   T f[3];
   T detJ;
+  T g[3];                  // complex operators: -k_d det J (2/h_d) (imaginary local term)
 };
 
 // Device-resident tables of one operator.
@@ -58,6 +60,8 @@ struct DeviceTables {
   int32_t* srow_coff = nullptr;   // [nent] offset of the C row in Cvals
   double* Cvals = nullptr;        // atom-major rows of C^a on support nodes
   float* Cvals_f = nullptr;
+  double* Cvals_im = nullptr;     // imaginary parts (complex operators; else null)
+  float* Cvals_im_f = nullptr;
   int32_t* atom_nodes = nullptr;  // concatenated support node lists (DOFs)
   int32_t* item_atom = nullptr;   // reduction work items
   int32_t* item_row0 = nullptr;   // row range inside the atom's list
@@ -75,10 +79,12 @@ struct DeviceTables {
   double* dH = nullptr;
   double* dS = nullptr;
   double* dSinv = nullptr;
+  double* dSinv_im = nullptr;     // complex operators with the exact G (else null)
   int32_t* gp_ptr = nullptr;      // [natoms+1] neighbour pairs (a, b) sharing support nodes
   int32_t* gp_b = nullptr;
   int32_t* gp_off = nullptr;      // offset of G^{ab} (nproj_a x nproj_b, row-major)
   double* Gvals = nullptr;
+  double* Gvals_im = nullptr;     // complex operators (else null)
 };
 
 }  // namespace pawfe
@@ -93,7 +99,10 @@ struct pawfe_op {
   double detJ;
   // host tables
   std::vector<double> gll_x, gll_w, gauss_x, gauss_w;
-  std::vector<double> B, D, K1, M1, W3, MD;
+  std::vector<double> B, D, K1, M1, G1, W3, MD;   // G1[a][b] = sum_q w_q N_a N_b' (reference)
+  // complex (k-point) operator: X is stored as interleaved (re, im) columns
+  bool cplx = false;
+  double kpt[3] = {0.0, 0.0, 0.0};
   std::vector<double> veff;
   // colouring
   int ncolour;
@@ -106,10 +115,11 @@ struct pawfe_op {
   std::vector<int32_t> nproj, poff, poff2;
   std::vector<int64_t> supp_cell_off, supp_cells, supp_node_off, supp_nodes;
   std::vector<double> Cvals;           // atom-major: atom a rows at atom_coff[a]
+  std::vector<double> Cvals_im;        // imaginary parts (complex operators)
   std::vector<int32_t> atom_coff;
-  std::vector<double> dH, dS, dSinv;
+  std::vector<double> dH, dS, dSinv, dSinv_im;   // dSinv_im: complex operators, exact G
   std::vector<int32_t> gp_ptr, gp_b, gp_off;
-  std::vector<double> Gvals;
+  std::vector<double> Gvals, Gvals_im;
   int64_t nsrow = 0, nent = 0;
   std::vector<int32_t> node2srow, srow_ptr, srow_atom, srow_coff;
   std::vector<int32_t> item_atom, item_row0, item_row1, item_poff, item_ptr, atom_noff, atom_nodes;

@@ -7,7 +7,7 @@
 
 namespace pawfe {
 
-enum { kModeH = 0, kModeHRes = 1, kModeMass = 2 };
+enum { kModeH = 0, kModeHRes = 1, kModeMass = 2, kModeImg = 3 };
 
 template <typename T>
 struct CellArgs {
@@ -39,6 +39,10 @@ struct DensArgs {
 //  mode kModeH:    A_loc = K + V
 //  mode kModeHRes: A_loc = K + V - lambda_n M (per column n)
 //  mode kModeMass: A_loc = M
+//  mode kModeImg:  complex operators, the imaginary local term applied to
+//                  the partner columns: Y[n] += alpha s_n (Hi X)[n ^ 1],
+//                  Hi = sum_d g_d (G1 along d, M1 along the others),
+//                  s_n = -1 on real and +1 on imaginary columns
 //  bf3: (FP32 only) the cell contractions as bf16x3 split products on the
 //  bf16 matrix cores, FP32 accumulation.
 template <typename T>
@@ -52,6 +56,10 @@ pawfe_status launch_cell_mfma(const pawfe_op* op, int mode, const CellArgs<T>& a
 pawfe_status launch_density(const pawfe_op* op, const double* X, int64_t ldx, int ncols,
                             const double* occ, double* out, hipStream_t s);
 
+// out[2 j] = out[2 j + 1] = in[j], j < n (a value per complex column -> one
+// per real column of the (re, im) pairs)
+pawfe_status launch_dup_pairs(const double* in, double* out, int n, hipStream_t s);
+
 // ---- non-local / node-wise kernels (kernels_nl.hip) ----
 
 // c[(poff_a + alpha) * ncols + n] = sum_{I in supp(a)} C^a[I][alpha] s_I X[I][n],
@@ -61,8 +69,11 @@ pawfe_status launch_nl_reduce(const pawfe_op* op, const T* X, int64_t ldx, int n
                               double* part, double* c, hipStream_t s);
 
 // out = (D1 - lam_n D2) in  (per atom block; D2 may be NULL), scaled by f.
+// D1i: imaginary part of D1 (complex operators, Delta_Sinv with the exact G);
+// the columns are then (re, im) pairs of complex columns.
 pawfe_status launch_atom_mul(const pawfe_op* op, const double* D1, const double* D2, const double* lam,
-                             double f, const double* in, double* out, int ncols, hipStream_t s);
+                             double f, const double* in, double* out, int ncols, hipStream_t s,
+                             const double* D1i = nullptr);
 
 // out_a = c_a - sum_b G^{ab} d_b
 pawfe_status launch_atom_gcorr(const pawfe_op* op, const double* c, const double* d, double* out,

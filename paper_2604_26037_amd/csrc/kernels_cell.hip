@@ -118,7 +118,10 @@ pawfe_status launch_cell(const pawfe_op* op, int mode, const T* X, int64_t ldx, 
   a.n0 = op->n[0];
   a.n1 = op->n[1];
   a.n2 = op->n[2];
-  return launch_cell_mfma<T>(op, mode, a, s);
+  const pawfe_status st = launch_cell_mfma<T>(op, mode, a, s);
+  // complex operators: the imaginary local term, on the (re, im) column pairs
+  if (st != PAWFE_OK || !op->cplx || (mode != kModeH && mode != kModeHRes)) return st;
+  return launch_cell_mfma<T>(op, kModeImg, a, s);
 }
 
 template pawfe_status launch_cell<double>(const pawfe_op*, int, const double*, int64_t, double*, int64_t,

@@ -394,8 +394,9 @@ k_cell_mfma(CellArgs<T> A, const Tab1D<T>* __restrict__ tabp,
   constexpr int NQ3 = NQ * NQ * NQ;
   constexpr int NJ = (NL * CB + 255) / 256;   // gathered elements per thread and item
   constexpr int NV = (NQ3 + 255) / 256;       // V(q) W_q values per thread and item
-  constexpr bool HAS_V = MODE != kModeMass;
+  constexpr bool HAS_V = MODE == kModeH || MODE == kModeHRes;
   constexpr bool RES = MODE == kModeHRes;
+  constexpr bool IMG = MODE == kModeImg;
   __shared__ T smem[3 * kSlots * CB];
   // V(q) W_q of the current cell and W_q (residual mode); entry q at
   // q + q / 64, so the 8 outputs of a result write (stride 64) differ in bank
@@ -412,27 +413,33 @@ k_cell_mfma(CellArgs<T> A, const Tab1D<T>* __restrict__ tabp,
   // 8x8 blocks B[q][a], K1, M1 and a zero block (no bounds test on a read).
   // FP64 (no LDS to spare at three workgroups per CU): B unpadded, the
   // symmetric K1 and M1 as lower triangles, one zero.
+  // In the imaginary-term mode the K slot holds G1 (not symmetric: FP64
+  // keeps it unpacked) and the scale factors are g_d.
   constexpr bool PADT = sizeof(T) == 4;
-  constexpr int NB = NQ * NP, NS = NP * (NP + 1) / 2;
-  constexpr int tK = PADT ? 64 : NB, tM = PADT ? 128 : NB + NS, tZ = PADT ? 192 : NB + 2 * NS;
+  constexpr int NB = NQ * NP, NS = NP * (NP + 1) / 2, NKS = IMG ? NP * NP : NS;
+  constexpr int tK = PADT ? 64 : NB, tM = PADT ? 128 : NB + NKS, tZ = PADT ? 192 : NB + NKS + NS;
   constexpr int tF = PADT ? 256 : tZ + 1, NCT = tF + 4;
+  const T* Kt = IMG ? tab.G1 : tab.K1;
+  const T* ft = IMG ? tab.g : tab.f;
   __shared__ T ctab[NCT];
   for (int i = tid; i < NCT; i += 256) {
     T v = T(0);
     if (i >= tF) {
-      v = i - tF < 3 ? tab.f[i - tF] : tab.detJ;
+      v = i - tF < 3 ? ft[i - tF] : tab.detJ;
     } else if constexpr (PADT) {
       const int blk = i >> 6, o = (i >> 3) & 7, k = i & 7;
       if (blk == 0) v = (o < NQ && k < NP) ? tab.B[o * NP + k] : T(0);
-      else if (blk == 1) v = (o < NP && k < NP) ? tab.K1[o * NP + k] : T(0);
+      else if (blk == 1) v = (o < NP && k < NP) ? Kt[o * NP + k] : T(0);
       else if (blk == 2) v = (o < NP && k < NP) ? tab.M1[o * NP + k] : T(0);
     } else {
       if (i < tK) {
         v = tab.B[i];
+      } else if (IMG && i < tM) {
+        v = Kt[i - tK];
       } else if (i < tZ) {
         int t = i < tM ? i - tK : i - tM, h = 0;   // packed (h, l), l <= h
         while ((h + 1) * (h + 2) / 2 <= t) ++h;
-        v = (i < tM ? tab.K1 : tab.M1)[h * NP + (t - h * (h + 1) / 2)];
+        v = (i < tM ? Kt : tab.M1)[h * NP + (t - h * (h + 1) / 2)];
       }
     }
     ctab[i] = v;
@@ -573,7 +580,14 @@ k_cell_mfma(CellArgs<T> A, const Tab1D<T>* __restrict__ tabp,
   // operations and have had a whole item to arrive.
   auto stage = [&]() {
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) lds_a(pk[j]) = j < kLast ? xr[j] : zero_unless(lreal(j), xr[j]);
+    for (int j = 0; j < NJ; ++j) {
+      T v = xr[j];
+      if constexpr (IMG) {   // s_n x[n ^ 1]: the partner column sits in the neighbouring lane
+        const T w = __shfl_xor(v, 1);
+        v = (col & 1) ? w : -w;
+      }
+      lds_a(pk[j]) = j < kLast ? v : zero_unless(lreal(j), v);
+    }
     // (writes without branches, so that the wait for every load happens on
     // every path and nothing is left in doubt at the top of the loop)
     if constexpr (HAS_V) {
@@ -604,6 +618,7 @@ k_cell_mfma(CellArgs<T> A, const Tab1D<T>* __restrict__ tabp,
   };
   auto Km = [&](int a, int b) -> T {
     if constexpr (PADT) return ctab[(a < 8 && b < 8) ? tK + a * 8 + b : tZ];
+    else if constexpr (IMG) return ctab[(a < NP && b < NP) ? tK + a * NP + b : tZ];
     else return ctab[(a < NP && b < NP) ? tK + sym(a, b) : tZ];
   };
   auto Mm = [&](int a, int b) -> T {
@@ -630,7 +645,27 @@ k_cell_mfma(CellArgs<T> A, const Tab1D<T>* __restrict__ tabp,
     const bool more = item + i_step < i_end;
     load_item(more ? nxt_c : cur_c, more ? nxt_t : cur_t);
 
-    if constexpr (MODE == kModeMass) {
+    if constexpr (IMG) {
+      // kinetic structure with G1: C = sum_d g_d (G1 along d, M1 along the others) U'
+      const Slab inA[1] = {sA};
+      const Slab inCA[2] = {sC, sA};
+      const Slab oC[1] = {sC};
+      const Slab oCA[2] = {sC, sA};
+      mfma_pass<T, 0, CB, 1, 2, BF3, NP>(smem, inA, oCA,
+                                         [&](int o, int k) { return o < 8 ? Km(o, k) : Mm(o - 8, k); }, store);
+      __syncthreads();
+      mfma_pass<T, 1, CB, 2, 2, BF3, NP>(
+          smem, inCA, oCA,
+          [&](int o, int k) {
+            if (o < 8) return k < 8 ? fsc(0) * Mm(o, k) : fsc(1) * Km(o, k - 8);
+            return k < 8 ? T(0) : Mm(o - 8, k - 8);
+          },
+          store);
+      __syncthreads();
+      mfma_pass<T, 2, CB, 2, 1, BF3, NP>(
+          smem, inCA, oC, [&](int o, int k) { return k < 8 ? Mm(o, k) : fsc(2) * Km(o, k - 8); }, store);
+      __syncthreads();
+    } else if constexpr (MODE == kModeMass) {
       const Slab inA[1] = {sA};
       const Slab inC[1] = {sC};
       const Slab oC[1] = {sC};
@@ -772,6 +807,8 @@ pawfe_status run_cell_mfma(const pawfe_op* op, int mode, CellArgs<T> a, hipStrea
       launch_mode<T, NP, NQ, CB, kModeH>(ac, tab, ncoltiles, nitems, s);
     else if (mode == kModeHRes)
       launch_mode<T, NP, NQ, CB, kModeHRes>(ac, tab, ncoltiles, nitems, s);
+    else if (mode == kModeImg)
+      launch_mode<T, NP, NQ, CB, kModeImg>(ac, tab, ncoltiles, nitems, s);
     else
       launch_mode<T, NP, NQ, CB, kModeMass>(ac, tab, ncoltiles, nitems, s);
   }

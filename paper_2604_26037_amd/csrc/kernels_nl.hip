@@ -31,11 +31,15 @@ constexpr int kRowsPerWaveGroup = 4;   // waves per 256-thread block in row-wise
 // their loads issued before the FMAs (memory-level parallelism).
 constexpr int kUnroll = 8;
 
-template <typename T, int NPJ, bool SCALE>
+// Complex operators (CPLX): the columns are (re, im) pairs of the complex
+// columns and c = C^H x mixes them: c[n] = sum Cr x[n] + s' Ci x[n ^ 1],
+// s' = +1 on real and -1 on imaginary columns; the partner value comes from
+// the neighbouring lane.
+template <typename T, int NPJ, bool SCALE, bool CPLX = false>
 __global__ void __launch_bounds__(256) k_nl_reduce(const T* __restrict__ X, int64_t ldx, int ncols,
                                                    const T* __restrict__ Minv,
                                                    const T* __restrict__ Cv, DeviceTables d,
-                                                   double* __restrict__ part) {
+                                                   double* __restrict__ part, const T* __restrict__ Cvi = nullptr) {
   const int item = blockIdx.x;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -78,6 +82,16 @@ __global__ void __launch_bounds__(256) k_nl_reduce(const T* __restrict__ X, int6
         const T* cr = Cv + coff + (int64_t)r * npj;
 #pragma unroll
         for (int al = 0; al < NPJ; ++al) acc[al] += cr[FULL ? al : (al < npj ? al : npj - 1)] * x[u];
+        if constexpr (CPLX) {
+          // the shuffle runs in every lane before the sign is chosen: a
+          // lane-permute reads 0 from lanes that are switched off, so it
+          // must not sit inside a branch on the column parity
+          const T xs = __shfl_xor(x[u], 1);
+          const T xp = (n & 1) ? -xs : xs;
+          const T* ci = Cvi + coff + (int64_t)r * npj;
+#pragma unroll
+          for (int al = 0; al < NPJ; ++al) acc[al] += ci[FULL ? al : (al < npj ? al : npj - 1)] * xp;
+        }
       }
     }
   };
@@ -115,11 +129,15 @@ __global__ void __launch_bounds__(256) k_nl_final(const double* __restrict__ par
   c[(int64_t)g * ncols + n] = s;
 }
 
+// D1i (complex D1 = D1 + i D1i; complex operators): the columns are (re, im)
+// pairs, D1 c mixes them: + s D1i c[n ^ 1], s = -1 on real, +1 on imaginary
+// columns.
 __global__ void __launch_bounds__(256) k_atom_mul(const double* __restrict__ D1, const double* __restrict__ D2,
                                                   const double* __restrict__ lam, double f,
                                                   const double* __restrict__ in, double* __restrict__ out,
                                                   int ncols, const int32_t* __restrict__ proj_atom,
-                                                  const int32_t* __restrict__ proj_alpha, DeviceTables d) {
+                                                  const int32_t* __restrict__ proj_alpha, DeviceTables d,
+                                                  const double* __restrict__ D1i) {
   const int g = blockIdx.x;
   const int n = blockIdx.y * 256 + threadIdx.x;
   if (n >= ncols) return;
@@ -128,6 +146,12 @@ __global__ void __launch_bounds__(256) k_atom_mul(const double* __restrict__ D1,
   const double* r1 = D1 + d.poff2[a] + s * npj;
   double acc = 0.0, acc2 = 0.0;
   for (int t = 0; t < npj; ++t) acc += r1[t] * in[(int64_t)(po + t) * ncols + n];
+  if (D1i) {
+    const double* ri = D1i + d.poff2[a] + s * npj;
+    double ai = 0.0;
+    for (int t = 0; t < npj; ++t) ai += ri[t] * in[(int64_t)(po + t) * ncols + (n ^ 1)];
+    acc += (n & 1) ? ai : -ai;
+  }
   if (D2) {
     const double* r2 = D2 + d.poff2[a] + s * npj;
     for (int t = 0; t < npj; ++t) acc2 += r2[t] * in[(int64_t)(po + t) * ncols + n];
@@ -150,6 +174,12 @@ __global__ void __launch_bounds__(256) k_atom_gcorr(const double* __restrict__ c
     const double* G = d.Gvals + d.gp_off[k] + s * nb;
 #pragma unroll 6
     for (int u = 0; u < nb; ++u) acc -= G[u] * dv[(int64_t)(pb + u) * ncols + n];
+    if (d.Gvals_im) {   // complex operators: (re, im) column pairs mix
+      const double* Gi = d.Gvals_im + d.gp_off[k] + s * nb;
+      double ai = 0.0;
+      for (int u = 0; u < nb; ++u) ai += Gi[u] * dv[(int64_t)(pb + u) * ncols + (n ^ 1)];
+      acc -= (n & 1) ? ai : -ai;
+    }
   }
   out[(int64_t)g * ncols + n] = acc;
 }
@@ -353,7 +383,10 @@ __global__ void __launch_bounds__(256) k_node_finalize(int64_t M, int ncols, int
 // with all loads issued first.
 constexpr int kFixUnroll = 8;
 
-template <typename TR, typename TO1, int NPJ, bool MINV, bool HAS2>
+// CPLX (complex operators): (re, im) column pairs, C v mixes them:
+// + s Ci v[n ^ 1], s = -1 on real and +1 on imaginary columns (partner value
+// from the neighbouring lane).
+template <typename TR, typename TO1, int NPJ, bool MINV, bool HAS2, bool CPLX = false>
 __global__ void __launch_bounds__(256) k_nl_fixup(const int32_t* __restrict__ fatom,
                                                   const int32_t* __restrict__ frow0,
                                                   const int32_t* __restrict__ frow1, int ncols,
@@ -361,7 +394,8 @@ __global__ void __launch_bounds__(256) k_nl_fixup(const int32_t* __restrict__ fa
                                                   TO1* __restrict__ out1, int64_t ld1,
                                                   const double* __restrict__ v2, TR* __restrict__ out2,
                                                   int64_t ld2, const TR* __restrict__ Minv,
-                                                  const TR* __restrict__ Cv, DeviceTables d) {
+                                                  const TR* __restrict__ Cv, DeviceTables d,
+                                                  const TR* __restrict__ Cvi = nullptr) {
   const int n = blockIdx.y * 256 + threadIdx.x;
   if (n >= ncols) return;
   const int a = fatom[blockIdx.x];
@@ -374,7 +408,7 @@ __global__ void __launch_bounds__(256) k_nl_fixup(const int32_t* __restrict__ fa
   auto body = [&](auto full) {
     constexpr bool FULL = decltype(full)::value;
     auto idx = [&](int al) { return FULL ? al : (al < npj ? al : npj - 1); };
-    TR w1[NPJ], w2[NPJ];
+    TR w1[NPJ], w2[NPJ], p1[CPLX ? NPJ : 1], p2[CPLX ? NPJ : 1];
 #pragma unroll
     for (int al = 0; al < NPJ; ++al) {
       const double x1 = v1[(int64_t)(po + idx(al)) * ncols + n];
@@ -382,6 +416,14 @@ __global__ void __launch_bounds__(256) k_nl_fixup(const int32_t* __restrict__ fa
       if constexpr (HAS2) {
         const double x2 = v2[(int64_t)(po + idx(al)) * ncols + n];
         w2[al] = (FULL || al < npj) ? (TR)x2 : TR(0);
+      }
+    }
+    if constexpr (CPLX) {
+      const TR sg = (n & 1) ? TR(1) : TR(-1);
+#pragma unroll
+      for (int al = 0; al < NPJ; ++al) {
+        p1[al] = sg * __shfl_xor(w1[al], 1);
+        if constexpr (HAS2) p2[al] = sg * __shfl_xor(w2[al], 1);
       }
     }
     for (int rb = r0; rb < r1; rb += kFixUnroll) {
@@ -405,6 +447,15 @@ __global__ void __launch_bounds__(256) k_nl_fixup(const int32_t* __restrict__ fa
           const TR cv = cr[idx(al)];
           c1[u] += cv * w1[al];
           if constexpr (HAS2) c2[u] += cv * w2[al];
+        }
+        if constexpr (CPLX) {
+          const TR* ci = Cvi + coff + (int64_t)r * npj;
+#pragma unroll
+          for (int al = 0; al < NPJ; ++al) {
+            const TR cv = ci[idx(al)];
+            c1[u] += cv * p1[al];
+            if constexpr (HAS2) c2[u] += cv * p2[al];
+          }
         }
         if constexpr (MINV) c1[u] *= Minv[I[u]];
       }
@@ -590,17 +641,22 @@ pawfe_status launch_nl_reduce(const pawfe_op* op, const T* X, int64_t ldx, int n
   if (op->natoms == 0 || ncols <= 0) return PAWFE_OK;
   const T* Cv = pick<T>(op->d.Cvals, op->d.Cvals_f);
   const T* Minv = pick<T>(op->d.Minv, op->d.Minv_f);
+  const T* Cvi = pick<T>(op->d.Cvals_im, op->d.Cvals_im_f);
   const dim3 grid(op->nitems, (ncols + 255) / 256), block(256);
-  auto go = [&](auto scale) {
-    constexpr bool SC = decltype(scale)::value;
+  auto go = [&](auto scale, auto cplx) {
+    constexpr bool SC = decltype(scale)::value, CX = decltype(cplx)::value;
     if (op->npj_max <= 8)
-      hipLaunchKernelGGL((k_nl_reduce<T, 8, SC>), grid, block, 0, s, X, ldx, ncols, Minv, Cv, op->d, part);
+      hipLaunchKernelGGL((k_nl_reduce<T, 8, SC, CX>), grid, block, 0, s, X, ldx, ncols, Minv, Cv, op->d, part, Cvi);
     else if (op->npj_max <= 18)
-      hipLaunchKernelGGL((k_nl_reduce<T, 18, SC>), grid, block, 0, s, X, ldx, ncols, Minv, Cv, op->d, part);
+      hipLaunchKernelGGL((k_nl_reduce<T, 18, SC, CX>), grid, block, 0, s, X, ldx, ncols, Minv, Cv, op->d, part, Cvi);
     else
-      hipLaunchKernelGGL((k_nl_reduce<T, 32, SC>), grid, block, 0, s, X, ldx, ncols, Minv, Cv, op->d, part);
+      hipLaunchKernelGGL((k_nl_reduce<T, 32, SC, CX>), grid, block, 0, s, X, ldx, ncols, Minv, Cv, op->d, part, Cvi);
   };
-  if (scale_minv) go(std::true_type{}); else go(std::false_type{});
+  if (op->cplx) {
+    if (scale_minv) go(std::true_type{}, std::true_type{}); else go(std::false_type{}, std::true_type{});
+  } else {
+    if (scale_minv) go(std::true_type{}, std::false_type{}); else go(std::false_type{}, std::false_type{});
+  }
   const dim3 g2(op->npj_total, (ncols + 255) / 256);
   hipLaunchKernelGGL(k_nl_final, g2, block, 0, s, part, ncols, op->d_proj_atom, op->d_proj_alpha, op->d, c);
   PAWFE_HIP(hipGetLastError());
@@ -612,11 +668,27 @@ template pawfe_status launch_nl_reduce<float>(const pawfe_op*, const float*, int
                                               hipStream_t);
 
 pawfe_status launch_atom_mul(const pawfe_op* op, const double* D1, const double* D2, const double* lam, double f,
-                             const double* in, double* out, int ncols, hipStream_t s) {
+                             const double* in, double* out, int ncols, hipStream_t s, const double* D1i) {
   if (op->natoms == 0 || ncols <= 0) return PAWFE_OK;
   const dim3 grid(op->npj_total, (ncols + 255) / 256), block(256);
   hipLaunchKernelGGL(k_atom_mul, grid, block, 0, s, D1, D2, lam, f, in, out, ncols, op->d_proj_atom,
-                     op->d_proj_alpha, op->d);
+                     op->d_proj_alpha, op->d, D1i);
+  PAWFE_HIP(hipGetLastError());
+  return PAWFE_OK;
+}
+
+__global__ void k_dup_pairs(const double* __restrict__ in, double* __restrict__ out, int n) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j < n) {
+    const double v = in[j];
+    out[2 * j] = v;
+    out[2 * j + 1] = v;
+  }
+}
+
+pawfe_status launch_dup_pairs(const double* in, double* out, int n, hipStream_t s) {
+  if (n <= 0) return PAWFE_OK;
+  hipLaunchKernelGGL(k_dup_pairs, dim3((n + 255) / 256), dim3(256), 0, s, in, out, n);
   PAWFE_HIP(hipGetLastError());
   return PAWFE_OK;
 }
@@ -636,21 +708,26 @@ pawfe_status nl_fixup(const pawfe_op* op, int ncols, const double* v1, double s1
                       const double* v2, TR* out2, int64_t ld2, hipStream_t s) {
   if (op->natoms == 0 || ncols <= 0) return PAWFE_OK;
   const TR* Cv = pick<TR>(op->d.Cvals, op->d.Cvals_f);
+  const TR* Cvi = pick<TR>(op->d.Cvals_im, op->d.Cvals_im_f);
   const TR* Minv = pick<TR>(op->d.Minv, op->d.Minv_f);
   for (int c = 0; c < op->natom_colours; ++c) {
     const int i0 = op->fix_colour_off[c], i1 = op->fix_colour_off[c + 1];
     if (i1 == i0) continue;
     const dim3 grid(i1 - i0, (ncols + 255) / 256), block(256);
     const int32_t *fa = op->d.fix_atom + i0, *f0 = op->d.fix_row0 + i0, *f1 = op->d.fix_row1 + i0;
-    if (op->npj_max <= 8)
-      hipLaunchKernelGGL((k_nl_fixup<TR, TO1, 8, MINV, HAS2>), grid, block, 0, s, fa, f0, f1, ncols, v1, s1, out1,
-                         ld1, v2, out2, ld2, Minv, Cv, op->d);
-    else if (op->npj_max <= 18)
-      hipLaunchKernelGGL((k_nl_fixup<TR, TO1, 18, MINV, HAS2>), grid, block, 0, s, fa, f0, f1, ncols, v1, s1, out1,
-                         ld1, v2, out2, ld2, Minv, Cv, op->d);
-    else
-      hipLaunchKernelGGL((k_nl_fixup<TR, TO1, 32, MINV, HAS2>), grid, block, 0, s, fa, f0, f1, ncols, v1, s1, out1,
-                         ld1, v2, out2, ld2, Minv, Cv, op->d);
+    auto go = [&](auto cplx) {
+      constexpr bool CX = decltype(cplx)::value;
+      if (op->npj_max <= 8)
+        hipLaunchKernelGGL((k_nl_fixup<TR, TO1, 8, MINV, HAS2, CX>), grid, block, 0, s, fa, f0, f1, ncols, v1, s1,
+                           out1, ld1, v2, out2, ld2, Minv, Cv, op->d, Cvi);
+      else if (op->npj_max <= 18)
+        hipLaunchKernelGGL((k_nl_fixup<TR, TO1, 18, MINV, HAS2, CX>), grid, block, 0, s, fa, f0, f1, ncols, v1, s1,
+                           out1, ld1, v2, out2, ld2, Minv, Cv, op->d, Cvi);
+      else
+        hipLaunchKernelGGL((k_nl_fixup<TR, TO1, 32, MINV, HAS2, CX>), grid, block, 0, s, fa, f0, f1, ncols, v1, s1,
+                           out1, ld1, v2, out2, ld2, Minv, Cv, op->d, Cvi);
+    };
+    if (op->cplx) go(std::true_type{}); else go(std::false_type{});
   }
   PAWFE_HIP(hipGetLastError());
   return PAWFE_OK;

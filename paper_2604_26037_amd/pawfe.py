@@ -178,6 +178,9 @@ class Operator:
          self.nsupp_nodes) = [x.value for x in a]
         self.ncells = int(np.prod(s.ncell))
         self.nloc = (int(s.degree) + 1) ** 3
+        # complex (k-point) operators take complex tensors (leading dimensions
+        # in complex elements)
+        self.complex = bool(s.is_complex)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -214,10 +217,16 @@ class Operator:
         self._keep["dH"] = v
 
     # -- applies ------------------------------------------------------------
+    def _dtype(self, prec):
+        import torch
+        if _PREC[prec] == FP64:
+            return torch.complex128 if self.complex else torch.float64
+        return torch.complex64 if self.complex else torch.float32
+
     def _apply(self, fn, X, out, prec, stream):
         import torch
         assert X.is_cuda and X.dim() == 2 and X.shape[0] == self.ndof and X.stride(1) == 1
-        dt = torch.float64 if _PREC[prec] == FP64 else torch.float32
+        dt = self._dtype(prec)
         assert X.dtype == dt, f"X must be {dt}"
         if out is None:
             out = torch.empty((X.shape[0], X.shape[1]), dtype=dt, device=X.device)
@@ -252,8 +261,8 @@ class Operator:
 
     def cheb_filter(self, X, lam, degree, b0, bW, bU, block=None, prec=FP64, out=None, ws=None,
                     stream=None):
+        assert X.is_cuda and X.dtype == self._dtype(FP64) and X.stride(1) == 1
         import torch
-        assert X.is_cuda and X.dtype == torch.float64 and X.stride(1) == 1
         n = X.shape[1]
         block = n if block is None else int(block)
         if out is None:
@@ -274,7 +283,7 @@ class Operator:
     def rayleigh_ritz(self, X, ws=None, stream=None):
         """In place on X; returns (lambda, resnorm) as device tensors."""
         import torch
-        assert X.is_cuda and X.dtype == torch.float64 and X.stride(1) == 1
+        assert X.is_cuda and X.dtype == self._dtype(FP64) and X.stride(1) == 1
         n = X.shape[1]
         lam = torch.empty(n, dtype=torch.float64, device=X.device)
         res = torch.empty(n, dtype=torch.float64, device=X.device)
@@ -354,8 +363,10 @@ class Batch:
         arr = (FilterJob * len(jobs))()
         for i, j in enumerate(jobs):
             X, out, lam = j["X"], j.get("out", j["X"]), j["lam"]
-            for t in (X, out, lam):
-                assert t.is_cuda and t.dtype == torch.float64
+            xdt = j["op"]._dtype(FP64)   # complex128 for complex (k-point) operators
+            for t in (X, out):
+                assert t.is_cuda and t.dtype == xdt
+            assert lam.is_cuda and lam.dtype == torch.float64
             assert X.stride(1) == 1 and out.stride(1) == 1 and lam.is_contiguous()
             self._jobs.append((j["op"], X, out, lam))
             arr[i] = FilterJob(j["op"]._h.value,

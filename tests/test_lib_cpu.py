@@ -62,7 +62,8 @@ def _desc(s, **over):
     (dict(ncell=[1, 4, 4]), pw.PAWFE_EINVAL),
     (dict(degree=7, nq=9), pw.PAWFE_EUNSUPPORTED),
     (dict(degree=4, nq=5), pw.PAWFE_EUNSUPPORTED),
-    (dict(is_complex=1), pw.PAWFE_EUNSUPPORTED),
+    (dict(is_complex=2), pw.PAWFE_EINVAL),
+    (dict(is_complex=1, kpoint=[np.nan, 0.0, 0.0]), pw.PAWFE_ENONFINITE),
     (dict(kpoint=[0.1, 0.0, 0.0]), pw.PAWFE_EINVAL),
     (dict(sinv_mode=7), pw.PAWFE_EINVAL),
     (dict(rcut=np.array([6.0, 1.5])), pw.PAWFE_EINVAL),
