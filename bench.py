@@ -141,8 +141,10 @@ def kernels_mode(op, s, gen, dev, args):
 def batch_mode(dev, args):
     """Uneven real problems (6^3-14^3 cells of degree 5, 8-64 atoms x 18
     projectors, 64-384 states, Chebyshev degree 25, FP32 recurrence) filtered
-    as one graph-captured, autotuned multi-stream batch, against the same
-    filters issued one after another on one stream."""
+    as a graph-captured, autotuned multi-stream batch, against the same
+    filters issued one after another on one stream.  (Not reachable while
+    the full-size batch crash in pawfe_batch_create is open; main() exits
+    before it.)"""
     import torch
 
     from paper_2604_26037_amd import FP32, Batch, Operator
@@ -154,7 +156,8 @@ def batch_mode(dev, args):
     for i, s in enumerate(systems):
         op = Operator(s)
         gen.manual_seed(int(s.x_seed) % (2 ** 63))
-        X = torch.randn((op.ndof, s.nstates), generator=gen, dtype=torch.float64, device=dev)
+        X = torch.randn((op.ndof, s.nstates), generator=gen, device=dev,
+                        dtype=torch.complex128 if op.complex else torch.float64)
         lam, _ = op.rayleigh_ritz(X)
         tmin, tmax, beta = op.lanczos_bounds(k=20)
         lam_h = lam.cpu().numpy()
@@ -163,11 +166,13 @@ def batch_mode(dev, args):
         ops.append(op)
     ndof = [o.ndof for o in ops]
     log(f"{len(jobs)} problems built in {time.time() - t0:.1f} s: DOFs {min(ndof)}-{max(ndof)}, "
-        f"states {min(s.nstates for s in systems)}-{max(s.nstates for s in systems)}")
+        f"states {min(s.nstates for s in systems)}-{max(s.nstates for s in systems)}, "
+        f"{sum(o.complex for o in ops)} complex")
     t0 = time.time()
     b = Batch(jobs, prec=FP32)
     ns, blocks, sof = b.schedule()
-    log(f"batch created (autotune + capture) in {time.time() - t0:.1f} s: {ns} streams, blocks {sorted(set(blocks.tolist()))}")
+    log(f"batch created (autotune + capture) in {time.time() - t0:.1f} s: {ns} streams, {b.ngraphs} graphs, "
+        f"blocks {sorted(set(blocks.tolist()))}")
     reps = max(1, args.steps)
     b.run()
     torch.cuda.synchronize()
@@ -187,7 +192,8 @@ def batch_mode(dev, args):
     t_eager = e1.elapsed_time(e2) / reps / 1e3
     work = sum(o.ndof * s.nstates for o, s in zip(ops, systems))
     log(f"graph replay {t_graph:.3f} s, one stream eager {t_eager:.3f} s")
-    print(json.dumps({"mode": "batch", "problems": len(jobs), "streams": ns, "blocks": blocks.tolist(),
+    print(json.dumps({"mode": "batch", "problems": len(jobs), "streams": ns, "graphs": b.ngraphs,
+                      "blocks": blocks.tolist(),
                       "stream_of_job": sof.tolist(), "t_graph_s": t_graph, "t_eager_one_stream_s": t_eager,
                       "dof_columns_per_s_graph": work * 25 / t_graph}), flush=True)
     b.close()
@@ -211,6 +217,13 @@ def main():
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the filter shards "
               "by column blocks across GPUs but no multi-GPU path is built here.", file=sys.stderr)
         sys.exit(2)
+    if args.mode == "batch":
+        # The 24-problem batch (27,000-343,000 DOFs) ends the process with a
+        # host segmentation fault early in pawfe_batch_create with the current
+        # library (real and complex problems alike); the cause is not found
+        # yet, so this mode stays off.  Small batches are covered by the tests.
+        sys.exit("bench --mode batch is disabled: the full-size batch crashes in pawfe_batch_create "
+                 "(host segmentation fault, cause not found)")
 
     import torch
 
@@ -219,8 +232,6 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    if args.mode == "batch":
-        return batch_mode(dev, args)
     t0 = time.time()
     s = make_system(args.config)
     op = Operator(s)

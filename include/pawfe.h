@@ -255,11 +255,15 @@ pawfe_status pawfe_lanczos_bounds(const pawfe_op* op, int32_t k, uint64_t seed, 
  * counts, polynomial degrees and bounds; the sum over k-points or small
  * cells of the band-energy expression, FE governing equations section)
  * are filtered together: each job is one pawfe_cheb_filter call.  The batch
- * sorts the jobs by estimated cost (largest first), assigns them to
- * nstreams streams by longest-processing-time-first, captures the whole
- * multi-stream schedule once into a HIP graph and replays it.  Every
- * pointer of every job is baked into the graph: a replay re-reads the
- * current CONTENTS of Xin and lambda_in and overwrites Xout.
+ * sorts the jobs by estimated cost (largest first), cuts them in that order
+ * into groups of at most max_graph_launches kernel launches (at least one
+ * job per group; <= 0: 16384), spreads each group's jobs over nstreams
+ * streams by longest-processing-time-first, captures each group's
+ * multi-stream schedule once into its own HIP graph, and replays the graphs
+ * one after another.  The budget bounds the size and the longest dependency
+ * chain of every graph.  Every pointer of every job is baked into the
+ * graphs: a replay re-reads the current CONTENTS of Xin and lambda_in and
+ * overwrites Xout.
  *
  * Column block sizes: a job with block <= 0 gets its block size from the
  * autotuner, which times the candidates {64, 128, 256} (those <= nvec, and
@@ -294,15 +298,17 @@ typedef struct {
  * (the recurrence precision of every job).  The operators must outlive the
  * batch and must not be used by other calls while the batch runs. */
 pawfe_status pawfe_batch_create(const pawfe_filter_job* jobs, int32_t njobs, int32_t prec, int32_t nstreams,
-                                void* stream, pawfe_batch** out);
+                                int32_t max_graph_launches, void* stream, pawfe_batch** out);
 
-/* Enqueues one replay of the captured graph on `stream` (asynchronous). */
+/* Enqueues one replay (every captured graph, in order) on `stream`
+ * (asynchronous). */
 pawfe_status pawfe_batch_run(pawfe_batch* batch, void* stream);
 
 /* Chosen schedule: number of streams, per-job block size and stream index
- * (host arrays of njobs entries, may be NULL). */
+ * (host arrays of njobs entries), number of captured graphs.  Any pointer
+ * may be NULL. */
 pawfe_status pawfe_batch_query(const pawfe_batch* batch, int32_t* nstreams, int32_t* blocks,
-                               int32_t* stream_of_job);
+                               int32_t* stream_of_job, int32_t* ngraphs);
 
 /* Frees the graph, the streams and the workspaces (synchronizes first). */
 void pawfe_batch_destroy(pawfe_batch* batch);

@@ -2,12 +2,17 @@
 // into a HIP graph (the k-point / small-cell batching pattern of the band
 // energy sum, FE governing equations section).
 //
-// Schedule: jobs sorted by estimated cost, assigned to nstreams streams by
-// longest-processing-time-first; the capture forks the streams from the
+// Schedule: jobs sorted by estimated cost and cut, in that order, into
+// consecutive groups of at most a budget of kernel launches; each group is
+// one captured graph, its jobs spread over nstreams streams by
+// longest-processing-time-first (the capture forks the streams from the
 // first one with an event and joins them back, so independent small filters
-// overlap on the chip.  Each job is exactly one pawfe_cheb_filter call with
-// its own workspace; the filter path enqueues kernel launches only (no
-// memset, copy or allocation), which is what makes it capturable.
+// overlap on the chip).  A replay launches the groups' graphs one after
+// another.  The budget bounds the size and the longest dependency chain of
+// every graph (a single graph of every filter of a large batch runs to
+// 10^5 launches).  Each job is exactly one pawfe_cheb_filter call with its
+// own workspace; the filter path enqueues kernel launches only (no memset,
+// copy or allocation), which is what makes it capturable.
 //
 // Autotuner: per job, the column block size among {64, 128, 256} (and
 // nvec when smaller) by timing a degree-3 filter of the job itself; per
@@ -41,20 +46,24 @@ struct pawfe_batch {
   int32_t nstreams = 1;
   std::vector<hipStream_t> streams;
   std::vector<hipEvent_t> events;   // [0] fork, [1..] joins
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  std::vector<std::vector<int>> groups;   // job indices of each graph, in launch order
+  std::vector<hipGraph_t> graphs;
+  std::vector<hipGraphExec_t> execs;
 };
 
 namespace {
 
 using pawfe::fail;
 
+// launches per captured graph unless the caller sets another budget
+constexpr int64_t kDefaultGraphLaunches = 16384;
+
 void release(pawfe_batch* b) {
   if (!b) return;
   if (!b->streams.empty()) (void)hipStreamSynchronize(b->streams[0]);
   (void)hipDeviceSynchronize();
-  if (b->exec) (void)hipGraphExecDestroy(b->exec);
-  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (hipGraphExec_t e : b->execs) (void)hipGraphExecDestroy(e);
+  for (hipGraph_t g : b->graphs) (void)hipGraphDestroy(g);
   for (hipEvent_t e : b->events) (void)hipEventDestroy(e);
   for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
   for (void* p : b->ws)
@@ -92,29 +101,59 @@ pawfe_status time_filter(const pawfe_filter_job& j, int32_t block, int32_t m, in
   return st;
 }
 
-// longest-processing-time-first assignment of jobs (by cost) to ns streams
-std::vector<int32_t> lpt(const std::vector<double>& cost, int ns, std::vector<int>& order) {
-  order.resize(cost.size());
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-  std::vector<double> load(ns, 0.0);
-  std::vector<int32_t> of(cost.size(), 0);
-  for (int j : order) {
-    const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-    of[j] = k;
-    load[k] += cost[j];
-  }
-  return of;
+// kernel launches of one filter of job j with the given block (an upper
+// bound: the step sequence of pawfe_cheb_filter, one launch per non-empty
+// cell colour and atom colour; complex operators add the imaginary-term cell
+// launches and the lambda duplication)
+int64_t est_launches(const pawfe_filter_job& J, int32_t block) {
+  const pawfe_op* op = J.op;
+  int64_t nC = 0, nA = 0;
+  for (int c = 0; c < op->ncolour; ++c) nC += op->colour_off[c + 1] > op->colour_off[c];
+  for (int c = 0; c < op->natom_colours; ++c) nA += op->fix_colour_off[c + 1] > op->fix_colour_off[c];
+  const int64_t cx = op->cplx ? 1 : 0, cell = nC * (1 + cx);
+  const int64_t residual = 4 + nA + cell, step = 6 + nA + cell, final = 4 + nA;
+  const int64_t per_block = residual + cx + 1 + (int64_t)(J.degree - 1) * step + final;
+  return per_block * ((J.nvec + block - 1) / block);
 }
 
-// enqueue the multi-stream schedule: fork from streams[0], jobs, join back
-pawfe_status enqueue(pawfe_batch* b, const std::vector<int>& order, const std::vector<void*>& outs) {
+// cut the jobs (by decreasing cost) into graphs of at most `budget`
+// estimated launches (at least one job each) and spread each graph's jobs
+// over ns streams, longest-processing-time-first
+void plan(pawfe_batch* b, int ns, const std::vector<double>& cost, const std::vector<int64_t>& est,
+          int64_t budget) {
+  std::vector<int> order(cost.size());
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+  b->groups.clear();
+  int64_t acc = 0;
+  for (int j : order) {
+    if (b->groups.empty() || acc + est[j] > budget) {
+      b->groups.emplace_back();
+      acc = 0;
+    }
+    b->groups.back().push_back(j);
+    acc += est[j];
+  }
+  b->nstreams = ns;
+  b->stream_of.assign(cost.size(), 0);
+  for (const std::vector<int>& grp : b->groups) {
+    std::vector<double> load(ns, 0.0);
+    for (int j : grp) {
+      const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      b->stream_of[j] = k;
+      load[k] += cost[j];
+    }
+  }
+}
+
+// enqueue one group: fork from streams[0], its jobs, join back
+pawfe_status enqueue_group(pawfe_batch* b, const std::vector<int>& grp, const std::vector<void*>& outs) {
   const int ns = b->nstreams;
   if (ns > 1) {
     PAWFE_HIP(hipEventRecord(b->events[0], b->streams[0]));
     for (int k = 1; k < ns; ++k) PAWFE_HIP(hipStreamWaitEvent(b->streams[k], b->events[0], 0));
   }
-  for (int j : order) {
+  for (int j : grp) {
     const pawfe_filter_job& J = b->jobs[j];
     void* out = outs.empty() ? J.Xout : outs[j];
     const int64_t ldo = outs.empty() ? J.ldo : J.nvec;
@@ -146,7 +185,8 @@ pawfe_status make_streams(pawfe_batch* b, int ns) {
   return PAWFE_OK;
 }
 
-pawfe_status build(pawfe_batch* b, const pawfe_filter_job* jobs, int32_t njobs, int32_t nstreams, hipStream_t s) {
+pawfe_status build(pawfe_batch* b, const pawfe_filter_job* jobs, int32_t njobs, int32_t nstreams, int64_t budget,
+                   hipStream_t s) {
   const int n = njobs;
   b->jobs.assign(jobs, jobs + n);
   b->block.assign(n, 0);
@@ -212,11 +252,11 @@ pawfe_status build(pawfe_batch* b, const pawfe_filter_job* jobs, int32_t njobs, 
     // degree-3 time -> degree-m estimate (two applies at set-up, one per theta)
     cost[j] = (double)best * (J.degree + 1) / 4.0;
   }
+  std::vector<int64_t> est(n);
+  for (int j = 0; j < n; ++j) est[j] = est_launches(b->jobs[j], b->block[j]);
   // number of streams: given, or the fastest of 1, 2, 4 for the whole batch
-  std::vector<int> order;
   if (nstreams > 0) {
-    b->nstreams = std::min(nstreams, 16);
-    b->stream_of = lpt(cost, b->nstreams, order);
+    plan(b, std::min(nstreams, 16), cost, est, budget);
     CHECK(make_streams(b, b->nstreams));
   } else {
     CHECK(make_streams(b, 4));
@@ -226,11 +266,10 @@ pawfe_status build(pawfe_batch* b, const pawfe_filter_job* jobs, int32_t njobs, 
     PAWFE_HIP(hipEventCreate(&e0));
     PAWFE_HIP(hipEventCreate(&e1));
     for (int ns : {1, 2, 4}) {
-      b->nstreams = ns;
-      b->stream_of = lpt(cost, ns, order);
+      plan(b, ns, cost, est, budget);
       PAWFE_HIP(hipStreamSynchronize(b->streams[0]));
       PAWFE_HIP(hipEventRecord(e0, b->streams[0]));
-      CHECK(enqueue(b, order, tmp));
+      for (const std::vector<int>& grp : b->groups) CHECK(enqueue_group(b, grp, tmp));
       PAWFE_HIP(hipEventRecord(e1, b->streams[0]));
       PAWFE_HIP(hipEventSynchronize(e1));
       float ms = 0.f;
@@ -242,22 +281,26 @@ pawfe_status build(pawfe_batch* b, const pawfe_filter_job* jobs, int32_t njobs, 
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    b->nstreams = best_ns;
-    b->stream_of = lpt(cost, best_ns, order);
+    plan(b, best_ns, cost, est, budget);
   }
   PAWFE_HIP(hipDeviceSynchronize());
-  // capture the schedule once
-  PAWFE_HIP(hipStreamBeginCapture(b->streams[0], hipStreamCaptureModeRelaxed));
-  const pawfe_status st = enqueue(b, order, {});
-  hipGraph_t g = nullptr;
-  const hipError_t ec = hipStreamEndCapture(b->streams[0], &g);
-  if (st != PAWFE_OK) {
-    if (g) (void)hipGraphDestroy(g);
-    return st;
+  // capture each group once
+  for (const std::vector<int>& grp : b->groups) {
+    PAWFE_HIP(hipStreamBeginCapture(b->streams[0], hipStreamCaptureModeRelaxed));
+    const pawfe_status st = enqueue_group(b, grp, {});
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(b->streams[0], &g);
+    if (st != PAWFE_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (ec != hipSuccess || !g)
+      return fail(PAWFE_EHIP, std::string("graph capture failed: ") + hipGetErrorString(ec));
+    b->graphs.push_back(g);
+    hipGraphExec_t ex = nullptr;
+    PAWFE_HIP(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+    b->execs.push_back(ex);
   }
-  if (ec != hipSuccess || !g) return fail(PAWFE_EHIP, std::string("graph capture failed: ") + hipGetErrorString(ec));
-  b->graph = g;
-  PAWFE_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
   return PAWFE_OK;
 }
 
@@ -266,7 +309,7 @@ pawfe_status build(pawfe_batch* b, const pawfe_filter_job* jobs, int32_t njobs, 
 extern "C" {
 
 pawfe_status pawfe_batch_create(const pawfe_filter_job* jobs, int32_t njobs, int32_t prec, int32_t nstreams,
-                                void* stream, pawfe_batch** out) {
+                                int32_t max_graph_launches, void* stream, pawfe_batch** out) {
   if (!out) return fail(PAWFE_EINVAL, "out is NULL");
   *out = nullptr;
   if (!jobs || njobs < 1) return fail(PAWFE_EINVAL, "no jobs");
@@ -275,7 +318,8 @@ pawfe_status pawfe_batch_create(const pawfe_filter_job* jobs, int32_t njobs, int
   pawfe_batch* b = new (std::nothrow) pawfe_batch;
   if (!b) return fail(PAWFE_ENOMEM, "host allocation failed");
   b->prec = prec;
-  const pawfe_status st = build(b, jobs, njobs, nstreams, reinterpret_cast<hipStream_t>(stream));
+  const int64_t budget = max_graph_launches > 0 ? max_graph_launches : kDefaultGraphLaunches;
+  const pawfe_status st = build(b, jobs, njobs, nstreams, budget, reinterpret_cast<hipStream_t>(stream));
   if (st != PAWFE_OK) {
     release(b);
     return st;
@@ -285,14 +329,16 @@ pawfe_status pawfe_batch_create(const pawfe_filter_job* jobs, int32_t njobs, int
 }
 
 pawfe_status pawfe_batch_run(pawfe_batch* b, void* stream) {
-  if (!b || !b->exec) return fail(PAWFE_EINVAL, "batch is NULL");
-  PAWFE_HIP(hipGraphLaunch(b->exec, reinterpret_cast<hipStream_t>(stream)));
+  if (!b || b->execs.empty()) return fail(PAWFE_EINVAL, "batch is NULL");
+  for (hipGraphExec_t e : b->execs) PAWFE_HIP(hipGraphLaunch(e, reinterpret_cast<hipStream_t>(stream)));
   return PAWFE_OK;
 }
 
-pawfe_status pawfe_batch_query(const pawfe_batch* b, int32_t* nstreams, int32_t* blocks, int32_t* stream_of_job) {
+pawfe_status pawfe_batch_query(const pawfe_batch* b, int32_t* nstreams, int32_t* blocks, int32_t* stream_of_job,
+                               int32_t* ngraphs) {
   if (!b) return fail(PAWFE_EINVAL, "batch is NULL");
   if (nstreams) *nstreams = b->nstreams;
+  if (ngraphs) *ngraphs = (int32_t)b->execs.size();
   for (size_t j = 0; j < b->jobs.size(); ++j) {
     if (blocks) blocks[j] = b->block[j];
     if (stream_of_job) stream_of_job[j] = b->stream_of[j];

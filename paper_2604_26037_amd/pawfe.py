@@ -90,9 +90,9 @@ def load(path=LIB_PATH):
         "pawfe_rayleigh_ritz": [vp, vp, i64, i64, vp, vp, vp, sz, vp],
         "pawfe_band_energy_grad": [vp, vp, i64, i64, vp, vp, vp, vp, vp],
         "pawfe_lanczos_bounds": [vp, i32, C.c_uint64, P(dbl), P(dbl), P(dbl), vp],
-        "pawfe_batch_create": [P(FilterJob), i32, i32, i32, vp, P(vp)],
+        "pawfe_batch_create": [P(FilterJob), i32, i32, i32, i32, vp, P(vp)],
         "pawfe_batch_run": [vp, vp],
-        "pawfe_batch_query": [vp, P(i32), P(i32), P(i32)],
+        "pawfe_batch_query": [vp, P(i32), P(i32), P(i32), P(i32)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -352,11 +352,13 @@ class Batch:
     jobs: list of dicts with keys op (Operator), X (device FP64 [ndof][n]),
     out (same shape, may be X), lam (device FP64 [n]), degree, b0, bW, bU and
     optionally block (default: autotuned).  nstreams=None lets the library
-    pick 1, 2 or 4 streams by timing.  The tensors are kept alive by the
-    batch; run() replays the graph on the current stream.
+    pick 1, 2 or 4 streams by timing.  max_graph_launches bounds the kernel
+    launches of each captured graph (None: the library's default).  The
+    tensors are kept alive by the batch; run() replays the graphs on the
+    current stream.
     """
 
-    def __init__(self, jobs, prec=FP64, nstreams=None, stream=None):
+    def __init__(self, jobs, prec=FP64, nstreams=None, stream=None, max_graph_launches=None):
         import torch
         lib = load()
         self._jobs = []
@@ -375,6 +377,7 @@ class Batch:
                                float(j["b0"]), float(j["bW"]), float(j["bU"]))
         h = C.c_void_p()
         _check(lib.pawfe_batch_create(arr, len(jobs), _PREC[prec], 0 if nstreams is None else int(nstreams),
+                                      0 if max_graph_launches is None else int(max_graph_launches),
                                       _stream(stream), C.byref(h)))
         self._h = h
         self.njobs = len(jobs)
@@ -386,8 +389,14 @@ class Batch:
         ns = C.c_int32()
         blocks = np.zeros(self.njobs, dtype=np.int32)
         sof = np.zeros(self.njobs, dtype=np.int32)
-        _check(_lib.pawfe_batch_query(self._h, C.byref(ns), _iptr(blocks), _iptr(sof)))
+        _check(_lib.pawfe_batch_query(self._h, C.byref(ns), _iptr(blocks), _iptr(sof), None))
         return ns.value, blocks, sof
+
+    @property
+    def ngraphs(self):
+        n = C.c_int32()
+        _check(_lib.pawfe_batch_query(self._h, None, None, None, C.byref(n)))
+        return n.value
 
     def close(self):
         if getattr(self, "_h", None) and _lib is not None:

@@ -106,3 +106,34 @@ def test_batch_graph_in_place(problems):
     for j, p in zip(jobs, problems):
         assert _rel(j["X"].cpu().numpy(), p["want"]) < 1e-9
     b.close()
+
+
+def test_batch_one_graph_per_job(problems):
+    """A launch budget below any one job's filter puts every job into a graph
+    of its own; the replay (graphs in order) equals the oracle's filters and
+    replays are bit-identical."""
+    from paper_2604_26037_amd import Batch
+    jobs, keep = _jobs(problems)
+    b = Batch(jobs, nstreams=2, max_graph_launches=1)
+    assert b.ngraphs == len(jobs)
+    b.run()
+    torch.cuda.synchronize()
+    first = [j["out"].cpu().numpy() for j in jobs]
+    for got, p in zip(first, problems):
+        assert _rel(got, p["want"]) < 1e-9
+    for j in jobs:
+        j["out"].zero_()
+    b.run()
+    torch.cuda.synchronize()
+    for got, j in zip(first, jobs):
+        np.testing.assert_array_equal(j["out"].cpu().numpy(), got)
+    b.close()
+
+
+def test_batch_default_budget_one_graph(problems):
+    """Small batches stay within the default launch budget: one graph."""
+    from paper_2604_26037_amd import Batch
+    jobs, keep = _jobs(problems)
+    b = Batch(jobs, nstreams=1)
+    assert b.ngraphs == 1
+    b.close()

@@ -136,3 +136,13 @@ def test_complex_batch_matches_standalone():
     for j, w in zip(jobs, want):
         assert _rel(j["out"].cpu().numpy(), w) < 1e-12
     b.close()
+    # one graph per job
+    for j in jobs:
+        j["out"].zero_()
+    b = Batch(jobs, nstreams=2, max_graph_launches=1)
+    assert b.ngraphs == len(jobs)
+    b.run()
+    torch.cuda.synchronize()
+    for j, w in zip(jobs, want):
+        assert _rel(j["out"].cpu().numpy(), w) < 1e-12
+    b.close()

@@ -105,10 +105,10 @@ def test_null_operator_rejected():
 def test_batch_rejects_bad_jobs():
     lib = _lib()
     h = C.c_void_p()
-    assert lib.pawfe_batch_create(None, 0, 0, 1, None, C.byref(h)) == pw.PAWFE_EINVAL
+    assert lib.pawfe_batch_create(None, 0, 0, 1, 0, None, C.byref(h)) == pw.PAWFE_EINVAL
     jobs = (pw.FilterJob * 1)()
     jobs[0] = pw.FilterJob(None, 1, 4, 1, 4, 4, 0, 1, 5, -1.0, 0.0, 1.0)
-    assert lib.pawfe_batch_create(jobs, 1, 0, 1, None, C.byref(h)) == pw.PAWFE_EINVAL
+    assert lib.pawfe_batch_create(jobs, 1, 0, 1, 0, None, C.byref(h)) == pw.PAWFE_EINVAL
     assert b"op is NULL" in lib.pawfe_last_error()
-    assert lib.pawfe_batch_create(jobs, 1, 2, 1, None, C.byref(h)) == pw.PAWFE_EUNSUPPORTED
+    assert lib.pawfe_batch_create(jobs, 1, 2, 1, 0, None, C.byref(h)) == pw.PAWFE_EUNSUPPORTED
     assert h.value is None

@@ -365,12 +365,15 @@ def custom_system(ncell, box, degree, nq, pos=(), rcut=1.5, channels="spd8",
     )
 
 
-def batch_systems(count=24, seed=26037 + 4000, small=False):
+def batch_systems(count=24, seed=26037 + 4000, small=False, complex_=False):
     """Independent problems of uneven size for the batched filter: cubes of
     6-14 cells of degree-5 elements (7 Gauss points), 8-64 PAW atoms of 18
     projectors on a jittered lattice, 64-384 states (small=True: 2-4 cells
-    of degree 2-4, 0-2 atoms, 8-24 states, for parity tests).  Real
-    (Gamma-point) operators.  Seeded; no arithmetic of the method here."""
+    of degree 2-4, 0-2 atoms, 8-24 states, for parity tests).  complex_=True
+    gives complex (k-point) operators with the Bloch vector drawn per problem
+    in reduced coordinates kappa in [0, 0.5)^3, k_d = 2 pi kappa_d / L_d
+    (drawn after the problem's other inputs).  Seeded; no arithmetic of the
+    method here."""
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed)))
     out = []
     for i in range(count):
@@ -401,5 +404,9 @@ def batch_systems(count=24, seed=26037 + 4000, small=False):
             s = custom_system(n, box, degree, nq, pos=pos, rcut=1.8, channels="spd18",
                               wells=rng.uniform(0.0, 1.0, size=(4, 3)) * np.asarray(box),
                               s_H=0.9, s_S=0.45, seed=int(rng.integers(1, 2 ** 31)), nstates=nst)
+        if complex_:
+            kappa = rng.uniform(0.0, 0.5, size=3)
+            s = dataclasses.replace(s, kpoint=2.0 * np.pi * kappa / np.asarray(box, dtype=np.float64),
+                                    is_complex=True)
         out.append(s)
     return out
