@@ -205,14 +205,17 @@ struct Lanes {
   T v[V];
 };
 
+// The row kernels touch each streamed element once per launch: their loads
+// and stores carry the non-temporal hint, so the stream does not displace
+// cached data (the projector tables, the other stream's working set).
 template <int V, typename T>
 __device__ __forceinline__ Lanes<T, V> vld(const T* p) {
   Lanes<T, V> r;
   if constexpr (V == 1) {
-    r.v[0] = *p;
+    r.v[0] = __builtin_nontemporal_load(p);
   } else {
     typedef T VT __attribute__((ext_vector_type(V)));
-    const VT x = *reinterpret_cast<const VT*>(p);
+    const VT x = __builtin_nontemporal_load(reinterpret_cast<const VT*>(p));
 #pragma unroll
     for (int i = 0; i < V; ++i) r.v[i] = x[i];
   }
@@ -222,13 +225,13 @@ __device__ __forceinline__ Lanes<T, V> vld(const T* p) {
 template <int V, typename T>
 __device__ __forceinline__ void vst(T* p, const Lanes<T, V>& r) {
   if constexpr (V == 1) {
-    *p = r.v[0];
+    __builtin_nontemporal_store(r.v[0], p);
   } else {
     typedef T VT __attribute__((ext_vector_type(V)));
     VT x;
 #pragma unroll
     for (int i = 0; i < V; ++i) x[i] = r.v[i];
-    *reinterpret_cast<VT*>(p) = x;
+    __builtin_nontemporal_store(x, reinterpret_cast<VT*>(p));
   }
 }
 
@@ -433,9 +436,9 @@ __global__ void __launch_bounds__(256) k_nl_fixup(const int32_t* __restrict__ fa
 #pragma unroll
       for (int u = 0; u < kFixUnroll; ++u) I[u] = d.atom_nodes[noff + rb + u];   // list padded
 #pragma unroll
-      for (int u = 0; u < kFixUnroll; ++u) {
-        o1[u] = out1[(int64_t)I[u] * ld1 + n];
-        if constexpr (HAS2) o2[u] = out2[(int64_t)I[u] * ld2 + n];
+      for (int u = 0; u < kFixUnroll; ++u) {   // rows touched once: non-temporal
+        o1[u] = __builtin_nontemporal_load(out1 + (int64_t)I[u] * ld1 + n);
+        if constexpr (HAS2) o2[u] = __builtin_nontemporal_load(out2 + (int64_t)I[u] * ld2 + n);
       }
 #pragma unroll
       for (int u = 0; u < kFixUnroll; ++u) {
@@ -462,8 +465,8 @@ __global__ void __launch_bounds__(256) k_nl_fixup(const int32_t* __restrict__ fa
 #pragma unroll
       for (int u = 0; u < kFixUnroll; ++u) {
         if (rb + u >= r1) break;
-        out1[(int64_t)I[u] * ld1 + n] = o1[u] + (TO1)c1[u];
-        if constexpr (HAS2) out2[(int64_t)I[u] * ld2 + n] = o2[u] + c2[u];
+        __builtin_nontemporal_store(o1[u] + (TO1)c1[u], out1 + (int64_t)I[u] * ld1 + n);
+        if constexpr (HAS2) __builtin_nontemporal_store(o2[u] + c2[u], out2 + (int64_t)I[u] * ld2 + n);
       }
     }
   };
