@@ -365,6 +365,7 @@ pawfe_status upload(pawfe_op* op, hipStream_t s) {
     for (int k = 0; k < 3; ++k) t64.f[k] = 0.5 * op->detJ * (2.0 / op->h[k]) * (2.0 / op->h[k]);
     for (int k = 0; k < 3; ++k) t64.g[k] = -op->kpt[k] * op->detJ * (2.0 / op->h[k]);
     t64.detJ = op->detJ;
+    for (int q = 0; q < nq; ++q) t64.w[q] = op->gauss_w[q];
     for (int i = 0; i < kNqMax * kNpMax; ++i) t32.B[i] = (float)t64.B[i];
     for (int i = 0; i < kNpMax * kNpMax; ++i) {
       t32.K1[i] = (float)t64.K1[i];
@@ -374,6 +375,7 @@ pawfe_status upload(pawfe_op* op, hipStream_t s) {
     for (int k = 0; k < 3; ++k) t32.f[k] = (float)t64.f[k];
     for (int k = 0; k < 3; ++k) t32.g[k] = (float)t64.g[k];
     t32.detJ = (float)t64.detJ;
+    for (int q = 0; q < kNqMax; ++q) t32.w[q] = (float)t64.w[q];
     CHECK(up(op, &d.tab64, &t64, 1, s));
     CHECK(up(op, &d.tab32, &t32, 1, s));
   }

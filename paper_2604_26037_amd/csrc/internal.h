@@ -39,6 +39,7 @@ struct Tab1D {
   T f[3];
   T detJ;
   T g[3];                  // complex operators: -k_d det J (2/h_d) (imaginary local term)
+  T w[kNqMax];             // 1-D Gauss weights (W_q = w_qx w_qy w_qz detJ), zero past nq
 };
 
 // Device-resident tables of one operator.

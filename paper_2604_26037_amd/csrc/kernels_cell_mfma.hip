@@ -384,10 +384,11 @@ __device__ __forceinline__ void mfma_pass(T* smem, const Slab* in, const Slab* o
   }
 }
 
-// FP32: registers held to three waves per SIMD (the LDS of three
-// workgroups fits in a CU).
+// FP32, and the FP64 residual mode: registers held to three waves per
+// SIMD (the LDS of three workgroups fits in a CU; the residual mode forms
+// W_q from the 1-D weights instead of keeping a table of nq^3 of them).
 template <typename T, int NP, int NQ, int CB, int MODE, bool BF3>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((sizeof(T) == 4 || MODE == kModeHRes) ? 3 : 1)))
 k_cell_mfma(CellArgs<T> A, const Tab1D<T>* __restrict__ tabp,
                                                    int ncoltiles, int nitems) {
   constexpr int NL = NP * NP * NP;
@@ -398,11 +399,10 @@ k_cell_mfma(CellArgs<T> A, const Tab1D<T>* __restrict__ tabp,
   constexpr bool RES = MODE == kModeHRes;
   constexpr bool IMG = MODE == kModeImg;
   __shared__ T smem[3 * kSlots * CB];
-  // V(q) W_q of the current cell and W_q (residual mode); entry q at
-  // q + q / 64, so the 8 outputs of a result write (stride 64) differ in bank
+  // V(q) W_q of the current cell; entry q at q + q / 64, so the 8 outputs
+  // of a result write (stride 64) differ in bank
   constexpr int NQP = NQ3 + NQ3 / 64;
   __shared__ T vws[HAS_V ? NQP : 1];
-  __shared__ T w3s[RES ? NQP : 1];
   __shared__ T lams[RES ? CB : 1];            // lambda_n of the item's columns (residual mode)
   const Tab1D<T>& tab = *tabp;
   const int tid = threadIdx.x;
@@ -418,14 +418,17 @@ k_cell_mfma(CellArgs<T> A, const Tab1D<T>* __restrict__ tabp,
   constexpr bool PADT = sizeof(T) == 4;
   constexpr int NB = NQ * NP, NS = NP * (NP + 1) / 2, NKS = IMG ? NP * NP : NS;
   constexpr int tK = PADT ? 64 : NB, tM = PADT ? 128 : NB + NKS, tZ = PADT ? 192 : NB + NKS + NS;
-  constexpr int tF = PADT ? 256 : tZ + 1, NCT = tF + 4;
+  // (residual mode: the 1-D Gauss weights follow the scale factors, so that
+  // W_q = w_qx w_qy w_qz detJ needs no table of its own)
+  constexpr int tF = PADT ? 256 : tZ + 1, NCT = tF + 4 + (RES ? 8 : 0);
   const T* Kt = IMG ? tab.G1 : tab.K1;
   const T* ft = IMG ? tab.g : tab.f;
   __shared__ T ctab[NCT];
   for (int i = tid; i < NCT; i += 256) {
     T v = T(0);
     if (i >= tF) {
-      v = i - tF < 3 ? ft[i - tF] : tab.detJ;
+      const int k = i - tF;
+      v = k < 3 ? ft[k] : (k == 3 ? tab.detJ : tab.w[(k - 4) & 7]);
     } else if constexpr (PADT) {
       const int blk = i >> 6, o = (i >> 3) & 7, k = i & 7;
       if (blk == 0) v = (o < NQ && k < NP) ? tab.B[o * NP + k] : T(0);
@@ -602,8 +605,6 @@ k_cell_mfma(CellArgs<T> A, const Tab1D<T>* __restrict__ tabp,
   // the padded slots are zero once and stay zero: every pass only ever
   // writes zeros there (zero inputs, zero coefficients)
   for (int i = tid; i < 3 * kSlots * CB; i += 256) smem[i] = T(0);
-  if constexpr (RES)
-    for (int q = tid; q < NQ3; q += 256) w3s[q + q / 64] = A.W3[q];
   if (item < i_end) load_item(cur_c, cur_t);
   __syncthreads();
   if (item < i_end) stage();
@@ -712,7 +713,13 @@ k_cell_mfma(CellArgs<T> A, const Tab1D<T>* __restrict__ tabp,
           return qin(L, o) ? w : T(0);
         };
         auto vpost = [&](int L, int o, int c, T v, T, T w) {
-          if constexpr (RES) return qin(L, o) ? v * (w - lams[c] * w3s[qidx(L, o)]) : T(0);
+          if constexpr (RES) {
+            // W_q of point (qa, qb, qc) = (L & 7, L >> 3, o), multiplied in the
+            // order the host forms it (bit-identical weights)
+            const T* wq = &ctab[tF + 4];
+            const T wgt = wq[L & 7] * wq[L >> 3] * wq[o & 7] * fsc(3);
+            return qin(L, o) ? v * (w - lams[c] * wgt) : T(0);
+          }
           else return v * w;
         };
         mfma_pass<T, 2, CB, 1, 1, BF3, NQ>(smem, inB, oB, [&](int o, int k) { return Bm(o, k); }, vpost, vpre);
