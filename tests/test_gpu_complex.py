@@ -35,7 +35,7 @@ def _dev(x):
     return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
 
 
-@pytest.mark.parametrize("p", [3, 6])
+@pytest.mark.parametrize("p", [2, 3, 4, 5, 6])
 @pytest.mark.parametrize("sinv", ["exact_g", "pp"])
 def test_complex_applies(p, sinv):
     from oracle.paw import PAWOperator
@@ -71,11 +71,12 @@ def test_complex_k_zero_matches_real_operator():
     assert _rel(got, re + 1j * im) < 1e-12
 
 
-def test_complex_filter_and_rr():
+@pytest.mark.parametrize("p", [3, 5])
+def test_complex_filter_and_rr(p):
     from oracle import chfsi
     from oracle.paw import PAWOperator
     from paper_2604_26037_amd import Operator
-    s = _system(3, nst=10)
+    s = _system(p, nst=10)
     ref = PAWOperator(s)
     op = Operator(s)
     X = s.trial(10)
