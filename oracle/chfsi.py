@@ -192,3 +192,21 @@ def chfsi_iterations(op, X, niter, m, bU, block=None, apply_Sinv=None, filt=None
         Psi, lam, res = rayleigh_ritz(op, Xf)
         hist.append((lam, res))
     return Psi, lam, hist
+
+
+def chfsi_solve(op, X, m, bU, tol, max_iter, nwanted=None, block=None):
+    """Algorithm 1 run to convergence: Rayleigh-Ritz of the start, then
+    filter + Rayleigh-Ritz until the residual norms of the lowest nwanted
+    Ritz pairs (all when None) are <= tol, or max_iter filter passes have
+    run (the convergence test on the residual norms of the algorithm's
+    last step).  b_0 and b_W are the lowest and highest current Ritz values,
+    b_U is given.  Returns (Psi, lambda, resnorm, iterations)."""
+    Psi, lam, res = rayleigh_ritz(op, X)
+    nw = len(lam) if nwanted is None else int(nwanted)
+    it = 0
+    while np.max(res[:nw]) > tol and it < max_iter:
+        b0, bW = float(lam[0]), float(lam[-1])
+        Xf = rchfsi_filter(op, Psi, lam, m, b0, bW, bU, block=block)
+        Psi, lam, res = rayleigh_ritz(op, Xf)
+        it += 1
+    return Psi, lam, res, it

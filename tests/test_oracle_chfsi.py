@@ -178,3 +178,24 @@ def test_chfsi_iterations_converge(tiny):
     assert all(b < 0.5 * a for a, b in zip(errs, errs[1:]))     # monotone, fast
     assert np.all(th >= lam[:len(th)] - 1e-12)
     assert errs[-1] < 0.05
+
+
+def test_chfsi_solve_residual_bound(tiny):
+    """The convergence loop stops at the first Rayleigh-Ritz whose wanted
+    residuals are <= tol, and each converged Ritz value then lies within the
+    residual bound of the dense eigenvalue of the same index:
+    |theta_i - lambda_i| <= ||r_i||_2 / sqrt(lambda_min(S)) (S-orthonormal
+    Ritz vectors, residual measured in the S^{-1} norm)."""
+    op, H, S, lam, V = tiny
+    s = op.system
+    X = s.trial()
+    bU = float(lam[-1]) * 1.01
+    nw, tol = 8, 2e-3
+    Psi, th, res, it = chfsi.chfsi_solve(op, X, s.cheb_degree, bU, tol, 30, nwanted=nw)
+    assert 1 <= it < 30
+    assert np.max(res[:nw]) <= tol
+    smin = float(np.linalg.eigvalsh(0.5 * (S + S.conj().T))[0])
+    assert np.all(np.abs(th[:nw] - lam[:nw]) <= res[:nw] / np.sqrt(smin) * (1 + 1e-9))
+    # one pass fewer does not meet the tolerance
+    _, th1, res1, it1 = chfsi.chfsi_solve(op, X, s.cheb_degree, bU, tol, it - 1, nwanted=nw)
+    assert it1 == it - 1 and np.max(res1[:nw]) > tol
