@@ -249,6 +249,31 @@ pawfe_status pawfe_band_energy_grad(const pawfe_op* op, const void* X, int64_t l
 pawfe_status pawfe_lanczos_bounds(const pawfe_op* op, int32_t k, uint64_t seed, double* theta_min,
                                   double* theta_max, double* beta_k, void* stream);
 
+/* Bytes of workspace pawfe_chfsi_solve needs: the larger of the filter's
+ * (two block states when nvec > block) and Rayleigh-Ritz's. */
+pawfe_status pawfe_chfsi_solve_workspace(const pawfe_op* op, int64_t nvec, int32_t block, int32_t prec,
+                                         size_t* bytes);
+
+/* Algorithm 1 run to convergence (the outer ChFSI loop, with the
+ * residual-norm test of its last step): b_U = bU if bU > 0, else the
+ * Lanczos estimate theta_max + |beta_k| (pawfe_lanczos_bounds with
+ * lanczos_k steps, seed 1234); Rayleigh-Ritz of the start X; then, while
+ * the largest residual norm of the lowest nwanted Ritz pairs (all when
+ * nwanted = 0) exceeds tol and fewer than max_iter passes have run: one
+ * pawfe_cheb_filter pass in place (degree, block, prec; b_0 and b_W the
+ * lowest and highest current Ritz values, lambda_in the Ritz values) and
+ * one FP64 pawfe_rayleigh_ritz.  X device FP64 [ndof][ldx] (complex
+ * operators: complex columns), replaced by the Ritz vectors; lambda and
+ * resnorm device FP64 [nvec] (the last Rayleigh-Ritz); *iterations (host,
+ * may be NULL) receives the number of filter passes.  Not reaching tol
+ * within max_iter is not an error (check resnorm).  Needs nvec >= 2.
+ * Synchronizes the stream after every Rayleigh-Ritz (reads the residual
+ * norms). */
+pawfe_status pawfe_chfsi_solve(const pawfe_op* op, void* X, int64_t ldx, int64_t nvec, int64_t nwanted,
+                               int32_t degree, int32_t block, int32_t prec, double bU, int32_t lanczos_k,
+                               double tol, int32_t max_iter, double* lambda, double* resnorm,
+                               int32_t* iterations, void* ws, size_t ws_bytes, void* stream);
+
 /* ---- Batched filter over independent problems (HIP graph) ----------------
  *
  * Several independent problems of uneven size (different operators, column

@@ -965,4 +965,62 @@ pawfe_status pawfe_lanczos_bounds(const pawfe_op* cop, int32_t k, uint64_t seed,
   return PAWFE_OK;
 }
 
+// ---- ChFSI outer loop ----------------------------------------------------------
+
+pawfe_status pawfe_chfsi_solve_workspace(const pawfe_op* op, int64_t nvec, int32_t block, int32_t prec,
+                                         size_t* bytes) {
+  if (!op || !bytes) return fail(PAWFE_EINVAL, "op or bytes is NULL");
+  size_t f = 0, r = 0;
+  CHECK(pawfe_cheb_filter_workspace(op, nvec, block, prec, &f));
+  CHECK(pawfe_rayleigh_ritz_workspace(op, nvec, &r));
+  *bytes = std::max(f, r);   // the filter and Rayleigh-Ritz never overlap
+  return PAWFE_OK;
+}
+
+pawfe_status pawfe_chfsi_solve(const pawfe_op* op, void* X, int64_t ldx, int64_t nvec, int64_t nwanted,
+                               int32_t degree, int32_t block, int32_t prec, double bU, int32_t lanczos_k,
+                               double tol, int32_t max_iter, double* lambda, double* resnorm, int32_t* iterations,
+                               void* ws, size_t ws_bytes, void* stream) {
+  if (!op) return fail(PAWFE_EINVAL, "op is NULL");
+  if (!X || !lambda || !resnorm || !ws) return fail(PAWFE_EINVAL, "NULL buffer");
+  if (nvec < 2 || ldx < nvec) return fail(PAWFE_EINVAL, "need nvec >= 2 and ldx >= nvec");
+  if (nwanted < 0 || nwanted > nvec) return fail(PAWFE_EINVAL, "nwanted must be in 0..nvec");
+  if (degree < 2 || block < 1 || max_iter < 0) return fail(PAWFE_EINVAL, "degree >= 2, block >= 1, max_iter >= 0");
+  if (!(std::isfinite(tol) && tol > 0.0) || !std::isfinite(bU)) return fail(PAWFE_EINVAL, "tol must be > 0, bU finite");
+  CHECK(check_prec(prec));
+  size_t need = 0;
+  CHECK(pawfe_chfsi_solve_workspace(op, nvec, block, prec, &need));
+  if (ws_bytes < need) return fail(PAWFE_EINVAL, "workspace too small");
+  const int64_t nw = nwanted > 0 ? nwanted : nvec;
+  // step 1 of Algorithm 1: the upper bound of the spectrum (given, or Lanczos)
+  if (!(bU > 0.0)) {
+    double tmin = 0.0, tmax = 0.0, beta = 0.0;
+    CHECK(pawfe_lanczos_bounds(op, lanczos_k, 1234, &tmin, &tmax, &beta, stream));
+    bU = tmax + beta;
+  }
+  std::vector<double> lh(nvec), rh(nvec);
+  auto fetch = [&]() -> pawfe_status {
+    hipStream_t s = S(stream);
+    PAWFE_HIP(hipMemcpyAsync(lh.data(), lambda, nvec * 8, hipMemcpyDeviceToHost, s));
+    PAWFE_HIP(hipMemcpyAsync(rh.data(), resnorm, nvec * 8, hipMemcpyDeviceToHost, s));
+    PAWFE_HIP(hipStreamSynchronize(s));
+    return PAWFE_OK;
+  };
+  auto worst = [&]() { return *std::max_element(rh.begin(), rh.begin() + nw); };
+  CHECK(pawfe_rayleigh_ritz(op, X, ldx, nvec, lambda, resnorm, ws, ws_bytes, stream));
+  CHECK(fetch());
+  int32_t it = 0;
+  while (worst() > tol && it < max_iter) {
+    // b_0, b_W: lowest and highest current Ritz values (lambda stays the
+    // filter's eigenvalue estimate; the filter runs in place)
+    CHECK(pawfe_cheb_filter(op, X, ldx, X, ldx, nvec, block, lambda, degree, lh.front(), lh.back(), bU, prec, ws,
+                            ws_bytes, stream));
+    CHECK(pawfe_rayleigh_ritz(op, X, ldx, nvec, lambda, resnorm, ws, ws_bytes, stream));
+    CHECK(fetch());
+    ++it;
+  }
+  if (iterations) *iterations = it;
+  return PAWFE_OK;
+}
+
 }  // extern "C"

@@ -29,6 +29,7 @@ EXPORTS = [
     "pawfe_apply_local",
     "pawfe_cheb_filter_workspace", "pawfe_cheb_filter", "pawfe_rayleigh_ritz_workspace",
     "pawfe_rayleigh_ritz", "pawfe_band_energy_grad", "pawfe_lanczos_bounds", "pawfe_last_error",
+    "pawfe_chfsi_solve_workspace", "pawfe_chfsi_solve",
     "pawfe_batch_create", "pawfe_batch_run", "pawfe_batch_query", "pawfe_batch_destroy",
 ]
 
@@ -90,6 +91,8 @@ def load(path=LIB_PATH):
         "pawfe_rayleigh_ritz": [vp, vp, i64, i64, vp, vp, vp, sz, vp],
         "pawfe_band_energy_grad": [vp, vp, i64, i64, vp, vp, vp, vp, vp],
         "pawfe_lanczos_bounds": [vp, i32, C.c_uint64, P(dbl), P(dbl), P(dbl), vp],
+        "pawfe_chfsi_solve_workspace": [vp, i64, i32, i32, P(sz)],
+        "pawfe_chfsi_solve": [vp, vp, i64, i64, i64, i32, i32, i32, dbl, i32, dbl, i32, vp, vp, P(i32), vp, sz, vp],
         "pawfe_batch_create": [P(FilterJob), i32, i32, i32, i32, vp, P(vp)],
         "pawfe_batch_run": [vp, vp],
         "pawfe_batch_query": [vp, P(i32), P(i32), P(i32), P(i32)],
@@ -311,6 +314,28 @@ class Operator:
         _check(_lib.pawfe_lanczos_bounds(self._h, int(k), C.c_uint64(seed), C.byref(a), C.byref(b),
                                          C.byref(c), _stream(stream)))
         return a.value, b.value, c.value
+
+    def chfsi_solve(self, X, degree, tol, max_iter, nwanted=None, block=None, prec=FP64, bU=None,
+                    lanczos_k=20, ws=None, stream=None):
+        """Filter + Rayleigh-Ritz in place on X until the lowest nwanted
+        residual norms are <= tol (pawfe_chfsi_solve).  Returns (lambda,
+        resnorm, iterations); lambda and resnorm are device tensors."""
+        import torch
+        assert X.is_cuda and X.dtype == self._dtype(FP64) and X.stride(1) == 1
+        n = X.shape[1]
+        block = n if block is None else int(block)
+        lam = torch.empty(n, dtype=torch.float64, device=X.device)
+        res = torch.empty(n, dtype=torch.float64, device=X.device)
+        if ws is None:
+            b = C.c_size_t()
+            _check(_lib.pawfe_chfsi_solve_workspace(self._h, n, block, _PREC[prec], C.byref(b)))
+            ws = self.workspace(b.value, X.device)
+        it = C.c_int32()
+        _check(_lib.pawfe_chfsi_solve(self._h, _tptr(X), X.stride(0), n, 0 if nwanted is None else int(nwanted),
+                                      int(degree), block, _PREC[prec], 0.0 if bU is None else float(bU),
+                                      int(lanczos_k), float(tol), int(max_iter), _tptr(lam), _tptr(res),
+                                      C.byref(it), _tptr(ws), ws.numel(), _stream(stream)))
+        return lam, res, it.value
 
 
 def band_energy_function():

@@ -99,6 +99,8 @@ def test_null_operator_rejected():
     a = C.c_double()
     assert lib.pawfe_lanczos_bounds(None, 10, 1, C.byref(a), C.byref(a), C.byref(a), None) \
         == pw.PAWFE_EINVAL
+    assert lib.pawfe_chfsi_solve(None, x, 4, 4, 0, 10, 4, 0, 0.0, 20, 1e-6, 10, x, x, None, x, 1, None) \
+        == pw.PAWFE_EINVAL
     assert lib.pawfe_destroy_operator(None) == pw.PAWFE_OK
 
 
