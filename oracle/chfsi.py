@@ -122,10 +122,14 @@ def cheb_filter_spectral(H, S, X, m, b0, bW, bU, eig=None):
     return V @ (f[:, None] * (V.conj().T @ (S @ X)))
 
 
-def rayleigh_ritz(op, X):
+def rayleigh_ritz(op, X, mixed_sr=False):
     """Algorithm 1 steps 4-6 plus the residual norms (FP64).
 
     Returns (Psi, lambda ascending, resnorm) with Psi^H S Psi = I.
+    mixed_sr: the subspace rotation in mixed precision (the paper's RR-SR
+    strategy): Psi = X diag(Q) in FP64 plus X Q_off with Q_off = Q with a
+    zero diagonal, X and Q_off rounded to FP32 and the product formed in
+    FP32; the residual norms are then those of the rotated Psi.
     """
     HX = op.apply_H(X)
     SX = op.apply_S(X)
@@ -134,9 +138,22 @@ def rayleigh_ritz(op, X):
     Hp = 0.5 * (Hp + Hp.conj().T)
     Sp = 0.5 * (Sp + Sp.conj().T)
     lam, Q = sla.eigh(Hp, Sp)
-    Psi = X @ Q
-    R = HX @ Q - (SX @ Q) * lam[None, :]
-    return Psi, lam, np.linalg.norm(R, axis=0)
+    if not mixed_sr:
+        Psi = X @ Q
+        R = HX @ Q - (SX @ Q) * lam[None, :]
+        return Psi, lam, np.linalg.norm(R, axis=0)
+    Psi = mixed_rotation(X, Q)
+    return Psi, lam, residual_norms(op, Psi, lam)
+
+
+def mixed_rotation(X, Q):
+    """X Q as X diag(Q) (FP64) + fl32(fl32(X) fl32(Q_off)), Q_off = Q - diag(Q)."""
+    d = np.diag(Q)
+    Qoff = Q - np.diag(d)
+    out = np.result_type(X.dtype, Q.dtype)
+    f32 = np.complex64 if np.iscomplexobj(np.zeros(0, out)) else np.float32
+    off = (X.astype(f32) @ Qoff.astype(f32)).astype(out)
+    return X * d[None, :] + off
 
 
 def residual_norms(op, Psi, lam):

@@ -199,3 +199,28 @@ def test_chfsi_solve_residual_bound(tiny):
     # one pass fewer does not meet the tolerance
     _, th1, res1, it1 = chfsi.chfsi_solve(op, X, s.cheb_degree, bU, tol, it - 1, nwanted=nw)
     assert it1 == it - 1 and np.max(res1[:nw]) > tol
+
+
+def test_mixed_rotation_pins(tiny):
+    """Mixed-precision subspace rotation: exact for a diagonal Q; otherwise
+    within the FP32 rounding bound of the off-diagonal product, elementwise
+    |Psi_mixed - X Q| <= 2 (N + 2) u32 |X| |Q_off| (u32 = 2^-24); the Ritz
+    values do not depend on it."""
+    op, H, S, lam, V = tiny
+    s = op.system
+    rng = np.random.Generator(np.random.PCG64(11))
+    X = s.trial()
+    N = X.shape[1]
+    Dq = np.diag(rng.uniform(0.5, 2.0, N))
+    np.testing.assert_array_equal(chfsi.mixed_rotation(X, Dq), X * np.diag(Dq)[None, :])
+    Q = Dq + 1e-2 * rng.standard_normal((N, N))
+    Qoff = Q - np.diag(np.diag(Q))
+    err = np.abs(chfsi.mixed_rotation(X, Q) - X @ Q)
+    bound = 2 * (N + 2) * 2.0 ** -24 * (np.abs(X) @ np.abs(Qoff))
+    assert np.all(err <= bound + 1e-300)
+    assert err.max() > 0                                   # FP32 did round
+    P1, l1, r1 = chfsi.rayleigh_ritz(op, X)
+    P2, l2, r2 = chfsi.rayleigh_ritz(op, X, mixed_sr=True)
+    np.testing.assert_array_equal(l1, l2)
+    assert np.abs(P2 - P1).max() <= 1e-5 * np.abs(P1).max()
+    np.testing.assert_allclose(r2, r1, rtol=1e-3, atol=1e-5 * np.abs(r1).max())
