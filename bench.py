@@ -293,6 +293,21 @@ def main():
     t_filter = float(np.mean([a.elapsed_time(b) for a, b, _ in ev])) / 1e3
     t_rr = float(np.mean([b.elapsed_time(c) for _, b, c in ev])) / 1e3
 
+    # --- Rayleigh-Ritz with the mixed-precision subspace rotation, same input ---
+    Xm = X.clone()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    lam_m, res_m = op.rayleigh_ritz(Xm, ws=ws_r, sr_prec=FP32)
+    e1.record()
+    Xd64 = X.clone()
+    lam_d, res_d = op.rayleigh_ritz(Xd64, ws=ws_r)
+    torch.cuda.synchronize()
+    t_rr_mixed = e0.elapsed_time(e1) / 1e3
+    sr_res_change = float(((res_m[:nw] - res_d[:nw]).abs() / res_d[:nw]).max().item())
+    del Xm, Xd64
+    log(f"Rayleigh-Ritz with mixed-precision rotation {t_rr_mixed:.3f} s (FP64 rotation {t_rr:.3f} s); "
+        f"wanted residual norms change by at most {sr_res_change:.2e} (relative)")
+
     # --- FP64 filter pass timing (same work) ---
     t_filter64 = None
     if not args.skip_fp64:
@@ -390,6 +405,8 @@ def main():
         "filter_bf16x3_s_per_pass": t_filter_bf3,
         "speedup_mixed_vs_fp64": (t_filter64 / t_filter) if t_filter64 else None,
         "rayleigh_ritz_s": t_rr,
+        "rayleigh_ritz_mixed_rotation_s": t_rr_mixed,
+        "mixed_rotation_resnorm_rel_change": sr_res_change,
         "eig_err_mixed_vs_fp64_ha": eig_err,
         "hx": hx,
         "roofline": roof,

@@ -222,12 +222,17 @@ pawfe_status pawfe_rayleigh_ritz_workspace(const pawfe_op* op, int64_t nvec, siz
  * eigen-residual check).  X device FP64 [ndof][ldx]; lambda (ascending)
  * and resnorm: device FP64 [nvec].  Returns PAWFE_ENOTSPD if S^p is not
  * positive definite. Synchronizes the stream (it reads the solver status).
+ * sr_prec: PAWFE_FP64 (the rotation as one FP64 GEMM) or PAWFE_FP32 (the
+ * mixed-precision subspace rotation of the Rayleigh-Ritz subsection:
+ * X diag(Q) in FP64 plus fl32(X) fl32(Q_off) as an FP32 GEMM, Q_off = Q with
+ * its diagonal -- the complex diagonal entries -- set to zero; the residual
+ * norms are those of the rotated vectors).
  * Complex operators: X holds nvec complex columns; the projected problem is
  * complex Hermitian (H^p, S^p and Q complex), lambda and resnorm stay real,
  * one entry per complex column. */
 pawfe_status pawfe_rayleigh_ritz(const pawfe_op* op, void* X, int64_t ldx, int64_t nvec,
-                                 double* lambda, double* resnorm, void* ws, size_t ws_bytes,
-                                 void* stream);
+                                 double* lambda, double* resnorm, int32_t sr_prec, void* ws,
+                                 size_t ws_bytes, void* stream);
 
 /* Band energy E = sum_n occ_n x_n^H H x_n and its gradient (the density and
  * projector contractions of the FE governing equations):

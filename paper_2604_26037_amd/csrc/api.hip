@@ -309,6 +309,44 @@ __global__ void k_pair_norm(int N, const double* __restrict__ sq, double* __rest
   if (j < N) out[j] = sqrt(sq[2 * j] + sq[2 * j + 1]);
 }
 
+// Mixed-precision subspace rotation, preparation: X32 = fl32(X) (row-major,
+// ld N) and Q32 = fl32(Q) with the diagonal blocks (1x1, or the 2x2 blocks
+// of a complex entry in the realified form) set to zero (column-major, ld N).
+__global__ void k_sr_prep(int64_t M, int N, int bs, const double* __restrict__ X, int64_t ldx,
+                          float* __restrict__ X32, const double* __restrict__ Q, float* __restrict__ Q32) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nx = M * N;
+  if (t < nx) {
+    const int64_t i = t / N;
+    const int j = (int)(t - i * N);
+    X32[t] = (float)X[i * ldx + j];
+  } else if (t < nx + (int64_t)N * N) {
+    const int64_t u = t - nx;
+    const int c = (int)(u / N), r = (int)(u - (int64_t)c * N);
+    Q32[u] = (r / bs == c / bs) ? 0.0f : (float)Q[u];
+  }
+}
+
+// X <- X diag(Q) + Y32 (FP64), diag(Q) the diagonal blocks of Q (column-major,
+// ld N); one thread per row and diagonal block, so the in-place update reads
+// the block's inputs before it writes.
+__global__ void k_sr_combine(int64_t M, int N, int bs, double* __restrict__ X, int64_t ldx,
+                             const float* __restrict__ Y32, const double* __restrict__ Q) {
+  const int nb = N / bs;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= M * nb) return;
+  const int64_t i = t / nb;
+  const int j0 = (int)(t - i * nb) * bs;
+  double x[2], o[2];
+  for (int r = 0; r < bs; ++r) x[r] = X[i * ldx + j0 + r];
+  for (int c = 0; c < bs; ++c) {
+    double v = (double)Y32[i * N + j0 + c];
+    for (int r = 0; r < bs; ++r) v += x[r] * Q[(int64_t)(j0 + c) * N + j0 + r];
+    o[c] = v;
+  }
+  for (int c = 0; c < bs; ++c) X[i * ldx + j0 + c] = o[c];
+}
+
 // P[i*ldp + j0 + j] = sum_b part[b][j + i*nc] (split-K partials of a block column)
 __global__ void k_part_reduce(const double* __restrict__ part, int nb, int nc, int N, double* __restrict__ P,
                               int64_t ldp, int64_t j0) {
@@ -718,11 +756,12 @@ pawfe_status pawfe_rayleigh_ritz_workspace(const pawfe_op* op, int64_t nvec, siz
 }
 
 pawfe_status pawfe_rayleigh_ritz(const pawfe_op* cop, void* Xv, int64_t ldx, int64_t N, double* lambda,
-                                 double* resnorm, void* ws, size_t ws_bytes, void* stream) {
+                                 double* resnorm, int32_t sr_prec, void* ws, size_t ws_bytes, void* stream) {
   if (!cop) return fail(PAWFE_EINVAL, "op is NULL");
   if (!Xv || !lambda || !resnorm || !ws) return fail(PAWFE_EINVAL, "NULL buffer");
   if (N < 1 || ldx < N) return fail(PAWFE_EINVAL, "bad nvec / ldx");
   if (N > 65536) return fail(PAWFE_EUNSUPPORTED, "nvec too large for the dense projected problem");
+  if (sr_prec != PAWFE_FP64 && sr_prec != PAWFE_FP32) return fail(PAWFE_EINVAL, "sr_prec must be FP64 or FP32");
   if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(PAWFE_EINVAL, "workspace must be 256-byte aligned");
   if (ws_bytes < rr_ws_bytes(cop, N)) return fail(PAWFE_EINVAL, "workspace too small");
   pawfe_op* op = const_cast<pawfe_op*>(cop);
@@ -820,15 +859,35 @@ pawfe_status pawfe_rayleigh_ritz(const pawfe_op* cop, void* Xv, int64_t ldx, int
   if (hinfo > Nc) return fail(PAWFE_ENOTSPD, "projected overlap S^p is not positive definite");
   if (hinfo > 0) return fail(PAWFE_ENONFINITE, "projected eigensolver did not converge");
   // rotation X <- X Q (Q column-major in Hp; real form for complex operators)
-  {
+  if (sr_prec == PAWFE_FP32) {
+    // mixed precision (the paper's RR-SR strategy): X diag(Q) in FP64 plus
+    // fl32(X) fl32(Q_off) on the FP32 matrix cores; X32 and Y32 share the
+    // rotated-copy buffer, Q32 the overlap buffer (free after the solve)
+    const int bs = op->cplx ? 2 : 1;
+    float* X32 = reinterpret_cast<float*>(Xr);
+    float* Y32 = X32 + (size_t)K * N;
+    float* Q32 = reinterpret_cast<float*>(Sp);
+    const int64_t nprep = K * N + N * N;
+    hipLaunchKernelGGL(k_sr_prep, dim3((unsigned)((nprep + 255) / 256)), dim3(256), 0, s, K, (int)N, bs, X, ldx,
+                       X32, Hp, Q32);
+    const float onef = 1.0f, zerof = 0.0f;
+    if (rocblas_sgemm(h, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)N, (rocblas_int)K,
+                      (rocblas_int)N, &onef, Q32, (rocblas_int)N, X32, (rocblas_int)N, &zerof, Y32,
+                      (rocblas_int)N) != rocblas_status_success)
+      return fail(PAWFE_EHIP, "rocblas_sgemm (rotation) failed");
+    const int64_t ncomb = K * (N / bs);
+    hipLaunchKernelGGL(k_sr_combine, dim3((unsigned)((ncomb + 255) / 256)), dim3(256), 0, s, K, (int)N, bs, X, ldx,
+                       Y32, Hp);
+    PAWFE_HIP(hipGetLastError());
+  } else {
     // Xr = X Q: column-major, Xr^T (N x K) = Q^T (N x N) X^T (N x K)
     const double one = 1.0, zero = 0.0;
     if (rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)N, (rocblas_int)K,
                       (rocblas_int)N, &one, Hp, (rocblas_int)N, X, (rocblas_int)ldx, &zero, Xr,
                       (rocblas_int)N) != rocblas_status_success)
       return fail(PAWFE_EHIP, "rocblas_dgemm (rotation) failed");
+    CHECK(launch_copy_cols(Xr, N, X, ldx, op->M, (int)N, s));
   }
-  CHECK(launch_copy_cols(Xr, N, X, ldx, op->M, (int)N, s));
   // residual norms ||H x - lambda S x||_2 (complex: over both parts)
   double* sq = op->cplx ? lam2 + N : nullptr;
   for (int64_t j0 = 0; j0 < N; j0 += B) {
@@ -1007,7 +1066,7 @@ pawfe_status pawfe_chfsi_solve(const pawfe_op* op, void* X, int64_t ldx, int64_t
     return PAWFE_OK;
   };
   auto worst = [&]() { return *std::max_element(rh.begin(), rh.begin() + nw); };
-  CHECK(pawfe_rayleigh_ritz(op, X, ldx, nvec, lambda, resnorm, ws, ws_bytes, stream));
+  CHECK(pawfe_rayleigh_ritz(op, X, ldx, nvec, lambda, resnorm, PAWFE_FP64, ws, ws_bytes, stream));
   CHECK(fetch());
   int32_t it = 0;
   while (worst() > tol && it < max_iter) {
@@ -1015,7 +1074,7 @@ pawfe_status pawfe_chfsi_solve(const pawfe_op* op, void* X, int64_t ldx, int64_t
     // filter's eigenvalue estimate; the filter runs in place)
     CHECK(pawfe_cheb_filter(op, X, ldx, X, ldx, nvec, block, lambda, degree, lh.front(), lh.back(), bU, prec, ws,
                             ws_bytes, stream));
-    CHECK(pawfe_rayleigh_ritz(op, X, ldx, nvec, lambda, resnorm, ws, ws_bytes, stream));
+    CHECK(pawfe_rayleigh_ritz(op, X, ldx, nvec, lambda, resnorm, PAWFE_FP64, ws, ws_bytes, stream));
     CHECK(fetch());
     ++it;
   }

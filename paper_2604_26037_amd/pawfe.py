@@ -88,7 +88,7 @@ def load(path=LIB_PATH):
         "pawfe_cheb_filter_workspace": [vp, i64, i32, i32, P(sz)],
         "pawfe_cheb_filter": [vp, vp, i64, vp, i64, i64, i32, vp, i32, dbl, dbl, dbl, i32, vp, sz, vp],
         "pawfe_rayleigh_ritz_workspace": [vp, i64, P(sz)],
-        "pawfe_rayleigh_ritz": [vp, vp, i64, i64, vp, vp, vp, sz, vp],
+        "pawfe_rayleigh_ritz": [vp, vp, i64, i64, vp, vp, i32, vp, sz, vp],
         "pawfe_band_energy_grad": [vp, vp, i64, i64, vp, vp, vp, vp, vp],
         "pawfe_lanczos_bounds": [vp, i32, C.c_uint64, P(dbl), P(dbl), P(dbl), vp],
         "pawfe_chfsi_solve_workspace": [vp, i64, i32, i32, P(sz)],
@@ -283,8 +283,9 @@ class Operator:
         _check(_lib.pawfe_rayleigh_ritz_workspace(self._h, nvec, C.byref(b)))
         return b.value
 
-    def rayleigh_ritz(self, X, ws=None, stream=None):
-        """In place on X; returns (lambda, resnorm) as device tensors."""
+    def rayleigh_ritz(self, X, ws=None, stream=None, sr_prec=FP64):
+        """In place on X; returns (lambda, resnorm) as device tensors.
+        sr_prec=FP32: mixed-precision subspace rotation."""
         import torch
         assert X.is_cuda and X.dtype == self._dtype(FP64) and X.stride(1) == 1
         n = X.shape[1]
@@ -293,7 +294,7 @@ class Operator:
         if ws is None:
             ws = self.workspace(self.rayleigh_ritz_workspace(n), X.device)
         _check(_lib.pawfe_rayleigh_ritz(self._h, _tptr(X), X.stride(0), n, _tptr(lam), _tptr(res),
-                                        _tptr(ws), ws.numel(), _stream(stream)))
+                                        _PREC[sr_prec], _tptr(ws), ws.numel(), _stream(stream)))
         return lam, res
 
     def band_energy_grad(self, X, occ=None, want_E=True, want_dV=True, want_dH=True, stream=None):

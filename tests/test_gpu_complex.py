@@ -101,6 +101,28 @@ def test_complex_filter_and_rr(p):
     assert _rel(got32, want) < 1e-4
 
 
+def test_complex_mixed_rotation():
+    """Mixed-precision subspace rotation of a complex operator: the FP64 part
+    is the complex diagonal of Q; vectors against the oracle's up to a unit
+    phase per column."""
+    from oracle import chfsi
+    from oracle.paw import PAWOperator
+    from paper_2604_26037_amd import Operator
+    s = _system(3, nst=10)
+    ref = PAWOperator(s)
+    op = Operator(s)
+    X = s.trial(10)
+    P_o, lam_o, res_o = chfsi.rayleigh_ritz(ref, X, mixed_sr=True)
+    Xd = _dev(X)
+    lam, res = op.rayleigh_ritz(Xd, sr_prec=1)
+    lam, res, P = lam.cpu().numpy(), res.cpu().numpy(), Xd.cpu().numpy()
+    assert np.abs(lam - lam_o).max() < 1e-10 * max(1.0, np.abs(lam_o).max())
+    ph = np.einsum("ij,ij->j", P.conj(), P_o)
+    ph = ph / np.abs(ph)
+    assert np.abs(P * ph[None, :] - P_o).max() <= 1e-5 * np.abs(P_o).max()
+    np.testing.assert_allclose(res, res_o, rtol=1e-3, atol=1e-6 * np.abs(res_o).max())
+
+
 def test_complex_lanczos_bounds():
     from oracle import chfsi
     from oracle.paw import PAWOperator

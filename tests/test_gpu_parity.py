@@ -135,6 +135,29 @@ def test_rayleigh_ritz_fp64(systems):
     np.testing.assert_allclose(Psi.T @ ref.apply_S(Psi), np.eye(16), atol=1e-10)
 
 
+@pytest.mark.parametrize("name,n", [("tiny", 16), ("mid", 40)])
+def test_rayleigh_ritz_mixed_rotation(systems, name, n):
+    """Mixed-precision subspace rotation (FP64 diagonal of Q, FP32 off-diagonal
+    GEMM) against the oracle's: the same Ritz values as FP64, the rotated
+    vectors within the FP32 rounding of the off-diagonal part (up to the sign
+    of each eigenvector), the residual norms of the rotated vectors."""
+    from oracle import chfsi
+    s, ref, op = systems[name]
+    X = s.trial(n)
+    P_o, lam_o, res_o = chfsi.rayleigh_ritz(ref, X, mixed_sr=True)
+    Xd = _to(X)
+    lam, res = op.rayleigh_ritz(Xd, sr_prec=1)
+    lam, res, P = lam.cpu().numpy(), res.cpu().numpy(), Xd.cpu().numpy()
+    assert np.abs(lam - lam_o).max() < 1e-10 * max(1.0, np.abs(lam_o).max())
+    sg = np.sign(np.einsum("ij,ij->j", P, P_o))
+    assert np.abs(P * sg[None, :] - P_o).max() <= 1e-5 * np.abs(P_o).max()
+    np.testing.assert_allclose(res, res_o, rtol=1e-3, atol=1e-6 * np.abs(res_o).max())
+    # not the FP64 rotation: the off-diagonal part was rounded
+    Xe = _to(X)
+    op.rayleigh_ritz(Xe)
+    assert np.abs(Xe.cpu().numpy() * sg[None, :] - P * sg[None, :]).max() > 0
+
+
 def test_chfsi_iterations_fp64_vs_oracle_and_dense(systems):
     """Config 'tiny': RR of the start, then 3 x (filter degree 20 + RR), all on the GPU."""
     from oracle import chfsi

@@ -94,7 +94,7 @@ def test_null_operator_rejected():
     assert lib.pawfe_rayleigh_ritz_workspace(None, 4, C.byref(b)) == pw.PAWFE_EINVAL
     assert lib.pawfe_cheb_filter(None, x, 4, x, 4, 4, 4, None, 10, 0.0, 1.0, 2.0, 0, x, 1, None) \
         == pw.PAWFE_EINVAL
-    assert lib.pawfe_rayleigh_ritz(None, x, 4, 4, x, x, x, 1, None) == pw.PAWFE_EINVAL
+    assert lib.pawfe_rayleigh_ritz(None, x, 4, 4, x, x, 0, x, 1, None) == pw.PAWFE_EINVAL
     assert lib.pawfe_band_energy_grad(None, x, 4, 4, None, None, None, None, None) == pw.PAWFE_EINVAL
     a = C.c_double()
     assert lib.pawfe_lanczos_bounds(None, 10, 1, C.byref(a), C.byref(a), C.byref(a), None) \
