@@ -70,9 +70,11 @@ struct Carve {
   bool ok() const { return off <= cap; }
 };
 
-// Scratch of one apply over `ncols` columns: partial sums, c, d/q, t.
+// Scratch of one apply over `ncols` columns: partial sums, c, d/q, t (each at
+// least one row, as carve_nl takes them, also for an operator without atoms).
 size_t nl_scratch_bytes(const pawfe_op* op, int64_t ncols) {
-  return align256((size_t)op->item_rows_total * ncols * 8) + 3 * align256((size_t)op->npj_total * ncols * 8) + 256;
+  return align256((size_t)std::max<int64_t>(op->item_rows_total, 1) * ncols * 8) +
+         3 * align256((size_t)std::max(op->npj_total, 1) * ncols * 8) + 256;
 }
 
 pawfe_status ensure_scratch(pawfe_op* op, size_t bytes) {
@@ -156,6 +158,7 @@ pawfe_status apply_entry(const pawfe_op* cop, int which, const void* X, int64_t 
   CHECK(ensure_scratch(op, nl_scratch_bytes(op, cmax)));
   Carve cv(op->scratch, op->scratch_bytes);
   NlBufs b = carve_nl(op, cv, cmax);
+  if (!cv.ok()) return fail(PAWFE_EINVAL, "internal: apply scratch smaller than its carve");
   hipStream_t s = S(stream);
   for (int64_t j0 = 0; j0 < nvec; j0 += chunk) {
     const int nc = (int)std::min<int64_t>(chunk, nvec - j0);
@@ -192,6 +195,7 @@ pawfe_status filter_block(const pawfe_op* op, const double* X, int64_t ldx, doub
   NlBufs nb = carve_nl(op, cv, B);
   double* lamX = cv.take<double>(B);
   double* lamY = cv.take<double>(B);
+  if (!cv.ok()) return fail(PAWFE_EINVAL, "internal: filter workspace smaller than its carve");
   const int64_t ld = nc;   // block-local leading dimension
   // step 1 (Algorithm 2): polynomial scalars
   const double e = (bU - bW) / 2.0, c = (bU + bW) / 2.0;
@@ -785,6 +789,7 @@ pawfe_status pawfe_rayleigh_ritz(const pawfe_op* cop, void* Xv, int64_t ldx, int
   rocblas_int* info = cv.take<rocblas_int>(1);
   double* npart_buf = cv.take<double>((size_t)((op->M + 4095) / 4096) * B);
   NlBufs nb = carve_nl(op, cv, B);
+  if (!cv.ok()) return fail(PAWFE_EINVAL, "internal: Rayleigh-Ritz workspace smaller than its carve");
   if (!op->blas) {
     rocblas_handle h;
     if (rocblas_create_handle(&h) != rocblas_status_success) return fail(PAWFE_EHIP, "rocblas_create_handle failed");
@@ -922,6 +927,7 @@ pawfe_status pawfe_band_energy_grad(const pawfe_op* cop, const void* Xv, int64_t
   NlBufs nb = carve_nl(op, cv, std::max<int64_t>(N, B));
   double* HXb = cv.take<double>((size_t)op->M * B);
   double* pbuf = cv.take<double>((size_t)nchunks * B);
+  if (!cv.ok()) return fail(PAWFE_EINVAL, "internal: gradient scratch smaller than its carve");
   if (E) {
     CHECK(launch_fill<double>(E, 1, 0.0, s));
     for (int64_t j0 = 0; j0 < N; j0 += B) {
@@ -962,6 +968,7 @@ pawfe_status pawfe_lanczos_bounds(const pawfe_op* cop, int32_t k, uint64_t seed,
   double* u = cv.take<double>(M);
   double* pbuf = cv.take<double>(nchunks);
   double* dot = cv.take<double>(2);
+  if (!cv.ok()) return fail(PAWFE_EINVAL, "internal: Lanczos scratch smaller than its carve");
   // seeded start vector (splitmix64 -> uniform(-1, 1)), generated on the host
   std::vector<double> h(M);
   uint64_t st = seed;

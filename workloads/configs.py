@@ -49,7 +49,7 @@ class ConfigSpec:
     lattice_a: float
     jitter: float
     rcut: float
-    channels: str           # "spd8" (8 channels, one radial) or "spd18"
+    channels: str           # "spd8" (8 channels, one radial), "spd18", "spd27", "max32"
     wells: str              # "random2" or "per_atom"
     nstates: int
     block: int
@@ -183,6 +183,17 @@ def _channels(kind, rcut):
             for sig in (rcut / 3.0, rcut / 5.0):
                 for m in range(-l, l + 1):
                     ch.append((l, m, sig))
+        return ch
+    if kind in ("spd27", "max32"):
+        # (s, p, d) x three radial widths; "max32" adds d at a fourth width
+        # (32 channels, the most the library takes per atom)
+        ch = []
+        for l in range(3):
+            for sig in (rcut / 3.0, rcut / 4.0, rcut / 5.0):
+                for m in range(-l, l + 1):
+                    ch.append((l, m, sig))
+        if kind == "max32":
+            ch += [(2, m, rcut / 6.0) for m in range(-2, 3)]
         return ch
     raise ValueError(kind)
 
