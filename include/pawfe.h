@@ -242,7 +242,8 @@ pawfe_status pawfe_rayleigh_ritz(const pawfe_op* op, void* X, int64_t ldx, int64
  * X device FP64; occ device FP64 [nvec] or NULL (all ones); E device FP64
  * scalar; dE_dVq device [E*nq^3]; dE_dDH device [sum nproj^2].  Any output
  * may be NULL.  Nothing cell-local is stored between cell batches.
- * Real operators only: a complex operator gives PAWFE_EUNSUPPORTED. */
+ * Complex operators: X holds complex columns; E = sum_n occ_n x_n^H H x_n,
+ * the density sums |u_n|^2, and dE_dDH = Re sum_n occ_n conj(P_n) P_n^T. */
 pawfe_status pawfe_band_energy_grad(const pawfe_op* op, const void* X, int64_t ldx, int64_t nvec,
                                     const double* occ, double* E, double* dE_dVq, double* dE_dDH,
                                     void* stream);

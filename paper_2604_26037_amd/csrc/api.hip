@@ -914,20 +914,32 @@ pawfe_status pawfe_band_energy_grad(const pawfe_op* cop, const void* Xv, int64_t
                                     double* E, double* dE_dVq, double* dE_dDH, void* stream) {
   if (!cop) return fail(PAWFE_EINVAL, "op is NULL");
   if (!Xv || N < 1 || ldx < N) return fail(PAWFE_EINVAL, "bad X / nvec / ldx");
-  if (cop->cplx) return fail(PAWFE_EUNSUPPORTED, "band_energy_grad: real (Gamma-point) operators only");
   pawfe_op* op = const_cast<pawfe_op*>(cop);
   hipStream_t s = S(stream);
   const double* X = (const double*)Xv;
+  // complex operators: the (re, im) real view; x^H H x, |u|^2 and
+  // Re(conj(P_a) P_b) are then the real formulas summed over both columns of
+  // a pair, each with the pair's occupation
+  const int64_t Nc = N;
+  if (op->cplx) {
+    N *= 2;
+    ldx *= 2;
+  }
   const int64_t B = std::min<int64_t>(256, N);
   const int64_t nchunks = (op->M + 4095) / 4096;
   size_t need = nl_scratch_bytes(op, std::max<int64_t>(N, B)) + align256((size_t)op->M * B * 8) +
-                align256((size_t)nchunks * B * 8) + 1024;
+                align256((size_t)nchunks * B * 8) + align256((size_t)N * 8) + 1024;
   CHECK(ensure_scratch(op, need));
   Carve cv(op->scratch, op->scratch_bytes);
   NlBufs nb = carve_nl(op, cv, std::max<int64_t>(N, B));
   double* HXb = cv.take<double>((size_t)op->M * B);
   double* pbuf = cv.take<double>((size_t)nchunks * B);
+  double* occ2 = cv.take<double>((size_t)N);
   if (!cv.ok()) return fail(PAWFE_EINVAL, "internal: gradient scratch smaller than its carve");
+  if (op->cplx && occ) {
+    CHECK(launch_dup_pairs(occ, occ2, (int)Nc, s));
+    occ = occ2;
+  }
   if (E) {
     CHECK(launch_fill<double>(E, 1, 0.0, s));
     for (int64_t j0 = 0; j0 < N; j0 += B) {

@@ -299,7 +299,7 @@ class Operator:
 
     def band_energy_grad(self, X, occ=None, want_E=True, want_dV=True, want_dH=True, stream=None):
         import torch
-        assert X.is_cuda and X.dtype == torch.float64 and X.stride(1) == 1
+        assert X.is_cuda and X.dtype == self._dtype(FP64) and X.stride(1) == 1
         dev = X.device
         E = torch.zeros(1, dtype=torch.float64, device=dev) if want_E else None
         dV = torch.empty(self.nquad, dtype=torch.float64, device=dev) if want_dV else None

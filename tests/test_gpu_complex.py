@@ -123,6 +123,23 @@ def test_complex_mixed_rotation():
     np.testing.assert_allclose(res, res_o, rtol=1e-3, atol=1e-6 * np.abs(res_o).max())
 
 
+def test_complex_band_energy_gradient():
+    """E = sum occ x^H H x, dE/dV(q) and dE/dDelta_H of a complex operator
+    against the oracle's (the real part of the Hermitian projector form)."""
+    from oracle import grad
+    from oracle.paw import PAWOperator
+    from paper_2604_26037_amd import Operator
+    s = _system(3, nst=6)
+    ref = PAWOperator(s)
+    op = Operator(s)
+    X = s.trial(6)
+    occ = np.linspace(2.0, 0.5, 6)
+    E, dV, dD = op.band_energy_grad(_dev(X), occ=torch.from_numpy(occ))
+    assert abs(float(E.cpu()[0]) - grad.band_energy(ref, X, occ)) < 1e-10 * abs(grad.band_energy(ref, X, occ))
+    assert _rel(dV.cpu().numpy().ravel(), grad.grad_veff(ref, X, occ).ravel()) < 1e-10
+    assert _rel(dD.cpu().numpy(), grad.grad_dH(ref, X, occ)) < 1e-10
+
+
 def test_complex_lanczos_bounds():
     from oracle import chfsi
     from oracle.paw import PAWOperator
