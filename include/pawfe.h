@@ -57,7 +57,7 @@ enum {
   PAWFE_EHIP = 3,          /* a HIP runtime call failed */
   PAWFE_ENOTSPD = 4,       /* I + G Delta_S singular, or S^p not positive definite */
   PAWFE_ENONFINITE = 5,    /* NaN / Inf met where a finite value is required */
-  PAWFE_EUNSUPPORTED = 6   /* valid request this build does not implement */
+  PAWFE_EUNSUPPORTED = 6   /* valid request the library does not implement */
 };
 
 /* Arithmetic of the filter's recurrence part (mixed-precision paragraph of

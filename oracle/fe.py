@@ -12,7 +12,7 @@ Everything is computed from its definition: basis values by the Lagrange
 product formula, element matrices by summing over all 3-D quadrature points
 (no sum factorization), global matrices by scipy.sparse assembly.
 
-Conventions (not fixed by the paper; chosen for this build):
+Conventions (not fixed by the paper; chosen here):
   cell e = i + nx*(j + ny*k), origin (i*hx, j*hy, k*hz)
   local node l = a + np*(b + np*c), (a, b, c) in [0, p]^3, a along x
   periodic DOF I = gx + Gx*(gy + Gy*gz), gx = (i*p + a) mod (nx*p)
