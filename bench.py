@@ -265,6 +265,8 @@ def main():
                     help="kernels: only the cell-local operator and a calibration copy (for counters); "
                          "batch: the graph-captured filter of 24 uneven problems")
     ap.add_argument("--batch-count", type=int, default=24)
+    ap.add_argument("--one-stream", action="store_true",
+                    help="filter blocks one after another on one stream (no two blocks in flight)")
     ap.add_argument("--complex", action="store_true",
                     help="time the filter of the workload as a complex (k-point) operator instead")
     args = ap.parse_args()
@@ -305,7 +307,9 @@ def main():
     bU = tmax + beta
     log(f"Lanczos: theta in [{tmin:.4f}, {tmax:.4f}], |beta_k| = {beta:.3e}, b_U = {bU:.4f}")
 
-    ws_f = op.workspace(max(op.cheb_filter_workspace(N, B, FP64), op.cheb_filter_workspace(N, B, FP32)))
+    # a workspace of one block state keeps the filter on one stream
+    nws = B if args.one_stream else N
+    ws_f = op.workspace(max(op.cheb_filter_workspace(nws, B, FP64), op.cheb_filter_workspace(nws, B, FP32)))
     ws_r = op.workspace(op.rayleigh_ritz_workspace(N))
     lam, res = op.rayleigh_ritz(X, ws=ws_r)
     torch.cuda.synchronize()
@@ -457,6 +461,7 @@ def main():
                         f"{s.degree} ({M} DOFs), nq={s.nq}, {len(s.pos)} atoms x {int(s.nproj[0])} "
                         f"projectors, N={N}, block={B}, Chebyshev degree {m}",
             "step": "mixed filter pass over all states + FP64 Rayleigh-Ritz + residual norms",
+            "filter_streams": 1 if args.one_stream else 2,
         },
         "filter_fp64_s_per_pass": t_filter64,
         "filter_bf16x3_s_per_pass": t_filter_bf3,
