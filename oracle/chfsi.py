@@ -12,6 +12,10 @@
   the residual norms ||H psi_i - lambda_i S psi_i||_2 of the residual check.
 * ``lanczos_bounds`` is a k-step Lanczos on H Sinv_hat in the Sinv_hat inner
   product, giving the upper bound b_U = theta_max + |beta_k|.
+* ``chfsi_solve`` repeats filter + Rayleigh-Ritz until the wanted residual
+  norms meet a tolerance (the residual check of Algorithm 1).
+* ``mixed_rotation`` is the mixed-precision subspace rotation of the
+  Rayleigh-Ritz subsection (FP64 diagonal of Q, FP32 off-diagonal product).
 """
 
 from __future__ import annotations
