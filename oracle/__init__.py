@@ -16,12 +16,14 @@ Modules
   paw     projectors, projector matrix C^a, PAW H/S, approximate inverse
           overlap (FE non-local contribution; Sinv approximation)
   chfsi   Algorithm 1 steps 2-6 and Algorithm 2 (residual-based filter),
-          the standard scaled Chebyshev filter, Rayleigh-Ritz, residual norms,
-          k-step Lanczos bounds
+          the standard scaled Chebyshev filter, Rayleigh-Ritz (also with the
+          mixed-precision subspace rotation), residual norms, k-step Lanczos
+          bounds, the outer loop to a residual tolerance
   grad    band energy E = sum_n x_n^H H x_n and its gradient with respect to
           V_eff at quadrature points and Delta_H
-  mixed   FP32 / bf16x3 emulation of the mixed-precision filter
 
-Parity unpinned: the mixed-precision emulation (``mixed``) has no closed form;
-it is checked only through eigenvalues after an FP64 Rayleigh-Ritz.
+Every function is pinned by tests/test_oracle_*.py.  The oracle has no
+emulation of the FP32 / bf16x3 filter: the library's mixed paths are
+checked against the FP64 oracle directly (filter output within the FP32
+error, eigenvalues after an FP64 Rayleigh-Ritz within 1e-6 Ha).
 """
