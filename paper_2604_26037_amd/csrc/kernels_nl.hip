@@ -197,7 +197,7 @@ __global__ void __launch_bounds__(256) k_atom_gcorr(const double* __restrict__ c
 // coefficients of the atoms in that slab stay in its L2.  The host takes
 // V = 1 when a leading dimension, a base pointer or the column count does
 // not allow 16-byte accesses.
-constexpr int kRowsPerWave = 2;
+constexpr int kRowsPerWave = 4;
 constexpr int kPersistBlocks = 2048;
 
 template <typename T, int V>
