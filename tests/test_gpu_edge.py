@@ -78,3 +78,28 @@ def test_zero_columns_leave_outputs_untouched():
     assert lib.pawfe_apply_local(op._h, 0, X.data_ptr(), 4, Y.data_ptr(), 4, 0, 1.0, 0, None) == 0
     torch.cuda.synchronize()
     assert bool((Y == 7.0).all())
+
+
+def test_more_columns_than_one_chunk():
+    """Applies over 600 columns (the entry points work in chunks of 512) and
+    Rayleigh-Ritz over 300 (projections in blocks of 256), both with a ragged
+    last piece, against the oracle."""
+    from oracle import chfsi
+    from oracle.paw import PAWOperator
+    from paper_2604_26037_amd import Operator
+    from workloads import make_system
+    s = make_system("tiny")
+    ref = PAWOperator(s)
+    op = Operator(s)
+    X = s.trial(600)
+    Xd = _dev(X)
+    for which in ("H", "S", "Sinv"):
+        got = getattr(op, "apply_" + which)(Xd).cpu().numpy()
+        assert _rel(got, getattr(ref, "apply_" + which)(X)) < 1e-10, which
+    X3 = np.ascontiguousarray(X[:, :300])
+    _, lam_o, res_o = chfsi.rayleigh_ritz(ref, X3)
+    X3d = _dev(X3)
+    lam, res = op.rayleigh_ritz(X3d)
+    lam, res = lam.cpu().numpy(), res.cpu().numpy()
+    assert np.abs(lam - lam_o).max() < 1e-9 * max(1.0, np.abs(lam_o).max())
+    np.testing.assert_allclose(res, res_o, rtol=1e-6, atol=1e-9 * np.abs(res_o).max())
