@@ -105,7 +105,7 @@ enum { PAWFE_SINV_EXACT_G = 0, PAWFE_SINV_PP = 1 };
  *            argument of a complex operator is complex: (re, im) pairs of
  *            doubles (or floats at PAWFE_FP32), and ld and nvec count
  *            complex entries.  Any other value: PAWFE_EINVAL.
- * Supported (degree, nq): (2,4) (3,5) (4,6) (5,7) (6,8); each n_d >= 2. */
+ * Supported (degree, nq): (2,4) (3,5) (4,6) (5,7) (6,8); 2 <= n_d <= 1024. */
 typedef struct {
   int32_t ncell[3];
   double box[3];

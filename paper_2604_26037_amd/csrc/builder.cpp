@@ -231,6 +231,8 @@ pawfe_status build_host(const pawfe_op_desc* d, pawfe_op* op) {
   if (!d) return fail(PAWFE_EINVAL, "desc is NULL");
   for (int k = 0; k < 3; ++k) {
     if (d->ncell[k] < 2) return fail(PAWFE_EINVAL, "each ncell must be >= 2 (periodic mesh)");
+    // the cell kernel packs a cell's coordinates into 10 bits each
+    if (d->ncell[k] > 1024) return fail(PAWFE_EINVAL, "each ncell must be <= 1024");
     if (!(d->box[k] > 0.0) || !std::isfinite(d->box[k])) return fail(PAWFE_EINVAL, "box lengths must be positive");
   }
   const int p = d->degree, nq = d->nq1d;

@@ -60,6 +60,7 @@ def _desc(s, **over):
 
 @pytest.mark.parametrize("over,code", [
     (dict(ncell=[1, 4, 4]), pw.PAWFE_EINVAL),
+    (dict(ncell=[4, 1025, 4]), pw.PAWFE_EINVAL),
     (dict(degree=7, nq=9), pw.PAWFE_EUNSUPPORTED),
     (dict(degree=4, nq=5), pw.PAWFE_EUNSUPPORTED),
     (dict(is_complex=2), pw.PAWFE_EINVAL),
