@@ -68,7 +68,7 @@ __global__ void __launch_bounds__(256) k_nl_reduce(const T* __restrict__ X, int6
       T x[kUnroll], m[kUnroll];
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
-        x[u] = X[(int64_t)I[u] * ldx + nc];
+        x[u] = __builtin_nontemporal_load(X + (int64_t)I[u] * ldx + nc);
         if constexpr (SCALE) m[u] = Minv[I[u]];
       }
 #pragma unroll
