@@ -230,7 +230,14 @@ def element_potential(cq: CellQuadrature, vq_e):
 
 
 def element_kterm(cq: CellQuadrature, k):
-    """1/2 |k|^2 M^e_IJ - i sum_q W_q N_I (k . grad N_J)  (complex, eq. hij)."""
+    """1/2 |k|^2 M^e_IJ - i sum_q W_q N_I (k . grad N_J)  (complex).
+
+    The Galerkin matrix of the k terms of eq. "PAW Hamiltonian" acting on the
+    periodic part u of psi = e^{ik.x} u.  Eq. "FEM Ham entries" prints this term
+    with the gradient on N_I, which assembles to the opposite sign; the form here
+    is the one consistent with the e^{-ik.x} phase of C^a (eq. "FEM Cmatrix"),
+    pinned by the symmetric-form identity and the k -> k+G gauge check.
+    """
     k = np.asarray(k, dtype=np.float64)
     G = sum(k[d] * (cq.N.T @ (cq.W[:, None] * cq.dN[d])) for d in range(3))
     return 0.5 * float(k @ k) * element_mass(cq) - 1j * G

@@ -152,3 +152,49 @@ def test_sinv_two_atoms_is_approximate(tiny):
         assert 1e-12 < err < 0.5
     else:
         assert err < 1e-12
+
+
+def test_kterm_is_symmetric_bloch_form():
+    """The k-dependent local operator of eq. "PAW Hamiltonian", -1/2 lap - i k.grad + 1/2|k|^2,
+    is 1/2 (-i grad + k)^2, whose Galerkin matrix is the symmetric form
+    1/2 sum_q W (grad N_I + i k N_I)^* . (grad N_J + i k N_J).  Element by element it
+    differs from the oracle's K + 1/2|k|^2 M - i N_I (k.grad N_J) by i/2 k.grad(N_I N_J),
+    which integrates to zero over the periodic mesh (the Gauss rule is exact for it),
+    so the assembled matrices agree to rounding.  A flipped k-term sign fails this."""
+    k = np.array([0.37, -0.21, 0.13])
+    s = custom_system((3, 2, 3), (4.5, 3.2, 3.9), 3, 5, kpoint=k, is_complex=True)
+    op = PAWOperator(s)
+    cq = op.cq
+    Z = (cq.dN + 1j * k[:, None, None] * cq.N[None]).astype(np.complex128)   # (3, nq^3, nloc)
+    Ae = 0.5 * sum(Z[d].conj().T @ (cq.W[:, None] * Z[d]) for d in range(3))
+    sym = op.loc._assemble(lambda e: Ae).toarray()
+    ref = op.loc._assemble(lambda e: op.loc.Ke + op.loc.KTe).toarray()
+    assert np.abs(ref.imag).max() > 1e-2                 # the k term is really there
+    assert np.abs(sym - ref).max() < 1e-12 * np.abs(ref).max()
+    # element-wise the two forms differ (only the assembly removes the difference)
+    assert np.abs(Ae - (op.loc.Ke + op.loc.KTe)).max() > 1e-3
+
+
+def _lowest_bloch(L, nc, p, k, nev=8):
+    R = (0.45 * L, 0.55 * L, 0.5 * L)
+    s = custom_system((nc,) * 3, (L,) * 3, p, p + 2, pos=[R], rcut=1.8, channels="spd8",
+                      wells=[R], s_H=2.0, s_S=1.0, kpoint=k, is_complex=True)
+    op = PAWOperator(s)
+    return sla.eigh(op.H_dense(), op.S_dense(), eigvals_only=True, subset_by_index=[0, nev - 1])
+
+
+def test_bloch_gauge_k_plus_reciprocal_vector():
+    """k and k + G (G a reciprocal lattice vector) describe the same Bloch states
+    (u_{k+G} = e^{-iG.x} u_k), so with an atom present the lowest eigenvalues agree up to
+    the discretization error, which shrinks under p-refinement.  The k-term of the local
+    operator and the phase e^{-ik.x} of C^a (eq. "FEM Cmatrix") must carry consistent
+    signs for this: flipping either one leaves a k-dependent mismatch of ~3e-2 Ha here
+    that does not shrink (measured on modified copies of the oracle)."""
+    L = 5.0
+    k = np.array([0.3, -0.2, 0.15])
+    G = np.array([2.0 * np.pi / L, 0.0, 0.0])
+    diffs = []
+    for p in (4, 5):
+        diffs.append(np.abs(_lowest_bloch(L, 3, p, k) - _lowest_bloch(L, 3, p, k + G)).max())
+    assert diffs[1] < 2e-3, diffs
+    assert diffs[1] < 0.2 * diffs[0], diffs
