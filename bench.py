@@ -77,32 +77,62 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(system, nstates, degree, ncols=8):
-    """The oracle as it stands, on a bounded sample: one H and one Sinv_hat
-    apply on `ncols` columns of the same operator, extrapolated to a filter
-    pass (nstates/ncols blocks x degree steps, each step one H + one Sinv)."""
+def host_info():
+    """Host cores, CPU model and the BLAS library NumPy calls (with its threads)."""
+    import platform
     import threadpoolctl
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas = [i for i in threadpoolctl.threadpool_info() if i.get("user_api") == "blas"]
+    return {
+        "os_cpu_count": os.cpu_count(),
+        "cpu_model": model,
+        "blas": ", ".join(f"{i.get('internal_api')} ({os.path.basename(i.get('filepath', ''))}, "
+                          f"{i.get('num_threads')} threads)" for i in blas) or "none found",
+        "blas_threads": max([int(i.get("num_threads", 1)) for i in blas] + [1]),
+    }
 
+
+def cpu_baseline(system, nstates, degree, ncols=16):
+    """The oracle as it stands, on a bounded sample of the same workload:
+    apply_H, apply_S and apply_Sinv on `ncols` columns, and Algorithm 2 with
+    degree 2 on the same columns (initial residual, one Chebyshev step,
+    finalize).  A filter pass is extrapolated as nstates/ncols such blocks,
+    each the degree-2 filter plus (degree - 2) further steps of one H and one
+    Sinv apply."""
+    from oracle import chfsi
     from oracle.paw import PAWOperator
+    info = host_info()
     t0 = time.time()
     ref = PAWOperator(system)
     t_build = time.time() - t0
     X = system.trial(ncols)
+    tm = {}
+    for name in ("H", "S", "Sinv"):
+        t0 = time.perf_counter()
+        getattr(ref, "apply_" + name)(X)
+        tm[name] = time.perf_counter() - t0
+    lam = np.linspace(-0.5, 0.5, ncols)
     t0 = time.perf_counter()
-    ref.apply_H(X)
-    t_h = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    ref.apply_Sinv(X)
-    t_s = time.perf_counter() - t0
-    step = t_h + t_s
-    per_pass = (nstates / ncols) * degree * step
-    info = threadpoolctl.threadpool_info()
-    cores = max([i.get("num_threads", 1) for i in info] + [1])
+    chfsi.rchfsi_filter(ref, X, lam, 2, -1.0, 1.0, 300.0)
+    tm["filter_m2"] = time.perf_counter() - t0
+    step = tm["H"] + tm["Sinv"]
+    per_pass = (nstates / ncols) * (tm["filter_m2"] + (degree - 2) * step)
     return {
-        "value": per_pass, "unit": "s/pass (extrapolated)", "cores": int(cores), "kind": "oracle",
-        "sample": f"apply_H + apply_Sinv on {ncols} of {nstates} columns of the same operator "
-                  f"(H {t_h:.2f} s, Sinv {t_s:.2f} s), x{nstates // ncols} column blocks x{degree} "
-                  f"steps; oracle build {t_build:.1f} s not counted",
+        "value": per_pass, "unit": "s/pass (extrapolated)", "cores": int(info["blas_threads"]),
+        "kind": "oracle",
+        "sample": f"oracle on {ncols} of {nstates} columns of the same operator: apply_H {tm['H']:.2f} s, "
+                  f"apply_S {tm['S']:.2f} s, apply_Sinv {tm['Sinv']:.2f} s, Algorithm 2 with degree 2 "
+                  f"{tm['filter_m2']:.2f} s; pass = {nstates // ncols} blocks x (degree-2 filter + "
+                  f"{degree - 2} x (H + Sinv)); oracle build {t_build:.1f} s not counted",
+        "host": info,
     }
 
 
@@ -320,19 +350,33 @@ def main():
         return op.cheb_filter(Xc, lamc, m, float(lc[0]), float(lc[-1]), bU, block=B, prec=prec,
                               out=Xc, ws=ws_f)
 
-    # --- precision check: one ChFSI iteration FP64 vs mixed from the same start ---
-    Xa = X.clone()
-    filt(Xa, lam, FP64)
-    lam64, res64 = op.rayleigh_ritz(Xa, ws=ws_r)
-    del Xa
-    Xb = X.clone()
-    filt(Xb, lam, FP32)
-    lam32, res32 = op.rayleigh_ritz(Xb, ws=ws_r)
-    del Xb
+    # --- precision check: three ChFSI iterations (filter + FP64 Rayleigh-Ritz)
+    # in FP64, FP32 and bf16x3 from the same Rayleigh-Ritz start; per
+    # iteration the largest wanted-eigenvalue deviation from the FP64
+    # trajectory and the largest wanted residual norm of each ---
     nw = int(np.ceil(N / 1.2))
-    eig_err = float((lam32[:nw] - lam64[:nw]).abs().max().item())
-    log(f"mixed vs FP64 wanted-eigenvalue error after FP64 RR: {eig_err:.3e} Ha "
-        f"(max residual {res32[:nw].max().item():.3e})")
+    traj = {}
+    for name, prec in (("fp64", FP64), ("fp32", FP32), ("bf16x3", BF16X3)):
+        Xp, lp = X.clone(), lam.clone()
+        rows = []
+        for it in range(3):
+            filt(Xp, lp, prec)
+            lp, rp = op.rayleigh_ritz(Xp, ws=ws_r)
+            rows.append((lp[:nw].clone(), float(rp[:nw].max().item())))
+        traj[name] = rows
+        del Xp
+    precision = {}
+    for name in ("fp32", "bf16x3"):
+        precision[name] = [
+            {"iteration": it + 1,
+             "eig_err_vs_fp64_ha": float((traj[name][it][0] - traj["fp64"][it][0]).abs().max().item()),
+             "max_wanted_resnorm": traj[name][it][1],
+             "max_wanted_resnorm_fp64": traj["fp64"][it][1]} for it in range(3)]
+        log(f"{name} vs FP64 over 3 iterations: eigenvalue error "
+            + ", ".join(f"{r['eig_err_vs_fp64_ha']:.2e}" for r in precision[name])
+            + " Ha; max wanted residual " + ", ".join(f"{r['max_wanted_resnorm']:.2e}" for r in precision[name]))
+    eig_err = max(r["eig_err_vs_fp64_ha"] for r in precision["fp32"])
+    del traj
 
     # --- warmup and timed steps: mixed filter pass + FP64 RR ---
     for _ in range(args.warmup):
@@ -417,13 +461,37 @@ def main():
         t_h = e1.elapsed_time(e2) / 1e3 / args.hx_reps
         esz = 8 if prec == FP64 else 4
         loc_bytes = (3.0 * M * B + op.nquad) * esz      # read X, read+write Y, V(q)W
+        # algorithmic HBM bytes of apply_H: read X, write Y, read the support
+        # rows of every atom for C^T X, the V(q)W table and the C^a values
+        hx_bytes = ((2.0 * M + float(np.sum(supp_nodes))) * B + op.nquad
+                    + float(np.sum(supp_nodes * np.asarray(s.nproj)))) * esz
         hx[name] = dict(t_local=t_loc, t_apply_H=t_h,
                         hx_gflops=(nloc_flops + nl_flops) * B / t_h / 1e9,
                         local_tflops=nloc_flops * B / t_loc / 1e12,
-                        local_bytes=loc_bytes)
-        log(f"HX {name}: apply_H {t_h * 1e3:.2f} ms ({hx[name]['hx_gflops']:.0f} GFLOP/s), "
+                        local_bytes=loc_bytes,
+                        hx_bytes=hx_bytes,
+                        hx_gbs=hx_bytes / t_h / 1e9,
+                        hx_hbm_frac=hx_bytes / t_h / 1e9 / PEAK_HBM_GBS)
+        log(f"HX {name}: apply_H {t_h * 1e3:.2f} ms ({hx[name]['hx_gflops']:.0f} GFLOP/s, "
+            f"{hx[name]['hx_gbs']:.0f} GB/s = {100 * hx[name]['hx_hbm_frac']:.1f} % of HBM), "
             f"local {t_loc * 1e3:.2f} ms ({hx[name]['local_tflops']:.2f} TFLOP/s)")
         del Xs, Ys
+
+    # --- band-energy gradient (differentiation workload): 512 states ---
+    ng = min(512, N)
+    Xg = X[:, :ng].contiguous()
+    op.band_energy_grad(Xg)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3):
+        Eg, dVg, dDg = op.band_energy_grad(Xg)
+    e1.record()
+    torch.cuda.synchronize()
+    grad_info = {"states": ng, "s_per_call": e0.elapsed_time(e1) / 3 / 1e3,
+                 "outputs": f"E, dE/dV at {op.nquad} quadrature points, dE/dDelta_H ({int(dDg.numel())} entries)"}
+    log(f"band-energy gradient on {ng} states: {grad_info['s_per_call'] * 1e3:.1f} ms per call")
+    del Xg, Eg, dVg, dDg
 
     # roofline of the dominant kernel: the cell-local operator on the matrix
     # cores (FP32 MFMA), one colour (1/8 of the cells) x 256 columns per launch;
@@ -470,6 +538,8 @@ def main():
         "rayleigh_ritz_mixed_rotation_s": t_rr_mixed,
         "mixed_rotation_resnorm_rel_change": sr_res_change,
         "eig_err_mixed_vs_fp64_ha": eig_err,
+        "precision_3_iterations": precision,
+        "band_energy_grad": grad_info,
         "hx": hx,
         "roofline": roof,
     }

@@ -25,11 +25,13 @@ def band_energy(op, X, occ=None):
     return float(np.real(np.einsum("in,in,n->", X.conj(), HX, occ)))
 
 
-def grad_veff(op, X, occ=None):
-    """dE/dV at every quadrature point, shape (E, nq^3)."""
+def grad_veff(op, X, occ=None, cells=None):
+    """dE/dV at every quadrature point, shape (E, nq^3); with ``cells`` only at
+    the points of those cells, shape (len(cells), nq^3)."""
     occ = np.ones(X.shape[1]) if occ is None else np.asarray(occ, dtype=np.float64)
     cq = op.cq
-    Xe = X[op.cell_dofs]                                   # (E, nloc, ncol)
+    cd = op.cell_dofs if cells is None else op.cell_dofs[np.asarray(cells)]
+    Xe = X[cd]                                             # (ncells, nloc, ncol)
     U = cq.N @ Xe                                          # (E, nq^3, ncol)
     dens = np.einsum("eqn,eqn,n->eq", U.conj(), U, occ).real
     return cq.W[None, :] * dens

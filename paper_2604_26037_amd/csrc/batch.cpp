@@ -223,30 +223,36 @@ pawfe_status build(pawfe_batch* b, const pawfe_filter_job* jobs, int32_t njobs, 
         if (c <= J.nvec) cand.push_back(c);
       if (J.nvec < 256 && (cand.empty() || cand.back() != J.nvec)) cand.push_back((int32_t)J.nvec);
     }
+    // One block state per job: the batch's own streams provide the overlap,
+    // so every filter of a job keeps all its blocks on the job's stream.
+    // Each filter call (timed candidates and the captured one) is handed
+    // exactly the bytes of one state of its own block size, which is below
+    // two states of that size, so the filter never forks blocks onto the
+    // operator's internal streams inside a batch.  The allocation holds the
+    // largest candidate's state.
+    std::vector<size_t> wc(cand.size(), 0);
     size_t wmax = 0;
-    for (int32_t c : cand) {
-      size_t w = 0;
-      // one block state: the batch's own streams provide the overlap, the
-      // filter then keeps every block of a job on the job's stream
-      CHECK(pawfe_cheb_filter_workspace(J.op, std::min<int64_t>(J.nvec, c), c, b->prec, &w));
-      wmax = std::max(wmax, w);
+    for (size_t i = 0; i < cand.size(); ++i) {
+      CHECK(pawfe_cheb_filter_workspace(J.op, std::min<int64_t>(J.nvec, cand[i]), cand[i], b->prec, &wc[i]));
+      wmax = std::max(wmax, wc[i]);
     }
     if (hipMalloc(&b->ws[j], wmax) != hipSuccess) return fail(PAWFE_ENOMEM, "batch workspace allocation failed");
-    b->ws_bytes[j] = wmax;
     if (cand.size() == 1) {
       b->block[j] = cand[0];
+      b->ws_bytes[j] = wc[0];
       float ms = 0.f;
-      CHECK(time_filter(J, cand[0], 2, b->prec, b->ws[j], wmax, tmp[j], s, &ms));
+      CHECK(time_filter(J, cand[0], 2, b->prec, b->ws[j], wc[0], tmp[j], s, &ms));
       cost[j] = (double)ms * (J.degree + 1) / 3.0;
       continue;
     }
     float best = 0.f;
-    for (int32_t c : cand) {
+    for (size_t i = 0; i < cand.size(); ++i) {
       float ms = 0.f;
-      CHECK(time_filter(J, c, 3, b->prec, b->ws[j], wmax, tmp[j], s, &ms));
+      CHECK(time_filter(J, cand[i], 3, b->prec, b->ws[j], wc[i], tmp[j], s, &ms));
       if (b->block[j] == 0 || ms < best) {
         best = ms;
-        b->block[j] = c;
+        b->block[j] = cand[i];
+        b->ws_bytes[j] = wc[i];
       }
     }
     // degree-3 time -> degree-m estimate (two applies at set-up, one per theta)

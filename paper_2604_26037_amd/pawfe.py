@@ -343,13 +343,17 @@ def band_energy_function():
     """torch.autograd.Function for E = sum_n occ_n x_n^T H[V, Delta_H] x_n.
 
     Forward and backward both call pawfe_band_energy_grad; nothing is cached
-    between them except the inputs themselves.
+    between them except the inputs themselves.  For real operators the
+    gradient with respect to X is 2 H X diag(occ) (H is symmetric), one
+    pawfe_apply_H; for complex operators X must not require a gradient.
     """
     import torch
 
     class BandEnergy(torch.autograd.Function):
         @staticmethod
         def forward(ctx, X, veff_q, dH, op, occ=None):
+            if X.requires_grad and op.complex:
+                raise NotImplementedError("dE/dX is provided for real operators only; detach X")
             op.set_veff(veff_q.detach().cpu().numpy())
             op.set_dH(dH.detach().cpu().numpy())
             E, _, _ = op.band_energy_grad(X, occ, want_E=True, want_dV=False, want_dH=False)
@@ -367,7 +371,13 @@ def band_energy_function():
             _, dV, dD = ctx.op.band_energy_grad(X, ctx.occ, want_E=False, want_dV=True, want_dH=True)
             gv = (g * dV).view(ctx.vshape).to(ctx.vdev)
             gd = (g * dD).to(ctx.ddev)
-            return None, gv, gd, None, None
+            gx = None
+            if ctx.needs_input_grad[0]:
+                Xc = X.detach().contiguous()
+                HX = ctx.op.apply_H(Xc)
+                w = 2.0 * g if ctx.occ is None else 2.0 * g * ctx.occ.to(device=HX.device, dtype=HX.dtype)
+                gx = HX * w
+            return gx, gv, gd, None, None
 
     return BandEnergy
 

@@ -137,3 +137,63 @@ def test_batch_default_budget_one_graph(problems):
     b = Batch(jobs, nstreams=1)
     assert b.ngraphs == 1
     b.close()
+
+
+@pytest.fixture(scope="module")
+def wide_problems():
+    """Jobs of 64, 128 and 192 states, so the autotuner times several block
+    sizes per job (64, 128, then the job's own width)."""
+    from oracle import chfsi
+    from oracle.paw import PAWOperator
+    from paper_2604_26037_amd import Operator
+    from workloads.configs import custom_system
+    specs = [((3, 3, 3), 3, 64, [(1.1, 2.0, 0.7)]), ((3, 3, 3), 4, 128, [(2.0, 1.0, 2.6)]),
+             ((4, 3, 3), 4, 192, [(1.0, 1.2, 1.3), (3.9, 2.6, 2.4)])]
+    out = []
+    for i, (n, p, nst, pos) in enumerate(specs):
+        box = tuple(1.25 * v for v in n)
+        s = custom_system(n, box, p, p + 2, pos=pos, rcut=1.0, channels="spd8",
+                          wells=[(0.5, 0.5, 0.5), (2.0, 2.5, 1.0)], s_H=0.5, s_S=0.4, seed=40 + i,
+                          nstates=nst)
+        ref = PAWOperator(s)
+        op = Operator(s)
+        X = s.trial(nst)
+        Psi, lam, _ = chfsi.rayleigh_ritz(ref, X)
+        t0, t1, beta = chfsi.lanczos_bounds(ref, k=20)
+        bU = 1.02 * max(t1 + abs(beta), float(lam[-1])) + 1.0
+        m = 4 + i
+        b0, bW = float(lam[0]), float(lam[-1])
+        want = chfsi.rchfsi_filter(ref, Psi, lam, m, b0, bW, bU, block=nst)
+        out.append(dict(s=s, ref=ref, op=op, Psi=Psi, lam=lam, m=m, b0=b0, bW=bW, bU=bU, want=want))
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batch_autotuned_several_block_candidates(wide_problems, prec):
+    """Jobs with 64 or more states: the autotuner times several block sizes on
+    one job workspace, and each filter of the batch gets one block state of its
+    own block size, so it keeps all blocks on the job's stream.  Every job's
+    result matches the oracle's filter (FP64 1e-9, FP32 1e-4) on the first
+    replay and bit-identically on the next."""
+    from paper_2604_26037_amd import FP32, FP64, Batch
+    jobs, keep = _jobs(wide_problems)
+    b = Batch(jobs, prec=FP64 if prec == "fp64" else FP32)
+    ns, blocks, sof = b.schedule()
+    for j, p in enumerate(wide_problems):
+        n = p["s"].nstates
+        assert int(blocks[j]) in {c for c in (64, 128, 256) if c <= n} | {n}
+    tol = 1e-9 if prec == "fp64" else 1e-4
+    for rep in range(2):
+        for j in jobs:
+            j["out"].zero_()
+        b.run()
+        torch.cuda.synchronize()
+        got = [j["out"].cpu().numpy() for j in jobs]
+        if rep == 0:
+            first = got
+            for g, p in zip(got, wide_problems):
+                assert _rel(g, p["want"]) < tol
+        else:
+            for g, f in zip(got, first):
+                np.testing.assert_array_equal(g, f)
+    b.close()

@@ -240,6 +240,28 @@ def test_band_energy_autograd_fd(systems):
     op.set_dH(s.dH)
 
 
+def test_band_energy_autograd_dX(systems):
+    """The X gradient of the band energy (2 H X diag(occ)) through torch.autograd
+    against central differences along a random direction (E is quadratic in X,
+    so the central difference is exact up to rounding)."""
+    from paper_2604_26037_amd import band_energy_function
+    s, ref, op = systems["tiny"]
+    BE = band_energy_function()
+    X0 = _to(s.trial(4))
+    occ = torch.tensor([2.0, 1.5, 1.0, 0.5], dtype=torch.float64, device=X0.device)
+    V = torch.from_numpy(s.veff_q.copy())
+    D = torch.from_numpy(s.dH.copy())
+    X = X0.clone().requires_grad_(True)
+    BE.apply(X, V, D, op, occ).backward()
+    dirn = _to(np.random.default_rng(5).standard_normal(X0.shape))
+    h = 1e-3
+    Ep = op.band_energy_grad(X0 + h * dirn, occ, want_dV=False, want_dH=False)[0].item()
+    Em = op.band_energy_grad(X0 - h * dirn, occ, want_dV=False, want_dH=False)[0].item()
+    fd = (Ep - Em) / (2 * h)
+    an = float((X.grad * dirn).sum())
+    assert abs(fd - an) < 1e-9 * abs(an), (fd, an)
+
+
 def test_lanczos_bounds(systems):
     from oracle import chfsi
     s, ref, op = systems["tiny"]

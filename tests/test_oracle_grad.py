@@ -70,3 +70,12 @@ def test_gradient_identities(setup):
     opnl = PAWOperator(s.with_dH(np.zeros_like(s.dH)))
     E_nl = E - grad.band_energy(opnl, X, occ)
     assert abs(np.dot(s.dH, gD) - E_nl) < 1e-10 * abs(E)
+
+
+def test_grad_veff_cell_subset(setup):
+    """The per-cell form used on sampled cells of large meshes equals the rows
+    of the full gradient."""
+    s, op, X, occ = setup
+    full = grad.grad_veff(op, X, occ)
+    cells = [0, 7, 33, 63]
+    np.testing.assert_array_equal(grad.grad_veff(op, X, occ, cells=cells), full[cells])
