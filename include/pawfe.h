@@ -173,6 +173,21 @@ pawfe_status pawfe_apply_H(const pawfe_op* op, const void* X, int64_t ldx, void*
                            int64_t nvec, int32_t prec, void* stream);
 pawfe_status pawfe_apply_S(const pawfe_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy,
                            int64_t nvec, int32_t prec, void* stream);
+
+/* pawfe_apply_H for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * same arguments, layouts and result as pawfe_apply_H, but it calls no
+ * hipMalloc / hipFree or allocating library routine.  The projector scratch
+ * (partial sums and coefficients) lives in a 64 MiB static device array of
+ * the library, one per GPU, held from the library's load on that GPU until
+ * the process ends; the columns are processed in chunks (at most 512 real
+ * columns) sized to fit it.  Returns PAWFE_EINVAL when the operator's
+ * scratch for a single column exceeds 64 MiB.  Every call on a GPU shares
+ * that GPU's array: calls that overlap on one GPU (other streams, other
+ * threads) race and must be serialized by the caller. */
+pawfe_status pawfe_apply_H_noalloc(const pawfe_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy,
+                                   int64_t nvec, int32_t prec, void* stream);
+
 pawfe_status pawfe_apply_Sinv(const pawfe_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy,
                               int64_t nvec, int32_t prec, void* stream);
 

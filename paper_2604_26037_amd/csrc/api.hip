@@ -8,6 +8,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <string>
 #include <new>
 #include <vector>
 
@@ -522,6 +524,41 @@ void free_device(pawfe_op* op) {
 
 using namespace pawfe;
 
+// ---- static scratch of the allocation-free apply ----------------------------
+
+// Projector scratch of pawfe_apply_H_noalloc: one array per GPU, resident
+// from the library's load on that GPU until the process ends.  Host code
+// never uses the array's name as an address: each device's address comes
+// from hipGetSymbolAddress, taken once per device with that device current.
+// Every call on a GPU shares that GPU's array, so calls that overlap on one
+// GPU race.  Nothing in it has to start at zero: each apply writes every
+// partial sum and coefficient it reads.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
+namespace pawfe {
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+pawfe_status static_scratch(void** out) {
+  int dev = 0;
+  PAWFE_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(PAWFE_EUNSUPPORTED, "device index beyond the static scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    PAWFE_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(PAWFE_EHIP, "hipGetSymbolAddress returned NULL for the static scratch");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return PAWFE_OK;
+}
+}  // namespace
+}  // namespace pawfe
+
 extern "C" {
 
 const char* pawfe_last_error(void) { return g_last_error.c_str(); }
@@ -620,6 +657,42 @@ pawfe_status pawfe_set_dH(pawfe_op* op, const double* dH, void* stream) {
 pawfe_status pawfe_apply_H(const pawfe_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy, int64_t nvec,
                            int32_t prec, void* stream) {
   return apply_entry(op, 0, X, ldx, Y, ldy, nvec, prec, stream);
+}
+
+pawfe_status pawfe_apply_H_noalloc(const pawfe_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy,
+                                   int64_t nvec, int32_t prec, void* stream) {
+  if (!op) return fail(PAWFE_EINVAL, "op is NULL");
+  if (nvec < 0) return fail(PAWFE_EINVAL, "nvec < 0");
+  if (nvec == 0) return PAWFE_OK;
+  if (!X || !Y) return fail(PAWFE_EINVAL, "X or Y is NULL");
+  if (ldx < nvec || ldy < nvec) return fail(PAWFE_EINVAL, "leading dimension smaller than nvec");
+  CHECK(check_prec(prec));
+  const int64_t cf = op->cplx ? 2 : 1;   // complex columns as (re, im) pairs of real columns
+  nvec *= cf;
+  ldx *= cf;
+  ldy *= cf;
+  // column chunk: the widest (at most 512 real columns) whose projector
+  // scratch fits the static array
+  if (nl_scratch_bytes(op, cf) > kStaticScratchBytes)
+    return fail(PAWFE_EINVAL, "the operator's projector scratch for one column exceeds the " +
+                                  std::to_string(kStaticScratchBytes >> 20) + " MiB static scratch of this entry point");
+  int64_t chunk = std::min<int64_t>(512, nvec);
+  while (chunk > cf && nl_scratch_bytes(op, chunk) > kStaticScratchBytes) chunk -= cf;
+  void* base = nullptr;
+  CHECK(static_scratch(&base));
+  Carve cv(base, kStaticScratchBytes);
+  NlBufs b = carve_nl(op, cv, chunk);
+  if (!cv.ok()) return fail(PAWFE_EINVAL, "internal: static scratch smaller than its carve");
+  hipStream_t s = S(stream);
+  for (int64_t j0 = 0; j0 < nvec; j0 += chunk) {
+    const int nc = (int)std::min<int64_t>(chunk, nvec - j0);
+    if (prec == PAWFE_FP64)
+      CHECK(do_apply<double>(op, 0, (const double*)X + j0, ldx, (double*)Y + j0, ldy, nc, b, s));
+    else
+      CHECK(do_apply<float>(op, 0, (const float*)X + j0, ldx, (float*)Y + j0, ldy, nc, b, s,
+                            prec == PAWFE_BF16X3));
+  }
+  return PAWFE_OK;
 }
 
 pawfe_status pawfe_apply_S(const pawfe_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy, int64_t nvec,

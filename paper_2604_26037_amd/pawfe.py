@@ -31,6 +31,7 @@ EXPORTS = [
     "pawfe_rayleigh_ritz", "pawfe_band_energy_grad", "pawfe_lanczos_bounds", "pawfe_last_error",
     "pawfe_chfsi_solve_workspace", "pawfe_chfsi_solve",
     "pawfe_batch_create", "pawfe_batch_run", "pawfe_batch_query", "pawfe_batch_destroy",
+    "pawfe_apply_H_noalloc",
 ]
 
 
@@ -82,6 +83,7 @@ def load(path=LIB_PATH):
         "pawfe_set_veff": [vp, P(dbl), vp],
         "pawfe_set_dH": [vp, P(dbl), vp],
         "pawfe_apply_H": [vp, vp, i64, vp, i64, i64, i32, vp],
+        "pawfe_apply_H_noalloc": [vp, vp, i64, vp, i64, i64, i32, vp],
         "pawfe_apply_S": [vp, vp, i64, vp, i64, i64, i32, vp],
         "pawfe_apply_Sinv": [vp, vp, i64, vp, i64, i64, i32, vp],
         "pawfe_apply_local": [vp, i32, vp, i64, vp, i64, i64, dbl, i32, vp],
@@ -239,6 +241,11 @@ class Operator:
 
     def apply_H(self, X, out=None, prec=FP64, stream=None):
         return self._apply(_lib.pawfe_apply_H, X, out, prec, stream)
+
+    def apply_H_noalloc(self, X, out, prec=FP64, stream=None):
+        """H X through the allocation-free entry point (out must be given)."""
+        assert out is not None
+        return self._apply(_lib.pawfe_apply_H_noalloc, X, out, prec, stream)
 
     def apply_S(self, X, out=None, prec=FP64, stream=None):
         return self._apply(_lib.pawfe_apply_S, X, out, prec, stream)
