@@ -175,11 +175,21 @@ pawfe_status apply_entry(const pawfe_op* cop, int which, const void* X, int64_t 
 
 // ---- filter ------------------------------------------------------------------
 
+// The FP32 recurrence of a real operator runs the fused step: the cell
+// kernel forms T = M_D^{-1}(R_Y - C d) at its gather and the node terms of
+// the recurrence at each node's first cell colour (no T block, no separate
+// node pass); the projector terms C d and a C q sit in two node-major blocks
+// that are zero outside the supports.
+bool fused_step(const pawfe_op* op, int32_t prec) {
+  return !op->cplx && prec == PAWFE_FP32 && op->nq == op->p + 2 && op->p >= 2 && op->p <= 6;
+}
+
 // B: real columns of one block (two per complex column)
 size_t filter_ws_bytes(const pawfe_op* op, int64_t B, int32_t prec) {
   const size_t tr = prec == PAWFE_FP64 ? 8 : 4;
   size_t b = align256((size_t)op->M * B * 8);            // Y
-  b += 3 * align256((size_t)op->M * B * tr);            // RX, RY, T
+  // RX, RY and T (fused step: RX, RY, CD, CQ)
+  b += (fused_step(op, prec) ? 4 : 3) * align256((size_t)op->M * B * tr);
   b += nl_scratch_bytes(op, B);
   b += 2 * align256((size_t)B * 8);                      // lamX, lamY
   if (op->cplx) b += align256((size_t)B * 8);             // lambda per real column
@@ -190,10 +200,12 @@ template <typename TR>
 pawfe_status filter_block(const pawfe_op* op, const double* X, int64_t ldx, double* Xo, int64_t ldo, int nc,
                           int64_t B, const double* lam_in, int m, double b0, double bW, double bU, Carve cv,
                           hipStream_t s, bool bf3 = false) {
+  const bool fused = std::is_same<TR, float>::value && !bf3 && fused_step(op, PAWFE_FP32);
   double* Y = cv.take<double>((size_t)op->M * B);
   TR* RX = cv.take<TR>((size_t)op->M * B);
   TR* RY = cv.take<TR>((size_t)op->M * B);
-  TR* Tb = cv.take<TR>((size_t)op->M * B);
+  TR* Tb = cv.take<TR>((size_t)op->M * B);       // T, or C d in the fused step
+  TR* CQ = fused ? cv.take<TR>((size_t)op->M * B) : nullptr;
   NlBufs nb = carve_nl(op, cv, B);
   double* lamX = cv.take<double>(B);
   double* lamY = cv.take<double>(B);
@@ -207,6 +219,10 @@ pawfe_status filter_block(const pawfe_op* op, const double* X, int64_t ldx, doub
   CHECK(do_residual(op, X, ldx, lam_in, Y, ld, nc, nb, s));
   // step 3
   CHECK(launch_cheb_init<TR>(op, Y, ld, RY, RX, ld, zeta1 / e, c, lam_in, lamY, lamX, nc, s));
+  if (fused) {   // the projector blocks stay zero outside the supports
+    CHECK(launch_fill<TR>(Tb, op->M * ld, TR(0), s));
+    CHECK(launch_fill<TR>(CQ, op->M * ld, TR(0), s));
+  }
   // step 4
   for (int theta = 2; theta <= m; ++theta) {
     const double znew = 1.0 / (gamma - zeta);
@@ -216,11 +232,21 @@ pawfe_status filter_block(const pawfe_op* op, const double* X, int64_t ldx, doub
     CHECK(launch_atom_mul(op, op->d.dSinv, nullptr, nullptr, 1.0, nb.c, nb.d, nc, s, op->d.dSinv_im));
     CHECK(launch_atom_gcorr(op, nb.c, nb.d, nb.t, nc, s));
     CHECK(launch_atom_mul(op, op->d.dH, nullptr, nullptr, a, nb.t, nb.c, nc, s));   // q = a Dh t (into c)
-    // T = Sinv_hat R_Y; R_X <- -a c R_Y - zeta zeta' R_X + a C q + a Y Lambda_Y
-    CHECK(launch_node_cheb<TR>(op, RY, RX, Tb, ld, Y, ld, nb.d, nb.c, lamY, lamX, lam_in, a, a * c, zeta * znew,
-                               nc, s));
-    // R_X += a H_loc T
-    CHECK(launch_cell<TR>(op, kModeH, Tb, ld, RX, ld, nc, nullptr, a, s, bf3));
+    bool done = false;
+    if (fused) {
+      // C d, a C q on the support nodes; Lambda_X; then per node
+      // R_X <- -a c R_Y - zeta zeta' R_X + a Y Lambda_Y + a C q + a H_loc T
+      CHECK(launch_step_nl<TR>(op, nb.d, nb.c, nc, Tb, CQ, ld, s));
+      CHECK(launch_lam_step(lamY, lamX, lam_in, a, a * c, zeta * znew, nc, s));
+      CHECK(launch_cell_step<TR>(op, RY, RX, Tb, CQ, ld, Y, ld, lamY, a, a * c, zeta * znew, nc, s, &done));
+      if (!done) return fail(PAWFE_EINVAL, "internal: fused step without a compiled variant");
+    } else {
+      // T = Sinv_hat R_Y; R_X <- -a c R_Y - zeta zeta' R_X + a C q + a Y Lambda_Y
+      CHECK(launch_node_cheb<TR>(op, RY, RX, Tb, ld, Y, ld, nb.d, nb.c, lamY, lamX, lam_in, a, a * c,
+                                 zeta * znew, nc, s));
+      // R_X += a H_loc T
+      CHECK(launch_cell<TR>(op, kModeH, Tb, ld, RX, ld, nc, nullptr, a, s, bf3));
+    }
     std::swap(RX, RY);
     std::swap(lamX, lamY);
     zeta = znew;
@@ -353,16 +379,17 @@ __global__ void k_sr_combine(int64_t M, int N, int bs, double* __restrict__ X, i
   for (int c = 0; c < bs; ++c) X[i * ldx + j0 + c] = o[c];
 }
 
-// P[i*ldp + j0 + j] = sum_b part[b][j + i*nc] (split-K partials of a block column)
-__global__ void k_part_reduce(const double* __restrict__ part, int nb, int nc, int N, double* __restrict__ P,
-                              int64_t ldp, int64_t j0) {
+// P[(i0 + i)*ldp + j0 + j] = sum_b part[b][j + i*nc], i < nrow (split-K
+// partials of rows i0 .. i0 + nrow of a block column)
+__global__ void k_part_reduce(const double* __restrict__ part, int nb, int nc, int nrow, double* __restrict__ P,
+                              int64_t ldp, int64_t j0, int64_t i0) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)nc * N) return;
-  const int64_t pstride = (int64_t)nc * N;
+  if (idx >= (int64_t)nc * nrow) return;
+  const int64_t pstride = (int64_t)nc * nrow;
   double acc = 0.0;
   for (int b = 0; b < nb; ++b) acc += part[b * pstride + idx];
   const int64_t i = idx / nc, j = idx % nc;
-  P[i * ldp + j0 + j] = acc;
+  P[(i0 + i) * ldp + j0 + j] = acc;
 }
 
 }  // namespace
@@ -438,6 +465,23 @@ pawfe_status upload(pawfe_op* op, hipStream_t s) {
     const int e = op->cells_by_colour[t];
     cpk[t] = (e % op->n[0]) | ((e / op->n[0]) % op->n[1]) << 10 | (e / (op->n[0] * op->n[1])) << 20;
   }
+  {
+    // bit 30: the cell has a node in some atom's support (the fused step then
+    // reads the projector terms of its nodes)
+    std::vector<char> has(op->E, 0);
+    const int p = op->p, np = op->np;
+    const int64_t Gx = (int64_t)op->n[0] * p, Gy = (int64_t)op->n[1] * p, Gz = (int64_t)op->n[2] * p;
+    for (int e = 0; e < op->E && op->nsrow > 0; ++e) {
+      const int i = e % op->n[0], j = (e / op->n[0]) % op->n[1], k = e / (op->n[0] * op->n[1]);
+      for (int l = 0; l < np * np * np && !has[e]; ++l) {
+        const int a = l % np, b = (l / np) % np, c = l / (np * np);
+        const int64_t I = (i * p + a) % Gx + Gx * (((j * p + b) % Gy) + Gy * ((k * p + c) % Gz));
+        if (op->node2srow[I] >= 0) has[e] = 1;
+      }
+    }
+    for (size_t t = 0; t < cpk.size(); ++t)
+      if (has[op->cells_by_colour[t]]) cpk[t] |= 1 << 30;
+  }
   CHECK(up(op, &d.cell_pack, cpk, s));
   CHECK(up(op, &d.node2srow, op->node2srow, s));
   CHECK(up(op, &d.srow_ptr, op->srow_ptr, s));
@@ -469,6 +513,20 @@ pawfe_status upload(pawfe_op* op, hipStream_t s) {
   CHECK(up(op, &d.fix_atom, op->fix_atom, s));
   CHECK(up(op, &d.fix_row0, op->fix_row0, s));
   CHECK(up(op, &d.fix_row1, op->fix_row1, s));
+  {
+    // per (atom, support node): 1 when the atom has the lowest colour of the
+    // atoms whose supports hold the node (its add-back writes, later ones add)
+    std::vector<int8_t> first(op->atom_nodes.size() + 16, 0);
+    for (int a = 0; a < op->natoms; ++a)
+      for (int64_t r = op->supp_node_off[a]; r < op->supp_node_off[a + 1]; ++r) {
+        const int32_t sr = op->node2srow[op->atom_nodes[r]];
+        int lo = op->atom_colour[a];
+        for (int32_t k = op->srow_ptr[sr]; k < op->srow_ptr[sr + 1]; ++k)
+          lo = std::min(lo, op->atom_colour[op->srow_atom[k]]);
+        first[r] = op->atom_colour[a] == lo ? 1 : 0;
+      }
+    CHECK(up(op, &d.atom_first, first, s));
+  }
   CHECK(up(op, &d.atom_noff, op->atom_noff, s));
   CHECK(up(op, &d.atom_coff, op->atom_coff, s));
   CHECK(up(op, &d.nproj, op->nproj, s));
@@ -877,33 +935,41 @@ pawfe_status pawfe_rayleigh_ritz(const pawfe_op* cop, void* Xv, int64_t ldx, int
   // Row-major X [K][ldx] is the column-major matrix X^T, so the block
   // P[:, j0:j0+nc] (row-major) is the column-major product HXb^T-block
   // (nc x K) times X (K x N).
+  // Real operators: only the rows i >= j0 of block column j0 (the lower
+  // triangle in row-major order, which is the upper triangle the dense solver
+  // reads in its column-major view) are formed, as the paper's projection
+  // step evaluates one triangle; complex operators form the whole realified
+  // matrices (the Hermitian fold reads both triangles) and symmetrize them.
   const int64_t K = op->M;
+  const bool lower_only = !op->cplx;
   for (int which = 0; which < 2; ++which) {
     double* P = which == 0 ? Hp : Sp;
     for (int64_t j0 = 0; j0 < N; j0 += B) {
       const int nc = (int)std::min<int64_t>(B, N - j0);
+      const int64_t i0 = lower_only ? j0 : 0, nrow = N - i0;
       CHECK(do_apply<double>(op, which, X + j0, ldx, HXb, nc, nc, nb, s));
-      const int64_t pbytes = (int64_t)nc * N;
+      const int64_t pbytes = (int64_t)nc * nrow;
       int64_t nsk = std::min<int64_t>(32, std::max<int64_t>(1, (int64_t)(npart / (size_t)pbytes) - 1));
       nsk = std::max<int64_t>(1, std::min<int64_t>(nsk, K / 1024));
       const int64_t kc = K / nsk, krem = K - nsk * kc;
       const double one = 1.0, zero = 0.0;
-      if (rocblas_dgemm_strided_batched(h, rocblas_operation_none, rocblas_operation_transpose, nc, (rocblas_int)N,
-                                        (rocblas_int)kc, &one, HXb, nc, kc * nc, X, (rocblas_int)ldx, kc * ldx, &zero,
-                                        part, nc, pbytes, (rocblas_int)nsk) != rocblas_status_success)
+      if (rocblas_dgemm_strided_batched(h, rocblas_operation_none, rocblas_operation_transpose, nc, (rocblas_int)nrow,
+                                        (rocblas_int)kc, &one, HXb, nc, kc * nc, X + i0, (rocblas_int)ldx, kc * ldx,
+                                        &zero, part, nc, pbytes, (rocblas_int)nsk) != rocblas_status_success)
         return fail(PAWFE_EHIP, "rocblas_dgemm_strided_batched failed");
       int64_t nparts = nsk;
       if (krem > 0) {
-        if (rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, nc, (rocblas_int)N,
-                          (rocblas_int)krem, &one, HXb + nsk * kc * nc, nc, X + nsk * kc * ldx, (rocblas_int)ldx,
-                          &zero, part + nsk * pbytes, nc) != rocblas_status_success)
+        if (rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, nc, (rocblas_int)nrow,
+                          (rocblas_int)krem, &one, HXb + nsk * kc * nc, nc, X + nsk * kc * ldx + i0,
+                          (rocblas_int)ldx, &zero, part + nsk * pbytes, nc) != rocblas_status_success)
           return fail(PAWFE_EHIP, "rocblas_dgemm failed");
         ++nparts;
       }
       hipLaunchKernelGGL(k_part_reduce, dim3((unsigned)((pbytes + 255) / 256)), dim3(256), 0, s, part, (int)nparts,
-                         nc, (int)N, P, (int64_t)N, j0);
+                         nc, (int)nrow, P, (int64_t)N, j0, i0);
     }
-    hipLaunchKernelGGL(k_symmetrize, dim3((unsigned)((N * N + 255) / 256)), dim3(256), 0, s, (int)N, P);
+    if (!lower_only)
+      hipLaunchKernelGGL(k_symmetrize, dim3((unsigned)((N * N + 255) / 256)), dim3(256), 0, s, (int)N, P);
   }
   PAWFE_HIP(hipGetLastError());
   // projected generalized eigenproblem (dense, FP64); complex operators: the

@@ -650,6 +650,7 @@ pawfe_status build_host(const pawfe_op_desc* d, pawfe_op* op) {
     ncol = std::max(ncol, c + 1);
   }
   op->natom_colours = ncol;
+  op->atom_colour = acol;
   const int kFixRows = 16;   // rows per add-back work item
   op->fix_atom.clear();
   op->fix_row0.clear();

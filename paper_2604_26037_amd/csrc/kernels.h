@@ -7,7 +7,7 @@
 
 namespace pawfe {
 
-enum { kModeH = 0, kModeHRes = 1, kModeMass = 2, kModeImg = 3 };
+enum { kModeH = 0, kModeHRes = 1, kModeMass = 2, kModeImg = 3, kModeStep = 4 };
 
 template <typename T>
 struct CellArgs {
@@ -23,6 +23,14 @@ struct CellArgs {
   T alpha;
   int n0, n1, n2;
   int bf3;             // FP32 data, contractions as bf16x3 split products
+  // fused Chebyshev step (kModeStep, vector-ALU kernel): X = R_Y, Y = R_X
+  const T* cd;         // [M][ldx] C d on the support nodes, 0 elsewhere
+  const T* cq;         // [M][ldx] a C q on the support nodes, 0 elsewhere
+  const double* yres;  // [M][ldyr] the block's residual Y (FP64)
+  int64_t ldyr;
+  const double* lamY;  // per column
+  double sac, szz;     // a c and zeta zeta' (alpha holds a)
+  double detJ;
 };
 
 struct DensArgs {
@@ -51,6 +59,11 @@ pawfe_status launch_cell(const pawfe_op* op, int mode, const T* X, int64_t ldx, 
 
 template <typename T>
 pawfe_status launch_cell_mfma(const pawfe_op* op, int mode, const CellArgs<T>& a, hipStream_t s);
+
+// K + V on the vector ALUs (kernels_cell_valu.hip); *done is false when no
+// variant is compiled for the operator's degree and Gauss rule.
+template <typename T>
+pawfe_status launch_cell_valu(const pawfe_op* op, const CellArgs<T>& a, hipStream_t s, bool* done);
 
 // out[e][q] = W_q sum_n occ_n |u_n(x_{e,q})|^2
 pawfe_status launch_density(const pawfe_op* op, const double* X, int64_t ldx, int ncols,
@@ -97,6 +110,27 @@ pawfe_status launch_node_cheb(const pawfe_op* op, const TR* RY, TR* RX, TR* Tb, 
                               const double* Y, int64_t ldy, const double* d, const double* q,
                               const double* lamY, double* lamX, const double* lam_in, double a,
                               double ac, double zz, int ncols, hipStream_t s);
+
+// Fused Chebyshev step, projector part: CD = C d, CQ = C q (q scaled by a)
+// on the support nodes (first atom colour writes, later ones add; other rows
+// untouched)
+template <typename TR>
+pawfe_status launch_step_nl(const pawfe_op* op, const double* dv, const double* qv, int ncols, TR* CD, TR* CQ,
+                            int64_t ld, hipStream_t s);
+
+// lamX = a lamY lam_in - ac lamY - zz lamX
+pawfe_status launch_lam_step(const double* lamY, double* lamX, const double* lam_in, double a, double ac,
+                             double zz, int ncols, hipStream_t s);
+
+// Fused Chebyshev step, cell part (real operators, vector-ALU kernel):
+//   T = M_D^{-1}(RY - CD) formed at the gather, and per node
+//   RX <- [-ac RY - zz RX + a Y lamY + CQ] (first cell colour touching the
+//   node) + a H_loc T (every cell), colour by colour.  *done false: no
+//   compiled variant (the caller then takes the unfused path).
+template <typename TR>
+pawfe_status launch_cell_step(const pawfe_op* op, const TR* RY, TR* RX, const TR* CD, const TR* CQ, int64_t ld,
+                              const double* Y, int64_t ldy, const double* lamY, double a, double ac, double zz,
+                              int ncols, hipStream_t s, bool* done);
 
 // Xout = M_D^{-1}(RY - C d) + X lamY
 template <typename TR>

@@ -483,7 +483,7 @@ k_cell_mfma(CellArgs<T> A, const Tab1D<T>* __restrict__ tabp,
     CellPos c;
     c.ci = packed & 1023;
     c.cj = (packed >> 10) & 1023;
-    c.ck = packed >> 20;
+    c.ck = (packed >> 20) & 1023;
     c.e = c.ci + A.n0 * (c.cj + A.n1 * c.ck);
     c.base = c.ci * p + Gx * (c.cj * p + Gy * c.ck * p);
     c.inner = off_fits && c.ci + 1 < A.n0 && c.cj + 1 < A.n1 && c.ck + 1 < A.n2;

@@ -389,7 +389,10 @@ constexpr int kFixUnroll = 8;
 // CPLX (complex operators): (re, im) column pairs, C v mixes them:
 // + s Ci v[n ^ 1], s = -1 on real and +1 on imaginary columns (partner value
 // from the neighbouring lane).
-template <typename TR, typename TO1, int NPJ, bool MINV, bool HAS2, bool CPLX = false>
+// FW (first write): the outputs are overwritten, not added to, on the rows
+// where this atom has the lowest colour of the atoms sharing the node
+// (d.atom_first), so they need no clearing between uses.
+template <typename TR, typename TO1, int NPJ, bool MINV, bool HAS2, bool CPLX = false, bool FW = false>
 __global__ void __launch_bounds__(256) k_nl_fixup(const int32_t* __restrict__ fatom,
                                                   const int32_t* __restrict__ frow0,
                                                   const int32_t* __restrict__ frow1, int ncols,
@@ -437,8 +440,14 @@ __global__ void __launch_bounds__(256) k_nl_fixup(const int32_t* __restrict__ fa
       for (int u = 0; u < kFixUnroll; ++u) I[u] = d.atom_nodes[noff + rb + u];   // list padded
 #pragma unroll
       for (int u = 0; u < kFixUnroll; ++u) {   // rows touched once: non-temporal
-        o1[u] = __builtin_nontemporal_load(out1 + (int64_t)I[u] * ld1 + n);
-        if constexpr (HAS2) o2[u] = __builtin_nontemporal_load(out2 + (int64_t)I[u] * ld2 + n);
+        if constexpr (FW) {
+          const bool fresh = d.atom_first[noff + rb + u] != 0;   // list padded like atom_nodes
+          o1[u] = fresh ? (TO1)0 : __builtin_nontemporal_load(out1 + (int64_t)I[u] * ld1 + n);
+          if constexpr (HAS2) o2[u] = fresh ? (TR)0 : __builtin_nontemporal_load(out2 + (int64_t)I[u] * ld2 + n);
+        } else {
+          o1[u] = __builtin_nontemporal_load(out1 + (int64_t)I[u] * ld1 + n);
+          if constexpr (HAS2) o2[u] = __builtin_nontemporal_load(out2 + (int64_t)I[u] * ld2 + n);
+        }
       }
 #pragma unroll
       for (int u = 0; u < kFixUnroll; ++u) {
@@ -706,7 +715,8 @@ pawfe_status launch_atom_gcorr(const pawfe_op* op, const double* c, const double
 }
 
 // out1 += s1 w C v1 (w = M_D^{-1} if MINV), out2 += C v2 (if HAS2), atom colour by colour
-template <typename TR, typename TO1, bool MINV, bool HAS2>
+// (FW: written instead of added on each node's first atom colour)
+template <typename TR, typename TO1, bool MINV, bool HAS2, bool FW = false>
 pawfe_status nl_fixup(const pawfe_op* op, int ncols, const double* v1, double s1, TO1* out1, int64_t ld1,
                       const double* v2, TR* out2, int64_t ld2, hipStream_t s) {
   if (op->natoms == 0 || ncols <= 0) return PAWFE_OK;
@@ -721,13 +731,13 @@ pawfe_status nl_fixup(const pawfe_op* op, int ncols, const double* v1, double s1
     auto go = [&](auto cplx) {
       constexpr bool CX = decltype(cplx)::value;
       if (op->npj_max <= 8)
-        hipLaunchKernelGGL((k_nl_fixup<TR, TO1, 8, MINV, HAS2, CX>), grid, block, 0, s, fa, f0, f1, ncols, v1, s1,
+        hipLaunchKernelGGL((k_nl_fixup<TR, TO1, 8, MINV, HAS2, CX, FW>), grid, block, 0, s, fa, f0, f1, ncols, v1, s1,
                            out1, ld1, v2, out2, ld2, Minv, Cv, op->d, Cvi);
       else if (op->npj_max <= 18)
-        hipLaunchKernelGGL((k_nl_fixup<TR, TO1, 18, MINV, HAS2, CX>), grid, block, 0, s, fa, f0, f1, ncols, v1, s1,
+        hipLaunchKernelGGL((k_nl_fixup<TR, TO1, 18, MINV, HAS2, CX, FW>), grid, block, 0, s, fa, f0, f1, ncols, v1, s1,
                            out1, ld1, v2, out2, ld2, Minv, Cv, op->d, Cvi);
       else
-        hipLaunchKernelGGL((k_nl_fixup<TR, TO1, 32, MINV, HAS2, CX>), grid, block, 0, s, fa, f0, f1, ncols, v1, s1,
+        hipLaunchKernelGGL((k_nl_fixup<TR, TO1, 32, MINV, HAS2, CX, FW>), grid, block, 0, s, fa, f0, f1, ncols, v1, s1,
                            out1, ld1, v2, out2, ld2, Minv, Cv, op->d, Cvi);
     };
     if (op->cplx) go(std::true_type{}); else go(std::false_type{});
@@ -802,6 +812,34 @@ template pawfe_status launch_node_cheb<double>(const pawfe_op*, const double*, d
 template pawfe_status launch_node_cheb<float>(const pawfe_op*, const float*, float*, float*, int64_t, const double*,
                                               int64_t, const double*, const double*, const double*, double*,
                                               const double*, double, double, double, int, hipStream_t);
+
+// Fused Chebyshev step, projector part: CD = C d and CQ = C q (q already
+// scaled by a) on the support nodes, written per node by its first atom
+// colour and added to by the later ones; rows outside every support are not
+// touched (the caller keeps them zero).
+template <typename TR>
+pawfe_status launch_step_nl(const pawfe_op* op, const double* dv, const double* qv, int ncols, TR* CD, TR* CQ,
+                            int64_t ld, hipStream_t s) {
+  return nl_fixup<TR, TR, false, true, true>(op, ncols, dv, 1.0, CD, ld, qv, CQ, ld, s);
+}
+template pawfe_status launch_step_nl<double>(const pawfe_op*, const double*, const double*, int, double*, double*,
+                                             int64_t, hipStream_t);
+template pawfe_status launch_step_nl<float>(const pawfe_op*, const double*, const double*, int, float*, float*,
+                                            int64_t, hipStream_t);
+
+__global__ void k_lam_step(int ncols, const double* __restrict__ lamY, double* __restrict__ lamX,
+                           const double* __restrict__ lam_in, double a, double ac, double zz) {
+  const int n = blockIdx.x * 256 + threadIdx.x;
+  if (n < ncols) lamX[n] = a * lamY[n] * lam_in[n] - ac * lamY[n] - zz * lamX[n];
+}
+
+pawfe_status launch_lam_step(const double* lamY, double* lamX, const double* lam_in, double a, double ac,
+                             double zz, int ncols, hipStream_t s) {
+  if (ncols <= 0) return PAWFE_OK;
+  hipLaunchKernelGGL(k_lam_step, dim3((ncols + 255) / 256), dim3(256), 0, s, ncols, lamY, lamX, lam_in, a, ac, zz);
+  PAWFE_HIP(hipGetLastError());
+  return PAWFE_OK;
+}
 
 template <typename TR>
 pawfe_status launch_node_finalize(const pawfe_op* op, const TR* RY, int64_t ld, const double* dv, const double* X,

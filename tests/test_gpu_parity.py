@@ -158,6 +158,53 @@ def test_rayleigh_ritz_mixed_rotation(systems, name, n):
     assert np.abs(Xe.cpu().numpy() * sg[None, :] - P * sg[None, :]).max() > 0
 
 
+def test_mixed_rotation_degenerate_states():
+    """The mixed-precision rotation near convergence on a spectrum with
+    degenerate levels (free electrons in a cube: levels of multiplicity 1, 6,
+    12, 8), where Q is not close to the identity inside each degenerate
+    cluster.  The change of every residual norm against the FP64 rotation is
+    bounded by the FP32 rounding of the off-diagonal product:
+    | ||r_i^32|| - ||r_i^64|| | <= ||H - lambda_i S||_2 ||E_i||_2 with
+    |E_i| <= gamma_{N+2}(u32) |X| |Q_off|[:, i]."""
+    from oracle import chfsi
+    from oracle.paw import PAWOperator
+    from paper_2604_26037_amd import Operator
+    from workloads.configs import custom_system
+    s = custom_system((3, 3, 3), (6.0, 6.0, 6.0), 4, 6, nstates=20)
+    ref, op = PAWOperator(s), Operator(s)
+    H, S = ref.H_dense(), ref.S_dense()
+    evS = np.linalg.eigvalsh(S)
+    X = _to(s.trial(20))
+    lam, res = op.rayleigh_ritz(X)
+    lam_all = ref.dense_eigs()[0]
+    bU = 1.01 * float(lam_all[-1])
+    for it in range(7):
+        lh = lam.cpu().numpy()
+        op.cheb_filter(X, lam, 12, float(lh[0]), float(lh[-1]), bU, out=X)
+        if it < 6:
+            lam, res = op.rayleigh_ritz(X)
+    Xh = X.cpu().numpy()                                  # filtered, not yet rotated
+    X64, X32 = _to(Xh), _to(Xh)
+    lam64, res64 = op.rayleigh_ritz(X64)
+    lam32, res32 = op.rayleigh_ritz(X32, sr_prec=1)
+    lam64, res64, res32 = lam64.cpu().numpy(), res64.cpu().numpy(), res32.cpu().numpy()
+    P64 = X64.cpu().numpy()
+    G = Xh.T @ (S @ Xh)
+    Q = np.linalg.solve(G, Xh.T @ (S @ P64))              # P64 = X Q
+    Qoff = Q - np.diag(np.diag(Q))
+    assert np.abs(Qoff).max() > 1e-3                      # the off-diagonal product is not trivial
+    u32 = 2.0 ** -24
+    gam = (20 + 2) * u32 / (1 - (20 + 2) * u32)
+    Ebound = gam * np.linalg.norm(np.abs(Xh) @ np.abs(Qoff), axis=0)
+    normS = float(evS[-1])
+    normH = float(np.abs(np.linalg.eigvalsh(H)).max())
+    bound = (normH + np.abs(lam64) * normS) * Ebound
+    diff = np.abs(res32 - res64)
+    assert np.all(diff <= bound), (diff / bound).max()
+    print(f"[mixed-rotation] max |Q_off| {np.abs(Qoff).max():.2f}, residual change "
+          f"{diff.max():.2e} (bound {bound.min():.2e}..{bound.max():.2e}), FP64 residuals {res64.max():.2e}")
+
+
 def test_chfsi_iterations_fp64_vs_oracle_and_dense(systems):
     """Config 'tiny': RR of the start, then 3 x (filter degree 20 + RR), all on the GPU."""
     from oracle import chfsi
