@@ -141,7 +141,7 @@ def kernels_mode(op, s, gen, dev, args):
     on one block, then a plain device copy of known size (counter calibration)."""
     import torch
 
-    from paper_2604_26037_amd import FP32, FP64
+    from paper_2604_26037_amd import BF16X3, FP32, FP64
     B = s.block
     X = torch.randn((op.ndof, B), generator=gen, dtype=torch.float64, device=dev)
     res = {}
@@ -157,6 +157,13 @@ def kernels_mode(op, s, gen, dev, args):
         torch.cuda.synchronize()
         res[name] = e0.elapsed_time(e1) / args.hx_reps / op.ncolour
         log(f"cell-local {name}: {res[name]:.3f} ms per colour launch")
+        # the whole H and Sinv_hat applies (projector reductions included)
+        for _ in range(2):
+            op.apply_H(Xs, out=Ys, prec=prec)
+            op.apply_Sinv(Xs, out=Ys, prec=prec)
+        if prec == FP32:
+            op.apply_H(Xs, out=Ys, prec=BF16X3)
+        torch.cuda.synchronize()
         del Xs, Ys
     nbytes = 1 << 30
     a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
@@ -477,6 +484,34 @@ def main():
             f"local {t_loc * 1e3:.2f} ms ({hx[name]['local_tflops']:.2f} TFLOP/s)")
         del Xs, Ys
 
+    # --- BF16 halo of a z-slab (one GPU's part of the reduced-precision
+    # nearest-neighbour exchange): pack and unpack-add of the two shared node
+    # planes of a 5-layer slab, one 256-column block ---
+    Yh = X[:, :B].to(torch.float32).contiguous()
+    hbuf = op.halo_pack_bf16(Yh, 5, 10)
+    op.halo_unpack_bf16(hbuf, Yh, 5, 10)
+    torch.cuda.synchronize()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    reps = 20
+    e0.record()
+    for _ in range(reps):
+        op.halo_pack_bf16(Yh, 5, 10, buf=hbuf)
+    e1.record()
+    for _ in range(reps):
+        op.halo_unpack_bf16(hbuf, Yh, 5, 10)
+    e2.record()
+    torch.cuda.synchronize()
+    prow = (s.ncell[0] * s.degree) * (s.ncell[1] * s.degree)
+    t_pack, t_unpack = e0.elapsed_time(e1) / reps / 1e3, e1.elapsed_time(e2) / reps / 1e3
+    halo_info = {"planes": 2, "nodes_per_plane": prow, "columns": B,
+                 "message_bytes_bf16": 2 * prow * B * 2, "message_bytes_fp64": 2 * prow * B * 8,
+                 "pack_us": t_pack * 1e6, "unpack_add_us": t_unpack * 1e6,
+                 "pack_gbs": 2 * prow * B * (4 + 2) / t_pack / 1e9,
+                 "unpack_gbs": 2 * prow * B * (2 + 4 + 4) / t_unpack / 1e9}
+    log(f"BF16 halo: pack {t_pack * 1e6:.1f} us, unpack-add {t_unpack * 1e6:.1f} us for 2 x {prow} nodes x {B} "
+        f"columns ({halo_info['message_bytes_bf16'] / 1e6:.1f} MB in BF16, 4x less than FP64)")
+    del Yh, hbuf
+
     # --- band-energy gradient (differentiation workload): 512 states ---
     ng = min(512, N)
     Xg = X[:, :ng].contiguous()
@@ -540,6 +575,7 @@ def main():
         "eig_err_mixed_vs_fp64_ha": eig_err,
         "precision_3_iterations": precision,
         "band_energy_grad": grad_info,
+        "halo_bf16": halo_info,
         "hx": hx,
         "roofline": roof,
     }

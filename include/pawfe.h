@@ -191,6 +191,26 @@ pawfe_status pawfe_apply_H_noalloc(const pawfe_op* op, const void* X, int64_t ld
 pawfe_status pawfe_apply_Sinv(const pawfe_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy,
                               int64_t nvec, int32_t prec, void* stream);
 
+/* BF16 halo of a slab decomposition along z (Reduced precision
+ * inter-processor communication paragraph and the BF16-communication
+ * figure: partial sums on the node planes shared with a neighbouring
+ * processor travel in BF16 and are cast back to FP32 and added by the
+ * receiver).  A slab is the cell layers [kz0, kz1) (0 <= kz0 < kz1 <= nz,
+ * kz1 - kz0 < nz: a slab spanning the whole periodic mesh shares no plane
+ * with another one; PAWFE_EINVAL) of the periodic mesh; its shared node
+ * planes are gz0 = kz0 p and gz1 = (kz1 p) mod (nz p).
+ *   pack:   buf[t][i][n] = BF16 bits of Y[plane_t row i][n], rounded to
+ *           nearest, ties to even (NaN stays NaN);
+ *   unpack: Y[plane_t row i][n] += (float) buf[t][i][n]   (FP32 add)
+ * Y: device FP32 [ndof][ldy] (complex operators: (re, im) pairs, nvec
+ * complex columns); buf: device [2][Gx*Gy][nvec] uint16 (complex: 2 nvec),
+ * plane gz0 first, a plane's nodes in DOF order (gy, gx row-major).  The
+ * buffer is caller-owned; Y and buf must not overlap. */
+pawfe_status pawfe_halo_pack_bf16(const pawfe_op* op, const float* Y, int64_t ldy, int64_t nvec, int32_t kz0,
+                                  int32_t kz1, uint16_t* buf, void* stream);
+pawfe_status pawfe_halo_unpack_bf16(const pawfe_op* op, const uint16_t* buf, int64_t nvec, int32_t kz0, int32_t kz1,
+                                    float* Y, int64_t ldy, void* stream);
+
 /* Local (cell) part only:  Y += alpha * A_loc X, A_loc = K + V (which = 0)
  * or the consistent mass M (which = 1): the cell-level step of the
  * operator-action subsection (extraction, per-cell contraction, assembly),

@@ -111,7 +111,7 @@ template <typename T>
 pawfe_status do_apply(const pawfe_op* op, int which, const T* X, int64_t ldx, T* Y, int64_t ldy, int ncols,
                       const NlBufs& b, hipStream_t s, bool bf3 = false) {
   if (which == 0 || which == 1) {   // H or S
-    CHECK(launch_nl_reduce<T>(op, X, ldx, ncols, false, b.part, b.c, s));
+    CHECK(launch_nl_reduce<T>(op, X, ldx, ncols, false, b.part, b.c, s, bf3));
     CHECK(launch_atom_mul(op, which == 0 ? op->d.dH : op->d.dS, nullptr, nullptr, 1.0, b.c, b.d, ncols, s));
     if (op->natoms)
       CHECK(launch_node_nl_init<T>(op, b.d, ncols, Y, ldy, s));
@@ -120,7 +120,7 @@ pawfe_status do_apply(const pawfe_op* op, int which, const T* X, int64_t ldx, T*
     return launch_cell<T>(op, which == 0 ? kModeH : kModeMass, X, ldx, Y, ldy, ncols, nullptr, 1.0, s, bf3);
   }
   // Sinv_hat
-  CHECK(launch_nl_reduce<T>(op, X, ldx, ncols, true, b.part, b.c, s));
+  CHECK(launch_nl_reduce<T>(op, X, ldx, ncols, true, b.part, b.c, s, bf3));
   CHECK(launch_atom_mul(op, op->d.dSinv, nullptr, nullptr, 1.0, b.c, b.d, ncols, s, op->d.dSinv_im));
   return launch_node_sinv<T>(op, X, ldx, b.d, ncols, Y, ldy, s);
 }
@@ -175,21 +175,11 @@ pawfe_status apply_entry(const pawfe_op* cop, int which, const void* X, int64_t 
 
 // ---- filter ------------------------------------------------------------------
 
-// The FP32 recurrence of a real operator runs the fused step: the cell
-// kernel forms T = M_D^{-1}(R_Y - C d) at its gather and the node terms of
-// the recurrence at each node's first cell colour (no T block, no separate
-// node pass); the projector terms C d and a C q sit in two node-major blocks
-// that are zero outside the supports.
-bool fused_step(const pawfe_op* op, int32_t prec) {
-  return !op->cplx && prec == PAWFE_FP32 && op->nq == op->p + 2 && op->p >= 2 && op->p <= 6;
-}
-
 // B: real columns of one block (two per complex column)
 size_t filter_ws_bytes(const pawfe_op* op, int64_t B, int32_t prec) {
   const size_t tr = prec == PAWFE_FP64 ? 8 : 4;
   size_t b = align256((size_t)op->M * B * 8);            // Y
-  // RX, RY and T (fused step: RX, RY, CD, CQ)
-  b += (fused_step(op, prec) ? 4 : 3) * align256((size_t)op->M * B * tr);
+  b += 3 * align256((size_t)op->M * B * tr);            // RX, RY, T
   b += nl_scratch_bytes(op, B);
   b += 2 * align256((size_t)B * 8);                      // lamX, lamY
   if (op->cplx) b += align256((size_t)B * 8);             // lambda per real column
@@ -200,12 +190,10 @@ template <typename TR>
 pawfe_status filter_block(const pawfe_op* op, const double* X, int64_t ldx, double* Xo, int64_t ldo, int nc,
                           int64_t B, const double* lam_in, int m, double b0, double bW, double bU, Carve cv,
                           hipStream_t s, bool bf3 = false) {
-  const bool fused = std::is_same<TR, float>::value && !bf3 && fused_step(op, PAWFE_FP32);
   double* Y = cv.take<double>((size_t)op->M * B);
   TR* RX = cv.take<TR>((size_t)op->M * B);
   TR* RY = cv.take<TR>((size_t)op->M * B);
-  TR* Tb = cv.take<TR>((size_t)op->M * B);       // T, or C d in the fused step
-  TR* CQ = fused ? cv.take<TR>((size_t)op->M * B) : nullptr;
+  TR* Tb = cv.take<TR>((size_t)op->M * B);
   NlBufs nb = carve_nl(op, cv, B);
   double* lamX = cv.take<double>(B);
   double* lamY = cv.take<double>(B);
@@ -219,40 +207,26 @@ pawfe_status filter_block(const pawfe_op* op, const double* X, int64_t ldx, doub
   CHECK(do_residual(op, X, ldx, lam_in, Y, ld, nc, nb, s));
   // step 3
   CHECK(launch_cheb_init<TR>(op, Y, ld, RY, RX, ld, zeta1 / e, c, lam_in, lamY, lamX, nc, s));
-  if (fused) {   // the projector blocks stay zero outside the supports
-    CHECK(launch_fill<TR>(Tb, op->M * ld, TR(0), s));
-    CHECK(launch_fill<TR>(CQ, op->M * ld, TR(0), s));
-  }
   // step 4
   for (int theta = 2; theta <= m; ++theta) {
     const double znew = 1.0 / (gamma - zeta);
     const double a = 2.0 * znew / e;
     // projector coefficients of Sinv_hat R_Y and of H's non-local term on T
-    CHECK(launch_nl_reduce<TR>(op, RY, ld, nc, true, nb.part, nb.c, s));
+    CHECK(launch_nl_reduce<TR>(op, RY, ld, nc, true, nb.part, nb.c, s, bf3));
     CHECK(launch_atom_mul(op, op->d.dSinv, nullptr, nullptr, 1.0, nb.c, nb.d, nc, s, op->d.dSinv_im));
     CHECK(launch_atom_gcorr(op, nb.c, nb.d, nb.t, nc, s));
     CHECK(launch_atom_mul(op, op->d.dH, nullptr, nullptr, a, nb.t, nb.c, nc, s));   // q = a Dh t (into c)
-    bool done = false;
-    if (fused) {
-      // C d, a C q on the support nodes; Lambda_X; then per node
-      // R_X <- -a c R_Y - zeta zeta' R_X + a Y Lambda_Y + a C q + a H_loc T
-      CHECK(launch_step_nl<TR>(op, nb.d, nb.c, nc, Tb, CQ, ld, s));
-      CHECK(launch_lam_step(lamY, lamX, lam_in, a, a * c, zeta * znew, nc, s));
-      CHECK(launch_cell_step<TR>(op, RY, RX, Tb, CQ, ld, Y, ld, lamY, a, a * c, zeta * znew, nc, s, &done));
-      if (!done) return fail(PAWFE_EINVAL, "internal: fused step without a compiled variant");
-    } else {
-      // T = Sinv_hat R_Y; R_X <- -a c R_Y - zeta zeta' R_X + a C q + a Y Lambda_Y
-      CHECK(launch_node_cheb<TR>(op, RY, RX, Tb, ld, Y, ld, nb.d, nb.c, lamY, lamX, lam_in, a, a * c,
-                                 zeta * znew, nc, s));
-      // R_X += a H_loc T
-      CHECK(launch_cell<TR>(op, kModeH, Tb, ld, RX, ld, nc, nullptr, a, s, bf3));
-    }
+    // T = Sinv_hat R_Y; R_X <- -a c R_Y - zeta zeta' R_X + a C q + a Y Lambda_Y
+    CHECK(launch_node_cheb<TR>(op, RY, RX, Tb, ld, Y, ld, nb.d, nb.c, lamY, lamX, lam_in, a, a * c, zeta * znew,
+                               nc, s));
+    // R_X += a H_loc T
+    CHECK(launch_cell<TR>(op, kModeH, Tb, ld, RX, ld, nc, nullptr, a, s, bf3));
     std::swap(RX, RY);
     std::swap(lamX, lamY);
     zeta = znew;
   }
   // step 5: Xout = Sinv_hat R_Y + X Lambda_Y
-  CHECK(launch_nl_reduce<TR>(op, RY, ld, nc, true, nb.part, nb.c, s));
+  CHECK(launch_nl_reduce<TR>(op, RY, ld, nc, true, nb.part, nb.c, s, bf3));
   CHECK(launch_atom_mul(op, op->d.dSinv, nullptr, nullptr, 1.0, nb.c, nb.d, nc, s, op->d.dSinv_im));
   return launch_node_finalize<TR>(op, RY, ld, nb.d, X, ldx, lamY, Xo, ldo, nc, s);
 }
@@ -465,23 +439,6 @@ pawfe_status upload(pawfe_op* op, hipStream_t s) {
     const int e = op->cells_by_colour[t];
     cpk[t] = (e % op->n[0]) | ((e / op->n[0]) % op->n[1]) << 10 | (e / (op->n[0] * op->n[1])) << 20;
   }
-  {
-    // bit 30: the cell has a node in some atom's support (the fused step then
-    // reads the projector terms of its nodes)
-    std::vector<char> has(op->E, 0);
-    const int p = op->p, np = op->np;
-    const int64_t Gx = (int64_t)op->n[0] * p, Gy = (int64_t)op->n[1] * p, Gz = (int64_t)op->n[2] * p;
-    for (int e = 0; e < op->E && op->nsrow > 0; ++e) {
-      const int i = e % op->n[0], j = (e / op->n[0]) % op->n[1], k = e / (op->n[0] * op->n[1]);
-      for (int l = 0; l < np * np * np && !has[e]; ++l) {
-        const int a = l % np, b = (l / np) % np, c = l / (np * np);
-        const int64_t I = (i * p + a) % Gx + Gx * (((j * p + b) % Gy) + Gy * ((k * p + c) % Gz));
-        if (op->node2srow[I] >= 0) has[e] = 1;
-      }
-    }
-    for (size_t t = 0; t < cpk.size(); ++t)
-      if (has[op->cells_by_colour[t]]) cpk[t] |= 1 << 30;
-  }
   CHECK(up(op, &d.cell_pack, cpk, s));
   CHECK(up(op, &d.node2srow, op->node2srow, s));
   CHECK(up(op, &d.srow_ptr, op->srow_ptr, s));
@@ -513,20 +470,6 @@ pawfe_status upload(pawfe_op* op, hipStream_t s) {
   CHECK(up(op, &d.fix_atom, op->fix_atom, s));
   CHECK(up(op, &d.fix_row0, op->fix_row0, s));
   CHECK(up(op, &d.fix_row1, op->fix_row1, s));
-  {
-    // per (atom, support node): 1 when the atom has the lowest colour of the
-    // atoms whose supports hold the node (its add-back writes, later ones add)
-    std::vector<int8_t> first(op->atom_nodes.size() + 16, 0);
-    for (int a = 0; a < op->natoms; ++a)
-      for (int64_t r = op->supp_node_off[a]; r < op->supp_node_off[a + 1]; ++r) {
-        const int32_t sr = op->node2srow[op->atom_nodes[r]];
-        int lo = op->atom_colour[a];
-        for (int32_t k = op->srow_ptr[sr]; k < op->srow_ptr[sr + 1]; ++k)
-          lo = std::min(lo, op->atom_colour[op->srow_atom[k]]);
-        first[r] = op->atom_colour[a] == lo ? 1 : 0;
-      }
-    CHECK(up(op, &d.atom_first, first, s));
-  }
   CHECK(up(op, &d.atom_noff, op->atom_noff, s));
   CHECK(up(op, &d.atom_coff, op->atom_coff, s));
   CHECK(up(op, &d.nproj, op->nproj, s));
@@ -751,6 +694,32 @@ pawfe_status pawfe_apply_H_noalloc(const pawfe_op* op, const void* X, int64_t ld
                             prec == PAWFE_BF16X3));
   }
   return PAWFE_OK;
+}
+
+static pawfe_status halo_args(const pawfe_op* op, const void* Y, int64_t ldy, int64_t nvec, int32_t kz0,
+                              int32_t kz1, const void* buf) {
+  if (!op) return fail(PAWFE_EINVAL, "op is NULL");
+  if (nvec < 0) return fail(PAWFE_EINVAL, "nvec < 0");
+  if (nvec > 0 && (!Y || !buf)) return fail(PAWFE_EINVAL, "Y or buf is NULL");
+  if (ldy < nvec) return fail(PAWFE_EINVAL, "leading dimension smaller than nvec");
+  if (!(0 <= kz0 && kz0 < kz1 && kz1 <= op->n[2] && kz1 - kz0 < op->n[2]))
+    return fail(PAWFE_EINVAL, "slab must satisfy 0 <= kz0 < kz1 <= nz and be thinner than the mesh");
+  if (nvec * (op->cplx ? 2 : 1) > (int64_t)1 << 30) return fail(PAWFE_EINVAL, "nvec too large");
+  return PAWFE_OK;
+}
+
+pawfe_status pawfe_halo_pack_bf16(const pawfe_op* op, const float* Y, int64_t ldy, int64_t nvec, int32_t kz0,
+                                  int32_t kz1, uint16_t* buf, void* stream) {
+  CHECK(halo_args(op, Y, ldy, nvec, kz0, kz1, buf));
+  const int64_t cf = op->cplx ? 2 : 1;
+  return launch_halo(op, true, const_cast<float*>(Y), ldy * cf, (int)(nvec * cf), kz0, kz1, buf, S(stream));
+}
+
+pawfe_status pawfe_halo_unpack_bf16(const pawfe_op* op, const uint16_t* buf, int64_t nvec, int32_t kz0, int32_t kz1,
+                                    float* Y, int64_t ldy, void* stream) {
+  CHECK(halo_args(op, Y, ldy, nvec, kz0, kz1, buf));
+  const int64_t cf = op->cplx ? 2 : 1;
+  return launch_halo(op, false, Y, ldy * cf, (int)(nvec * cf), kz0, kz1, const_cast<uint16_t*>(buf), S(stream));
 }
 
 pawfe_status pawfe_apply_S(const pawfe_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy, int64_t nvec,

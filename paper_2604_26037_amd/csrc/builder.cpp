@@ -650,7 +650,6 @@ pawfe_status build_host(const pawfe_op_desc* d, pawfe_op* op) {
     ncol = std::max(ncol, c + 1);
   }
   op->natom_colours = ncol;
-  op->atom_colour = acol;
   const int kFixRows = 16;   // rows per add-back work item
   op->fix_atom.clear();
   op->fix_row0.clear();

@@ -53,8 +53,7 @@ struct DeviceTables {
   double* Minv = nullptr;    // [M]        1 / M_D
   float* Minv_f = nullptr;
   int32_t* cells_by_colour = nullptr;  // [E]
-  int32_t* cell_pack = nullptr;        // [E] the same cells as i | j << 10 | k << 20, bit 30 set when
-                                       //     some node of the cell lies in an atom's support
+  int32_t* cell_pack = nullptr;        // [E] the same cells as i | j << 10 | k << 20
   // projector structure
   int32_t* node2srow = nullptr;   // [M]  support row of a DOF, -1 if none
   int32_t* srow_ptr = nullptr;    // [nsrow+1]
@@ -73,8 +72,6 @@ struct DeviceTables {
   int32_t* fix_atom = nullptr;    // add-back work items (atom, row range), ordered by atom colour
   int32_t* fix_row0 = nullptr;
   int32_t* fix_row1 = nullptr;
-  int8_t* atom_first = nullptr;   // [atom_noff[natoms] + 16] 1 when the atom has the lowest colour
-                                  //     of the atoms whose supports hold that node
   int32_t* atom_noff = nullptr;   // [natoms+1] offsets into atom_nodes
   int32_t* atom_coff = nullptr;   // [natoms]   offsets into Cvals
   int32_t* nproj = nullptr;       // [natoms]
@@ -131,7 +128,6 @@ struct pawfe_op {
   // atoms coloured so that atoms of one colour share no support node; the
   // add-back of C^a q_a runs one colour at a time without write conflicts
   int natom_colours = 0;
-  std::vector<int32_t> atom_colour;    // [natoms]
   std::vector<int32_t> fix_atom, fix_row0, fix_row1, fix_colour_off;
   int64_t item_rows_total = 0;         // sum over items of nproj (partial rows per column)
   int sinv_mode;

@@ -7,7 +7,7 @@
 
 namespace pawfe {
 
-enum { kModeH = 0, kModeHRes = 1, kModeMass = 2, kModeImg = 3, kModeStep = 4 };
+enum { kModeH = 0, kModeHRes = 1, kModeMass = 2, kModeImg = 3 };
 
 template <typename T>
 struct CellArgs {
@@ -23,14 +23,6 @@ struct CellArgs {
   T alpha;
   int n0, n1, n2;
   int bf3;             // FP32 data, contractions as bf16x3 split products
-  // fused Chebyshev step (kModeStep, vector-ALU kernel): X = R_Y, Y = R_X
-  const T* cd;         // [M][ldx] C d on the support nodes, 0 elsewhere
-  const T* cq;         // [M][ldx] a C q on the support nodes, 0 elsewhere
-  const double* yres;  // [M][ldyr] the block's residual Y (FP64)
-  int64_t ldyr;
-  const double* lamY;  // per column
-  double sac, szz;     // a c and zeta zeta' (alpha holds a)
-  double detJ;
 };
 
 struct DensArgs {
@@ -77,9 +69,11 @@ pawfe_status launch_dup_pairs(const double* in, double* out, int n, hipStream_t 
 
 // c[(poff_a + alpha) * ncols + n] = sum_{I in supp(a)} C^a[I][alpha] s_I X[I][n],
 // s_I = M_D^{-1}[I] if scale_minv, else 1.  part: >= item_rows_total*ncols doubles.
+// Real operators in FP32 run on the matrix cores (FP32, or bf16x3 split
+// products when bf3); FP64 and complex operators on the vector ALUs.
 template <typename T>
 pawfe_status launch_nl_reduce(const pawfe_op* op, const T* X, int64_t ldx, int ncols, bool scale_minv,
-                              double* part, double* c, hipStream_t s);
+                              double* part, double* c, hipStream_t s, bool bf3 = false);
 
 // out = (D1 - lam_n D2) in  (per atom block; D2 may be NULL), scaled by f.
 // D1i: imaginary part of D1 (complex operators, Delta_Sinv with the exact G);
@@ -111,27 +105,6 @@ pawfe_status launch_node_cheb(const pawfe_op* op, const TR* RY, TR* RX, TR* Tb, 
                               const double* lamY, double* lamX, const double* lam_in, double a,
                               double ac, double zz, int ncols, hipStream_t s);
 
-// Fused Chebyshev step, projector part: CD = C d, CQ = C q (q scaled by a)
-// on the support nodes (first atom colour writes, later ones add; other rows
-// untouched)
-template <typename TR>
-pawfe_status launch_step_nl(const pawfe_op* op, const double* dv, const double* qv, int ncols, TR* CD, TR* CQ,
-                            int64_t ld, hipStream_t s);
-
-// lamX = a lamY lam_in - ac lamY - zz lamX
-pawfe_status launch_lam_step(const double* lamY, double* lamX, const double* lam_in, double a, double ac,
-                             double zz, int ncols, hipStream_t s);
-
-// Fused Chebyshev step, cell part (real operators, vector-ALU kernel):
-//   T = M_D^{-1}(RY - CD) formed at the gather, and per node
-//   RX <- [-ac RY - zz RX + a Y lamY + CQ] (first cell colour touching the
-//   node) + a H_loc T (every cell), colour by colour.  *done false: no
-//   compiled variant (the caller then takes the unfused path).
-template <typename TR>
-pawfe_status launch_cell_step(const pawfe_op* op, const TR* RY, TR* RX, const TR* CD, const TR* CQ, int64_t ld,
-                              const double* Y, int64_t ldy, const double* lamY, double a, double ac, double zz,
-                              int ncols, hipStream_t s, bool* done);
-
 // Xout = M_D^{-1}(RY - C d) + X lamY
 template <typename TR>
 pawfe_status launch_node_finalize(const pawfe_op* op, const TR* RY, int64_t ld, const double* d,
@@ -152,6 +125,11 @@ pawfe_status launch_coldot(const double* A, int64_t lda, const double* B, int64_
 // dE/dDelta_H^a = sum_n occ_n P P^T, P = c rows of atom a
 pawfe_status launch_grad_dh(const pawfe_op* op, const double* c, int ncols, const double* occ,
                             double* out, hipStream_t s);
+
+// BF16 halo of a z-slab [kz0, kz1) of cell layers: pack (Y -> buf) or
+// unpack-add (Y += buf) on its two shared node planes (kernels_halo.hip)
+pawfe_status launch_halo(const pawfe_op* op, bool pack, float* Y, int64_t ldy, int ncols, int kz0, int kz1,
+                         uint16_t* buf, hipStream_t s);
 
 // elementwise copies / fills
 pawfe_status launch_copy_cols(const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t nrows,

@@ -3,7 +3,7 @@
 // launch_cell sets up the arguments of the cell operator (kinetic + V(q)W_q,
 // the residual variant with -lambda_n W_q, or the mass; the cell-level
 // product of the operator-action subsection) and runs, one launch per cell
-// colour, the vector-ALU kernel of kernels_cell_valu.hip (FP32 K + V) or the
+// colour, the vector-ALU kernel of kernels_cell_valu.hip (K + V) or the
 // matrix-core kernel of kernels_cell_mfma.hip (every other case).
 //
 // k_cell_density is the adjoint contraction of the potential term: the
@@ -121,11 +121,9 @@ pawfe_status launch_cell(const pawfe_op* op, int mode, const T* X, int64_t ldx, 
   a.n2 = op->n[2];
   pawfe_status st = PAWFE_OK;
   bool done = false;
-  if constexpr (std::is_same<T, float>::value) {
-    // FP32 K + V: vector-ALU kernel (the matrix-core kernel keeps the other
-    // modes, FP64 and bf16x3)
-    if (mode == kModeH && !bf3) st = launch_cell_valu(op, a, s, &done);
-  }
+  // K + V in FP32 or FP64: vector-ALU kernel (the matrix-core kernel keeps the
+  // residual, mass and imaginary-term modes and bf16x3)
+  if (mode == kModeH && !bf3) st = launch_cell_valu(op, a, s, &done);
   if (st == PAWFE_OK && !done) st = launch_cell_mfma<T>(op, mode, a, s);
   // complex operators: the imaginary local term, on the (re, im) column pairs
   if (st != PAWFE_OK || !op->cplx || (mode != kModeH && mode != kModeHRes)) return st;

@@ -356,10 +356,9 @@ constexpr int kCB = sizeof(T) == 4 ? 8 : 4;
 template <typename T>
 constexpr int kNT = 64 * kCB<T>;
 // Waves per SIMD the registers are held to: FP32 six (three workgroups of
-// eight waves per CU, as many as the LDS holds); the fused step keeps more
-// per-node values live and is held to four; FP64 three.
-template <typename T, int MODE>
-constexpr int kWaves = sizeof(T) == 4 ? (MODE == kModeStep ? 4 : 6) : 3;
+// eight waves per CU, as many as the LDS holds), FP64 three.
+template <typename T>
+constexpr int kWaves = sizeof(T) == 4 ? 6 : 3;
 constexpr int kXP = 9;
 // U: extents up to 8 x 8 x 8;  K, M: up to 7 x 7 x 7 (element offsets, col fastest)
 template <typename T>
@@ -395,9 +394,9 @@ struct Lines {
 }  // namespace
 
 template <typename T, int NP, int NQ, int MODE>
-__global__ void __launch_bounds__(kNT<T>) __attribute__((amdgpu_waves_per_eu(kWaves<T, MODE>)))
+__global__ void __launch_bounds__(kNT<T>) __attribute__((amdgpu_waves_per_eu(kWaves<T>)))
 k_cell_valu(CellArgs<T> A, int ncoltiles, int nitems, T fx, T fy, T fz) {
-  constexpr bool STEP = MODE == kModeStep;
+  static_assert(MODE == kModeH, "K + V only");
   constexpr int CB = kCB<T>;
   constexpr int NT = kNT<T>;
   constexpr int S = NT / CB;                   // line slots
@@ -444,12 +443,11 @@ k_cell_valu(CellArgs<T> A, int ncoltiles, int nitems, T fx, T fy, T fz) {
   };
   static_assert(offU<T>(3, 5, 6) - offK<T>(3, 5, 6) == 6 * kXP * CB, "K offset from U offset");
   struct CellPos {
-    int ci, cj, ck, e, base, supp;
+    int ci, cj, ck, e, base;
     bool inner;
   };
   auto cell_pos = [&](int packed) {
     CellPos cp;
-    cp.supp = (packed >> 30) & 1;
     cp.ci = packed & 1023;
     cp.cj = (packed >> 10) & 1023;
     cp.ck = (packed >> 20) & 1023;
@@ -503,11 +501,7 @@ k_cell_valu(CellArgs<T> A, int ncoltiles, int nitems, T fx, T fy, T fz) {
     }
   };
 
-  // step mode: ry = the current item's R_Y (for the node term), cdn = the
-  // next item's C d (0 outside the supports: cells without support nodes
-  // skip the loads)
   T xr[NJ], vr[NV];
-  T ry[STEP ? NJ : 1], cdn[STEP ? NJ : 1];
   auto load_item = [&](int c, int t) {
     const CellPos cp = cell_pos(cells[c]);
     const int n = t * CB + col;
@@ -516,50 +510,16 @@ k_cell_valu(CellArgs<T> A, int ncoltiles, int nitems, T fx, T fy, T fz) {
     const int nn = n < A.ncols ? n : 0;
 #pragma unroll
     for (int j = 0; j < NJ; ++j) xr[j] = *elem(A.X, ldxb, nn, node[j]);
-    if constexpr (STEP) {
-      if (cp.supp) {
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) cdn[j] = *elem(A.cd, ldxb, nn, node[j]);
-      } else {
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) cdn[j] = T(0);
-      }
-    }
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       const int q = tid + NT * v;
       if (NQ3 % NT == 0 || q < NQ3) vr[v] = A.Vw[(int64_t)cp.e * NQ3 + q];
     }
   };
-  // step mode: M_D^{-1} of the thread's local nodes (a, b, c), the same for
-  // every cell: 1 / (detJ w~a w~b w~c), w~ the GLL weight, doubled on the
-  // cell's faces (each face node is shared by two cells along its axis)
-  T mv[STEP ? NJ : 1];
-  if constexpr (STEP) {
-    using TB = ref1d::Tab<NP, NQ>;
-    auto wt = [](int i) -> double {
-      double w = 0.0;
-      sfor<NP>([&](auto q) {
-        if (i == q) w = (q == 0 || q == NP - 1) ? 2.0 * TB::t.W[0] : TB::t.W[q];
-      });
-      return w;
-    };
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      const int l = lreal(j) ? lnode(j) : 0;
-      const int a = l % NP, b = (l / NP) % NP, c = l / (NP * NP);
-      mv[j] = (T)(1.0 / (A.detJ * wt(a) * wt(b) * wt(c)));
-    }
-  }
   auto stage = [&]() {
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
-      T v = xr[j];
-      if constexpr (STEP) {
-        ry[j] = xr[j];
-        v = mv[j] * (xr[j] - cdn[j]);
-      }
-      if (lreal(j)) *reinterpret_cast<T*>(reinterpret_cast<char*>(sU) + (pk[j] & ((1u << kLdsBits) - 1))) = v;
+      if (lreal(j)) *reinterpret_cast<T*>(reinterpret_cast<char*>(sU) + (pk[j] & ((1u << kLdsBits) - 1))) = xr[j];
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v)
@@ -749,75 +709,16 @@ k_cell_valu(CellArgs<T> A, int ncoltiles, int nitems, T fx, T fy, T fz) {
     __syncthreads();
     // the next item's values into U (free now), then this item's assembly:
     // colour-ordered read-modify-write of CB contiguous columns per DOF
-    if constexpr (!STEP) {
-      stage();
-      if (valid) {
-        int node[NJ];
-        nodes_of(cp, node);
-#pragma unroll
-        for (int j = 0; j < NJ; ++j)
-          if (lreal(j))
-            *elem(A.Y, ldyb, n, node[j]) =
-                yo[j] + A.alpha * *reinterpret_cast<const T*>(reinterpret_cast<const char*>(sK) +
-                                                               k_of_u(pk[j] & ((1u << kLdsBits) - 1)));
-      }
-    } else {
-      // Fused step.  The first cell colour that touches a node replaces R_X
-      // there by the node term of the recurrence,
-      //   -ac R_Y - zz R_X (in T) + a Y lamY (FP64), rounded to T, plus a C q,
-      // and every cell adds a (H_loc T)_cell.  A node's first colour: along
-      // each axis a face node is shared with the neighbouring cell, and the
-      // cell whose 1-D colour is lower comes first (cell colours compare
-      // like their 1-D colours, axis by axis).
-      auto col1 = [](int i, int nn) { return ((nn & 1) && i == nn - 1) ? 2 : (i & 1); };
-      const int cx = col1(cp.ci, A.n0), cy = col1(cp.cj, A.n1), cz = col1(cp.ck, A.n2);
-      const bool lox = cx < col1(cp.ci == 0 ? A.n0 - 1 : cp.ci - 1, A.n0);
-      const bool hix = cx < col1(cp.ci + 1 == A.n0 ? 0 : cp.ci + 1, A.n0);
-      const bool loy = cy < col1(cp.cj == 0 ? A.n1 - 1 : cp.cj - 1, A.n1);
-      const bool hiy = cy < col1(cp.cj + 1 == A.n1 ? 0 : cp.cj + 1, A.n1);
-      const bool loz = cz < col1(cp.ck == 0 ? A.n2 - 1 : cp.ck - 1, A.n2);
-      const bool hiz = cz < col1(cp.ck + 1 == A.n2 ? 0 : cp.ck + 1, A.n2);
+    stage();
+    if (valid) {
       int node[NJ];
       nodes_of(cp, node);
-      bool ft[NJ];
-      double yr[NJ];
-      T cqv[NJ];
-      const int nn = valid ? n : 0;
-#pragma unroll
-      for (int j = 0; j < NJ; ++j) {
-        const int l = lreal(j) ? lnode(j) : 0;
-        const int a = l % NP, b = (l / NP) % NP, c = l / (NP * NP);
-        ft[j] = (a != 0 || lox) && (a != NP - 1 || hix) && (b != 0 || loy) && (b != NP - 1 || hiy) &&
-                (c != 0 || loz) && (c != NP - 1 || hiz);
-        yr[j] = 0.0;
-        cqv[j] = T(0);
-        if (ft[j]) {
-          yr[j] = A.yres[(int64_t)node[j] * A.ldyr + nn];
-          if (cp.supp) cqv[j] = *elem(A.cq, ldyb, nn, node[j]);
-        }
-      }
-      const double aly = A.alpha * A.lamY[valid ? n : 0];
-      T hT[NJ];
 #pragma unroll
       for (int j = 0; j < NJ; ++j)
-        hT[j] = *reinterpret_cast<const T*>(reinterpret_cast<const char*>(sK) + k_of_u(pk[j] & ((1u << kLdsBits) - 1)));
-      T out[NJ];
-#pragma unroll
-      for (int j = 0; j < NJ; ++j) {
-        if (ft[j]) {
-          const T part = (T)(-A.sac) * ry[j] - (T)A.szz * yo[j];
-          out[j] = (T)((double)part + yr[j] * aly) + cqv[j] + A.alpha * hT[j];
-        } else {
-          out[j] = yo[j] + A.alpha * hT[j];
-        }
-      }
-      // the next item's values into U (free now; ry is replaced here too)
-      stage();
-      if (valid) {
-#pragma unroll
-        for (int j = 0; j < NJ; ++j)
-          if (lreal(j)) *elem(A.Y, ldyb, n, node[j]) = out[j];
-      }
+        if (lreal(j))
+          *elem(A.Y, ldyb, n, node[j]) =
+              yo[j] + A.alpha * *reinterpret_cast<const T*>(reinterpret_cast<const char*>(sK) +
+                                                             k_of_u(pk[j] & ((1u << kLdsBits) - 1)));
     }
     __syncthreads();
     cur_c = nxt_c;
@@ -882,53 +783,6 @@ pawfe_status launch_cell_valu(const pawfe_op* op, const CellArgs<T>& a, hipStrea
     default: *done = false; return PAWFE_OK;
   }
 }
-
-template <typename T>
-pawfe_status launch_cell_step(const pawfe_op* op, const T* RY, T* RX, const T* CD, const T* CQ, int64_t ld,
-                              const double* Y, int64_t ldy, const double* lamY, double a, double ac, double zz,
-                              int ncols, hipStream_t s, bool* done) {
-  *done = false;
-  if (op->cplx || op->nq != op->p + 2 || op->p < 2 || op->p > 6) return PAWFE_OK;
-  if (ncols <= 0) {
-    *done = true;
-    return PAWFE_OK;
-  }
-  if (ld < 0 || ld * (int64_t)sizeof(T) >= (int64_t(1) << 32)) return fail(PAWFE_EINVAL, "row stride of 4 GiB or more");
-  CellArgs<T> c{};
-  c.X = RY;
-  c.ldx = ld;
-  c.Y = RX;
-  c.ldy = ld;
-  c.ncols = ncols;
-  c.Vw = std::is_same<T, double>::value ? (const T*)op->d.Vw : (const T*)op->d.Vw_f;
-  c.alpha = (T)a;
-  c.n0 = op->n[0];
-  c.n1 = op->n[1];
-  c.n2 = op->n[2];
-  c.cd = CD;
-  c.cq = CQ;
-  c.yres = Y;
-  c.ldyr = ldy;
-  c.lamY = lamY;
-  c.sac = ac;
-  c.szz = zz;
-  c.detJ = op->detJ;
-  *done = true;
-  switch (op->p) {
-    case 2: return run_cell_valu<T, 3, 4, kModeStep>(op, c, s);
-    case 3: return run_cell_valu<T, 4, 5, kModeStep>(op, c, s);
-    case 4: return run_cell_valu<T, 5, 6, kModeStep>(op, c, s);
-    case 5: return run_cell_valu<T, 6, 7, kModeStep>(op, c, s);
-    default: return run_cell_valu<T, 7, 8, kModeStep>(op, c, s);
-  }
-}
-
-template pawfe_status launch_cell_step<float>(const pawfe_op*, const float*, float*, const float*, const float*,
-                                              int64_t, const double*, int64_t, const double*, double, double, double,
-                                              int, hipStream_t, bool*);
-template pawfe_status launch_cell_step<double>(const pawfe_op*, const double*, double*, const double*,
-                                               const double*, int64_t, const double*, int64_t, const double*, double,
-                                               double, double, int, hipStream_t, bool*);
 
 template pawfe_status launch_cell_valu<float>(const pawfe_op*, const CellArgs<float>&, hipStream_t, bool*);
 template pawfe_status launch_cell_valu<double>(const pawfe_op*, const CellArgs<double>&, hipStream_t, bool*);

@@ -103,6 +103,118 @@ __global__ void __launch_bounds__(256) k_nl_reduce(const T* __restrict__ X, int6
     if (al < npj) part[(int64_t)(po + al) * ncols + n] = (double)acc[al];
 }
 
+// The same reduction on the matrix cores (real operators, FP32 data), as
+// the long-K skinny product  c[alpha][n] = sum_r C[r][alpha] x[r][n]:
+// projectors alpha on the M side (two 16-blocks), support rows r on K,
+// columns n on N.  Each wave owns 64 columns (four 16-column blocks).
+//   FP32:   v_mfma_f32_16x16x4f32, 4 rows per step; A[i][k] (lane i + 16k) =
+//           C[r0 + k][16 b + i], B[k][j] (lane j + 16k) = x[r0 + k][n + j].
+//   bf16x3: v_mfma_f32_16x16x16_bf16, 16 rows per step; lane (i, g) holds rows
+//           r0 + 4g + e (e = 0..3) of its projector / column; both operands
+//           split as hi = bf16(v), lo = bf16(v - hi), the product taken as
+//           lo*hi + hi*lo + hi*hi with FP32 accumulation.
+// D[i][j] sits in lane j + 16g, element e, i = 4g + e.
+typedef float RF4 __attribute__((ext_vector_type(4)));
+typedef short RB4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short nl_bf16(float x, float& back) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  back = __uint_as_float(u & 0xFFFF0000u);
+  return (short)(u >> 16);
+}
+
+template <bool SCALE, bool BF3>
+__global__ void __launch_bounds__(256) k_nl_reduce_mfma(const float* __restrict__ X, int64_t ldx, int ncols,
+                                                        const float* __restrict__ Minv,
+                                                        const float* __restrict__ Cv, DeviceTables d,
+                                                        double* __restrict__ part) {
+  const int item = blockIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nbase = (blockIdx.y * kRowsPerWaveGroup + w) * 64;
+  if (nbase >= ncols) return;   // wave-uniform
+  const int a = d.item_atom[item];
+  const int npj = d.nproj[a];
+  const int r0 = d.item_row0[item], r1 = d.item_row1[item];
+  const int noff = d.atom_noff[a], coff = d.atom_coff[a];
+  const int i = lane & 15, g = lane >> 4;
+  RF4 acc[2][4];
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) acc[b][cb] = RF4{0.f, 0.f, 0.f, 0.f};
+  constexpr int RPS = BF3 ? 16 : 4;            // support rows per step
+  constexpr int RPL = BF3 ? 4 : 1;             // of them per lane
+  for (int rb = r0; rb < r1; rb += RPS) {
+    float xv[4][RPL], cv[2][RPL];
+#pragma unroll
+    for (int e = 0; e < RPL; ++e) {
+      const int r = rb + g * RPL + e;
+      const bool rin = r < r1;
+      const int rr = rin ? r : r1 - 1;
+      const int I = d.atom_nodes[noff + rr];
+      const float m = SCALE ? Minv[I] : 1.0f;
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) {
+        const int n = nbase + 16 * cb + i;
+        const float v = X[(int64_t)I * ldx + (n < ncols ? n : 0)];
+        xv[cb][e] = (rin && n < ncols) ? v * m : 0.0f;
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int al = 16 * b + i;
+        const float c = Cv[coff + (int64_t)rr * npj + (al < npj ? al : 0)];
+        cv[b][e] = al < npj ? c : 0.0f;
+      }
+    }
+    if constexpr (!BF3) {
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+          acc[b][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(cv[b][0], xv[cb][0], acc[b][cb], 0, 0, 0);
+    } else {
+      RB4 chi[2], clo[2], xhi[4], xlo[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          float h, dummy;
+          chi[b][e] = nl_bf16(cv[b][e], h);
+          clo[b][e] = nl_bf16(cv[b][e] - h, dummy);
+        }
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+          float h, dummy;
+          xhi[cb][e] = nl_bf16(xv[cb][e], h);
+          xlo[cb][e] = nl_bf16(xv[cb][e] - h, dummy);
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+          acc[b][cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(clo[b], xhi[cb], acc[b][cb], 0, 0, 0);
+          acc[b][cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(chi[b], xlo[cb], acc[b][cb], 0, 0, 0);
+          acc[b][cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(chi[b], xhi[cb], acc[b][cb], 0, 0, 0);
+        }
+    }
+  }
+  const int po = d.item_poff[item];
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      const int n = nbase + 16 * cb + i;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int al = 16 * b + 4 * g + e;
+        if (al < npj && n < ncols) part[(int64_t)(po + al) * ncols + n] = (double)acc[b][cb][e];
+      }
+    }
+}
+
 __global__ void __launch_bounds__(256) k_nl_final(const double* __restrict__ part, int ncols,
                                                   const int32_t* __restrict__ proj_atom,
                                                   const int32_t* __restrict__ proj_alpha, DeviceTables d,
@@ -389,10 +501,7 @@ constexpr int kFixUnroll = 8;
 // CPLX (complex operators): (re, im) column pairs, C v mixes them:
 // + s Ci v[n ^ 1], s = -1 on real and +1 on imaginary columns (partner value
 // from the neighbouring lane).
-// FW (first write): the outputs are overwritten, not added to, on the rows
-// where this atom has the lowest colour of the atoms sharing the node
-// (d.atom_first), so they need no clearing between uses.
-template <typename TR, typename TO1, int NPJ, bool MINV, bool HAS2, bool CPLX = false, bool FW = false>
+template <typename TR, typename TO1, int NPJ, bool MINV, bool HAS2, bool CPLX = false>
 __global__ void __launch_bounds__(256) k_nl_fixup(const int32_t* __restrict__ fatom,
                                                   const int32_t* __restrict__ frow0,
                                                   const int32_t* __restrict__ frow1, int ncols,
@@ -440,14 +549,8 @@ __global__ void __launch_bounds__(256) k_nl_fixup(const int32_t* __restrict__ fa
       for (int u = 0; u < kFixUnroll; ++u) I[u] = d.atom_nodes[noff + rb + u];   // list padded
 #pragma unroll
       for (int u = 0; u < kFixUnroll; ++u) {   // rows touched once: non-temporal
-        if constexpr (FW) {
-          const bool fresh = d.atom_first[noff + rb + u] != 0;   // list padded like atom_nodes
-          o1[u] = fresh ? (TO1)0 : __builtin_nontemporal_load(out1 + (int64_t)I[u] * ld1 + n);
-          if constexpr (HAS2) o2[u] = fresh ? (TR)0 : __builtin_nontemporal_load(out2 + (int64_t)I[u] * ld2 + n);
-        } else {
-          o1[u] = __builtin_nontemporal_load(out1 + (int64_t)I[u] * ld1 + n);
-          if constexpr (HAS2) o2[u] = __builtin_nontemporal_load(out2 + (int64_t)I[u] * ld2 + n);
-        }
+        o1[u] = __builtin_nontemporal_load(out1 + (int64_t)I[u] * ld1 + n);
+        if constexpr (HAS2) o2[u] = __builtin_nontemporal_load(out2 + (int64_t)I[u] * ld2 + n);
       }
 #pragma unroll
       for (int u = 0; u < kFixUnroll; ++u) {
@@ -649,12 +752,29 @@ const T* pick(const double* d64, const float* d32) {
 
 template <typename T>
 pawfe_status launch_nl_reduce(const pawfe_op* op, const T* X, int64_t ldx, int ncols, bool scale_minv,
-                              double* part, double* c, hipStream_t s) {
+                              double* part, double* c, hipStream_t s, bool bf3) {
   if (op->natoms == 0 || ncols <= 0) return PAWFE_OK;
   const T* Cv = pick<T>(op->d.Cvals, op->d.Cvals_f);
   const T* Minv = pick<T>(op->d.Minv, op->d.Minv_f);
   const T* Cvi = pick<T>(op->d.Cvals_im, op->d.Cvals_im_f);
   const dim3 grid(op->nitems, (ncols + 255) / 256), block(256);
+  if constexpr (std::is_same<T, float>::value) {
+    if (!op->cplx) {   // real operators in FP32: the matrix-core reduction
+      auto go = [&](auto scale, auto b3) {
+        constexpr bool SC = decltype(scale)::value, B3 = decltype(b3)::value;
+        hipLaunchKernelGGL((k_nl_reduce_mfma<SC, B3>), grid, block, 0, s, X, ldx, ncols, Minv, Cv, op->d, part);
+      };
+      if (scale_minv) {
+        if (bf3) go(std::true_type{}, std::true_type{}); else go(std::true_type{}, std::false_type{});
+      } else {
+        if (bf3) go(std::false_type{}, std::true_type{}); else go(std::false_type{}, std::false_type{});
+      }
+      const dim3 g2(op->npj_total, (ncols + 255) / 256);
+      hipLaunchKernelGGL(k_nl_final, g2, block, 0, s, part, ncols, op->d_proj_atom, op->d_proj_alpha, op->d, c);
+      PAWFE_HIP(hipGetLastError());
+      return PAWFE_OK;
+    }
+  }
   auto go = [&](auto scale, auto cplx) {
     constexpr bool SC = decltype(scale)::value, CX = decltype(cplx)::value;
     if (op->npj_max <= 8)
@@ -675,9 +795,9 @@ pawfe_status launch_nl_reduce(const pawfe_op* op, const T* X, int64_t ldx, int n
   return PAWFE_OK;
 }
 template pawfe_status launch_nl_reduce<double>(const pawfe_op*, const double*, int64_t, int, bool, double*, double*,
-                                               hipStream_t);
+                                               hipStream_t, bool);
 template pawfe_status launch_nl_reduce<float>(const pawfe_op*, const float*, int64_t, int, bool, double*, double*,
-                                              hipStream_t);
+                                              hipStream_t, bool);
 
 pawfe_status launch_atom_mul(const pawfe_op* op, const double* D1, const double* D2, const double* lam, double f,
                              const double* in, double* out, int ncols, hipStream_t s, const double* D1i) {
@@ -715,8 +835,7 @@ pawfe_status launch_atom_gcorr(const pawfe_op* op, const double* c, const double
 }
 
 // out1 += s1 w C v1 (w = M_D^{-1} if MINV), out2 += C v2 (if HAS2), atom colour by colour
-// (FW: written instead of added on each node's first atom colour)
-template <typename TR, typename TO1, bool MINV, bool HAS2, bool FW = false>
+template <typename TR, typename TO1, bool MINV, bool HAS2>
 pawfe_status nl_fixup(const pawfe_op* op, int ncols, const double* v1, double s1, TO1* out1, int64_t ld1,
                       const double* v2, TR* out2, int64_t ld2, hipStream_t s) {
   if (op->natoms == 0 || ncols <= 0) return PAWFE_OK;
@@ -731,13 +850,13 @@ pawfe_status nl_fixup(const pawfe_op* op, int ncols, const double* v1, double s1
     auto go = [&](auto cplx) {
       constexpr bool CX = decltype(cplx)::value;
       if (op->npj_max <= 8)
-        hipLaunchKernelGGL((k_nl_fixup<TR, TO1, 8, MINV, HAS2, CX, FW>), grid, block, 0, s, fa, f0, f1, ncols, v1, s1,
+        hipLaunchKernelGGL((k_nl_fixup<TR, TO1, 8, MINV, HAS2, CX>), grid, block, 0, s, fa, f0, f1, ncols, v1, s1,
                            out1, ld1, v2, out2, ld2, Minv, Cv, op->d, Cvi);
       else if (op->npj_max <= 18)
-        hipLaunchKernelGGL((k_nl_fixup<TR, TO1, 18, MINV, HAS2, CX, FW>), grid, block, 0, s, fa, f0, f1, ncols, v1, s1,
+        hipLaunchKernelGGL((k_nl_fixup<TR, TO1, 18, MINV, HAS2, CX>), grid, block, 0, s, fa, f0, f1, ncols, v1, s1,
                            out1, ld1, v2, out2, ld2, Minv, Cv, op->d, Cvi);
       else
-        hipLaunchKernelGGL((k_nl_fixup<TR, TO1, 32, MINV, HAS2, CX, FW>), grid, block, 0, s, fa, f0, f1, ncols, v1, s1,
+        hipLaunchKernelGGL((k_nl_fixup<TR, TO1, 32, MINV, HAS2, CX>), grid, block, 0, s, fa, f0, f1, ncols, v1, s1,
                            out1, ld1, v2, out2, ld2, Minv, Cv, op->d, Cvi);
     };
     if (op->cplx) go(std::true_type{}); else go(std::false_type{});
@@ -812,34 +931,6 @@ template pawfe_status launch_node_cheb<double>(const pawfe_op*, const double*, d
 template pawfe_status launch_node_cheb<float>(const pawfe_op*, const float*, float*, float*, int64_t, const double*,
                                               int64_t, const double*, const double*, const double*, double*,
                                               const double*, double, double, double, int, hipStream_t);
-
-// Fused Chebyshev step, projector part: CD = C d and CQ = C q (q already
-// scaled by a) on the support nodes, written per node by its first atom
-// colour and added to by the later ones; rows outside every support are not
-// touched (the caller keeps them zero).
-template <typename TR>
-pawfe_status launch_step_nl(const pawfe_op* op, const double* dv, const double* qv, int ncols, TR* CD, TR* CQ,
-                            int64_t ld, hipStream_t s) {
-  return nl_fixup<TR, TR, false, true, true>(op, ncols, dv, 1.0, CD, ld, qv, CQ, ld, s);
-}
-template pawfe_status launch_step_nl<double>(const pawfe_op*, const double*, const double*, int, double*, double*,
-                                             int64_t, hipStream_t);
-template pawfe_status launch_step_nl<float>(const pawfe_op*, const double*, const double*, int, float*, float*,
-                                            int64_t, hipStream_t);
-
-__global__ void k_lam_step(int ncols, const double* __restrict__ lamY, double* __restrict__ lamX,
-                           const double* __restrict__ lam_in, double a, double ac, double zz) {
-  const int n = blockIdx.x * 256 + threadIdx.x;
-  if (n < ncols) lamX[n] = a * lamY[n] * lam_in[n] - ac * lamY[n] - zz * lamX[n];
-}
-
-pawfe_status launch_lam_step(const double* lamY, double* lamX, const double* lam_in, double a, double ac,
-                             double zz, int ncols, hipStream_t s) {
-  if (ncols <= 0) return PAWFE_OK;
-  hipLaunchKernelGGL(k_lam_step, dim3((ncols + 255) / 256), dim3(256), 0, s, ncols, lamY, lamX, lam_in, a, ac, zz);
-  PAWFE_HIP(hipGetLastError());
-  return PAWFE_OK;
-}
 
 template <typename TR>
 pawfe_status launch_node_finalize(const pawfe_op* op, const TR* RY, int64_t ld, const double* dv, const double* X,

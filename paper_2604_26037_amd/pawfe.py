@@ -31,7 +31,7 @@ EXPORTS = [
     "pawfe_rayleigh_ritz", "pawfe_band_energy_grad", "pawfe_lanczos_bounds", "pawfe_last_error",
     "pawfe_chfsi_solve_workspace", "pawfe_chfsi_solve",
     "pawfe_batch_create", "pawfe_batch_run", "pawfe_batch_query", "pawfe_batch_destroy",
-    "pawfe_apply_H_noalloc",
+    "pawfe_apply_H_noalloc", "pawfe_halo_pack_bf16", "pawfe_halo_unpack_bf16",
 ]
 
 
@@ -84,6 +84,8 @@ def load(path=LIB_PATH):
         "pawfe_set_dH": [vp, P(dbl), vp],
         "pawfe_apply_H": [vp, vp, i64, vp, i64, i64, i32, vp],
         "pawfe_apply_H_noalloc": [vp, vp, i64, vp, i64, i64, i32, vp],
+        "pawfe_halo_pack_bf16": [vp, vp, i64, i64, i32, i32, vp, vp],
+        "pawfe_halo_unpack_bf16": [vp, vp, i64, i32, i32, vp, i64, vp],
         "pawfe_apply_S": [vp, vp, i64, vp, i64, i64, i32, vp],
         "pawfe_apply_Sinv": [vp, vp, i64, vp, i64, i64, i32, vp],
         "pawfe_apply_local": [vp, i32, vp, i64, vp, i64, i64, dbl, i32, vp],
@@ -182,6 +184,8 @@ class Operator:
         (self.ndof, self.nquad, self.ncolour, self.nproj_total, self.nsupp_cells,
          self.nsupp_nodes) = [x.value for x in a]
         self.ncells = int(np.prod(s.ncell))
+        self.ncell = tuple(int(v) for v in s.ncell)
+        self.degree = int(s.degree)
         self.nloc = (int(s.degree) + 1) ** 3
         # complex (k-point) operators take complex tensors (leading dimensions
         # in complex elements)
@@ -246,6 +250,25 @@ class Operator:
         """H X through the allocation-free entry point (out must be given)."""
         assert out is not None
         return self._apply(_lib.pawfe_apply_H_noalloc, X, out, prec, stream)
+
+    def halo_pack_bf16(self, Y, kz0, kz1, buf=None, stream=None):
+        """BF16 bits of the FP32 block Y on the slab's two shared node planes:
+        a device int16 tensor [2][Gx*Gy][ncols] (the bits of each BF16)."""
+        import torch
+        assert Y.is_cuda and Y.dtype == (torch.complex64 if self.complex else torch.float32) and Y.stride(1) == 1
+        nc = Y.shape[1] * (2 if self.complex else 1)
+        prow = (self.ncell[0] * self.degree) * (self.ncell[1] * self.degree)
+        if buf is None:
+            buf = torch.empty((2, prow, nc), dtype=torch.int16, device=Y.device)
+        _check(_lib.pawfe_halo_pack_bf16(self._h, _tptr(Y), Y.stride(0), Y.shape[1], int(kz0), int(kz1),
+                                         _tptr(buf), _stream(stream)))
+        return buf
+
+    def halo_unpack_bf16(self, buf, Y, kz0, kz1, stream=None):
+        """Y += the BF16 planes of buf (cast to FP32), in place."""
+        _check(_lib.pawfe_halo_unpack_bf16(self._h, _tptr(buf), Y.shape[1], int(kz0), int(kz1), _tptr(Y),
+                                           Y.stride(0), _stream(stream)))
+        return Y
 
     def apply_S(self, X, out=None, prec=FP64, stream=None):
         return self._apply(_lib.pawfe_apply_S, X, out, prec, stream)

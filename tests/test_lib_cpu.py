@@ -24,7 +24,7 @@ def _lib():
 def test_exports_match_header():
     lib = _lib()
     hdr = open(os.path.join(ROOT, "include", "pawfe.h")).read()
-    declared = sorted(set(re.findall(r"\b(pawfe_[a-zA-Z_]+)\s*\(", hdr)))
+    declared = sorted(set(re.findall(r"\b(pawfe_[a-zA-Z0-9_]+)\s*\(", hdr)))
     assert sorted(pw.EXPORTS) == declared
     for name in declared:
         assert hasattr(lib, name), name
