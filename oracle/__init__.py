@@ -11,7 +11,8 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import it.  The product path never calls into it.
 
 Modules
-  fe      mesh, DOF map, colouring, reference element, local operators
+  fe      mesh (uniform or graded two-level), DOF map, colouring,
+          reference element, local operators with the optional GGA term
           (FE discretization section; cell-level H/M entries)
   paw     projectors, projector matrix C^a, PAW H/S, approximate inverse
           overlap (FE non-local contribution; Sinv approximation)

@@ -29,12 +29,13 @@ def grad_veff(op, X, occ=None, cells=None):
     """dE/dV at every quadrature point, shape (E, nq^3); with ``cells`` only at
     the points of those cells, shape (len(cells), nq^3)."""
     occ = np.ones(X.shape[1]) if occ is None else np.asarray(occ, dtype=np.float64)
-    cq = op.cq
-    cd = op.cell_dofs if cells is None else op.cell_dofs[np.asarray(cells)]
+    cells = np.arange(op.mesh.E) if cells is None else np.asarray(cells)
+    cd = op.cell_dofs[cells]
     Xe = X[cd]                                             # (ncells, nloc, ncol)
-    U = cq.N @ Xe                                          # (E, nq^3, ncol)
+    U = op.cq.N @ Xe                                       # (ncells, nq^3, ncol); N is size-free
     dens = np.einsum("eqn,eqn,n->eq", U.conj(), U, occ).real
-    return cq.W[None, :] * dens
+    W = np.stack([op.loc.cell_cq(e).W for e in cells])     # per-cell det J on graded meshes
+    return W * dens
 
 
 def grad_dH(op, X, occ=None):

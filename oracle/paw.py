@@ -53,18 +53,37 @@ def projector_value(l, m, sigma, rc, d):
     return np.where(inside, solid_harmonic(l, m, d) * g, 0.0)
 
 
+def _axis_images(bounds, L, lo, hi):
+    """(cell i, shift s) along one axis whose interval [b_i, b_{i+1}] + s L
+    meets [lo, hi]."""
+    out = []
+    for s in range(int(np.floor(lo / L)) - 1, int(np.floor(hi / L)) + 2):
+        for i in range(len(bounds) - 1):
+            if bounds[i] + s * L <= hi and bounds[i + 1] + s * L >= lo:
+                out.append((i, s))
+    return out
+
+
 def cell_image_pairs(mesh: Mesh, R, rc):
     """All (cell e, image shift vector s*L) whose cell box can reach the sphere.
 
-    Unwrapped cell index iu in [floor((R-rc)/h), floor((R+rc)/h)] per axis;
-    the actual cell is iu mod n and the point x of that cell sits at x + s*L
-    with s = floor(iu / n) in the unwrapped frame.
+    Uniform mesh: unwrapped cell index iu in [floor((R-rc)/h), floor((R+rc)/h)]
+    per axis; the actual cell is iu mod n and the point x of that cell sits at
+    x + s*L with s = floor(iu / n) in the unwrapped frame.  Graded mesh: per
+    axis every (cell, shift) whose shifted interval meets [R-rc, R+rc].
     """
     R = np.asarray(R, dtype=np.float64)
-    lo = np.floor((R - rc) / mesh.h).astype(int)
-    hi = np.floor((R + rc) / mesh.h).astype(int)
     nx, ny, nz = mesh.ncell
     out = []
+    if mesh.graded:
+        ax = [_axis_images(mesh.bounds[d], mesh.box[d], R[d] - rc, R[d] + rc) for d in range(3)]
+        for k, sk in ax[2]:
+            for j, sj in ax[1]:
+                for i, si in ax[0]:
+                    out.append((i + nx * (j + ny * k), np.array([si, sj, sk]) * mesh.box))
+        return out
+    lo = np.floor((R - rc) / mesh.h).astype(int)
+    hi = np.floor((R + rc) / mesh.h).astype(int)
     for ku in range(lo[2], hi[2] + 1):
         for ju in range(lo[1], hi[1] + 1):
             for iu in range(lo[0], hi[0] + 1):
@@ -80,12 +99,12 @@ class PAWOperator:
     def __init__(self, system, sinv_mode="exact_g"):
         s = system
         self.system = s
-        self.mesh = Mesh(s.ncell, s.box, s.degree)
+        self.mesh = Mesh(s.ncell, s.box, s.degree, getattr(s, "xgrid", None))
         k = np.asarray(s.kpoint, dtype=np.float64)
         self.kpoint = k if np.any(k) else None
         self.complex = bool(s.is_complex) or self.kpoint is not None
         self.dtype = np.complex128 if self.complex else np.float64
-        self.loc = LocalOperator(self.mesh, s.nq, s.veff_q, self.kpoint)
+        self.loc = LocalOperator(self.mesh, s.nq, s.veff_q, self.kpoint, getattr(s, "vgga_q", None))
         self.cq = self.loc.cq
         self.MD = lumped_mass(self.mesh)
         self.MDinv = 1.0 / self.MD
@@ -101,7 +120,7 @@ class PAWOperator:
 
     # -- eq. FEM Cmatrix ------------------------------------------------------
     def _build_projectors(self):
-        s, mesh, cq = self.system, self.mesh, self.cq
+        s, mesh = self.system, self.mesh
         rows, cols, vals = [], [], []
         self.supp_cells, self.supp_nodes = [], []
         self.Gpp = []
@@ -113,6 +132,7 @@ class PAWOperator:
             Cloc = {}     # cell -> (nloc, npj) contribution
             Gpp = np.zeros((npj, npj))
             for e, shift in cell_image_pairs(mesh, R, rc):
+                cq = self.loc.cell_cq(e)
                 xq = cq.points(mesh, e) + shift            # unwrapped positions
                 d = xq - R
                 if not np.any((d * d).sum(axis=1) < rc * rc):

@@ -138,6 +138,11 @@ class System:
     iterations: int
     x_seed: int
     spec: ConfigSpec = field(repr=False, default=None)
+    # graded mesh: per-axis cell boundaries (ncell[d] + 1 each, 0 .. box[d]);
+    # None = uniform cells
+    xgrid: tuple = None
+    # GGA vector field V_GGA at the Gauss points, [E][3][nq^3]; None = no GGA term
+    vgga_q: np.ndarray = field(repr=False, default=None)
 
     @property
     def ndof(self) -> int:
@@ -269,6 +274,103 @@ def sample_wells(wells, ncell, box, nq, depth=WELL_DEPTH, width=WELL_WIDTH,
         val = np.where(r2 < r2max, -depth * np.exp(-r2 / (2.0 * width * width)), 0.0)
         np.add.at(V, e, val)
     return V
+
+
+def two_level_grid(ncell, box, pos, r_fine):
+    """Per-axis cell boundaries of a two-level mesh: on the uniform grid of
+    ncell[d] cells, a cell whose centre lies within r_fine (periodically) of
+    some atom coordinate along that axis is fine, the others coarse, and the
+    coarse cells are made twice as long as the fine ones (each axis still
+    spans box[d] in ncell[d] cells)."""
+    out = []
+    pos = np.asarray(pos, dtype=np.float64).reshape(-1, 3)
+    for d in range(3):
+        n, L = int(ncell[d]), float(box[d])
+        centres = (np.arange(n) + 0.5) * L / n
+        fine = np.zeros(n, dtype=bool)
+        for x in pos[:, d]:
+            dist = np.abs(centres - x)
+            dist = np.minimum(dist, L - dist)
+            fine |= dist < r_fine
+        length = np.where(fine, 1.0, 2.0)
+        b = np.concatenate([[0.0], np.cumsum(length)]) * (L / length.sum())
+        b[-1] = L
+        out.append(b)
+    return tuple(out)
+
+
+def _gauss_1d(bounds, L, nq, lo, hi):
+    """Gauss points along one axis of every (cell, periodic image) whose
+    interval [b_i, b_{i+1}] + s L meets [lo, hi]: (cell indices, points[n, nq])."""
+    eta = _gauss_legendre(nq)
+    cells, pts = [], []
+    for s in range(int(np.floor(lo / L)) - 1, int(np.floor(hi / L)) + 2):
+        for i in range(len(bounds) - 1):
+            a, b = bounds[i] + s * L, bounds[i + 1] + s * L
+            if a <= hi and b >= lo:
+                cells.append(i)
+                pts.append(a + 0.5 * (eta + 1.0) * (b - a))
+    return np.asarray(cells, dtype=np.int64), np.asarray(pts).reshape(-1, nq)
+
+
+def sample_centred(centres, ncell, box, nq, xgrid, cutoff, fn, ncomp):
+    """Sum over centres c and periodic images of fn(d) at every Gauss point x
+    (d = x - c - L_r, terms with |d| >= cutoff dropped), on the uniform
+    (xgrid None) or graded grid.  fn maps d[..., 3] to [..., ncomp].
+    Returns [E][ncomp][nq^3]."""
+    ncell = np.asarray(ncell)
+    box = np.asarray(box, dtype=np.float64)
+    if xgrid is None:
+        xgrid = [np.arange(ncell[d] + 1) * (box[d] / ncell[d]) for d in range(3)]
+    E = int(np.prod(ncell))
+    out = np.zeros((E, ncomp, nq ** 3))
+    for c in np.asarray(centres, dtype=np.float64).reshape(-1, 3):
+        ax = [_gauss_1d(np.asarray(xgrid[d]), box[d], nq, c[d] - cutoff, c[d] + cutoff) for d in range(3)]
+        (ci, xi), (cj, yj), (ck, zk) = ax
+        # d[k, j, i, qz, qy, qx, 3]
+        dx = (xi - c[0])[None, None, :, None, None, :]
+        dy = (yj - c[1])[None, :, None, None, :, None]
+        dz = (zk - c[2])[:, None, None, :, None, None]
+        shape = (len(ck), len(cj), len(ci), nq, nq, nq)
+        d = np.stack(np.broadcast_arrays(dx, dy, dz), axis=-1).reshape(shape + (3,))
+        r2 = (d * d).sum(axis=-1)
+        val = np.where((r2 < cutoff * cutoff)[..., None], fn(d), 0.0)     # shape + (ncomp,)
+        e = (ci[None, None, :] + ncell[0] * (cj[None, :, None] + ncell[1] * ck[:, None, None])).ravel()
+        val = val.reshape(len(e), nq ** 3, ncomp).transpose(0, 2, 1)
+        np.add.at(out, e, val)
+    return out
+
+
+def sample_wells_graded(wells, ncell, box, nq, xgrid, depth=WELL_DEPTH, width=WELL_WIDTH,
+                        cutoff=WELL_CUTOFF):
+    """sample_wells on a uniform or graded grid: (E, nq^3)."""
+    fn = lambda d: (-depth * np.exp(-(d * d).sum(axis=-1) / (2.0 * width * width)))[..., None]
+    return sample_centred(wells, ncell, box, nq, xgrid, cutoff, fn, 1)[:, 0, :]
+
+
+def sample_gga(centres, ncell, box, nq, xgrid=None, amp=0.05, width=WELL_WIDTH, cutoff=WELL_CUTOFF):
+    """Synthetic GGA field (the gradient correction is a vector field): the
+    gradient of amp * sum exp(-|d|^2 / (2 width^2)) over centres and images,
+    i.e. -amp d / width^2 exp(-|d|^2 / (2 width^2)); [E][3][nq^3]."""
+    def fn(d):
+        g = np.exp(-(d * d).sum(axis=-1) / (2.0 * width * width))
+        return (-amp / (width * width)) * d * g[..., None]
+    return sample_centred(centres, ncell, box, nq, xgrid, cutoff, fn, 3)
+
+
+def with_two_level_gga(system, r_fine=1.0, gga_amp=0.05, graded=True, gga=True):
+    """The system on a two-level mesh around its atoms (graded=True) and/or
+    with a GGA field centred on its wells (gga=True); the potential is
+    resampled at the new Gauss points."""
+    xg = two_level_grid(system.ncell, system.box, system.pos, r_fine) if graded else None
+    vq = system.veff_q
+    if graded and len(system.wells):
+        vq = sample_wells_graded(system.wells, system.ncell, system.box, system.nq, xg)
+    vg = None
+    if gga:
+        centres = system.wells if len(system.wells) else system.pos
+        vg = np.ascontiguousarray(sample_gga(centres, system.ncell, system.box, system.nq, xg, amp=gga_amp))
+    return dataclasses.replace(system, xgrid=xg, veff_q=np.ascontiguousarray(vq), vgga_q=vg)
 
 
 def random_block(seed, nrows, col0, ncols, is_complex=False):
