@@ -124,6 +124,19 @@ typedef struct {
   const double* dH;
   const double* dS;
   int32_t sinv_mode;
+  /* Graded mesh (FE discretization section; the two-level meshes of the
+   * figure "Finite-element meshes employed in PAW-FE"): NULL for uniform
+   * cells of size box / ncell, else the cell boundaries of the three axes
+   * one after another, ncell[d] + 1 values per axis, rising strictly from 0
+   * to box[d].  Every cell is then an axis-aligned box of its own size (a
+   * diagonal Jacobian per cell); the DOF map and colouring are unchanged.
+   * HOST array, copied. */
+  const double* xgrid;
+  /* GGA term of eq. "FEM Ham entries": NULL, or V_GGA at the Gauss points,
+   * HOST [E][3][nq^3] (component d of cell e at point q), copied.  With a
+   * graded mesh or a GGA field the operator must be real (is_complex = 0)
+   * and PAWFE_BF16X3 is not accepted (PAWFE_EUNSUPPORTED). */
+  const double* vgga_q;
 } pawfe_op_desc;
 
 /* Builds the operator (FE discretization section; eq. "FEM Cmatrix" for the
@@ -158,6 +171,9 @@ pawfe_status pawfe_get_dofmap(const pawfe_op* op, int32_t* cell_dofs, int32_t* c
  * Enqueued on `stream`, synchronizes it.  Delta_Sinv does not depend on
  * either, so nothing else is rebuilt. */
 pawfe_status pawfe_set_veff(pawfe_op* op, const double* veff_q, void* stream);
+/* Replaces V_GGA (HOST array [E][3][nq^3]) of an operator built with one
+ * (PAWFE_EINVAL otherwise).  Enqueued on `stream`, synchronizes it. */
+pawfe_status pawfe_set_vgga(pawfe_op* op, const double* vgga_q, void* stream);
 pawfe_status pawfe_set_dH(pawfe_op* op, const double* dH, void* stream);
 
 /* Y = A X for nvec columns (FE discretization section; cell-matrix AX

@@ -136,9 +136,11 @@ pawfe_status do_residual(const pawfe_op* op, const double* X, int64_t ldx, const
 
 // PAWFE_BF16X3: FP32 data, the cell contractions as bf16x3 split products
 // (everything else as PAWFE_FP32).
-pawfe_status check_prec(int32_t prec) {
-  if (prec == PAWFE_FP64 || prec == PAWFE_FP32 || prec == PAWFE_BF16X3) return PAWFE_OK;
-  return fail(PAWFE_EINVAL, "unknown precision");
+pawfe_status check_prec(int32_t prec, const pawfe_op* op) {
+  if (prec != PAWFE_FP64 && prec != PAWFE_FP32 && prec != PAWFE_BF16X3) return fail(PAWFE_EINVAL, "unknown precision");
+  if (prec == PAWFE_BF16X3 && op->general)
+    return fail(PAWFE_EUNSUPPORTED, "bf16x3 is not built for graded meshes or the GGA term");
+  return PAWFE_OK;
 }
 
 pawfe_status apply_entry(const pawfe_op* cop, int which, const void* X, int64_t ldx, void* Y, int64_t ldy,
@@ -148,7 +150,7 @@ pawfe_status apply_entry(const pawfe_op* cop, int which, const void* X, int64_t 
   if (nvec == 0) return PAWFE_OK;
   if (!X || !Y) return fail(PAWFE_EINVAL, "X or Y is NULL");
   if (ldx < nvec || ldy < nvec) return fail(PAWFE_EINVAL, "leading dimension smaller than nvec");
-  CHECK(check_prec(prec));
+  CHECK(check_prec(prec, cop));
   pawfe_op* op = const_cast<pawfe_op*>(cop);
   if (op->cplx) {   // complex columns as (re, im) pairs of real columns
     nvec *= 2;
@@ -375,13 +377,67 @@ pawfe_status upload_veff(pawfe_op* op, hipStream_t s) {
   // the potential at the Gauss points (same quadrature)
   const double k2 = 0.5 * (op->kpt[0] * op->kpt[0] + op->kpt[1] * op->kpt[1] + op->kpt[2] * op->kpt[2]);
   std::vector<double> vw(op->veff.size());
-  for (int e = 0; e < op->E; ++e)
+  for (int e = 0; e < op->E; ++e) {
+    const double wsc = op->graded ? op->cell_detJ[e] / op->detJ : 1.0;   // the cell's det J
     for (int q = 0; q < op->nq3; ++q)
-      vw[(size_t)e * op->nq3 + q] = (op->veff[(size_t)e * op->nq3 + q] + k2) * op->W3[q];
+      vw[(size_t)e * op->nq3 + q] = (op->veff[(size_t)e * op->nq3 + q] + k2) * (wsc * op->W3[q]);
+  }
   std::vector<float> vwf(vw.begin(), vw.end());
   PAWFE_HIP(hipMemcpyAsync(op->d.Vw, vw.data(), vw.size() * 8, hipMemcpyHostToDevice, s));
   PAWFE_HIP(hipMemcpyAsync(op->d.Vw_f, vwf.data(), vwf.size() * 4, hipMemcpyHostToDevice, s));
   PAWFE_HIP(hipStreamSynchronize(s));
+  return PAWFE_OK;
+}
+
+// per-cell geometry and the GGA table of general operators
+pawfe_status upload_general(pawfe_op* op, hipStream_t s) {
+  if (!op->general) return PAWFE_OK;
+  DeviceTables& d = op->d;
+  const int E = op->E, nq = op->nq, nq3 = op->nq3;
+  std::vector<double> geo((size_t)E * 4), cs(E, 1.0);
+  std::vector<double> hh((size_t)E * 3);
+  for (int e = 0; e < E; ++e) {
+    const int ijk[3] = {e % op->n[0], (e / op->n[0]) % op->n[1], e / (op->n[0] * op->n[1])};
+    double h[3];
+    for (int k = 0; k < 3; ++k) h[k] = op->graded ? op->bnd[k][ijk[k] + 1] - op->bnd[k][ijk[k]] : op->h[k];
+    const double dJ = op->graded ? op->cell_detJ[e] : op->detJ;
+    for (int k = 0; k < 3; ++k) {
+      geo[(size_t)e * 4 + k] = 0.5 * dJ * (2.0 / h[k]) * (2.0 / h[k]);
+      hh[(size_t)e * 3 + k] = h[k];
+    }
+    geo[(size_t)e * 4 + 3] = dJ;
+    cs[e] = dJ / op->detJ;
+  }
+  CHECK(up(op, &d.geo, geo, s));
+  std::vector<float> geof = to_f32(geo);
+  CHECK(up(op, &d.geo_f, geof, s));
+  if (op->graded) CHECK(up(op, &d.cscale, cs, s));
+  if (op->gga) {
+    std::vector<double> vg((size_t)E * 3 * nq3);
+    for (int e = 0; e < E; ++e) {
+      const double dJ = op->graded ? op->cell_detJ[e] : op->detJ;
+      for (int k = 0; k < 3; ++k)
+        for (int qz = 0; qz < nq; ++qz)
+          for (int qy = 0; qy < nq; ++qy)
+            for (int qx = 0; qx < nq; ++qx) {
+              const int q = qx + nq * (qy + nq * qz);
+              const size_t i = ((size_t)e * 3 + k) * nq3 + q;
+              const double w = op->gauss_w[qx] * op->gauss_w[qy] * op->gauss_w[qz] * dJ;
+              vg[i] = w * (2.0 / hh[(size_t)e * 3 + k]) * op->vgga[i];
+            }
+    }
+    if (d.vg) {   // replaced (pawfe_set_vgga): same size, overwrite in place
+      PAWFE_HIP(hipMemcpyAsync(d.vg, vg.data(), vg.size() * 8, hipMemcpyHostToDevice, s));
+      std::vector<float> vgf = to_f32(vg);
+      PAWFE_HIP(hipMemcpyAsync(d.vg_f, vgf.data(), vgf.size() * 4, hipMemcpyHostToDevice, s));
+      PAWFE_HIP(hipStreamSynchronize(s));
+    } else {
+      CHECK(up(op, &d.vg, vg, s));
+      std::vector<float> vgf = to_f32(vg);
+      CHECK(up(op, &d.vg_f, vgf, s));
+    }
+  }
+  PAWFE_HIP(hipStreamSynchronize(s));   // the host vectors above are freed on return
   return PAWFE_OK;
 }
 
@@ -500,6 +556,7 @@ pawfe_status upload(pawfe_op* op, hipStream_t s) {
   CHECK(up(op, &op->d_g2_atom, ga, s));
   CHECK(up(op, &op->d_g2_s, gs, s));
   CHECK(up(op, &op->d_g2_t, gt, s));
+  CHECK(upload_general(op, s));
   return upload_veff(op, s);
 }
 
@@ -644,6 +701,16 @@ pawfe_status pawfe_set_veff(pawfe_op* op, const double* veff_q, void* stream) {
   return upload_veff(op, S(stream));
 }
 
+pawfe_status pawfe_set_vgga(pawfe_op* op, const double* vgga_q, void* stream) {
+  if (!op || !vgga_q) return fail(PAWFE_EINVAL, "op or vgga_q is NULL");
+  if (!op->gga) return fail(PAWFE_EINVAL, "the operator was built without a GGA field");
+  const size_t n = (size_t)op->E * 3 * op->nq3;
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(vgga_q[i])) return fail(PAWFE_ENONFINITE, "vgga_q has NaN/Inf");
+  op->vgga.assign(vgga_q, vgga_q + n);
+  return upload_general(op, S(stream));
+}
+
 pawfe_status pawfe_set_dH(pawfe_op* op, const double* dH, void* stream) {
   if (!op || (!dH && op->npj2_total)) return fail(PAWFE_EINVAL, "op or dH is NULL");
   for (int i = 0; i < op->npj2_total; ++i)
@@ -667,7 +734,7 @@ pawfe_status pawfe_apply_H_noalloc(const pawfe_op* op, const void* X, int64_t ld
   if (nvec == 0) return PAWFE_OK;
   if (!X || !Y) return fail(PAWFE_EINVAL, "X or Y is NULL");
   if (ldx < nvec || ldy < nvec) return fail(PAWFE_EINVAL, "leading dimension smaller than nvec");
-  CHECK(check_prec(prec));
+  CHECK(check_prec(prec, op));
   const int64_t cf = op->cplx ? 2 : 1;   // complex columns as (re, im) pairs of real columns
   nvec *= cf;
   ldx *= cf;
@@ -740,7 +807,7 @@ pawfe_status pawfe_apply_local(const pawfe_op* op, int32_t which, const void* X,
   if (nvec == 0) return PAWFE_OK;
   if (!X || !Y) return fail(PAWFE_EINVAL, "X or Y is NULL");
   if (ldx < nvec || ldy < nvec) return fail(PAWFE_EINVAL, "leading dimension smaller than nvec");
-  CHECK(check_prec(prec));
+  CHECK(check_prec(prec, op));
   const int mode = which == 0 ? kModeH : kModeMass;
   if (nvec > (int64_t)1 << 29) return fail(PAWFE_EINVAL, "nvec too large");
   if (op->cplx) {   // complex columns as (re, im) pairs of real columns
@@ -759,7 +826,7 @@ pawfe_status pawfe_cheb_filter_workspace(const pawfe_op* op, int64_t nvec, int32
                                          size_t* bytes) {
   if (!op || !bytes) return fail(PAWFE_EINVAL, "op or bytes is NULL");
   if (nvec < 1 || block < 1) return fail(PAWFE_EINVAL, "nvec and block must be >= 1");
-  CHECK(check_prec(prec));
+  CHECK(check_prec(prec, op));
   const int64_t B = std::min<int64_t>(block, nvec);
   // room for two blocks in flight when there is more than one block
   *bytes = filter_ws_bytes(op, B * (op->cplx ? 2 : 1), prec) * (nvec > B ? 2 : 1);
@@ -777,7 +844,7 @@ pawfe_status pawfe_cheb_filter(const pawfe_op* op, const void* Xin, int64_t ldx,
   if (!(std::isfinite(b0) && std::isfinite(bW) && std::isfinite(bU)))
     return fail(PAWFE_ENONFINITE, "bounds must be finite");
   if (!(b0 < bW && bW < bU)) return fail(PAWFE_EINVAL, "bounds must satisfy b0 < bW < bU");
-  CHECK(check_prec(prec));
+  CHECK(check_prec(prec, op));
   if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(PAWFE_EINVAL, "workspace must be 256-byte aligned");
   const int64_t cf = op->cplx ? 2 : 1;   // real columns per column
   const int64_t B = std::min<int64_t>(block, nvec);
@@ -1173,7 +1240,7 @@ pawfe_status pawfe_chfsi_solve(const pawfe_op* op, void* X, int64_t ldx, int64_t
   if (nwanted < 0 || nwanted > nvec) return fail(PAWFE_EINVAL, "nwanted must be in 0..nvec");
   if (degree < 2 || block < 1 || max_iter < 0) return fail(PAWFE_EINVAL, "degree >= 2, block >= 1, max_iter >= 0");
   if (!(std::isfinite(tol) && tol > 0.0) || !std::isfinite(bU)) return fail(PAWFE_EINVAL, "tol must be > 0, bU finite");
-  CHECK(check_prec(prec));
+  CHECK(check_prec(prec, op));
   size_t need = 0;
   CHECK(pawfe_chfsi_solve_workspace(op, nvec, block, prec, &need));
   if (ws_bytes < need) return fail(PAWFE_EINVAL, "workspace too small");

@@ -254,6 +254,22 @@ pawfe_status build_host(const pawfe_op_desc* d, pawfe_op* op) {
     op->L[k] = d->box[k];
     op->h[k] = d->box[k] / d->ncell[k];
   }
+  // cell boundaries: given (graded mesh) or i h (uniform)
+  op->graded = d->xgrid != nullptr;
+  {
+    const double* xg = d->xgrid;
+    for (int k = 0; k < 3; ++k) {
+      op->bnd[k].assign(op->n[k] + 1, 0.0);
+      for (int i = 0; i <= op->n[k]; ++i) op->bnd[k][i] = op->graded ? *xg++ : i * op->h[k];
+      if (!op->graded) continue;
+      const std::vector<double>& b = op->bnd[k];
+      if (b[0] != 0.0 || b[op->n[k]] != op->L[k])
+        return fail(PAWFE_EINVAL, "xgrid: each axis must start at 0 and end at the box length");
+      for (int i = 0; i < op->n[k]; ++i)
+        if (!std::isfinite(b[i + 1]) || !(b[i + 1] > b[i]))
+          return fail(PAWFE_EINVAL, "xgrid: cell boundaries must increase strictly");
+    }
+  }
   op->p = p;
   op->np = p + 1;
   op->nq = nq;
@@ -268,6 +284,24 @@ pawfe_status build_host(const pawfe_op_desc* d, pawfe_op* op) {
   const int np = op->np, E = op->E;
   const int64_t nquad = (int64_t)E * op->nq3;
   if (!finite_all(d->veff_q, nquad)) return fail(PAWFE_ENONFINITE, "veff_q has NaN/Inf");
+  op->gga = d->vgga_q != nullptr;
+  if (op->gga) {
+    if (!finite_all(d->vgga_q, 3 * nquad)) return fail(PAWFE_ENONFINITE, "vgga_q has NaN/Inf");
+    op->vgga.assign(d->vgga_q, d->vgga_q + 3 * nquad);
+  }
+  op->general = op->graded || op->gga;
+  if (op->general && op->cplx)
+    return fail(PAWFE_EUNSUPPORTED, "graded meshes and the GGA term are built for real (Gamma-point) operators");
+  // edge length of cell i along axis k, and per-cell det J (graded meshes)
+  auto cell_h = [op](int k, int i) { return op->graded ? op->bnd[k][i + 1] - op->bnd[k][i] : op->h[k]; };
+  op->cell_detJ.clear();
+  if (op->graded) {
+    op->cell_detJ.resize(E);
+    for (int e = 0; e < E; ++e) {
+      const int i = e % op->n[0], j = (e / op->n[0]) % op->n[1], k = e / (op->n[0] * op->n[1]);
+      op->cell_detJ[e] = cell_h(0, i) * cell_h(1, j) * cell_h(2, k) / 8.0;
+    }
+  }
 
   // reference element
   gll_rule(p, op->gll_x, op->gll_w);
@@ -310,11 +344,13 @@ pawfe_status build_host(const pawfe_op_desc* d, pawfe_op* op) {
 
   // lumped GLL mass
   op->MD.assign(op->M, 0.0);
-  for (int e = 0; e < E; ++e)
+  for (int e = 0; e < E; ++e) {
+    const double dJ = op->graded ? op->cell_detJ[e] : op->detJ;
     for (int l = 0; l < op->nloc; ++l) {
       int a = l % np, b = (l / np) % np, c = l / (np * np);
-      op->MD[dof(e, l)] += op->detJ * op->gll_w[a] * op->gll_w[b] * op->gll_w[c];
+      op->MD[dof(e, l)] += dJ * op->gll_w[a] * op->gll_w[b] * op->gll_w[c];
     }
+  }
 
   // colouring: 1-D colour i mod 2, the last cell of an odd direction gets 2
   auto col1 = [](int i, int n) { return (n % 2 == 1 && i == n - 1) ? 2 : i % 2; };
@@ -389,9 +425,16 @@ pawfe_status build_host(const pawfe_op_desc* d, pawfe_op* op) {
     // candidate cells: index window around R, wrapped, de-duplicated
     std::vector<int> cand[3];
     for (int k = 0; k < 3; ++k) {
-      int lo = (int)std::floor((R[k] - rc) / op->h[k]), hi = (int)std::floor((R[k] + rc) / op->h[k]);
       std::vector<int> v;
-      for (int i = lo; i <= hi; ++i) v.push_back(((i % op->n[k]) + op->n[k]) % op->n[k]);
+      if (!op->graded) {
+        int lo = (int)std::floor((R[k] - rc) / op->h[k]), hi = (int)std::floor((R[k] + rc) / op->h[k]);
+        for (int i = lo; i <= hi; ++i) v.push_back(((i % op->n[k]) + op->n[k]) % op->n[k]);
+      } else {   // cells whose interval, or a periodic image of it, meets [R - rc, R + rc]
+        for (int sh = -1; sh <= 1; ++sh)
+          for (int i = 0; i < op->n[k]; ++i)
+            if (op->bnd[k][i] + sh * op->L[k] <= R[k] + rc && op->bnd[k][i + 1] + sh * op->L[k] >= R[k] - rc)
+              v.push_back(i);
+      }
       std::sort(v.begin(), v.end());
       v.erase(std::unique(v.begin(), v.end()), v.end());
       cand[k] = v;
@@ -406,12 +449,18 @@ pawfe_status build_host(const pawfe_op_desc* d, pawfe_op* op) {
           int e = i + op->n[0] * (j + op->n[1] * k);
           std::vector<double> P((size_t)nq3 * npj, 0.0), TH(op->cplx ? nq3 : 0, 0.0);
           bool inside_any = false;
+          const int ijk[3] = {i, j, k};
           for (int qz = 0; qz < nq; ++qz)
             for (int qy = 0; qy < nq; ++qy)
               for (int qx = 0; qx < nq; ++qx) {
                 double x[3] = {(i + 0.5 * (op->gauss_x[qx] + 1.0)) * op->h[0],
                                (j + 0.5 * (op->gauss_x[qy] + 1.0)) * op->h[1],
                                (k + 0.5 * (op->gauss_x[qz] + 1.0)) * op->h[2]};
+                if (op->graded) {
+                  const int qq[3] = {qx, qy, qz};
+                  for (int t = 0; t < 3; ++t)
+                    x[t] = op->bnd[t][ijk[t]] + 0.5 * (op->gauss_x[qq[t]] + 1.0) * cell_h(t, ijk[t]);
+                }
                 double dd[3];
                 for (int t = 0; t < 3; ++t) {
                   dd[t] = x[t] - R[t];
@@ -437,11 +486,12 @@ pawfe_status build_host(const pawfe_op_desc* d, pawfe_op* op) {
           if (!inside_any) continue;
           cells.push_back(e);
           // <p|p> by the same quadrature
+          const double wsc = op->graded ? op->cell_detJ[e] / op->detJ : 1.0;
           for (int q = 0; q < nq3; ++q)
             for (int s = 0; s < npj; ++s) {
               double ps = P[(size_t)q * npj + s];
               if (ps == 0.0) continue;
-              for (int t = 0; t < npj; ++t) Gpp[a][s * npj + t] += op->W3[q] * ps * P[(size_t)q * npj + t];
+              for (int t = 0; t < npj; ++t) Gpp[a][s * npj + t] += wsc * op->W3[q] * ps * P[(size_t)q * npj + t];
             }
           Ppts.push_back(std::move(P));
           Pth.push_back(std::move(TH));
@@ -468,11 +518,12 @@ pawfe_status build_host(const pawfe_op_desc* d, pawfe_op* op) {
     for (int idx : order) {
       const int e = cells[idx];
       const std::vector<double>& P = Ppts[idx];
+      const double wsc = op->graded ? op->cell_detJ[e] / op->detJ : 1.0;
       // C = N^T W (p e^{-i k.x}): real part, then (complex) imaginary part
       for (int part = 0; part < (op->cplx ? 2 : 1); ++part)
       for (int t = 0; t < npj; ++t) {
         for (int q = 0; q < nq3; ++q) {
-          const double wp = op->W3[q] * P[(size_t)q * npj + t];
+          const double wp = wsc * op->W3[q] * P[(size_t)q * npj + t];
           F[q] = !op->cplx ? wp : (part == 0 ? wp * std::cos(Pth[idx][q]) : -wp * std::sin(Pth[idx][q]));
         }
         // x: F[qz][qy][qx] -> T1[qz][qy][a]

@@ -86,6 +86,12 @@ struct DeviceTables {
   int32_t* gp_off = nullptr;      // offset of G^{ab} (nproj_a x nproj_b, row-major)
   double* Gvals = nullptr;
   double* Gvals_im = nullptr;     // complex operators (else null)
+  // general operators (graded mesh and / or the GGA term)
+  double* geo = nullptr;          // [E][4] fx, fy, fz, det J of each cell
+  float* geo_f = nullptr;
+  double* vg = nullptr;           // [E][3][nq^3] W_q det J (2/h_d) V_GGA,d (GGA term)
+  float* vg_f = nullptr;
+  double* cscale = nullptr;       // [E] det J_e / det J (graded meshes; band-energy density)
 };
 
 }  // namespace pawfe
@@ -97,7 +103,17 @@ struct pawfe_op {
   int p, np, nq, nloc, nq3;
   int64_t M;
   int E;
-  double detJ;
+  double detJ;   // det J of a cell of the uniform size box / ncell
+  // graded mesh: per-axis cell boundaries (n[d] + 1 each) and per-cell det J;
+  // uniform meshes keep bnd[d][i] = i h[d] and an empty cell_detJ
+  bool graded = false;
+  std::vector<double> bnd[3];
+  std::vector<double> cell_detJ;
+  // GGA term: V_GGA at the Gauss points, [E][3][nq^3]
+  bool gga = false;
+  std::vector<double> vgga;
+  // graded or GGA: every local term runs on the general vector-ALU variants
+  bool general = false;
   // host tables
   std::vector<double> gll_x, gll_w, gauss_x, gauss_w;
   std::vector<double> B, D, K1, M1, G1, W3, MD;   // G1[a][b] = sum_q w_q N_a N_b' (reference)

@@ -23,6 +23,9 @@ struct CellArgs {
   T alpha;
   int n0, n1, n2;
   int bf3;             // FP32 data, contractions as bf16x3 split products
+  // general operators (vector-ALU kernel variants)
+  const T* geo;        // [E][4] per cell: fx, fy, fz (1/2 det J (2/h_d)^2) and det J
+  const T* vg;         // [E][3][nq^3] W_q det J (2/h_d) V_GGA,d (GGA term), or null
 };
 
 struct DensArgs {
@@ -32,6 +35,7 @@ struct DensArgs {
   const double* occ;
   double* out;
   const double* W3;
+  const double* cscale;   // [E] det J_e / det J of graded meshes, or null
   int n0, n1, n2;
 };
 
@@ -56,6 +60,12 @@ pawfe_status launch_cell_mfma(const pawfe_op* op, int mode, const CellArgs<T>& a
 // variant is compiled for the operator's degree and Gauss rule.
 template <typename T>
 pawfe_status launch_cell_valu(const pawfe_op* op, const CellArgs<T>& a, hipStream_t s, bool* done);
+
+// Every local term of a general operator (graded mesh and / or the GGA term)
+// on the vector ALUs (kernels_cell_gen_f32.hip / _f64.hip): kModeH, kModeMass
+// and kModeHRes (K + V [+ GGA] - lambda_n M).
+template <typename T>
+pawfe_status launch_cell_gen(const pawfe_op* op, int mode, const CellArgs<T>& a, hipStream_t s);
 
 // out[e][q] = W_q sum_n occ_n |u_n(x_{e,q})|^2
 pawfe_status launch_density(const pawfe_op* op, const double* X, int64_t ldx, int ncols,

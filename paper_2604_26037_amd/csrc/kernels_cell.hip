@@ -97,7 +97,8 @@ __global__ void __launch_bounds__(256) k_cell_density(DensArgs A, const Tab1D<do
     }
   }
   __syncthreads();
-  for (int q = tid; q < NQ3; q += 256) A.out[(int64_t)e * NQ3 + q] = A.W3[q] * acc[q];
+  const double cs = A.cscale ? A.cscale[e] : 1.0;
+  for (int q = tid; q < NQ3; q += 256) A.out[(int64_t)e * NQ3 + q] = A.W3[q] * cs * acc[q];
 }
 
 template <typename T>
@@ -119,6 +120,10 @@ pawfe_status launch_cell(const pawfe_op* op, int mode, const T* X, int64_t ldx, 
   a.n0 = op->n[0];
   a.n1 = op->n[1];
   a.n2 = op->n[2];
+  if (op->general) {   // graded mesh / GGA term: every local term on the vector-ALU variants
+    if (bf3) return fail(PAWFE_EUNSUPPORTED, "bf16x3 is not built for graded meshes or the GGA term");
+    return launch_cell_gen<T>(op, mode, a, s);
+  }
   pawfe_status st = PAWFE_OK;
   bool done = false;
   // K + V in FP32 or FP64: vector-ALU kernel (the matrix-core kernel keeps the
@@ -144,6 +149,7 @@ pawfe_status launch_density(const pawfe_op* op, const double* X, int64_t ldx, in
   a.occ = occ;
   a.out = out;
   a.W3 = op->d.W3;
+  a.cscale = op->d.cscale;
   a.n0 = op->n[0];
   a.n1 = op->n[1];
   a.n2 = op->n[2];

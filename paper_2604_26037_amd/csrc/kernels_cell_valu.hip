@@ -1,767 +1,9 @@
-// Local (cell) part of the Hamiltonian in FP32 on the vector ALUs:
-// Y += alpha (K + V) X over the cells of one colour (eq. "FEM Ham entries"
-// without the GGA term, applied cell by cell as in the operator-action
-// subsection), sum-factorized along the three axes of each hexahedral cell.
-//
-// Why not the matrix cores here: in FP32 the gfx950 matrix cores deliver the
-// same rate per SIMD as non-packed FP32 FMAs would at 2x (157 vs 79 TFLOP/s),
-// but every 1-D contraction of a degree-6 element has only 7 or 8 outputs,
-// so a 16x16x4 FP32 MFMA leaves half of its outputs in padding and the
-// padded contractions cost 2.2x the useful work.  Written as plain FMAs on
-// lines of 7-8 values, each 1-D operator can also use the reflection
-// symmetry of the GLL nodes and Gauss points (l_a(-x) = l_{p-a}(x)): with
-// e_a = x_a + x_{p-a} and o_a = x_a - x_{p-a} a 7 -> 8 contraction becomes a
-// 4x4 and a 4x3 product plus 8 additions (42 operations instead of 56 FMAs),
-// and the symmetric, centro-symmetric 1-D stiffness and mass tables a 4x4
-// and a 3x3 product.  The 1-D tables (Lagrange values of the GLL basis at the
-// Gauss points, reference stiffness and mass) depend only on the degree, so
-// they are compile-time constants of the kernel: every coefficient is an
-// instruction literal and no table is read at run time.
-//
-// One workgroup handles one (cell, column tile) item at a time: FP32 8
-// columns and 512 threads, FP64 4 columns and 256 threads; thread t owns
-// column t % CB and line t / CB (of at most 64) of each pass.  Data of the item live in three LDS slabs with the column
-// fastest and the x index padded to 9 (so the 8 lines of a wave start 8
-// banks apart along every axis: no bank conflicts beyond the two cycles a
-// 64-lane access needs):
-//   U: the gathered cell values, then the V path in place (up to 8^3),
-//   K, M: the x-contractions K1 U and M1 U, then the kinetic y and z passes.
-// Passes:
-//   P1 x: U -> B U (in place, 7 -> 8), K1 U -> K, M1 U -> M
-//   P2 y: B (U)   P3 z: B, times V(q) W_q   P4 z: B^T   P5 y: B^T
-//   P6 x: B^T -> U (the V term, 7^3)
-//   P7 y: K <- fx M1 K + fy K1 M,  M <- M1 M
-//   P8 z: K <- U + M1 K + fz K1 M  (the cell result)
-// then the colour-ordered read-modify-write of the result into Y.  The next
-// item's gathered values and this item's old output rows are loaded into
-// registers while the passes run, as in the matrix-core kernel.
+// K + V on the vector ALUs for operators whose cells share one geometry
+// (the kernel and its tables are in cell_valu.h).
 
-#include <type_traits>
-#include <utility>
-
-#include "kernels.h"
+#include "cell_valu.h"
 
 namespace pawfe {
-
-namespace {
-
-// ---- compile-time reference-element tables -----------------------------------
-
-namespace ref1d {
-
-constexpr double kPi = 3.14159265358979323846;
-
-// cos on [0, pi] by its Taylor series about 0 (after folding to [0, pi/2])
-constexpr double cos_c(double x) {
-  bool neg = false;
-  if (x > kPi / 2) {
-    x = kPi - x;
-    neg = true;
-  }
-  double term = 1.0, sum = 1.0;
-  for (int k = 1; k < 24; ++k) {
-    term *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
-    sum += term;
-  }
-  return neg ? -sum : sum;
-}
-
-constexpr double abs_c(double x) { return x < 0 ? -x : x; }
-
-// P_n(x), P_n'(x), P_n''(x) by the three-term recurrence and the Legendre ODE
-struct Leg {
-  double P, dP, d2P;
-};
-constexpr Leg legendre(int n, double x) {
-  double p0 = 1.0, p1 = x;
-  if (n == 0) return {1.0, 0.0, 0.0};
-  for (int k = 2; k <= n; ++k) {
-    const double pk = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
-    p0 = p1;
-    p1 = pk;
-  }
-  // p1 = P_n, p0 = P_{n-1}
-  const double dP = n * (x * p1 - p0) / (x * x - 1.0);
-  const double d2P = (2.0 * x * dP - n * (n + 1.0) * p1) / (1.0 - x * x);
-  return {p1, dP, d2P};
-}
-
-// P_n(x) alone (also at x = +-1)
-constexpr double legendre_P(int n, double x) {
-  double p0 = 1.0, p1 = x;
-  if (n == 0) return 1.0;
-  for (int k = 2; k <= n; ++k) {
-    const double pk = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
-    p0 = p1;
-    p1 = pk;
-  }
-  return p1;
-}
-
-template <int N>
-struct Rule {
-  double x[N] = {};
-  double w[N] = {};
-};
-
-// N-point Gauss-Legendre rule, ascending nodes
-template <int N>
-constexpr Rule<N> gauss() {
-  Rule<N> r{};
-  for (int i = 0; i < N; ++i) {
-    double xi = -cos_c(kPi * (i + 0.75) / (N + 0.5));
-    for (int it = 0; it < 60; ++it) {
-      const Leg l = legendre(N, xi);
-      const double dx = l.P / l.dP;
-      xi -= dx;
-      if (abs_c(dx) < 1e-17) break;
-    }
-    const Leg l = legendre(N, xi);
-    r.x[i] = xi;
-    r.w[i] = 2.0 / ((1.0 - xi * xi) * l.dP * l.dP);
-  }
-  return r;
-}
-
-// GLL nodes of degree P (P + 1 points, ascending): -1, the roots of P_P', +1
-template <int P>
-constexpr Rule<P + 1> gll() {
-  Rule<P + 1> r{};
-  r.x[0] = -1.0;
-  r.x[P] = 1.0;
-  for (int j = 1; j < P; ++j) {
-    double xj = -cos_c(kPi * j / P);
-    for (int it = 0; it < 60; ++it) {
-      const Leg l = legendre(P, xj);
-      const double dx = l.dP / l.d2P;
-      xj -= dx;
-      if (abs_c(dx) < 1e-17) break;
-    }
-    r.x[j] = xj;
-  }
-  return r;
-}
-
-// Even-odd form of the 1-D tables of degree NP - 1 with NQ Gauss points.
-//   B[q][a] = l_a(eta_q)   (Lagrange basis through the GLL nodes)
-//   K[a][b] = sum_q w_q l_a'(eta_q) l_b'(eta_q),  M[a][b] = sum_q w_q l_a l_b
-// Reflection: B[NQ-1-q][NP-1-a] = B[q][a], K and M centro-symmetric.
-//   BE[q][a] = (B[q][a] + B[q][NP-1-a]) / 2 (a < NP/2), B[q][mid] (a = mid)
-//   BO[q][a] = (B[q][a] - B[q][NP-1-a]) / 2
-// likewise KE/KO, ME/MO with the row index a in place of q.
-template <int NP, int NQ>
-struct Tables {
-  static constexpr int PH = NP / 2, PC = (NP + 1) / 2, QH = NQ / 2, QC = (NQ + 1) / 2;
-  double W[NP] = {};       // GLL weights (the lumped mass M_D of the element)
-  double BE[QC][PC] = {};
-  double BO[QH > 0 ? QH : 1][PH > 0 ? PH : 1] = {};
-  double KE[PC][PC] = {};
-  double KO[PH > 0 ? PH : 1][PH > 0 ? PH : 1] = {};
-  double ME[PC][PC] = {};
-  double MO[PH > 0 ? PH : 1][PH > 0 ? PH : 1] = {};
-};
-
-template <int NP, int NQ>
-constexpr Tables<NP, NQ> make_tables() {
-  constexpr Rule<NP> xi = gll<NP - 1>();
-  constexpr Rule<NQ> g = gauss<NQ>();
-  double B[NQ][NP] = {}, D[NQ][NP] = {}, K[NP][NP] = {}, M[NP][NP] = {};
-  for (int q = 0; q < NQ; ++q)
-    for (int a = 0; a < NP; ++a) {
-      double v = 1.0, d = 0.0;
-      for (int j = 0; j < NP; ++j)
-        if (j != a) v *= (g.x[q] - xi.x[j]) / (xi.x[a] - xi.x[j]);
-      for (int m = 0; m < NP; ++m) {
-        if (m == a) continue;
-        double t = 1.0 / (xi.x[a] - xi.x[m]);
-        for (int j = 0; j < NP; ++j)
-          if (j != a && j != m) t *= (g.x[q] - xi.x[j]) / (xi.x[a] - xi.x[j]);
-        d += t;
-      }
-      B[q][a] = v;
-      D[q][a] = d;
-    }
-  for (int a = 0; a < NP; ++a)
-    for (int b = 0; b < NP; ++b) {
-      double k = 0.0, m = 0.0;
-      for (int q = 0; q < NQ; ++q) {
-        k += g.w[q] * D[q][a] * D[q][b];
-        m += g.w[q] * B[q][a] * B[q][b];
-      }
-      K[a][b] = k;
-      M[a][b] = m;
-    }
-  Tables<NP, NQ> t{};
-  for (int a = 0; a < NP; ++a) {
-    const double P = legendre_P(NP - 1, xi.x[a]);
-    t.W[a] = 2.0 / ((NP - 1) * NP * P * P);
-  }
-  constexpr int PH = NP / 2, PC = (NP + 1) / 2, QC = (NQ + 1) / 2, QH = NQ / 2;
-  for (int q = 0; q < QC; ++q)
-    for (int a = 0; a < PC; ++a) t.BE[q][a] = a < PH ? 0.5 * (B[q][a] + B[q][NP - 1 - a]) : B[q][a];
-  for (int q = 0; q < QH; ++q)
-    for (int a = 0; a < PH; ++a) t.BO[q][a] = 0.5 * (B[q][a] - B[q][NP - 1 - a]);
-  for (int r = 0; r < PC; ++r)
-    for (int a = 0; a < PC; ++a) {
-      t.KE[r][a] = a < PH ? 0.5 * (K[r][a] + K[r][NP - 1 - a]) : K[r][a];
-      t.ME[r][a] = a < PH ? 0.5 * (M[r][a] + M[r][NP - 1 - a]) : M[r][a];
-    }
-  for (int r = 0; r < PH; ++r)
-    for (int a = 0; a < PH; ++a) {
-      t.KO[r][a] = 0.5 * (K[r][a] - K[r][NP - 1 - a]);
-      t.MO[r][a] = 0.5 * (M[r][a] - M[r][NP - 1 - a]);
-    }
-  return t;
-}
-
-template <int NP, int NQ>
-struct Tab {
-  static constexpr Tables<NP, NQ> t = make_tables<NP, NQ>();
-};
-
-}  // namespace ref1d
-
-// compile-time loop: f(std::integral_constant<int, i>) for i = 0 .. N-1
-template <typename F, int... I>
-__host__ __device__ __forceinline__ void sfor_impl(F&& f, std::integer_sequence<int, I...>) {
-  (f(std::integral_constant<int, I>{}), ...);
-}
-template <int N, typename F>
-__host__ __device__ __forceinline__ void sfor(F&& f) {
-  if constexpr (N > 0) sfor_impl(f, std::make_integer_sequence<int, N>{});
-}
-
-// ---- 1-D contractions on one line (values in registers) ------------------------
-
-template <typename T>
-__host__ __device__ __forceinline__ T fma_t(T a, T b, T c) {
-  if constexpr (sizeof(T) == 4) return fmaf(a, b, c); else return fma(a, b, c);
-}
-
-// y[NQ] = B x[NP]
-template <int NP, int NQ, typename T>
-__host__ __device__ __forceinline__ void line_B(const T (&x)[NP], T (&y)[NQ]) {
-  using TB = ref1d::Tab<NP, NQ>;
-  constexpr int PH = NP / 2, PC = (NP + 1) / 2, QH = NQ / 2, QC = (NQ + 1) / 2;
-  T e[PC], o[PH > 0 ? PH : 1];
-  sfor<PH>([&](auto a) {
-    e[a] = x[a] + x[NP - 1 - a];
-    o[a] = x[a] - x[NP - 1 - a];
-  });
-  if constexpr (NP % 2) e[PC - 1] = x[PC - 1];
-  sfor<QC>([&](auto q) {
-    T ye = T(0);
-    sfor<PC>([&](auto a) {
-      constexpr T c = (T)TB::t.BE[q][a];
-      ye = fma_t(c, e[a], ye);
-    });
-    if constexpr (q < QH) {
-      T yo = T(0);
-      sfor<PH>([&](auto a) {
-        constexpr T c = (T)TB::t.BO[q][a];
-        yo = fma_t(c, o[a], yo);
-      });
-      y[q] = ye + yo;
-      y[NQ - 1 - q] = ye - yo;
-    } else {
-      y[q] = ye;
-    }
-  });
-}
-
-// x[NP] = B^T y[NQ]
-template <int NP, int NQ, typename T>
-__host__ __device__ __forceinline__ void line_Bt(const T (&y)[NQ], T (&x)[NP]) {
-  using TB = ref1d::Tab<NP, NQ>;
-  constexpr int PH = NP / 2, PC = (NP + 1) / 2, QH = NQ / 2, QC = (NQ + 1) / 2;
-  T s[QC], d[QH > 0 ? QH : 1];
-  sfor<QH>([&](auto q) {
-    s[q] = y[q] + y[NQ - 1 - q];
-    d[q] = y[q] - y[NQ - 1 - q];
-  });
-  if constexpr (NQ % 2) s[QC - 1] = y[QC - 1];
-  sfor<PC>([&](auto a) {
-    T xe = T(0);
-    sfor<QC>([&](auto q) {
-      constexpr T c = (T)TB::t.BE[q][a];
-      xe = fma_t(c, s[q], xe);
-    });
-    if constexpr (a < PH) {
-      T xo = T(0);
-      sfor<QH>([&](auto q) {
-        constexpr T c = (T)TB::t.BO[q][a];
-        xo = fma_t(c, d[q], xo);
-      });
-      x[a] = xe + xo;
-      x[NP - 1 - a] = xe - xo;
-    } else {
-      x[a] = xe;
-    }
-  });
-}
-
-// even / odd parts of a line of NP node values
-template <int NP, typename T>
-struct EOIn {
-  T e[(NP + 1) / 2];
-  T o[NP / 2 > 0 ? NP / 2 : 1];
-};
-template <int NP, typename T>
-__host__ __device__ __forceinline__ EOIn<NP, T> split_eo(const T (&x)[NP]) {
-  constexpr int PH = NP / 2, PC = (NP + 1) / 2;
-  EOIn<NP, T> r;
-  sfor<PH>([&](auto a) {
-    r.e[a] = x[a] + x[NP - 1 - a];
-    r.o[a] = x[a] - x[NP - 1 - a];
-  });
-  if constexpr (NP % 2) r.e[PC - 1] = x[PC - 1];
-  return r;
-}
-
-// y = A x for a symmetric centro-symmetric NP x NP table (K1 if KT, else M1),
-// from the even / odd parts of x
-template <int NP, int NQ, bool KT, typename T>
-__host__ __device__ __forceinline__ void line_sym(const EOIn<NP, T>& in, T (&y)[NP]) {
-  using TB = ref1d::Tab<NP, NQ>;
-  constexpr int PH = NP / 2, PC = (NP + 1) / 2;
-  sfor<PC>([&](auto r) {
-    T ye = T(0);
-    sfor<PC>([&](auto a) {
-      constexpr T c = (T)(KT ? TB::t.KE[r][a] : TB::t.ME[r][a]);
-      ye = fma_t(c, in.e[a], ye);
-    });
-    if constexpr (r < PH) {
-      T yo = T(0);
-      sfor<PH>([&](auto a) {
-        constexpr T c = (T)(KT ? TB::t.KO[r][a] : TB::t.MO[r][a]);
-        yo = fma_t(c, in.o[a], yo);
-      });
-      y[r] = ye + yo;
-      y[NP - 1 - r] = ye - yo;
-    } else {
-      y[r] = ye;
-    }
-  });
-}
-
-// ---- LDS slabs ---------------------------------------------------------------------
-
-// Columns per item: 8 in FP32, 4 in FP64 (so three workgroups fit in the LDS
-// of a CU either way); the x index is padded to 9.
-template <typename T>
-constexpr int kCB = sizeof(T) == 4 ? 8 : 4;
-// Threads per workgroup: 64 line slots of CB columns each, one line per
-// thread and pass (FP32: 512 threads, so six waves per SIMD fit in the
-// register file; FP64: 256)
-template <typename T>
-constexpr int kNT = 64 * kCB<T>;
-// Waves per SIMD the registers are held to: FP32 six (three workgroups of
-// eight waves per CU, as many as the LDS holds), FP64 three.
-template <typename T>
-constexpr int kWaves = sizeof(T) == 4 ? 6 : 3;
-constexpr int kXP = 9;
-// U: extents up to 8 x 8 x 8;  K, M: up to 7 x 7 x 7 (element offsets, col fastest)
-template <typename T>
-__host__ __device__ constexpr int offU(int x, int y, int z) { return ((z * 8 + y) * kXP + x) * kCB<T>; }
-template <typename T>
-__host__ __device__ constexpr int offK(int x, int y, int z) { return ((z * 7 + y) * kXP + x) * kCB<T>; }
-template <typename T>
-constexpr int kSlabU = 8 * 8 * kXP * kCB<T>;
-template <typename T>
-constexpr int kSlabK = 7 * 7 * kXP * kCB<T>;
-
-// The R lines of one pass owned by a thread: line index L = slot + S r
-// (S = 256 / CB slots) enumerates (u, v) = (L % NU, L / NU); lines past
-// NU * NV are clamped to the last line: their loads stay in range, and the
-// lanes skip their arithmetic and stores (whole waves skip when all of their
-// lines are past the end).
-template <int NU, int NV, int S, int R>
-struct Lines {
-  int u[R], v[R];
-  bool on[R];
-  __device__ __forceinline__ Lines(int slot) {
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      int L = slot + S * r;
-      on[r] = L < NU * NV;
-      L = on[r] ? L : NU * NV - 1;
-      u[r] = L % NU;
-      v[r] = L / NU;
-    }
-  }
-};
-
-}  // namespace
-
-template <typename T, int NP, int NQ, int MODE>
-__global__ void __launch_bounds__(kNT<T>) __attribute__((amdgpu_waves_per_eu(kWaves<T>)))
-k_cell_valu(CellArgs<T> A, int ncoltiles, int nitems, T fx, T fy, T fz) {
-  static_assert(MODE == kModeH, "K + V only");
-  constexpr int CB = kCB<T>;
-  constexpr int NT = kNT<T>;
-  constexpr int S = NT / CB;                   // line slots
-  constexpr int R = (64 + S - 1) / S;          // lines per thread and pass (at most 64 lines)
-  constexpr int NL = NP * NP * NP;
-  constexpr int NQ3 = NQ * NQ * NQ;
-  constexpr int NJ = (NL * CB + NT - 1) / NT;  // gathered elements per thread and item
-  constexpr int NV = (NQ3 + NT - 1) / NT;      // V(q) W_q values per thread and item
-  static_assert(NP <= 7 && NQ <= 8, "slab extents");
-  __shared__ T sU[kSlabU<T>];
-  __shared__ T sK[kSlabK<T>];
-  __shared__ T sM[kSlabK<T>];
-  __shared__ T vws[NQ3];
-  const int tid = threadIdx.x;
-  const int col = tid & (CB - 1);
-  const int slot = tid / CB;
-
-  // gathered local node l = slot + S j = (a, b, c): pk[j] = (row offset of
-  // the node from the cell's first node << 15) | (byte offset in U); its
-  // byte offset in K (the result) follows from the U offset (K has 7 y rows
-  // per z where U has 8).  Threads past the last node carry a valid row and
-  // store nothing.
-  constexpr int kLdsBits = 15;
-  static_assert(kSlabU<T> * (int)sizeof(T) <= (1 << kLdsBits), "U offsets must fit the field");
-  const int p = NP - 1;
-  const int Gx = A.n0 * p, Gy = A.n1 * p, Gz = A.n2 * p;
-  const bool off_fits = (int64_t)p + (int64_t)Gx * (p + (int64_t)Gy * p) < (1 << (32 - kLdsBits));
-  constexpr int kLast = (NL * CB) % NT == 0 ? NJ : NJ - 1;
-  auto lnode = [&](int j) { return slot + S * j; };
-  auto lreal = [&](int j) { return j < kLast || lnode(j) < NL; };
-  unsigned pk[NJ];
-#pragma unroll
-  for (int j = 0; j < NJ; ++j) {
-    const int l = lreal(j) ? lnode(j) : 0;
-    const int a = l % NP, b = (l / NP) % NP, c = l / (NP * NP);
-    pk[j] = ((off_fits ? (unsigned)(a + Gx * (b + Gy * c)) : 0u) << kLdsBits) |
-            (unsigned)((offU<T>(a, b, c) + col) * (int)sizeof(T));
-  }
-  // byte offset in K of the element at byte offset u in U:
-  // offU - offK = z * 9 * CB elements, z = u / (8 * 9 * CB * sizeof(T))
-  auto k_of_u = [](unsigned u) -> int {
-    constexpr unsigned zb = 8u * kXP * CB * sizeof(T);
-    return (int)(u - (u / zb) * (kXP * CB * sizeof(T)));
-  };
-  static_assert(offU<T>(3, 5, 6) - offK<T>(3, 5, 6) == 6 * kXP * CB, "K offset from U offset");
-  struct CellPos {
-    int ci, cj, ck, e, base;
-    bool inner;
-  };
-  auto cell_pos = [&](int packed) {
-    CellPos cp;
-    cp.ci = packed & 1023;
-    cp.cj = (packed >> 10) & 1023;
-    cp.ck = (packed >> 20) & 1023;
-    cp.e = cp.ci + A.n0 * (cp.cj + A.n1 * cp.ck);
-    cp.base = cp.ci * p + Gx * (cp.cj * p + Gy * cp.ck * p);
-    cp.inner = off_fits && cp.ci + 1 < A.n0 && cp.cj + 1 < A.n1 && cp.ck + 1 < A.n2;
-    return cp;
-  };
-  auto nodes_of = [&](const CellPos& cp, int (&node)[NJ]) {
-    if (cp.inner) {
-#pragma unroll
-      for (int j = 0; j < NJ; ++j) node[j] = cp.base + (int)(pk[j] >> kLdsBits);
-    } else {
-#pragma unroll
-      for (int j = 0; j < NJ; ++j) {
-        const int l = lreal(j) ? lnode(j) : 0;
-        const int a = l % NP, b = (l / NP) % NP, c = l / (NP * NP);
-        int gx = cp.ci * p + a; gx = gx >= Gx ? gx - Gx : gx;
-        int gy = cp.cj * p + b; gy = gy >= Gy ? gy - Gy : gy;
-        int gz = cp.ck * p + c; gz = gz >= Gz ? gz - Gz : gz;
-        node[j] = gx + Gx * (gy + Gy * gz);
-      }
-    }
-  };
-  const uint32_t ldxb = (uint32_t)(A.ldx * (int64_t)sizeof(T)), ldyb = (uint32_t)(A.ldy * (int64_t)sizeof(T));
-  // element (row, column n) of a row-major block with a row stride of ldb bytes
-  auto elem = [](auto* base, uint32_t ldb, int n, int row) {
-    using P = decltype(base);
-    using C = typename std::conditional<std::is_const<typename std::remove_pointer<P>::type>::value, const char,
-                                        char>::type;
-    return reinterpret_cast<P>(reinterpret_cast<C*>(base + n) + (uint64_t)(uint32_t)row * ldb);
-  };
-
-  // items (cell of the colour, column tile), cell-major; XCD x takes the
-  // x-th eighth of them (block w runs on XCD w % 8); the cell list is read
-  // through the scalar cache
-  typedef const __attribute__((address_space(4))) int* ConstIntP;
-  const ConstIntP cells = (ConstIntP)A.cells;
-  const int xcd = blockIdx.x & 7;
-  const int i_end = (int)((int64_t)nitems * (xcd + 1) / 8);
-  const int i_step = gridDim.x >> 3;
-  int item = (int)((int64_t)nitems * xcd / 8) + (blockIdx.x >> 3);
-  const int st_c = i_step / ncoltiles, st_t = i_step % ncoltiles;
-  int cur_c = item / ncoltiles, cur_t = item % ncoltiles;
-  auto advance = [&](int& c, int& t) {
-    c += st_c;
-    t += st_t;
-    if (t >= ncoltiles) {
-      t -= ncoltiles;
-      ++c;
-    }
-  };
-
-  T xr[NJ], vr[NV];
-  auto load_item = [&](int c, int t) {
-    const CellPos cp = cell_pos(cells[c]);
-    const int n = t * CB + col;
-    int node[NJ];
-    nodes_of(cp, node);
-    const int nn = n < A.ncols ? n : 0;
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) xr[j] = *elem(A.X, ldxb, nn, node[j]);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const int q = tid + NT * v;
-      if (NQ3 % NT == 0 || q < NQ3) vr[v] = A.Vw[(int64_t)cp.e * NQ3 + q];
-    }
-  };
-  auto stage = [&]() {
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      if (lreal(j)) *reinterpret_cast<T*>(reinterpret_cast<char*>(sU) + (pk[j] & ((1u << kLdsBits) - 1))) = xr[j];
-    }
-#pragma unroll
-    for (int v = 0; v < NV; ++v)
-      if (NQ3 % NT == 0 || tid + NT * v < NQ3) vws[tid + NT * v] = vr[v];
-  };
-
-  if (item < i_end) load_item(cur_c, cur_t);
-  __syncthreads();
-  if (item < i_end) stage();
-  __syncthreads();
-
-  for (; item < i_end; item += i_step) {
-    const int n = cur_t * CB + col;
-    const bool valid = n < A.ncols;
-    const CellPos cp = cell_pos(cells[cur_c]);
-    // the line of each pass is recomputed from the slot in every item (a few
-    // integer operations) rather than held in registers across the loop
-    int lslot = slot;
-    asm volatile("" : "+v"(lslot));
-    T yo[NJ];
-    {
-      int node[NJ];
-      nodes_of(cp, node);
-      const int nn = valid ? n : 0;
-#pragma unroll
-      for (int j = 0; j < NJ; ++j) yo[j] = *elem(A.Y, ldyb, nn, node[j]);
-    }
-    int nxt_c = cur_c, nxt_t = cur_t;
-    advance(nxt_c, nxt_t);
-    const bool more = item + i_step < i_end;
-    load_item(more ? nxt_c : cur_c, more ? nxt_t : cur_t);
-
-    // P1 x: lines (b, c); U -> B U (in place), K1 U -> K, M1 U -> M
-    {
-      const Lines<NP, NP, S, R> ln(lslot);
-      T x[R][NP];
-#pragma unroll
-      for (int r = 0; r < R; ++r) sfor<NP>([&](auto a) { x[r][a] = sU[offU<T>(a, ln.u[r], ln.v[r]) + col]; });
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        if (!ln.on[r]) continue;
-        // each result is stored as soon as it is formed (fewer live registers)
-        const EOIn<NP, T> eo = split_eo<NP>(x[r]);
-        {
-          T yk[NP];
-          line_sym<NP, NQ, true>(eo, yk);
-          sfor<NP>([&](auto a) { sK[offK<T>(a, ln.u[r], ln.v[r]) + col] = yk[a]; });
-        }
-        {
-          T ym[NP];
-          line_sym<NP, NQ, false>(eo, ym);
-          sfor<NP>([&](auto a) { sM[offK<T>(a, ln.u[r], ln.v[r]) + col] = ym[a]; });
-        }
-        T yb[NQ];
-        line_B<NP, NQ>(x[r], yb);
-        sfor<NQ>([&](auto q) { sU[offU<T>(q, ln.u[r], ln.v[r]) + col] = yb[q]; });
-      }
-    }
-    __syncthreads();
-    // P2 y: lines (qx, c): By
-    {
-      const Lines<NQ, NP, S, R> ln(lslot);
-      T x[R][NP];
-#pragma unroll
-      for (int r = 0; r < R; ++r) sfor<NP>([&](auto b) { x[r][b] = sU[offU<T>(ln.u[r], b, ln.v[r]) + col]; });
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        if (!ln.on[r]) continue;
-        T y[NQ];
-        line_B<NP, NQ>(x[r], y);
-        sfor<NQ>([&](auto q) { sU[offU<T>(ln.u[r], q, ln.v[r]) + col] = y[q]; });
-      }
-    }
-    __syncthreads();
-    // P3 z: lines (qx, qy): Bz, times V(q) W_q
-    {
-      const Lines<NQ, NQ, S, R> ln(lslot);
-      T x[R][NP];
-#pragma unroll
-      for (int r = 0; r < R; ++r) sfor<NP>([&](auto c) { x[r][c] = sU[offU<T>(ln.u[r], ln.v[r], c) + col]; });
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        if (!ln.on[r]) continue;
-        T y[NQ];
-        line_B<NP, NQ>(x[r], y);
-        const int q0 = ln.u[r] + NQ * ln.v[r];
-        sfor<NQ>([&](auto q) { sU[offU<T>(ln.u[r], ln.v[r], q) + col] = y[q] * vws[q0 + NQ * NQ * q]; });
-      }
-    }
-    __syncthreads();
-    // P4 z: lines (qx, qy): Bz^T
-    {
-      const Lines<NQ, NQ, S, R> ln(lslot);
-      T y[R][NQ];
-#pragma unroll
-      for (int r = 0; r < R; ++r) sfor<NQ>([&](auto q) { y[r][q] = sU[offU<T>(ln.u[r], ln.v[r], q) + col]; });
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        if (!ln.on[r]) continue;
-        T x[NP];
-        line_Bt<NP, NQ>(y[r], x);
-        sfor<NP>([&](auto c) { sU[offU<T>(ln.u[r], ln.v[r], c) + col] = x[c]; });
-      }
-    }
-    __syncthreads();
-    // P5 y: lines (qx, c): By^T
-    {
-      const Lines<NQ, NP, S, R> ln(lslot);
-      T y[R][NQ];
-#pragma unroll
-      for (int r = 0; r < R; ++r) sfor<NQ>([&](auto q) { y[r][q] = sU[offU<T>(ln.u[r], q, ln.v[r]) + col]; });
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        if (!ln.on[r]) continue;
-        T x[NP];
-        line_Bt<NP, NQ>(y[r], x);
-        sfor<NP>([&](auto b) { sU[offU<T>(ln.u[r], b, ln.v[r]) + col] = x[b]; });
-      }
-    }
-    __syncthreads();
-    // P6 x: lines (b, c): Bx^T -> U (the V term)
-    {
-      const Lines<NP, NP, S, R> ln(lslot);
-      T y[R][NQ];
-#pragma unroll
-      for (int r = 0; r < R; ++r) sfor<NQ>([&](auto q) { y[r][q] = sU[offU<T>(q, ln.u[r], ln.v[r]) + col]; });
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        if (!ln.on[r]) continue;
-        T x[NP];
-        line_Bt<NP, NQ>(y[r], x);
-        sfor<NP>([&](auto a) { sU[offU<T>(a, ln.u[r], ln.v[r]) + col] = x[a]; });
-      }
-    }
-    // P7 y (kinetic; K and M are not touched by P2-P6, so no barrier is
-    // needed before it): lines (a, c); K <- fx M1 K + fy K1 M,  M <- M1 M
-    {
-      const Lines<NP, NP, S, R> ln(lslot);
-      T k[R][NP], m[R][NP];
-#pragma unroll
-      for (int r = 0; r < R; ++r)
-        sfor<NP>([&](auto b) {
-          k[r][b] = sK[offK<T>(ln.u[r], b, ln.v[r]) + col];
-          m[r][b] = sM[offK<T>(ln.u[r], b, ln.v[r]) + col];
-        });
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        if (!ln.on[r]) continue;
-        const EOIn<NP, T> em = split_eo<NP>(m[r]);
-        {
-          T mk[NP], km[NP];
-          line_sym<NP, NQ, false>(split_eo<NP>(k[r]), mk);
-          line_sym<NP, NQ, true>(em, km);
-          sfor<NP>([&](auto b) { sK[offK<T>(ln.u[r], b, ln.v[r]) + col] = fma_t(fx, mk[b], fy * km[b]); });
-        }
-        T mm[NP];
-        line_sym<NP, NQ, false>(em, mm);
-        sfor<NP>([&](auto b) { sM[offK<T>(ln.u[r], b, ln.v[r]) + col] = mm[b]; });
-      }
-    }
-    __syncthreads();
-    // P8 z: lines (a, b): K <- U + M1 K + fz K1 M (the cell result)
-    {
-      const Lines<NP, NP, S, R> ln(lslot);
-      T k[R][NP], m[R][NP];
-#pragma unroll
-      for (int r = 0; r < R; ++r)
-        sfor<NP>([&](auto c) {
-          k[r][c] = sK[offK<T>(ln.u[r], ln.v[r], c) + col];
-          m[r][c] = sM[offK<T>(ln.u[r], ln.v[r], c) + col];
-        });
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        if (!ln.on[r]) continue;
-        T acc[NP];
-        line_sym<NP, NQ, false>(split_eo<NP>(k[r]), acc);
-        {
-          T km[NP];
-          line_sym<NP, NQ, true>(split_eo<NP>(m[r]), km);
-          sfor<NP>([&](auto c) { acc[c] = fma_t(fz, km[c], acc[c]); });
-        }
-        sfor<NP>([&](auto c) {
-          sK[offK<T>(ln.u[r], ln.v[r], c) + col] = acc[c] + sU[offU<T>(ln.u[r], ln.v[r], c) + col];
-        });
-      }
-    }
-    __syncthreads();
-    // the next item's values into U (free now), then this item's assembly:
-    // colour-ordered read-modify-write of CB contiguous columns per DOF
-    stage();
-    if (valid) {
-      int node[NJ];
-      nodes_of(cp, node);
-#pragma unroll
-      for (int j = 0; j < NJ; ++j)
-        if (lreal(j))
-          *elem(A.Y, ldyb, n, node[j]) =
-              yo[j] + A.alpha * *reinterpret_cast<const T*>(reinterpret_cast<const char*>(sK) +
-                                                             k_of_u(pk[j] & ((1u << kLdsBits) - 1)));
-    }
-    __syncthreads();
-    cur_c = nxt_c;
-    cur_t = nxt_t;
-  }
-}
-
-namespace {
-
-template <auto K, int NT>
-int valu_grid(int nitems) {
-  static const int resident = [] {
-    int dev = 0, ncu = 0, per_cu = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
-      ncu = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, K, NT, 0) != hipSuccess || per_cu <= 0) per_cu = 1;
-    return std::max(8, ncu * per_cu / 8 * 8);
-  }();
-  return std::max(8, std::min(resident, (nitems + 7) / 8 * 8));
-}
-
-template <typename T, int NP, int NQ, int MODE>
-pawfe_status run_cell_valu(const pawfe_op* op, const CellArgs<T>& a, hipStream_t s) {
-  constexpr int CB = kCB<T>;
-  const int ncoltiles = (a.ncols + CB - 1) / CB;
-  const T fx = (T)(0.5 * op->detJ * (2.0 / op->h[0]) * (2.0 / op->h[0]));
-  const T fy = (T)(0.5 * op->detJ * (2.0 / op->h[1]) * (2.0 / op->h[1]));
-  const T fz = (T)(0.5 * op->detJ * (2.0 / op->h[2]) * (2.0 / op->h[2]));
-  for (int c = 0; c < op->ncolour; ++c) {
-    const int c0 = op->colour_off[c], c1 = op->colour_off[c + 1];
-    if (c1 == c0) continue;
-    CellArgs<T> ac = a;
-    ac.cells = op->d.cell_pack + c0;
-    const int nitems = (c1 - c0) * ncoltiles;
-    const dim3 grid(valu_grid<k_cell_valu<T, NP, NQ, MODE>, kNT<T>>(nitems)), block(kNT<T>);
-    hipLaunchKernelGGL((k_cell_valu<T, NP, NQ, MODE>), grid, block, 0, s, ac, ncoltiles, nitems, fx, fy, fz);
-  }
-  PAWFE_HIP(hipGetLastError());
-  return PAWFE_OK;
-}
-
-}  // namespace
 
 // K + V (mode kModeH) on the vector ALUs; *done is false when the degree /
 // Gauss rule has no compiled variant (the caller then uses the matrix-core
@@ -775,11 +17,11 @@ pawfe_status launch_cell_valu(const pawfe_op* op, const CellArgs<T>& a, hipStrea
   if (op->nq != op->p + 2) return PAWFE_OK;
   *done = true;
   switch (op->p) {
-    case 2: return run_cell_valu<T, 3, 4, kModeH>(op, a, s);
-    case 3: return run_cell_valu<T, 4, 5, kModeH>(op, a, s);
-    case 4: return run_cell_valu<T, 5, 6, kModeH>(op, a, s);
-    case 5: return run_cell_valu<T, 6, 7, kModeH>(op, a, s);
-    case 6: return run_cell_valu<T, 7, 8, kModeH>(op, a, s);
+    case 2: return run_cell_valu<T, 3, 4, kValuH>(op, a, s);
+    case 3: return run_cell_valu<T, 4, 5, kValuH>(op, a, s);
+    case 4: return run_cell_valu<T, 5, 6, kValuH>(op, a, s);
+    case 5: return run_cell_valu<T, 6, 7, kValuH>(op, a, s);
+    case 6: return run_cell_valu<T, 7, 8, kValuH>(op, a, s);
     default: *done = false; return PAWFE_OK;
   }
 }

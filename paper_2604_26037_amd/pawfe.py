@@ -25,7 +25,7 @@ _STATUS = {1: "EINVAL", 2: "ENOMEM", 3: "EHIP", 4: "ENOTSPD", 5: "ENONFINITE", 6
 # every symbol include/pawfe.h declares
 EXPORTS = [
     "pawfe_build_operator", "pawfe_destroy_operator", "pawfe_query", "pawfe_get_dofmap",
-    "pawfe_set_veff", "pawfe_set_dH", "pawfe_apply_H", "pawfe_apply_S", "pawfe_apply_Sinv",
+    "pawfe_set_veff", "pawfe_set_vgga", "pawfe_set_dH", "pawfe_apply_H", "pawfe_apply_S", "pawfe_apply_Sinv",
     "pawfe_apply_local",
     "pawfe_cheb_filter_workspace", "pawfe_cheb_filter", "pawfe_rayleigh_ritz_workspace",
     "pawfe_rayleigh_ritz", "pawfe_band_energy_grad", "pawfe_lanczos_bounds", "pawfe_last_error",
@@ -59,6 +59,7 @@ class Desc(C.Structure):
         ("proj_l", C.POINTER(C.c_int32)), ("proj_m", C.POINTER(C.c_int32)),
         ("proj_sigma", C.POINTER(C.c_double)), ("dH", C.POINTER(C.c_double)),
         ("dS", C.POINTER(C.c_double)), ("sinv_mode", C.c_int32),
+        ("xgrid", C.POINTER(C.c_double)), ("vgga_q", C.POINTER(C.c_double)),
     ]
 
 
@@ -81,6 +82,7 @@ def load(path=LIB_PATH):
         "pawfe_query": [vp, P(i64), P(i64), P(i32), P(i32), P(i64), P(i64)],
         "pawfe_get_dofmap": [vp, vp, vp, vp, vp, vp, vp],
         "pawfe_set_veff": [vp, P(dbl), vp],
+        "pawfe_set_vgga": [vp, P(dbl), vp],
         "pawfe_set_dH": [vp, P(dbl), vp],
         "pawfe_apply_H": [vp, vp, i64, vp, i64, i64, i32, vp],
         "pawfe_apply_H_noalloc": [vp, vp, i64, vp, i64, i64, i32, vp],
@@ -156,6 +158,12 @@ class Operator:
             dH=np.ascontiguousarray(s.dH, dtype=np.float64),
             dS=np.ascontiguousarray(s.dS, dtype=np.float64),
         )
+        xg = getattr(s, "xgrid", None)
+        vg = getattr(s, "vgga_q", None)
+        if xg is not None:
+            self._keep["xgrid"] = np.ascontiguousarray(np.concatenate([np.asarray(b, dtype=np.float64) for b in xg]))
+        if vg is not None:
+            self._keep["vgga"] = np.ascontiguousarray(vg, dtype=np.float64).ravel()
         k = self._keep
         d = Desc()
         d.ncell[:] = [int(n) for n in s.ncell]
@@ -175,6 +183,8 @@ class Operator:
         d.dH = _dptr(k["dH"])
         d.dS = _dptr(k["dS"])
         d.sinv_mode = {"exact_g": SINV_EXACT_G, "pp": SINV_PP}[sinv_mode]
+        d.xgrid = _dptr(k["xgrid"]) if "xgrid" in k else None
+        d.vgga_q = _dptr(k["vgga"]) if "vgga" in k else None
         self._desc = d
         h = C.c_void_p()
         _check(lib.pawfe_build_operator(C.byref(d), _stream(stream), C.byref(h)))
@@ -219,6 +229,11 @@ class Operator:
         v = np.ascontiguousarray(veff_q, dtype=np.float64).ravel()
         _check(_lib.pawfe_set_veff(self._h, _dptr(v), _stream(stream)))
         self._keep["veff"] = v
+
+    def set_vgga(self, vgga_q, stream=None):
+        v = np.ascontiguousarray(vgga_q, dtype=np.float64).ravel()
+        _check(_lib.pawfe_set_vgga(self._h, _dptr(v), _stream(stream)))
+        self._keep["vgga"] = v
 
     def set_dH(self, dH, stream=None):
         v = np.ascontiguousarray(dH, dtype=np.float64).ravel()
