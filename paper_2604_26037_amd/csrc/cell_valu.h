@@ -415,6 +415,12 @@ constexpr int kValuH = 0;        // K + V, every cell of one size (factors as ar
 constexpr int kValuGenH = 1;     // K + V, per-cell geometry
 constexpr int kValuGenHG = 2;    // K + V + the GGA term, per-cell geometry
 constexpr int kValuGenMass = 3;  // det J_e M, times -lambda_n per column when lam is given
+constexpr int kValuHRes = 4;     // K + V - lambda_n M, every cell of one size
+// variants that read the per-cell geometry table (and need it non-null)
+constexpr bool is_general_mode(int mode) {
+  return mode == kValuGenH || mode == kValuGenHG || mode == kValuGenMass;
+}
+static_assert(!is_general_mode(kValuH) && !is_general_mode(kValuHRes), "uniform variants");
 // Waves per SIMD the registers are held to: FP32 six (three workgroups of
 // eight waves per CU, as many as the LDS holds), FP64 three; the GGA variant
 // holds two more slabs in LDS (two workgroups per CU): FP32 four, FP64 two.
@@ -457,9 +463,11 @@ struct Lines {
 template <typename T, int NP, int NQ, int MODE>
 __global__ void __launch_bounds__(kNT<T>) __attribute__((amdgpu_waves_per_eu((kWaves<T, MODE>))))
 k_cell_valu(CellArgs<T> A, int ncoltiles, int nitems, T fx, T fy, T fz) {
-  constexpr bool GEN = MODE != kValuH;
+  constexpr bool GEN = is_general_mode(MODE);   // reads the per-cell table A.geo
   constexpr bool GGA = MODE == kValuGenHG;
   constexpr bool MASS = MODE == kValuGenMass;
+  constexpr bool RES = MODE == kValuHRes;
+  static_assert(!(RES && GEN), "the residual mode uses the uniform factors");
   constexpr int CB = kCB<T>;
   constexpr int NT = kNT<T>;
   constexpr int S = NT / CB;                   // line slots
@@ -634,7 +642,7 @@ k_cell_valu(CellArgs<T> A, int ncoltiles, int nitems, T fx, T fy, T fz) {
     load_item(more ? nxt_c : cur_c, more ? nxt_t : cur_t);
     // kinetic factors 1/2 det J (2/h_d)^2 and det J: the cell's own on a
     // general operator (read through the scalar cache), else the arguments
-    T ifx = fx, ify = fy, ifz = fz, idet = T(1);
+    T ifx = fx, ify = fy, ifz = fz, idet = A.detJ;
     if constexpr (GEN) {
       typedef const __attribute__((address_space(4))) T* ConstTP;
       const ConstTP g = (ConstTP)A.geo + 4 * cp.e;
@@ -845,10 +853,17 @@ k_cell_valu(CellArgs<T> A, int ncoltiles, int nitems, T fx, T fy, T fz) {
           sfor<NP>([&](auto c) { sK[offK<T>(ln.u[r], ln.v[r], c) + col] = acc[c]; });
         } else {
           line_sym<NP, NQ, false>(split_eo<NP>(k[r]), acc);
+          const EOIn<NP, T> em = split_eo<NP>(m[r]);
           {
             T km[NP];
-            line_sym<NP, NQ, true>(split_eo<NP>(m[r]), km);
+            line_sym<NP, NQ, true>(em, km);
             sfor<NP>([&](auto c) { acc[c] = fma_t(ifz, km[c], acc[c]); });
+          }
+          if constexpr (RES) {   // - lambda_n det J M1 M (the S part of the residual, local term)
+            T mm[NP];
+            line_sym<NP, NQ, false>(em, mm);
+            const T ml = valid ? -(T)A.lam[n] * idet : T(0);
+            sfor<NP>([&](auto c) { acc[c] = fma_t(ml, mm[c], acc[c]); });
           }
           sfor<NP>([&](auto c) {
             sK[offK<T>(ln.u[r], ln.v[r], c) + col] = acc[c] + sU[offU<T>(ln.u[r], ln.v[r], c) + col];
@@ -894,8 +909,13 @@ int valu_grid(int nitems) {
 }
 
 template <typename T, int NP, int NQ, int MODE>
-pawfe_status run_cell_valu(const pawfe_op* op, const CellArgs<T>& a, hipStream_t s) {
+pawfe_status run_cell_valu(const pawfe_op* op, const CellArgs<T>& a0, hipStream_t s) {
   constexpr int CB = kCB<T>;
+  CellArgs<T> a = a0;
+  a.detJ = (T)op->detJ;
+  if (is_general_mode(MODE) && !a.geo) return fail(PAWFE_EINVAL, "internal: general cell variant without geometry");
+  if (MODE == kValuGenHG && !a.vg) return fail(PAWFE_EINVAL, "internal: GGA cell variant without its table");
+  if (MODE == kValuHRes && !a.lam) return fail(PAWFE_EINVAL, "internal: residual cell variant without lambda");
   const int ncoltiles = (a.ncols + CB - 1) / CB;
   const T fx = (T)(0.5 * op->detJ * (2.0 / op->h[0]) * (2.0 / op->h[0]));
   const T fy = (T)(0.5 * op->detJ * (2.0 / op->h[1]) * (2.0 / op->h[1]));

@@ -26,6 +26,7 @@ struct CellArgs {
   // general operators (vector-ALU kernel variants)
   const T* geo;        // [E][4] per cell: fx, fy, fz (1/2 det J (2/h_d)^2) and det J
   const T* vg;         // [E][3][nq^3] W_q det J (2/h_d) V_GGA,d (GGA term), or null
+  T detJ;              // det J of every cell (residual mode of the vector-ALU kernel)
 };
 
 struct DensArgs {
@@ -56,10 +57,11 @@ pawfe_status launch_cell(const pawfe_op* op, int mode, const T* X, int64_t ldx, 
 template <typename T>
 pawfe_status launch_cell_mfma(const pawfe_op* op, int mode, const CellArgs<T>& a, hipStream_t s);
 
-// K + V on the vector ALUs (kernels_cell_valu.hip); *done is false when no
-// variant is compiled for the operator's degree and Gauss rule.
+// K + V (kModeH) or K + V - lambda_n M (kModeHRes) on the vector ALUs
+// (kernels_cell_valu.hip); *done is false when no variant is compiled for
+// the mode, the operator's degree and Gauss rule.
 template <typename T>
-pawfe_status launch_cell_valu(const pawfe_op* op, const CellArgs<T>& a, hipStream_t s, bool* done);
+pawfe_status launch_cell_valu(const pawfe_op* op, int mode, const CellArgs<T>& a, hipStream_t s, bool* done);
 
 // Every local term of a general operator (graded mesh and / or the GGA term)
 // on the vector ALUs (kernels_cell_gen_f32.hip / _f64.hip): kModeH, kModeMass

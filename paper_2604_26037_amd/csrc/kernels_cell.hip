@@ -126,9 +126,10 @@ pawfe_status launch_cell(const pawfe_op* op, int mode, const T* X, int64_t ldx, 
   }
   pawfe_status st = PAWFE_OK;
   bool done = false;
-  // K + V in FP32 or FP64: vector-ALU kernel (the matrix-core kernel keeps the
-  // residual, mass and imaginary-term modes and bf16x3)
-  if (mode == kModeH && !bf3) st = launch_cell_valu(op, a, s, &done);
+  // K + V and the residual K + V - lambda M in FP32 or FP64: vector-ALU
+  // kernel (the matrix-core kernel keeps the mass and imaginary-term modes
+  // and bf16x3)
+  if ((mode == kModeH || mode == kModeHRes) && !bf3) st = launch_cell_valu(op, mode, a, s, &done);
   if (st == PAWFE_OK && !done) st = launch_cell_mfma<T>(op, mode, a, s);
   // complex operators: the imaginary local term, on the (re, im) column pairs
   if (st != PAWFE_OK || !op->cplx || (mode != kModeH && mode != kModeHRes)) return st;
