@@ -35,7 +35,7 @@ PEAK_HBM_GBS = 8000.0
 PEAK_VALU_F32_TFLOPS = 157.3
 # the same without packed FP32 instructions (also the FP64 vector peak)
 PEAK_VALU_F32_SCALAR_TFLOPS = 78.6
-CELL_KERNEL_SRC = os.path.join(ROOT, "paper_2604_26037_amd", "csrc", "kernels_cell_valu.hip")
+CELL_KERNEL_SRC = os.path.join(ROOT, "paper_2604_26037_amd", "csrc", "cell_valu.h")
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "cell_valu_f32_paper_counters.md")
 METRIC = "ChFSI filter s/SCF pass & HX GFLOP/s, mixed vs FP64 at ≤1e-6 Ha eig err"
 
