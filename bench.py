@@ -171,7 +171,7 @@ def host_info():
     }
 
 
-def cpu_baseline(system, nstates, degree, ncols=16):
+def cpu_baseline(system, nstates, degree, ncols=64):
     """The oracle as it stands, on a bounded sample of the same workload:
     apply_H, apply_S and apply_Sinv on `ncols` columns, and Algorithm 2 with
     degree 2 on the same columns (initial residual, one Chebyshev step,
