@@ -193,3 +193,28 @@ def test_paper_graded_gga_sampled_rows():
     got32 = op.apply_H(_dev(X).float(), prec=1).cpu().numpy()[rows][:, cols]
     want32 = _rows_H(ref, X[:, cols].astype(np.float32).astype(np.float64), rows)
     assert _rel(got32.astype(np.float64), want32) < 2e-5
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_filter_mid_graded_gga(prec):
+    """The paper's element (degree 6, 8 Gauss points) on a two-level mesh with
+    the GGA term: 70 states in ragged blocks of 40, degree 12, against the
+    oracle's Algorithm 2 (FP64 1e-9, mixed 1e-4)."""
+    from oracle import chfsi
+    from oracle.paw import PAWOperator
+    from paper_2604_26037_amd import Operator
+    from workloads import make_system
+    from workloads.configs import with_two_level_gga
+    s = with_two_level_gga(make_system("mid"), r_fine=1.0)
+    assert any(len(set(np.round(np.diff(b), 9))) == 2 for b in s.xgrid)
+    ref, op = PAWOperator(s), Operator(s)
+    X = s.trial(70)
+    Psi, lam, _ = chfsi.rayleigh_ritz(ref, X)
+    t0, t1, beta = chfsi.lanczos_bounds(ref, k=20)
+    bU = 1.02 * max(t1 + abs(beta), float(lam[-1])) + 1.0
+    b0, bW = float(lam[0]), float(lam[-1])
+    want = chfsi.rchfsi_filter(ref, Psi, lam, 12, b0, bW, bU, block=40)
+    got = op.cheb_filter(_dev(Psi), _dev(lam), 12, b0, bW, bU, block=40,
+                         prec=0 if prec == "fp64" else 1).cpu().numpy()
+    err = float(np.max(np.abs(got - want).max(axis=0) / np.abs(want).max(axis=0)))
+    assert err < (1e-9 if prec == "fp64" else 1e-4), err

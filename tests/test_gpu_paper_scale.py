@@ -99,3 +99,35 @@ def test_rayleigh_ritz_paper(paper):
     lam = lam.cpu().numpy()
     assert np.abs(lam - lam_ref).max() < 1e-10 * max(1.0, np.abs(lam_ref).max())
     np.testing.assert_allclose(res.cpu().numpy(), res_ref, rtol=1e-7)
+
+
+def _colmax_rel(got, want):
+    """Largest element-wise deviation of each column relative to that
+    column's largest entry (no dilution by the column norm)."""
+    return float(np.max(np.abs(got - want).max(axis=0) / np.abs(want).max(axis=0)))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_filter_paper_block_degree30_elementwise(paper, prec):
+    """The bench's polynomial degree (30) on a 256-column block with Ritz-like
+    bounds; two sampled columns against the oracle's Algorithm 2, element by
+    element (FP64 1e-9, mixed 1e-4 of the column's largest entry)."""
+    from oracle import chfsi
+    s, ref, op, X = paper
+    lam = np.linspace(1.5, 9.0, 256)
+    b0, bW, bU = 1.4, 9.0, 346.0
+    cols = [0, 201]
+    got = op.cheb_filter(_dev(X), torch.from_numpy(lam), 30, b0, bW, bU, block=256,
+                         prec=0 if prec == "fp64" else 1).cpu().numpy()[:, cols]
+    want, _ = chfsi.rchfsi_block(ref.apply_H, ref.apply_S, ref.apply_Sinv, X[:, cols], lam[cols], 30,
+                                 b0, bW, bU)
+    err = _colmax_rel(got, want)
+    assert err < (1e-9 if prec == "fp64" else 1e-4), err
+
+
+@pytest.mark.parametrize("which", ["H", "Sinv"])
+def test_apply_fp64_paper_block_elementwise(paper, which):
+    s, ref, op, X = paper
+    Y = getattr(op, "apply_" + which)(_dev(X)).cpu().numpy()[:, SAMPLE]
+    Yr = getattr(ref, "apply_" + which)(X[:, SAMPLE])
+    assert _colmax_rel(Y, Yr) < 1e-12
