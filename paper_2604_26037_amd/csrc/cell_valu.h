@@ -34,6 +34,8 @@
 // Passes:
 //   P1 x: U -> B U (in place, 7 -> 8), K1 U -> K, M1 U -> M
 //   P2 y: B (U)   P3 z: B, times V(q) W_q   P4 z: B^T   P5 y: B^T
+//   (P3 and P4 run on the same lines, so one thread takes its line through
+//   both in registers, with no barrier between them)
 //   P6 x: B^T -> U (the V term, 7^3)
 //   P7 y: K <- fx M1 K + fy K1 M,  M <- M1 M
 //   P8 z: K <- U + M1 K + fz K1 M  (the cell result)
@@ -698,10 +700,10 @@ k_cell_valu(CellArgs<T> A, int ncoltiles, int nitems, T fx, T fy, T fz) {
         }
       }
       __syncthreads();
-      // P3 z: lines (qx, qy): Bz (the field u at the quadrature points), times
-      // V(q) W_q; with the GGA term u stays in U and V u plus the z part of the
-      // GGA term go to G
-      {
+      if constexpr (!GGA) {
+        // P3 + P4 z: lines (qx, qy): Bz, times V(q) W_q, then Bz^T, in
+        // registers (both passes run on the same lines, so the line stays
+        // with its thread and needs no barrier in between)
         const Lines<NQ, NQ, S, R> ln(lslot);
         T x[R][NP];
 #pragma unroll
@@ -712,7 +714,26 @@ k_cell_valu(CellArgs<T> A, int ncoltiles, int nitems, T fx, T fy, T fz) {
           T y[NQ];
           line_B<NP, NQ>(x[r], y);
           const int q0 = ln.u[r] + NQ * ln.v[r];
-          if constexpr (GGA) {
+          sfor<NQ>([&](auto q) { y[q] = y[q] * vws[q0 + NQ * NQ * q]; });
+          T xo[NP];
+          line_Bt<NP, NQ>(y, xo);
+          sfor<NP>([&](auto c) { sU[offU<T>(ln.u[r], ln.v[r], c) + col] = xo[c]; });
+        }
+        __syncthreads();
+      } else {
+        // P3 z: lines (qx, qy): Bz (the field u at the quadrature points); u
+        // stays in U and V(q) W_q u plus the z part of the GGA term go to G
+        {
+          const Lines<NQ, NQ, S, R> ln(lslot);
+          T x[R][NP];
+#pragma unroll
+          for (int r = 0; r < R; ++r) sfor<NP>([&](auto c) { x[r][c] = sU[offU<T>(ln.u[r], ln.v[r], c) + col]; });
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            if (!ln.on[r]) continue;
+            T y[NQ];
+            line_B<NP, NQ>(x[r], y);
+            const int q0 = ln.u[r] + NQ * ln.v[r];
             T v[NQ], t[NQ];
             sfor<NQ>([&](auto q) { v[q] = vgs[2 * NQ3 + q0 + NQ * NQ * q]; });
             line_gga<NP, NQ>(y, v, t);
@@ -720,62 +741,60 @@ k_cell_valu(CellArgs<T> A, int ncoltiles, int nitems, T fx, T fy, T fz) {
               sU[offU<T>(ln.u[r], ln.v[r], q) + col] = y[q];
               sG[offU<T>(ln.u[r], ln.v[r], q) + col] = fma_t(y[q], vws[q0 + NQ * NQ * q], t[q]);
             });
-          } else {
-            sfor<NQ>([&](auto q) { sU[offU<T>(ln.u[r], ln.v[r], q) + col] = y[q] * vws[q0 + NQ * NQ * q]; });
-          }
-        }
-      }
-      __syncthreads();
-      if constexpr (GGA) {
-        // G += the y part of the GGA term: lines (qx, qz) along y
-        {
-          const Lines<NQ, NQ, S, R> ln(lslot);
-#pragma unroll
-          for (int r = 0; r < R; ++r) {
-            if (!ln.on[r]) continue;
-            T u[NQ], v[NQ], t[NQ];
-            sfor<NQ>([&](auto q) {
-              u[q] = sU[offU<T>(ln.u[r], q, ln.v[r]) + col];
-              v[q] = vgs[NQ3 + ln.u[r] + NQ * (q + NQ * ln.v[r])];
-            });
-            line_gga<NP, NQ>(u, v, t);
-            sfor<NQ>([&](auto q) { sG[offU<T>(ln.u[r], q, ln.v[r]) + col] += t[q]; });
           }
         }
         __syncthreads();
-        // G += the x part: lines (qy, qz) along x
         {
+          // G += the y part of the GGA term: lines (qx, qz) along y
+          {
+            const Lines<NQ, NQ, S, R> ln(lslot);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+              if (!ln.on[r]) continue;
+              T u[NQ], v[NQ], t[NQ];
+              sfor<NQ>([&](auto q) {
+                u[q] = sU[offU<T>(ln.u[r], q, ln.v[r]) + col];
+                v[q] = vgs[NQ3 + ln.u[r] + NQ * (q + NQ * ln.v[r])];
+              });
+              line_gga<NP, NQ>(u, v, t);
+              sfor<NQ>([&](auto q) { sG[offU<T>(ln.u[r], q, ln.v[r]) + col] += t[q]; });
+            }
+          }
+          __syncthreads();
+          // G += the x part: lines (qy, qz) along x
+          {
+            const Lines<NQ, NQ, S, R> ln(lslot);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+              if (!ln.on[r]) continue;
+              T u[NQ], v[NQ], t[NQ];
+              sfor<NQ>([&](auto q) {
+                u[q] = sU[offU<T>(q, ln.u[r], ln.v[r]) + col];
+                v[q] = vgs[q + NQ * (ln.u[r] + NQ * ln.v[r])];
+              });
+              line_gga<NP, NQ>(u, v, t);
+              sfor<NQ>([&](auto q) { sG[offU<T>(q, ln.u[r], ln.v[r]) + col] += t[q]; });
+            }
+          }
+          __syncthreads();
+        }
+        // P4 z: lines (qx, qy): Bz^T of G
+        {
+          const T* src = sG;
           const Lines<NQ, NQ, S, R> ln(lslot);
+          T y[R][NQ];
+#pragma unroll
+          for (int r = 0; r < R; ++r) sfor<NQ>([&](auto q) { y[r][q] = src[offU<T>(ln.u[r], ln.v[r], q) + col]; });
 #pragma unroll
           for (int r = 0; r < R; ++r) {
             if (!ln.on[r]) continue;
-            T u[NQ], v[NQ], t[NQ];
-            sfor<NQ>([&](auto q) {
-              u[q] = sU[offU<T>(q, ln.u[r], ln.v[r]) + col];
-              v[q] = vgs[q + NQ * (ln.u[r] + NQ * ln.v[r])];
-            });
-            line_gga<NP, NQ>(u, v, t);
-            sfor<NQ>([&](auto q) { sG[offU<T>(q, ln.u[r], ln.v[r]) + col] += t[q]; });
+            T x[NP];
+            line_Bt<NP, NQ>(y[r], x);
+            sfor<NP>([&](auto c) { sU[offU<T>(ln.u[r], ln.v[r], c) + col] = x[c]; });
           }
         }
         __syncthreads();
       }
-      // P4 z: lines (qx, qy): Bz^T (from G with the GGA term)
-      {
-        const T* src = GGA ? sG : sU;
-        const Lines<NQ, NQ, S, R> ln(lslot);
-        T y[R][NQ];
-#pragma unroll
-        for (int r = 0; r < R; ++r) sfor<NQ>([&](auto q) { y[r][q] = src[offU<T>(ln.u[r], ln.v[r], q) + col]; });
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          if (!ln.on[r]) continue;
-          T x[NP];
-          line_Bt<NP, NQ>(y[r], x);
-          sfor<NP>([&](auto c) { sU[offU<T>(ln.u[r], ln.v[r], c) + col] = x[c]; });
-        }
-      }
-      __syncthreads();
       // P5 y: lines (qx, c): By^T
       {
         const Lines<NQ, NP, S, R> ln(lslot);
