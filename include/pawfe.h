@@ -395,6 +395,30 @@ pawfe_status pawfe_batch_query(const pawfe_batch* batch, int32_t* nstreams, int3
 /* Frees the graph, the streams and the workspaces (synchronizes first). */
 void pawfe_batch_destroy(pawfe_batch* batch);
 
+/* Timed tuning runs (block-size trials and stream-count trials) that
+ * pawfe_batch_create spent on this batch: 0 when every decision came from
+ * the tuning cache below or was fixed by the caller. */
+pawfe_status pawfe_batch_tuning_runs(const pawfe_batch* batch, int32_t* ntimed);
+
+/* Tuning cache of the batch autotuner: the decisions of pawfe_batch_create
+ * (block size and cost estimate per job, stream count per batch), kept
+ * process-wide and keyed by what they depend on (GPU architecture, the
+ * operator's cells, degree, Gauss rule, atoms and projectors, real or
+ * complex, graded / GGA, the job's column count, Chebyshev degree and the
+ * precision).  pawfe_batch_create consults it and adds what it tunes.
+ *   _save: writes the table to the text file `path` (through `path`.tmp,
+ *          then renamed); first line "pawfe-tune-cache 1", then one entry
+ *          per line "<key> <block or stream count> <cost ms>".
+ *   _load: merges a file written by _save; PAWFE_EINVAL for a missing
+ *          file, a wrong first line or a line that does not parse (the
+ *          table is then unchanged).
+ *   _clear: empties the table.  _size: number of entries.
+ * Host only, no GPU call; thread-safe. */
+pawfe_status pawfe_tune_cache_load(const char* path);
+pawfe_status pawfe_tune_cache_save(const char* path);
+pawfe_status pawfe_tune_cache_clear(void);
+pawfe_status pawfe_tune_cache_size(int64_t* nentries);
+
 /* Message for the last non-OK status on the calling thread ("" if none). */
 const char* pawfe_last_error(void);
 

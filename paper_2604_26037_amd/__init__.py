@@ -7,5 +7,5 @@ binding.
 
 from .pawfe import (  # noqa: F401
     Operator, Batch, PawfeError, load, band_energy_function, EXPORTS, LIB_PATH,
-    FP64, FP32, BF16X3,
+    FP64, FP32, BF16X3, tune_cache_load, tune_cache_save, tune_cache_clear, tune_cache_size,
 )

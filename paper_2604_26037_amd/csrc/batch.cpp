@@ -21,11 +21,25 @@
 // filter (its cost estimate, and the eager first launch of its kernels).
 // Tuning runs write into temporary outputs, never into the jobs' Xout
 // (which may alias Xin).
+//
+// Tuning cache: the decisions (block size and cost estimate per job, stream
+// count per batch) are kept in a process-wide table keyed by what they
+// depend on -- the GPU architecture, the operator's shape (cells, degree,
+// Gauss rule, atoms and projectors, real or complex, graded / GGA), the
+// column count and the precision -- and can be saved to and loaded from a
+// text file (pawfe_tune_cache_save / _load).  A job found in the table is
+// not timed again; it still runs one eager degree-2 filter before the
+// capture, as a job with a fixed block size does.
 
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <fstream>
+#include <map>
+#include <mutex>
 #include <numeric>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -49,6 +63,7 @@ struct pawfe_batch {
   std::vector<std::vector<int>> groups;   // job indices of each graph, in launch order
   std::vector<hipGraph_t> graphs;
   std::vector<hipGraphExec_t> execs;
+  int32_t ntimed = 0;   // timed filter runs (and stream-count trials) spent on tuning
 };
 
 namespace {
@@ -57,6 +72,34 @@ using pawfe::fail;
 
 // launches per captured graph unless the caller sets another budget
 constexpr int64_t kDefaultGraphLaunches = 16384;
+
+// ---- tuning cache ---------------------------------------------------------------
+
+struct TuneEntry {
+  int32_t block = 0;   // job entries: chosen block size; batch entries: stream count
+  double cost = 0.0;   // job entries: estimated ms of the job's filter
+};
+
+std::mutex g_cache_mu;
+std::map<std::string, TuneEntry> g_cache;
+
+std::string arch_name() {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+  std::string a(prop.gcnArchName);
+  return a.substr(0, a.find(':'));
+}
+
+// what the tuning of one job depends on (no spaces: one token of the file)
+std::string job_key(const pawfe_filter_job& J, int32_t prec, const std::string& arch) {
+  const pawfe_op* op = J.op;
+  std::ostringstream k;
+  k << "job/" << arch << "/n" << op->n[0] << "x" << op->n[1] << "x" << op->n[2] << "/p" << op->p << "/q" << op->nq
+    << "/a" << op->natoms << "/j" << op->npj_total << "/c" << (op->cplx ? 1 : 0) << "/g" << (op->graded ? 1 : 0)
+    << "/v" << (op->gga ? 1 : 0) << "/s" << op->nsrow << "/N" << J.nvec << "/m" << J.degree << "/P" << prec;
+  return k.str();
+}
 
 void release(pawfe_batch* b) {
   if (!b) return;
@@ -207,6 +250,8 @@ pawfe_status build(pawfe_batch* b, const pawfe_filter_job* jobs, int32_t njobs, 
   // filter into a temporary output), so all lazily initialized launch
   // parameters exist before capturing
   const bool tune_any = true;
+  const std::string arch = arch_name();
+  std::vector<std::string> keys(n);
   for (int j = 0; j < n; ++j) {
     const pawfe_filter_job& J = b->jobs[j];
     int64_t ndof = 0;
@@ -237,6 +282,26 @@ pawfe_status build(pawfe_batch* b, const pawfe_filter_job* jobs, int32_t njobs, 
       wmax = std::max(wmax, wc[i]);
     }
     if (hipMalloc(&b->ws[j], wmax) != hipSuccess) return fail(PAWFE_ENOMEM, "batch workspace allocation failed");
+    keys[j] = job_key(J, b->prec, arch);
+    TuneEntry hit;
+    bool cached = false;
+    if (cand.size() > 1) {
+      std::lock_guard<std::mutex> lk(g_cache_mu);
+      auto it = g_cache.find(keys[j]);
+      if (it != g_cache.end() && std::find(cand.begin(), cand.end(), it->second.block) != cand.end()) {
+        hit = it->second;
+        cached = true;
+      }
+    }
+    if (cached) {   // a tuned decision: one eager degree-2 filter of the chosen block
+      const size_t i = std::find(cand.begin(), cand.end(), hit.block) - cand.begin();
+      b->block[j] = hit.block;
+      b->ws_bytes[j] = wc[i];
+      float ms = 0.f;
+      CHECK(time_filter(J, hit.block, 2, b->prec, b->ws[j], wc[i], tmp[j], s, &ms));
+      cost[j] = hit.cost;
+      continue;
+    }
     if (cand.size() == 1) {
       b->block[j] = cand[0];
       b->ws_bytes[j] = wc[0];
@@ -249,6 +314,7 @@ pawfe_status build(pawfe_batch* b, const pawfe_filter_job* jobs, int32_t njobs, 
     for (size_t i = 0; i < cand.size(); ++i) {
       float ms = 0.f;
       CHECK(time_filter(J, cand[i], 3, b->prec, b->ws[j], wc[i], tmp[j], s, &ms));
+      ++b->ntimed;
       if (b->block[j] == 0 || ms < best) {
         best = ms;
         b->block[j] = cand[i];
@@ -257,15 +323,32 @@ pawfe_status build(pawfe_batch* b, const pawfe_filter_job* jobs, int32_t njobs, 
     }
     // degree-3 time -> degree-m estimate (two applies at set-up, one per theta)
     cost[j] = (double)best * (J.degree + 1) / 4.0;
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    g_cache[keys[j]] = TuneEntry{b->block[j], cost[j]};
   }
   std::vector<int64_t> est(n);
   for (int j = 0; j < n; ++j) est[j] = est_launches(b->jobs[j], b->block[j]);
-  // number of streams: given, or the fastest of 1, 2, 4 for the whole batch
+  // number of streams: given, cached under the sorted job keys and the
+  // launch budget, or the fastest of 1, 2, 4 for the whole batch
+  std::string bkey = "batch/" + std::to_string(budget);
+  {
+    std::vector<std::string> sk(keys);
+    std::sort(sk.begin(), sk.end());
+    for (const std::string& k : sk) bkey += "+" + k;
+  }
   if (nstreams > 0) {
     plan(b, std::min(nstreams, 16), cost, est, budget);
     CHECK(make_streams(b, b->nstreams));
   } else {
     CHECK(make_streams(b, 4));
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_cache.find(bkey);
+    if (it != g_cache.end() && (it->second.block == 1 || it->second.block == 2 || it->second.block == 4)) {
+      plan(b, it->second.block, cost, est, budget);
+      nstreams = it->second.block;
+    }
+  }
+  if (nstreams <= 0) {
     float best = 0.f;
     int best_ns = 1;
     hipEvent_t e0, e1;
@@ -280,6 +363,7 @@ pawfe_status build(pawfe_batch* b, const pawfe_filter_job* jobs, int32_t njobs, 
       PAWFE_HIP(hipEventSynchronize(e1));
       float ms = 0.f;
       PAWFE_HIP(hipEventElapsedTime(&ms, e0, e1));
+      ++b->ntimed;
       if (ns == 1 || ms < best) {
         best = ms;
         best_ns = ns;
@@ -288,6 +372,8 @@ pawfe_status build(pawfe_batch* b, const pawfe_filter_job* jobs, int32_t njobs, 
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     plan(b, best_ns, cost, est, budget);
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    g_cache[bkey] = TuneEntry{best_ns, 0.0};
   }
   PAWFE_HIP(hipDeviceSynchronize());
   // capture each group once
@@ -353,5 +439,65 @@ pawfe_status pawfe_batch_query(const pawfe_batch* b, int32_t* nstreams, int32_t*
 }
 
 void pawfe_batch_destroy(pawfe_batch* b) { release(b); }
+
+pawfe_status pawfe_batch_tuning_runs(const pawfe_batch* b, int32_t* ntimed) {
+  if (!b || !ntimed) return fail(PAWFE_EINVAL, "batch or ntimed is NULL");
+  *ntimed = b->ntimed;
+  return PAWFE_OK;
+}
+
+pawfe_status pawfe_tune_cache_clear(void) {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  g_cache.clear();
+  return PAWFE_OK;
+}
+
+pawfe_status pawfe_tune_cache_size(int64_t* nentries) {
+  if (!nentries) return fail(PAWFE_EINVAL, "nentries is NULL");
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  *nentries = (int64_t)g_cache.size();
+  return PAWFE_OK;
+}
+
+// File format: a first line "pawfe-tune-cache 1", then one entry per line:
+// "<key> <block or stream count> <cost in ms>".  Entries read from the file
+// replace those of the same key; lines that do not parse are an error.
+pawfe_status pawfe_tune_cache_load(const char* path) {
+  if (!path) return fail(PAWFE_EINVAL, "path is NULL");
+  std::ifstream in(path);
+  if (!in) return fail(PAWFE_EINVAL, std::string("cannot open ") + path);
+  std::string line;
+  if (!std::getline(in, line) || line != "pawfe-tune-cache 1") return fail(PAWFE_EINVAL, "not a pawfe tuning cache");
+  std::map<std::string, TuneEntry> rd;
+  while (std::getline(in, line)) {
+    if (line.empty()) continue;
+    std::istringstream ls(line);
+    std::string key;
+    TuneEntry e;
+    std::string rest;
+    if (!(ls >> key >> e.block >> e.cost) || (ls >> rest) || e.block < 1 || !(e.cost >= 0.0))
+      return fail(PAWFE_EINVAL, "malformed tuning-cache line: " + line);
+    rd[key] = e;
+  }
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  for (auto& kv : rd) g_cache[kv.first] = kv.second;
+  return PAWFE_OK;
+}
+
+pawfe_status pawfe_tune_cache_save(const char* path) {
+  if (!path) return fail(PAWFE_EINVAL, "path is NULL");
+  const std::string tmp = std::string(path) + ".tmp";
+  {
+    std::ofstream out(tmp, std::ios::trunc);
+    if (!out) return fail(PAWFE_EINVAL, std::string("cannot write ") + tmp);
+    out << "pawfe-tune-cache 1\n";
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    out.precision(17);
+    for (const auto& kv : g_cache) out << kv.first << " " << kv.second.block << " " << kv.second.cost << "\n";
+    if (!out) return fail(PAWFE_EINVAL, std::string("write failed: ") + tmp);
+  }
+  if (std::rename(tmp.c_str(), path) != 0) return fail(PAWFE_EINVAL, std::string("cannot rename to ") + path);
+  return PAWFE_OK;
+}
 
 }  // extern "C"

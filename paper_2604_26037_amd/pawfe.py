@@ -32,6 +32,8 @@ EXPORTS = [
     "pawfe_chfsi_solve_workspace", "pawfe_chfsi_solve",
     "pawfe_batch_create", "pawfe_batch_run", "pawfe_batch_query", "pawfe_batch_destroy",
     "pawfe_apply_H_noalloc", "pawfe_halo_pack_bf16", "pawfe_halo_unpack_bf16",
+    "pawfe_batch_tuning_runs", "pawfe_tune_cache_load", "pawfe_tune_cache_save", "pawfe_tune_cache_clear",
+    "pawfe_tune_cache_size",
 ]
 
 
@@ -102,6 +104,11 @@ def load(path=LIB_PATH):
         "pawfe_batch_create": [P(FilterJob), i32, i32, i32, i32, vp, P(vp)],
         "pawfe_batch_run": [vp, vp],
         "pawfe_batch_query": [vp, P(i32), P(i32), P(i32), P(i32)],
+        "pawfe_batch_tuning_runs": [vp, P(i32)],
+        "pawfe_tune_cache_load": [C.c_char_p],
+        "pawfe_tune_cache_save": [C.c_char_p],
+        "pawfe_tune_cache_clear": [],
+        "pawfe_tune_cache_size": [P(C.c_int64)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -427,6 +434,26 @@ def band_energy_function():
     return BandEnergy
 
 
+def tune_cache_load(path):
+    """Merge a tuning cache written by tune_cache_save into the process table."""
+    _check(load().pawfe_tune_cache_load(os.fsencode(path)))
+
+
+def tune_cache_save(path):
+    """Write the process-wide tuning cache of the batch autotuner to `path`."""
+    _check(load().pawfe_tune_cache_save(os.fsencode(path)))
+
+
+def tune_cache_clear():
+    _check(load().pawfe_tune_cache_clear())
+
+
+def tune_cache_size():
+    n = C.c_int64()
+    _check(load().pawfe_tune_cache_size(C.byref(n)))
+    return n.value
+
+
 class Batch:
     """Filters of several independent problems captured into one HIP graph.
 
@@ -472,6 +499,13 @@ class Batch:
         sof = np.zeros(self.njobs, dtype=np.int32)
         _check(_lib.pawfe_batch_query(self._h, C.byref(ns), _iptr(blocks), _iptr(sof), None))
         return ns.value, blocks, sof
+
+    @property
+    def tuning_runs(self):
+        """Timed tuning runs spent when the batch was created (0: all cached)."""
+        n = C.c_int32()
+        _check(_lib.pawfe_batch_tuning_runs(self._h, C.byref(n)))
+        return n.value
 
     @property
     def ngraphs(self):

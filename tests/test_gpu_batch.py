@@ -197,3 +197,33 @@ def test_batch_autotuned_several_block_candidates(wide_problems, prec):
             for g, f in zip(got, first):
                 np.testing.assert_array_equal(g, f)
     b.close()
+
+
+def test_batch_tuning_cache_round_trip(wide_problems, tmp_path):
+    """A batch tuned once, its decisions saved to a file, the table cleared
+    and loaded again: the second batch times nothing, keeps the schedule and
+    matches the oracle's filters."""
+    from paper_2604_26037_amd import FP64, Batch, tune_cache_clear, tune_cache_load, tune_cache_save
+    tune_cache_clear()
+    jobs, keep = _jobs(wide_problems)
+    b1 = Batch(jobs, prec=FP64)
+    assert b1.tuning_runs > 0
+    s1 = b1.schedule()
+    b1.close()
+    path = str(tmp_path / "tune.cache")
+    tune_cache_save(path)
+    tune_cache_clear()
+    tune_cache_load(path)
+    jobs2, keep2 = _jobs(wide_problems)
+    b2 = Batch(jobs2, prec=FP64)
+    assert b2.tuning_runs == 0
+    s2 = b2.schedule()
+    assert s1[0] == s2[0]
+    np.testing.assert_array_equal(s1[1], s2[1])
+    np.testing.assert_array_equal(s1[2], s2[2])
+    b2.run()
+    torch.cuda.synchronize()
+    for j, p in zip(jobs2, wide_problems):
+        assert _rel(j["out"].cpu().numpy(), p["want"]) < 1e-9
+    b2.close()
+    tune_cache_clear()

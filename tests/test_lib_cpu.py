@@ -115,3 +115,42 @@ def test_batch_rejects_bad_jobs():
     assert b"op is NULL" in lib.pawfe_last_error()
     assert lib.pawfe_batch_create(jobs, 1, 2, 1, 0, None, C.byref(h)) == pw.PAWFE_EUNSUPPORTED
     assert h.value is None
+
+
+def test_tune_cache_file_round_trip(tmp_path):
+    """The autotuner's cache file: entries load, merge and save unchanged;
+    a wrong first line or a malformed entry is refused and leaves the table
+    as it was (host only, no GPU call)."""
+    _lib()
+    pw.tune_cache_clear()
+    assert pw.tune_cache_size() == 0
+    src = tmp_path / "a.cache"
+    src.write_text("pawfe-tune-cache 1\n"
+                   "job/gfx950/n6x6x6/p5/q7/a8/j144/c0/g0/v0/s20000/N128/m25/P1 64 12.5\n"
+                   "batch/16384+job/gfx950/n6x6x6/p5/q7/a8/j144/c0/g0/v0/s20000/N128/m25/P1 2 0\n")
+    pw.tune_cache_load(str(src))
+    assert pw.tune_cache_size() == 2
+    out = tmp_path / "b.cache"
+    pw.tune_cache_save(str(out))
+    lines = out.read_text().splitlines()
+    assert lines[0] == "pawfe-tune-cache 1"
+    assert sorted(l.split()[:2] for l in lines[1:]) == sorted(l.split()[:2] for l in src.read_text().splitlines()[1:])
+    assert float([l for l in lines if l.startswith("job/")][0].split()[2]) == 12.5
+    # a second file merges (same key replaced, new key added)
+    more = tmp_path / "c.cache"
+    more.write_text("pawfe-tune-cache 1\n"
+                    "job/gfx950/n6x6x6/p5/q7/a8/j144/c0/g0/v0/s20000/N128/m25/P1 128 9\n"
+                    "job/gfx950/n8x8x8/p5/q7/a8/j144/c0/g0/v0/s30000/N64/m25/P1 64 3\n")
+    pw.tune_cache_load(str(more))
+    assert pw.tune_cache_size() == 3
+    for bad in ("not a cache\n", "pawfe-tune-cache 1\nkey-only\n", "pawfe-tune-cache 1\nk 0 1.0\n",
+                "pawfe-tune-cache 1\nk 4 1.0 extra\n"):
+        f = tmp_path / "bad.cache"
+        f.write_text(bad)
+        with pytest.raises(pw.PawfeError):
+            pw.tune_cache_load(str(f))
+        assert pw.tune_cache_size() == 3
+    with pytest.raises(pw.PawfeError):
+        pw.tune_cache_load(str(tmp_path / "missing.cache"))
+    pw.tune_cache_clear()
+    assert pw.tune_cache_size() == 0
