@@ -182,6 +182,7 @@ struct Tables {
   double ME[PC][PC] = {};
   double MO[PH > 0 ? PH : 1][PH > 0 ? PH : 1] = {};
   double DG[NQ][NQ] = {};  // DG[i][j] = g_j'(eta_i), g_j the Lagrange basis through the Gauss points
+  double G1[NP][NP] = {};  // G1[a][b] = sum_q w_q l_a(eta_q) l_b'(eta_q) (imaginary k term)
 };
 
 template <int NP, int NQ>
@@ -204,17 +205,19 @@ constexpr Tables<NP, NQ> make_tables() {
       B[q][a] = v;
       D[q][a] = d;
     }
+  Tables<NP, NQ> t{};
   for (int a = 0; a < NP; ++a)
     for (int b = 0; b < NP; ++b) {
-      double k = 0.0, m = 0.0;
+      double k = 0.0, m = 0.0, gi = 0.0;
       for (int q = 0; q < NQ; ++q) {
         k += g.w[q] * D[q][a] * D[q][b];
         m += g.w[q] * B[q][a] * B[q][b];
+        gi += g.w[q] * B[q][a] * D[q][b];
       }
       K[a][b] = k;
       M[a][b] = m;
+      t.G1[a][b] = gi;
     }
-  Tables<NP, NQ> t{};
   for (int i = 0; i < NQ; ++i)
     for (int jj = 0; jj < NQ; ++jj) {
       double d = 0.0;
@@ -379,6 +382,21 @@ __host__ __device__ __forceinline__ void line_sym(const EOIn<NP, T>& in, T (&y)[
   });
 }
 
+// y = G1 x on one line of NP node values (G1 is not symmetric: a plain
+// product with compile-time coefficients)
+template <int NP, int NQ, typename T>
+__host__ __device__ __forceinline__ void line_g1(const T (&x)[NP], T (&y)[NP]) {
+  using TB = ref1d::Tab<NP, NQ>;
+  sfor<NP>([&](auto a) {
+    T acc = T(0);
+    sfor<NP>([&](auto b) {
+      constexpr T c = (T)TB::t.G1[a][b];
+      acc = fma_t(c, x[b], acc);
+    });
+    y[a] = acc;
+  });
+}
+
 // t = v (Dg u) + Dg^T (v u) on one line of NQ quadrature values: the GGA
 // term along one axis, with v = W_q det J (2/h) V_GGA along that axis.  The
 // derivative of the FE field at the Gauss points is the collocation
@@ -418,16 +436,24 @@ constexpr int kValuGenH = 1;     // K + V, per-cell geometry
 constexpr int kValuGenHG = 2;    // K + V + the GGA term, per-cell geometry
 constexpr int kValuGenMass = 3;  // det J_e M, times -lambda_n per column when lam is given
 constexpr int kValuHRes = 4;     // K + V - lambda_n M, every cell of one size
+// complex (k-point) operators, every cell of one size: the two modes above
+// plus the imaginary k term s_n (Hi X)[n ^ 1] on the (re, im) column pairs
+constexpr int kValuHC = 5;
+constexpr int kValuHResC = 6;
 // variants that read the per-cell geometry table (and need it non-null)
 constexpr bool is_general_mode(int mode) {
   return mode == kValuGenH || mode == kValuGenHG || mode == kValuGenMass;
 }
-static_assert(!is_general_mode(kValuH) && !is_general_mode(kValuHRes), "uniform variants");
+static_assert(!is_general_mode(kValuH) && !is_general_mode(kValuHRes) && !is_general_mode(kValuHC) &&
+                  !is_general_mode(kValuHResC),
+              "uniform variants");
 // Waves per SIMD the registers are held to: FP32 six (three workgroups of
-// eight waves per CU, as many as the LDS holds), FP64 three; the GGA variant
-// holds two more slabs in LDS (two workgroups per CU): FP32 four, FP64 two.
+// eight waves per CU, as many as the LDS holds), FP64 three; the GGA and the
+// complex variants hold one or two more slabs in LDS (two workgroups per
+// CU): FP32 four, FP64 two.
 template <typename T, int MODE>
-constexpr int kWaves = MODE == kValuGenHG ? (sizeof(T) == 4 ? 4 : 2) : (sizeof(T) == 4 ? 6 : 3);
+constexpr int kWaves = (MODE == kValuGenHG || MODE == kValuHC || MODE == kValuHResC) ? (sizeof(T) == 4 ? 4 : 2)
+                                                                                     : (sizeof(T) == 4 ? 6 : 3);
 constexpr int kXP = 9;
 // U: extents up to 8 x 8 x 8;  K, M: up to 7 x 7 x 7 (element offsets, col fastest)
 template <typename T>
@@ -468,8 +494,10 @@ k_cell_valu(CellArgs<T> A, int ncoltiles, int nitems, T fx, T fy, T fz) {
   constexpr bool GEN = is_general_mode(MODE);   // reads the per-cell table A.geo
   constexpr bool GGA = MODE == kValuGenHG;
   constexpr bool MASS = MODE == kValuGenMass;
-  constexpr bool RES = MODE == kValuHRes;
+  constexpr bool RES = MODE == kValuHRes || MODE == kValuHResC;
+  constexpr bool CPLX = MODE == kValuHC || MODE == kValuHResC;
   static_assert(!(RES && GEN), "the residual mode uses the uniform factors");
+  static_assert(!(CPLX && GEN), "complex operators use the uniform factors");
   constexpr int CB = kCB<T>;
   constexpr int NT = kNT<T>;
   constexpr int S = NT / CB;                   // line slots
@@ -485,6 +513,7 @@ k_cell_valu(CellArgs<T> A, int ncoltiles, int nitems, T fx, T fy, T fz) {
   __shared__ T vws[MASS ? 1 : NQ3];
   __shared__ T sG[GGA ? kSlabU<T> : 1];   // GGA: V u plus the GGA term at the quadrature points
   __shared__ T vgs[GGA ? 3 * NQ3 : 1];    // GGA: W det J (2/h_d) V_GGA,d of the item's cell
+  __shared__ T sI[CPLX ? kSlabK<T> : 1];  // complex: the imaginary k term of the partner column
   const int tid = threadIdx.x;
   const int col = tid & (CB - 1);
   const int slot = tid / CB;
@@ -655,15 +684,27 @@ k_cell_valu(CellArgs<T> A, int ncoltiles, int nitems, T fx, T fy, T fz) {
     }
 
     // P1 x: lines (b, c); U -> B U (in place), K1 U -> K, M1 U -> M
-    // (mass: M1 U -> M only)
+    // (mass: M1 U -> M only; complex: also I <- G1 U' of the partner column)
     {
       const Lines<NP, NP, S, R> ln(lslot);
-      T x[R][NP];
+      T x[R][NP], xp[CPLX ? R : 1][NP];
 #pragma unroll
       for (int r = 0; r < R; ++r) sfor<NP>([&](auto a) { x[r][a] = sU[offU<T>(a, ln.u[r], ln.v[r]) + col]; });
+      if constexpr (CPLX) {
+        // the partner column's line (the neighbouring lane of this wave
+        // overwrites it below: its load is issued before any store)
+#pragma unroll
+        for (int r = 0; r < R; ++r) sfor<NP>([&](auto a) { xp[r][a] = sU[offU<T>(a, ln.u[r], ln.v[r]) + (col ^ 1)]; });
+        asm volatile("" ::: "memory");
+      }
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         if (!ln.on[r]) continue;
+        if constexpr (CPLX) {
+          T yi[NP];
+          line_g1<NP, NQ>(xp[r], yi);
+          sfor<NP>([&](auto a) { sI[offK<T>(a, ln.u[r], ln.v[r]) + col] = yi[a]; });
+        }
         // each result is stored as soon as it is formed (fewer live registers)
         const EOIn<NP, T> eo = split_eo<NP>(x[r]);
         if constexpr (!MASS) {
@@ -826,19 +867,35 @@ k_cell_valu(CellArgs<T> A, int ncoltiles, int nitems, T fx, T fy, T fz) {
       }
     }
     // P7 y (kinetic; K and M are not touched by P2-P6, so no barrier is
-    // needed before it): lines (a, c); K <- fx M1 K + fy K1 M,  M <- M1 M
+    // needed before it): lines (a, c); K <- fx M1 K + fy K1 M,  M <- M1 M;
+    // complex: I <- gx M1 I + gy G1 M' (M' the partner column's M)
     {
       const Lines<NP, NP, S, R> ln(lslot);
-      T k[R][NP], m[R][NP];
+      T k[R][NP], m[R][NP], mp[CPLX ? R : 1][NP], iv[CPLX ? R : 1][NP];
 #pragma unroll
       for (int r = 0; r < R; ++r)
         sfor<NP>([&](auto b) {
           if constexpr (!MASS) k[r][b] = sK[offK<T>(ln.u[r], b, ln.v[r]) + col];
           m[r][b] = sM[offK<T>(ln.u[r], b, ln.v[r]) + col];
         });
+      if constexpr (CPLX) {   // the partner's M line is overwritten below by its lane
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+          sfor<NP>([&](auto b) {
+            mp[r][b] = sM[offK<T>(ln.u[r], b, ln.v[r]) + (col ^ 1)];
+            iv[r][b] = sI[offK<T>(ln.u[r], b, ln.v[r]) + col];
+          });
+        asm volatile("" ::: "memory");
+      }
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         if (!ln.on[r]) continue;
+        if constexpr (CPLX) {
+          T mi[NP], gm[NP];
+          line_sym<NP, NQ, false>(split_eo<NP>(iv[r]), mi);
+          line_g1<NP, NQ>(mp[r], gm);
+          sfor<NP>([&](auto b) { sI[offK<T>(ln.u[r], b, ln.v[r]) + col] = fma_t(A.gk[0], mi[b], A.gk[1] * gm[b]); });
+        }
         const EOIn<NP, T> em = split_eo<NP>(m[r]);
         if constexpr (!MASS) {
           T mk[NP], km[NP];
@@ -853,15 +910,20 @@ k_cell_valu(CellArgs<T> A, int ncoltiles, int nitems, T fx, T fy, T fz) {
     }
     __syncthreads();
     // P8 z: lines (a, b): K <- U + M1 K + fz K1 M (the cell result);
-    // mass: K <- M1 M
+    // mass: K <- M1 M; complex: plus s_n (M1 I + gz G1 M'), s_n = -1 on real
+    // and +1 on imaginary columns
     {
       const Lines<NP, NP, S, R> ln(lslot);
-      T k[R][NP], m[R][NP];
+      T k[R][NP], m[R][NP], mp[CPLX ? R : 1][NP], iv[CPLX ? R : 1][NP];
 #pragma unroll
       for (int r = 0; r < R; ++r)
         sfor<NP>([&](auto c) {
           if constexpr (!MASS) k[r][c] = sK[offK<T>(ln.u[r], ln.v[r], c) + col];
           m[r][c] = sM[offK<T>(ln.u[r], ln.v[r], c) + col];
+          if constexpr (CPLX) {
+            mp[r][c] = sM[offK<T>(ln.u[r], ln.v[r], c) + (col ^ 1)];
+            iv[r][c] = sI[offK<T>(ln.u[r], ln.v[r], c) + col];
+          }
         });
 #pragma unroll
       for (int r = 0; r < R; ++r) {
@@ -883,6 +945,13 @@ k_cell_valu(CellArgs<T> A, int ncoltiles, int nitems, T fx, T fy, T fz) {
             line_sym<NP, NQ, false>(em, mm);
             const T ml = valid ? -(T)A.lam[n] * idet : T(0);
             sfor<NP>([&](auto c) { acc[c] = fma_t(ml, mm[c], acc[c]); });
+          }
+          if constexpr (CPLX) {
+            T mi[NP], gm[NP];
+            line_sym<NP, NQ, false>(split_eo<NP>(iv[r]), mi);
+            line_g1<NP, NQ>(mp[r], gm);
+            const T sg = (col & 1) ? T(1) : T(-1);
+            sfor<NP>([&](auto c) { acc[c] = fma_t(sg, fma_t(A.gk[2], gm[c], mi[c]), acc[c]); });
           }
           sfor<NP>([&](auto c) {
             sK[offK<T>(ln.u[r], ln.v[r], c) + col] = acc[c] + sU[offU<T>(ln.u[r], ln.v[r], c) + col];
@@ -932,9 +1001,13 @@ pawfe_status run_cell_valu(const pawfe_op* op, const CellArgs<T>& a0, hipStream_
   constexpr int CB = kCB<T>;
   CellArgs<T> a = a0;
   a.detJ = (T)op->detJ;
+  for (int d = 0; d < 3; ++d) a.gk[d] = (T)(-op->kpt[d] * op->detJ * (2.0 / op->h[d]));
+  if ((MODE == kValuHC || MODE == kValuHResC) && !op->cplx)
+    return fail(PAWFE_EINVAL, "internal: complex cell variant on a real operator");
   if (is_general_mode(MODE) && !a.geo) return fail(PAWFE_EINVAL, "internal: general cell variant without geometry");
   if (MODE == kValuGenHG && !a.vg) return fail(PAWFE_EINVAL, "internal: GGA cell variant without its table");
-  if (MODE == kValuHRes && !a.lam) return fail(PAWFE_EINVAL, "internal: residual cell variant without lambda");
+  if ((MODE == kValuHRes || MODE == kValuHResC) && !a.lam)
+    return fail(PAWFE_EINVAL, "internal: residual cell variant without lambda");
   const int ncoltiles = (a.ncols + CB - 1) / CB;
   const T fx = (T)(0.5 * op->detJ * (2.0 / op->h[0]) * (2.0 / op->h[0]));
   const T fy = (T)(0.5 * op->detJ * (2.0 / op->h[1]) * (2.0 / op->h[1]));

@@ -27,6 +27,7 @@ struct CellArgs {
   const T* geo;        // [E][4] per cell: fx, fy, fz (1/2 det J (2/h_d)^2) and det J
   const T* vg;         // [E][3][nq^3] W_q det J (2/h_d) V_GGA,d (GGA term), or null
   T detJ;              // det J of every cell (residual mode of the vector-ALU kernel)
+  T gk[3];             // complex operators: -k_d det J (2/h_d) (imaginary k term)
 };
 
 struct DensArgs {

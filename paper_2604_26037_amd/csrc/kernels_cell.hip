@@ -131,7 +131,9 @@ pawfe_status launch_cell(const pawfe_op* op, int mode, const T* X, int64_t ldx, 
   // and bf16x3)
   if ((mode == kModeH || mode == kModeHRes) && !bf3) st = launch_cell_valu(op, mode, a, s, &done);
   if (st == PAWFE_OK && !done) st = launch_cell_mfma<T>(op, mode, a, s);
-  // complex operators: the imaginary local term, on the (re, im) column pairs
+  if (done) return st;   // the vector-ALU variants include the imaginary k term
+  // complex operators on the matrix cores: the imaginary local term, on the
+  // (re, im) column pairs, as a second launch
   if (st != PAWFE_OK || !op->cplx || (mode != kModeH && mode != kModeHRes)) return st;
   return launch_cell_mfma<T>(op, kModeImg, a, s);
 }
