@@ -440,12 +440,13 @@ constexpr int kValuHRes = 4;     // K + V - lambda_n M, every cell of one size
 // plus the imaginary k term s_n (Hi X)[n ^ 1] on the (re, im) column pairs
 constexpr int kValuHC = 5;
 constexpr int kValuHResC = 6;
+constexpr int kValuMass = 7;     // det J M, every cell of one size (real and complex operators alike)
 // variants that read the per-cell geometry table (and need it non-null)
 constexpr bool is_general_mode(int mode) {
   return mode == kValuGenH || mode == kValuGenHG || mode == kValuGenMass;
 }
 static_assert(!is_general_mode(kValuH) && !is_general_mode(kValuHRes) && !is_general_mode(kValuHC) &&
-                  !is_general_mode(kValuHResC),
+                  !is_general_mode(kValuHResC) && !is_general_mode(kValuMass),
               "uniform variants");
 // Waves per SIMD the registers are held to: FP32 six (three workgroups of
 // eight waves per CU, as many as the LDS holds), FP64 three; the GGA and the
@@ -493,7 +494,7 @@ __global__ void __launch_bounds__(kNT<T>) __attribute__((amdgpu_waves_per_eu((kW
 k_cell_valu(CellArgs<T> A, int ncoltiles, int nitems, T fx, T fy, T fz) {
   constexpr bool GEN = is_general_mode(MODE);   // reads the per-cell table A.geo
   constexpr bool GGA = MODE == kValuGenHG;
-  constexpr bool MASS = MODE == kValuGenMass;
+  constexpr bool MASS = MODE == kValuGenMass || MODE == kValuMass;
   constexpr bool RES = MODE == kValuHRes || MODE == kValuHResC;
   constexpr bool CPLX = MODE == kValuHC || MODE == kValuHResC;
   static_assert(!(RES && GEN), "the residual mode uses the uniform factors");

@@ -126,10 +126,9 @@ pawfe_status launch_cell(const pawfe_op* op, int mode, const T* X, int64_t ldx, 
   }
   pawfe_status st = PAWFE_OK;
   bool done = false;
-  // K + V and the residual K + V - lambda M in FP32 or FP64: vector-ALU
-  // kernel (the matrix-core kernel keeps the mass and imaginary-term modes
-  // and bf16x3)
-  if ((mode == kModeH || mode == kModeHRes) && !bf3) st = launch_cell_valu(op, mode, a, s, &done);
+  // K + V, the residual K + V - lambda M and the mass term in FP32 or FP64:
+  // vector-ALU kernel (the matrix-core kernel keeps bf16x3)
+  if ((mode == kModeH || mode == kModeHRes || mode == kModeMass) && !bf3) st = launch_cell_valu(op, mode, a, s, &done);
   if (st == PAWFE_OK && !done) st = launch_cell_mfma<T>(op, mode, a, s);
   if (done) return st;   // the vector-ALU variants include the imaginary k term
   // complex operators on the matrix cores: the imaginary local term, on the

@@ -6,9 +6,9 @@
 
 namespace pawfe {
 
-// K + V (mode kModeH) or K + V - lambda_n M (mode kModeHRes) on the vector
-// ALUs, for complex operators with the imaginary k term on the (re, im)
-// column pairs in the same launch; *done is false when the mode, degree or
+// K + V (mode kModeH), K + V - lambda_n M (mode kModeHRes) or det J M (mode
+// kModeMass) on the vector ALUs, for complex operators with the imaginary k
+// term on the (re, im) column pairs in the same launch; *done is false when the mode, degree or
 // Gauss rule has no compiled variant (the caller then uses the matrix-core
 // kernel)
 template <typename T>
@@ -17,9 +17,19 @@ pawfe_status launch_cell_valu(const pawfe_op* op, int mode, const CellArgs<T>& a
   if (a.ldx < 0 || a.ldy < 0 || a.ldx * (int64_t)sizeof(T) >= (int64_t(1) << 32) ||
       a.ldy * (int64_t)sizeof(T) >= (int64_t(1) << 32))
     return fail(PAWFE_EINVAL, "row stride of 4 GiB or more");
-  if (op->nq != op->p + 2 || (mode != kModeH && mode != kModeHRes)) return PAWFE_OK;
+  if (op->nq != op->p + 2 || (mode != kModeH && mode != kModeHRes && mode != kModeMass)) return PAWFE_OK;
   if (mode == kModeHRes && !a.lam) return fail(PAWFE_EINVAL, "residual mode needs lambda");
   *done = true;
+  if (mode == kModeMass) {   // real, also for complex operators (both halves alike)
+    switch (op->p) {
+      case 2: return run_cell_valu<T, 3, 4, kValuMass>(op, a, s);
+      case 3: return run_cell_valu<T, 4, 5, kValuMass>(op, a, s);
+      case 4: return run_cell_valu<T, 5, 6, kValuMass>(op, a, s);
+      case 5: return run_cell_valu<T, 6, 7, kValuMass>(op, a, s);
+      case 6: return run_cell_valu<T, 7, 8, kValuMass>(op, a, s);
+      default: *done = false; return PAWFE_OK;
+    }
+  }
   const bool res = mode == kModeHRes;
   if (op->cplx) {   // the imaginary k term joins the same passes
     switch (op->p) {
