@@ -55,6 +55,9 @@ template <typename T>
 pawfe_status launch_cell(const pawfe_op* op, int mode, const T* X, int64_t ldx, T* Y, int64_t ldy,
                          int ncols, const double* lam, double alpha, hipStream_t s, bool bf3 = false);
 
+// bf16x3 split products on the matrix cores (kernels_cell_mfma.hip): K + V
+// (kModeH), the mass term (kModeMass) and the imaginary k term (kModeImg) of
+// FP32 data; any other request returns PAWFE_EUNSUPPORTED.
 template <typename T>
 pawfe_status launch_cell_mfma(const pawfe_op* op, int mode, const CellArgs<T>& a, hipStream_t s);
 

@@ -1,5 +1,12 @@
 // Local (cell) part of the FE operators on the gfx950 matrix cores.
 //
+// Built for the bf16x3 precision (FP32 data, every contraction as three
+// bf16 products with FP32 accumulation on v_mfma_f32_16x16x16_bf16): K + V,
+// the mass term and the imaginary k term.  FP32 and FP64 run on the
+// vector-ALU kernel (cell_valu.h), which avoids the padding of the 7- and
+// 8-wide contractions that the matrix-core tiles need; the FP32 / FP64 MFMA
+// forms described below remain in the templates but are not instantiated.
+//
 // Every 1-D contraction of the sum-factorized cell operator (kinetic
 // fx Mz My Kx + fy Mz Ky Mx + fz Kz My Mx, the potential term
 // B^T diag(V(q) W_q) B, the mass detJ Mz My Mx; eqs. "FEM Ham entries" and
@@ -787,17 +794,12 @@ int cell_grid(int nitems) {
   return std::max(8, std::min(resident, (nitems + 7) / 8 * 8));
 }
 
+// bf16x3 split products only (FP32 data): every other local term runs on the
+// vector-ALU kernel
 template <typename T, int NP, int NQ, int CB, int MODE>
 void launch_mode(const CellArgs<T>& ac, const Tab1D<T>* tab, int ncoltiles, int nitems, hipStream_t s) {
-  if constexpr (sizeof(T) == 4) {
-    if (ac.bf3) {
-      const dim3 grid(cell_grid<k_cell_mfma<T, NP, NQ, CB, MODE, true>>(nitems)), block(256);
-      hipLaunchKernelGGL((k_cell_mfma<T, NP, NQ, CB, MODE, true>), grid, block, 0, s, ac, tab, ncoltiles, nitems);
-      return;
-    }
-  }
-  const dim3 grid(cell_grid<k_cell_mfma<T, NP, NQ, CB, MODE, false>>(nitems)), block(256);
-  hipLaunchKernelGGL((k_cell_mfma<T, NP, NQ, CB, MODE, false>), grid, block, 0, s, ac, tab, ncoltiles, nitems);
+  const dim3 grid(cell_grid<k_cell_mfma<T, NP, NQ, CB, MODE, true>>(nitems)), block(256);
+  hipLaunchKernelGGL((k_cell_mfma<T, NP, NQ, CB, MODE, true>), grid, block, 0, s, ac, tab, ncoltiles, nitems);
 }
 
 template <typename T, int NP, int NQ, int CB>
@@ -812,8 +814,6 @@ pawfe_status run_cell_mfma(const pawfe_op* op, int mode, CellArgs<T> a, hipStrea
     const int nitems = (c1 - c0) * ncoltiles;
     if (mode == kModeH)
       launch_mode<T, NP, NQ, CB, kModeH>(ac, tab, ncoltiles, nitems, s);
-    else if (mode == kModeHRes)
-      launch_mode<T, NP, NQ, CB, kModeHRes>(ac, tab, ncoltiles, nitems, s);
     else if (mode == kModeImg)
       launch_mode<T, NP, NQ, CB, kModeImg>(ac, tab, ncoltiles, nitems, s);
     else
@@ -828,6 +828,8 @@ pawfe_status run_cell_mfma(const pawfe_op* op, int mode, CellArgs<T> a, hipStrea
 template <typename T>
 pawfe_status launch_cell_mfma(const pawfe_op* op, int mode, const CellArgs<T>& a, hipStream_t s) {
   constexpr int CB = sizeof(T) == 8 ? 4 : 8;
+  if (sizeof(T) != 4 || !a.bf3 || mode == kModeHRes)
+    return fail(PAWFE_EUNSUPPORTED, "the matrix-core cell kernel is built for bf16x3 (K + V, mass, imaginary term)");
   if (a.ldx < 0 || a.ldy < 0 || a.ldx * (int64_t)sizeof(T) >= (int64_t(1) << 32) ||
       a.ldy * (int64_t)sizeof(T) >= (int64_t(1) << 32))
     return fail(PAWFE_EINVAL, "row stride of 4 GiB or more");
@@ -841,7 +843,10 @@ pawfe_status launch_cell_mfma(const pawfe_op* op, int mode, const CellArgs<T>& a
   }
 }
 
-template pawfe_status launch_cell_mfma<double>(const pawfe_op*, int, const CellArgs<double>&, hipStream_t);
+template <>
+pawfe_status launch_cell_mfma<double>(const pawfe_op*, int, const CellArgs<double>&, hipStream_t) {
+  return fail(PAWFE_EUNSUPPORTED, "the matrix-core cell kernel is built for bf16x3 (FP32 data) only");
+}
 template pawfe_status launch_cell_mfma<float>(const pawfe_op*, int, const CellArgs<float>&, hipStream_t);
 
 }  // namespace pawfe
