@@ -69,9 +69,11 @@ enum {
  * local operator run as bf16x3 split products on the bf16 matrix cores
  * (x = hi + lo, two bf16 parts; a*b ~ lo_a hi_b + hi_a lo_b + hi_a hi_b with
  * FP32 accumulation; relative error ~2^-16 per product, the FP32 (TF32-like)
- * stand-in of the precision paragraph).  The projector contractions stay
- * FP32.  Accepted by the apply entry points, pawfe_apply_local,
- * pawfe_cheb_filter and its workspace query; data must be finite. */
+ * stand-in of the precision paragraph).  The projector reduction of real
+ * operators runs the same way on the matrix cores; the projector add-back
+ * stays FP32.  Accepted by the apply entry points, pawfe_apply_local,
+ * pawfe_cheb_filter and its workspace query (not for graded meshes or the
+ * GGA term: PAWFE_EUNSUPPORTED); data must be finite. */
 enum { PAWFE_FP64 = 0, PAWFE_FP32 = 1, PAWFE_BF16X3 = 2 };
 
 /* How G^a inside Delta_Sinv^a = (Delta_S^{a,-1} + G^a)^{-1} is formed

@@ -854,7 +854,7 @@ pawfe_status pawfe_cheb_filter(const pawfe_op* op, const void* Xin, int64_t ldx,
   // Blocks are uncoupled.  With room for two block states (and more than one
   // block), even blocks run on one internal stream and odd blocks on the
   // other, forked from and joined back into `s`: one block's HBM-bound node
-  // kernels then overlap the other's latency-bound cell kernel.
+  // kernels then overlap the other's ALU-bound cell kernel.
   const int nconc = (nvec > B && ws_bytes >= 2 * one) ? 2 : 1;
   pawfe_op* mop = const_cast<pawfe_op*>(op);
   if (nconc == 2) {

@@ -1,10 +1,13 @@
 // Cell-level entry of the FE operators and the band-energy density.
 //
 // launch_cell sets up the arguments of the cell operator (kinetic + V(q)W_q,
-// the residual variant with -lambda_n W_q, or the mass; the cell-level
-// product of the operator-action subsection) and runs, one launch per cell
-// colour, the vector-ALU kernel of kernels_cell_valu.hip (K + V) or the
-// matrix-core kernel of kernels_cell_mfma.hip (every other case).
+// the residual variant with -lambda_n M, or the mass; the cell-level product
+// of the operator-action subsection) and runs, one launch per cell colour,
+// the vector-ALU kernel (cell_valu.h: kernels_cell_valu.hip for operators
+// whose cells share one size, with the imaginary k term of complex
+// operators in the same launch; kernels_cell_gen_*.hip for graded meshes and
+// the GGA term) or, for bf16x3, the matrix-core kernel of
+// kernels_cell_mfma.hip.
 //
 // k_cell_density is the adjoint contraction of the potential term: the
 // band-energy density W_q sum_n occ_n |u_n(x_q)|^2 at the Gauss points of
