@@ -177,11 +177,20 @@ pawfe_status apply_entry(const pawfe_op* cop, int which, const void* X, int64_t 
 
 // ---- filter ------------------------------------------------------------------
 
+// The filter step fused into the cell kernel (cells of one size, FP64 or
+// FP32 recurrence); otherwise the node-wise step with an explicit T.
+bool fused_step(const pawfe_op* op, int32_t prec) { return prec != PAWFE_BF16X3 && cell_step_available(op); }
+
 // B: real columns of one block (two per complex column)
 size_t filter_ws_bytes(const pawfe_op* op, int64_t B, int32_t prec) {
   const size_t tr = prec == PAWFE_FP64 ? 8 : 4;
   size_t b = align256((size_t)op->M * B * 8);            // Y
-  b += 3 * align256((size_t)op->M * B * tr);            // RX, RY, T
+  if (fused_step(op, prec)) {
+    b += 2 * align256((size_t)op->M * B * tr);                              // RX, RY
+    b += 4 * align256((size_t)std::max(op->npj_total, 1) * B * 8);         // c', d_prev, nw (two)
+  } else {
+    b += 3 * align256((size_t)op->M * B * tr);          // RX, RY, T
+  }
   b += nl_scratch_bytes(op, B);
   b += 2 * align256((size_t)B * 8);                      // lamX, lamY
   if (op->cplx) b += align256((size_t)B * 8);             // lambda per real column
@@ -231,6 +240,83 @@ pawfe_status filter_block(const pawfe_op* op, const double* X, int64_t ldx, doub
   CHECK(launch_nl_reduce<TR>(op, RY, ld, nc, true, nb.part, nb.c, s, bf3));
   CHECK(launch_atom_mul(op, op->d.dSinv, nullptr, nullptr, 1.0, nb.c, nb.d, nc, s, op->d.dSinv_im));
   return launch_node_finalize<TR>(op, RY, ld, nb.d, X, ldx, lamY, Xo, ldo, nc, s);
+}
+
+// The same filter with the step's node part fused into the cell kernel
+// (cells of one size, FP64 or FP32 recurrence).  R_Y is kept as
+// R~ = R - C w with w the projector vector whose C w the previous step still
+// owes it (nw = -w is stored), and R_X as R' = R - C d of its own step:
+//   c = C^T M_D^{-1} R = reduce(R~) - G nw_prev      (G = C^T M_D^{-1} C)
+//   d = Delta_Sinv c,  t = c - G d,  q = a Delta_H t
+//   R_Y <- R~ - C (nw_prev + d) = R - C d            (one add-back)
+//   R_X <- -a c R_Y - zeta zeta' R_X + a Y Lambda_Y + a H_loc M_D^{-1} R_Y
+//          (cell kernel; node part at the first visit of each DOF)
+//   nw  = -q + a c d + zeta zeta' d_prev             (R_X is then R~ of the
+//                                                      next step)
+// which is Algorithm 2's step 4 with T = M_D^{-1}(R_Y - C d) never stored.
+template <typename TR>
+pawfe_status filter_block_fused(const pawfe_op* op, const double* X, int64_t ldx, double* Xo, int64_t ldo, int nc,
+                                int64_t B, const double* lam_in, int m, double b0, double bW, double bU, Carve cv,
+                                hipStream_t s) {
+  double* Y = cv.take<double>((size_t)op->M * B);
+  TR* RX = cv.take<TR>((size_t)op->M * B);
+  TR* RY = cv.take<TR>((size_t)op->M * B);
+  NlBufs nb = carve_nl(op, cv, B);
+  const size_t na = (size_t)std::max(op->npj_total, 1) * B;
+  double* c2 = cv.take<double>(na);
+  double* dprev = cv.take<double>(na);
+  double* nwp = cv.take<double>(na);
+  double* nwn = cv.take<double>(na);
+  double* lamX = cv.take<double>(B);
+  double* lamY = cv.take<double>(B);
+  if (!cv.ok()) return fail(PAWFE_EINVAL, "internal: filter workspace smaller than its carve");
+  const int64_t ld = nc;
+  // step 1: polynomial scalars
+  const double e = (bU - bW) / 2.0, c = (bU + bW) / 2.0;
+  double zeta = e / (b0 - c);
+  const double zeta1 = zeta, gamma = 2.0 / zeta1;
+  // step 2: residual of the input pairs, FP64
+  CHECK(do_residual(op, X, ldx, lam_in, Y, ld, nc, nb, s));
+  // step 3
+  CHECK(launch_cheb_init<TR>(op, Y, ld, RY, RX, ld, zeta1 / e, c, lam_in, lamY, lamX, nc, s));
+  // step 4
+  double* dk = nb.d;
+  bool first = true;
+  for (int theta = 2; theta <= m; ++theta) {
+    const double znew = 1.0 / (gamma - zeta);
+    const double a = 2.0 * znew / e;
+    const double zz = zeta * znew;
+    CHECK(launch_nl_reduce<TR>(op, RY, ld, nc, true, nb.part, nb.c, s));
+    const double* cc = nb.c;
+    if (!first) {
+      CHECK(launch_atom_gcorr(op, nb.c, nwp, c2, nc, s));
+      cc = c2;
+    }
+    CHECK(launch_atom_mul(op, op->d.dSinv, nullptr, nullptr, 1.0, cc, dk, nc, s, op->d.dSinv_im));
+    CHECK(launch_atom_gcorr(op, cc, dk, nb.t, nc, s));
+    CHECK(launch_atom_mul(op, op->d.dH, nullptr, nullptr, a, nb.t, nb.c, nc, s));   // q = a Dh t (into c)
+    CHECK(launch_step_combine(op, nb.c, dk, first ? nullptr : dprev, first ? nullptr : nwp, nb.t, nwn, lamX, lamY,
+                              lam_in, a, a * c, zz, nc, s));
+    CHECK(launch_node_fixup<TR>(op, nb.t, -1.0, nc, RY, ld, s));
+    CHECK(launch_cell_step<TR>(op, RY, RX, ld, Y, ld, lamY, a, a * c, zz, nc, s));
+    std::swap(RX, RY);
+    std::swap(lamX, lamY);
+    std::swap(dk, dprev);
+    std::swap(nwp, nwn);
+    first = false;
+    zeta = znew;
+  }
+  // step 5: Xout = Sinv_hat R + X Lambda_Y with R = R~ + C w
+  CHECK(launch_nl_reduce<TR>(op, RY, ld, nc, true, nb.part, nb.c, s));
+  const double* cc = nb.c;
+  if (!first) {
+    CHECK(launch_atom_gcorr(op, nb.c, nwp, c2, nc, s));
+    cc = c2;
+  }
+  CHECK(launch_atom_mul(op, op->d.dSinv, nullptr, nullptr, 1.0, cc, dk, nc, s, op->d.dSinv_im));
+  CHECK(launch_step_combine(op, nullptr, dk, nullptr, first ? nullptr : nwp, nb.t, nullptr, nullptr, nullptr, nullptr,
+                            0.0, 0.0, 0.0, nc, s));   // v = nw + d
+  return launch_node_finalize<TR>(op, RY, ld, nb.t, X, ldx, lamY, Xo, ldo, nc, s);
 }
 
 // ---- small host helpers -----------------------------------------------------
@@ -496,6 +582,7 @@ pawfe_status upload(pawfe_op* op, hipStream_t s) {
     cpk[t] = (e % op->n[0]) | ((e / op->n[0]) % op->n[1]) << 10 | (e / (op->n[0] * op->n[1])) << 20;
   }
   CHECK(up(op, &d.cell_pack, cpk, s));
+  CHECK(up(op, &d.cell_own, op->cell_own, s));
   CHECK(up(op, &d.node2srow, op->node2srow, s));
   CHECK(up(op, &d.srow_ptr, op->srow_ptr, s));
   CHECK(up(op, &d.srow_atom, op->srow_atom, s));
@@ -880,6 +967,11 @@ pawfe_status pawfe_cheb_filter(const pawfe_op* op, const void* Xin, int64_t ldx,
       lam = lam2;
     }
     if (st != PAWFE_OK) {
+    } else if (fused_step(op, prec)) {
+      st = prec == PAWFE_FP64 ? filter_block_fused<double>(op, X, ldx * cf, Xo, ldo * cf, (int)(nc * cf), B * cf, lam,
+                                                           degree, b0, bW, bU, cv, sb)
+                              : filter_block_fused<float>(op, X, ldx * cf, Xo, ldo * cf, (int)(nc * cf), B * cf, lam,
+                                                          degree, b0, bW, bU, cv, sb);
     } else if (prec == PAWFE_FP64) {
       st = filter_block<double>(op, X, ldx * cf, Xo, ldo * cf, (int)(nc * cf), B * cf, lam, degree, b0, bW, bU, cv,
                                 sb);

@@ -369,6 +369,37 @@ pawfe_status build_host(const pawfe_op_desc* d, pawfe_op* op) {
     std::vector<int32_t> fill(op->colour_off.begin(), op->colour_off.end() - 1);
     for (int e = 0; e < E; ++e) op->cells_by_colour[fill[op->cell_colour[e]]++] = e;
   }
+  // First visit of each DOF in the colour-ordered assembly (colours run in
+  // ascending order): the cell of the lowest colour among the cells sharing
+  // the DOF.  A local node's position class per axis is 0 (low face), 1
+  // (inside) or 2 (high face); the cells sharing it are this cell and its
+  // neighbours across the faces the node lies on.  Bit ca + 3 cb + 9 cc of
+  // cell_own[e] is set when cell e makes the first visit of its nodes of
+  // class (ca, cb, cc).
+  op->cell_own.assign(E, 0);
+  for (int e = 0; e < E; ++e) {
+    const int ijk[3] = {e % op->n[0], (e / op->n[0]) % op->n[1], e / (op->n[0] * op->n[1])};
+    for (int cls = 0; cls < 27; ++cls) {
+      const int cl[3] = {cls % 3, (cls / 3) % 3, cls / 9};
+      int nb[3][2], nn[3];
+      for (int d = 0; d < 3; ++d) {
+        nb[d][0] = ijk[d];
+        nn[d] = 1;
+        if (cl[d] != 1) nb[d][nn[d]++] = (ijk[d] + (cl[d] == 0 ? op->n[d] - 1 : 1)) % op->n[d];
+      }
+      bool first = true;
+      for (int z = 0; z < nn[2]; ++z)
+        for (int y = 0; y < nn[1]; ++y)
+          for (int x = 0; x < nn[0]; ++x) {
+            const int e2 = nb[0][x] + op->n[0] * (nb[1][y] + op->n[1] * nb[2][z]);
+            if (e2 == e) continue;
+            if (op->cell_colour[e2] == op->cell_colour[e])
+              return fail(PAWFE_EINVAL, "internal: cells sharing a DOF have one colour");
+            if (op->cell_colour[e2] < op->cell_colour[e]) first = false;
+          }
+      if (first) op->cell_own[e] |= 1u << cls;
+    }
+  }
 
   // ---- atoms ----------------------------------------------------------------
   const int na = d->natoms;

@@ -168,6 +168,13 @@ constexpr Rule<P + 1> gll() {
 //   B[q][a] = l_a(eta_q)   (Lagrange basis through the GLL nodes)
 //   K[a][b] = sum_q w_q l_a'(eta_q) l_b'(eta_q),  M[a][b] = sum_q w_q l_a l_b
 // Reflection: B[NQ-1-q][NP-1-a] = B[q][a], K and M centro-symmetric.
+// Scaled tables (sc): every column (the input index a, and b of G1) divided
+// by m_a = W_a (GLL weight), doubled on the two end nodes.  On a mesh of
+// cells of one size the lumped mass of a DOF is det J prod_d m_{a_d} (an end
+// node's weight comes from the two cells that share it), so contracting
+// with the scaled tables along all three axes applies det J M_D^{-1} to the
+// input first; m is symmetric, so the scaled tables keep the reflection
+// symmetry.
 //   BE[q][a] = (B[q][a] + B[q][NP-1-a]) / 2 (a < NP/2), B[q][mid] (a = mid)
 //   BO[q][a] = (B[q][a] - B[q][NP-1-a]) / 2
 // likewise KE/KO, ME/MO with the row index a in place of q.
@@ -186,7 +193,7 @@ struct Tables {
 };
 
 template <int NP, int NQ>
-constexpr Tables<NP, NQ> make_tables() {
+constexpr Tables<NP, NQ> make_tables(bool sc) {
   constexpr Rule<NP> xi = gll<NP - 1>();
   constexpr Rule<NQ> g = gauss<NQ>();
   double B[NQ][NP] = {}, D[NQ][NP] = {}, K[NP][NP] = {}, M[NP][NP] = {};
@@ -234,6 +241,17 @@ constexpr Tables<NP, NQ> make_tables() {
     const double P = legendre_P(NP - 1, xi.x[a]);
     t.W[a] = 2.0 / ((NP - 1) * NP * P * P);
   }
+  if (sc) {
+    for (int a = 0; a < NP; ++a) {
+      const double inv = 1.0 / (t.W[a] * ((a == 0 || a == NP - 1) ? 2.0 : 1.0));
+      for (int q = 0; q < NQ; ++q) B[q][a] *= inv;
+      for (int r = 0; r < NP; ++r) {
+        K[r][a] *= inv;
+        M[r][a] *= inv;
+        t.G1[r][a] *= inv;
+      }
+    }
+  }
   constexpr int PH = NP / 2, PC = (NP + 1) / 2, QC = (NQ + 1) / 2, QH = NQ / 2;
   for (int q = 0; q < QC; ++q)
     for (int a = 0; a < PC; ++a) t.BE[q][a] = a < PH ? 0.5 * (B[q][a] + B[q][NP - 1 - a]) : B[q][a];
@@ -254,7 +272,8 @@ constexpr Tables<NP, NQ> make_tables() {
 
 template <int NP, int NQ>
 struct Tab {
-  static constexpr Tables<NP, NQ> t = make_tables<NP, NQ>();
+  static constexpr Tables<NP, NQ> t = make_tables<NP, NQ>(false);
+  static constexpr Tables<NP, NQ> ts = make_tables<NP, NQ>(true);   // columns over m_a
 };
 
 }  // namespace ref1d
@@ -276,8 +295,8 @@ __host__ __device__ __forceinline__ T fma_t(T a, T b, T c) {
   if constexpr (sizeof(T) == 4) return fmaf(a, b, c); else return fma(a, b, c);
 }
 
-// y[NQ] = B x[NP]
-template <int NP, int NQ, typename T>
+// y[NQ] = B x[NP]  (SC: the scaled table)
+template <int NP, int NQ, bool SC = false, typename T>
 __host__ __device__ __forceinline__ void line_B(const T (&x)[NP], T (&y)[NQ]) {
   using TB = ref1d::Tab<NP, NQ>;
   constexpr int PH = NP / 2, PC = (NP + 1) / 2, QH = NQ / 2, QC = (NQ + 1) / 2;
@@ -290,13 +309,13 @@ __host__ __device__ __forceinline__ void line_B(const T (&x)[NP], T (&y)[NQ]) {
   sfor<QC>([&](auto q) {
     T ye = T(0);
     sfor<PC>([&](auto a) {
-      constexpr T c = (T)TB::t.BE[q][a];
+      constexpr T c = (T)(SC ? TB::ts.BE[q][a] : TB::t.BE[q][a]);
       ye = fma_t(c, e[a], ye);
     });
     if constexpr (q < QH) {
       T yo = T(0);
       sfor<PH>([&](auto a) {
-        constexpr T c = (T)TB::t.BO[q][a];
+        constexpr T c = (T)(SC ? TB::ts.BO[q][a] : TB::t.BO[q][a]);
         yo = fma_t(c, o[a], yo);
       });
       y[q] = ye + yo;
@@ -356,22 +375,23 @@ __host__ __device__ __forceinline__ EOIn<NP, T> split_eo(const T (&x)[NP]) {
   return r;
 }
 
-// y = A x for a symmetric centro-symmetric NP x NP table (K1 if KT, else M1),
-// from the even / odd parts of x
-template <int NP, int NQ, bool KT, typename T>
+// y = A x for a centro-symmetric NP x NP table (K1 if KT, else M1; SC: the
+// scaled table), from the even / odd parts of x
+template <int NP, int NQ, bool KT, bool SC = false, typename T>
 __host__ __device__ __forceinline__ void line_sym(const EOIn<NP, T>& in, T (&y)[NP]) {
   using TB = ref1d::Tab<NP, NQ>;
+  constexpr const ref1d::Tables<NP, NQ>& tb = SC ? TB::ts : TB::t;
   constexpr int PH = NP / 2, PC = (NP + 1) / 2;
   sfor<PC>([&](auto r) {
     T ye = T(0);
     sfor<PC>([&](auto a) {
-      constexpr T c = (T)(KT ? TB::t.KE[r][a] : TB::t.ME[r][a]);
+      constexpr T c = (T)(KT ? tb.KE[r][a] : tb.ME[r][a]);
       ye = fma_t(c, in.e[a], ye);
     });
     if constexpr (r < PH) {
       T yo = T(0);
       sfor<PH>([&](auto a) {
-        constexpr T c = (T)(KT ? TB::t.KO[r][a] : TB::t.MO[r][a]);
+        constexpr T c = (T)(KT ? tb.KO[r][a] : tb.MO[r][a]);
         yo = fma_t(c, in.o[a], yo);
       });
       y[r] = ye + yo;
@@ -383,14 +403,14 @@ __host__ __device__ __forceinline__ void line_sym(const EOIn<NP, T>& in, T (&y)[
 }
 
 // y = G1 x on one line of NP node values (G1 is not symmetric: a plain
-// product with compile-time coefficients)
-template <int NP, int NQ, typename T>
+// product with compile-time coefficients; SC: the scaled table)
+template <int NP, int NQ, bool SC = false, typename T>
 __host__ __device__ __forceinline__ void line_g1(const T (&x)[NP], T (&y)[NP]) {
   using TB = ref1d::Tab<NP, NQ>;
   sfor<NP>([&](auto a) {
     T acc = T(0);
     sfor<NP>([&](auto b) {
-      constexpr T c = (T)TB::t.G1[a][b];
+      constexpr T c = (T)(SC ? TB::ts.G1[a][b] : TB::t.G1[a][b]);
       acc = fma_t(c, x[b], acc);
     });
     y[a] = acc;
@@ -441,20 +461,31 @@ constexpr int kValuHRes = 4;     // K + V - lambda_n M, every cell of one size
 constexpr int kValuHC = 5;
 constexpr int kValuHResC = 6;
 constexpr int kValuMass = 7;     // det J M, every cell of one size (real and complex operators alike)
+// Chebyshev step of the filter on cells of one size (real; complex with the
+// imaginary k term): Y += alpha (K + V) M_D^{-1} X through the scaled 1-D
+// tables, and at the first visit of each DOF the node part of the step
+// applied to the old value of Y first (see the kernel)
+constexpr int kValuStep = 8;
+constexpr int kValuStepC = 9;
 // variants that read the per-cell geometry table (and need it non-null)
 constexpr bool is_general_mode(int mode) {
   return mode == kValuGenH || mode == kValuGenHG || mode == kValuGenMass;
 }
 static_assert(!is_general_mode(kValuH) && !is_general_mode(kValuHRes) && !is_general_mode(kValuHC) &&
-                  !is_general_mode(kValuHResC) && !is_general_mode(kValuMass),
+                  !is_general_mode(kValuHResC) && !is_general_mode(kValuMass) && !is_general_mode(kValuStep) &&
+                  !is_general_mode(kValuStepC),
               "uniform variants");
 // Waves per SIMD the registers are held to: FP32 six (three workgroups of
 // eight waves per CU, as many as the LDS holds), FP64 three; the GGA and the
 // complex variants hold one or two more slabs in LDS (two workgroups per
-// CU): FP32 four, FP64 two.
+// CU): FP32 four, FP64 two.  The FP32 step variant is held to four as well:
+// at six its first-visit loads spill registers, and the spills cost more
+// than the third workgroup gains (measured on the degree-6 filter step).
 template <typename T, int MODE>
-constexpr int kWaves = (MODE == kValuGenHG || MODE == kValuHC || MODE == kValuHResC) ? (sizeof(T) == 4 ? 4 : 2)
-                                                                                     : (sizeof(T) == 4 ? 6 : 3);
+constexpr int kWaves = (MODE == kValuGenHG || MODE == kValuHC || MODE == kValuHResC || MODE == kValuStepC)
+                           ? (sizeof(T) == 4 ? 4 : 2)
+                       : MODE == kValuStep ? (sizeof(T) == 4 ? 4 : 3)
+                                           : (sizeof(T) == 4 ? 6 : 3);
 constexpr int kXP = 9;
 // U: extents up to 8 x 8 x 8;  K, M: up to 7 x 7 x 7 (element offsets, col fastest)
 template <typename T>
@@ -496,9 +527,12 @@ k_cell_valu(CellArgs<T> A, int ncoltiles, int nitems, T fx, T fy, T fz) {
   constexpr bool GGA = MODE == kValuGenHG;
   constexpr bool MASS = MODE == kValuGenMass || MODE == kValuMass;
   constexpr bool RES = MODE == kValuHRes || MODE == kValuHResC;
-  constexpr bool CPLX = MODE == kValuHC || MODE == kValuHResC;
+  constexpr bool STEP = MODE == kValuStep || MODE == kValuStepC;
+  constexpr bool CPLX = MODE == kValuHC || MODE == kValuHResC || MODE == kValuStepC;
+  constexpr bool SC = STEP;   // input-side 1-D contractions with the scaled tables
   static_assert(!(RES && GEN), "the residual mode uses the uniform factors");
   static_assert(!(CPLX && GEN), "complex operators use the uniform factors");
+  static_assert(!(STEP && (GEN || RES)), "the step mode uses the uniform factors");
   constexpr int CB = kCB<T>;
   constexpr int NT = kNT<T>;
   constexpr int S = NT / CB;                   // line slots
@@ -539,6 +573,19 @@ k_cell_valu(CellArgs<T> A, int ncoltiles, int nitems, T fx, T fy, T fz) {
     const int a = l % NP, b = (l / NP) % NP, c = l / (NP * NP);
     pk[j] = ((off_fits ? (unsigned)(a + Gx * (b + Gy * c)) : 0u) << kLdsBits) |
             (unsigned)((offU<T>(a, b, c) + col) * (int)sizeof(T));
+  }
+  // step mode: the position class (0-26, 31 past the last node) of each of
+  // the thread's gathered nodes, 5 bits per node in one register
+  unsigned cls_pack = 0;
+  if constexpr (STEP) {
+    static_assert(NJ * 5 <= 32, "position classes must fit one register");
+    auto cls1 = [](int a) { return a == 0 ? 0 : (a == NP - 1 ? 2 : 1); };
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int l = lnode(j);
+      const int a = l % NP, b = (l / NP) % NP, c = l / (NP * NP);
+      cls_pack |= (lreal(j) ? (unsigned)(cls1(a) + 3 * cls1(b) + 9 * cls1(c)) : 31u) << (5 * j);
+    }
   }
   // byte offset in K of the element at byte offset u in U:
   // offU - offK = z * 9 * CB elements, z = u / (8 * 9 * CB * sizeof(T))
@@ -660,14 +707,45 @@ k_cell_valu(CellArgs<T> A, int ncoltiles, int nitems, T fx, T fy, T fz) {
     // integer operations) rather than held in registers across the loop
     int lslot = slot;
     asm volatile("" : "+v"(lslot));
+    // FP32 step mode: the old output rows are read at the assembly (the
+    // registers that would hold them across the passes are what the step's
+    // own loads need there)
+    constexpr bool kLateYo = STEP && sizeof(T) == 4;
     T yo[NJ];
-    {
+    if constexpr (!kLateYo) {
       int node[NJ];
       nodes_of(cp, node);
       const int nn = valid ? n : 0;
 #pragma unroll
       for (int j = 0; j < NJ; ++j) yo[j] = *elem(A.Y, ldyb, nn, node[j]);
     }
+    // step mode: which of the thread's nodes this cell visits first (the
+    // cell of the lowest colour sharing a DOF), and X and the FP64 residual
+    // block at those nodes
+    unsigned sown = 0;
+    T sxv[STEP ? NJ : 1];
+    double syf[STEP ? NJ : 1];
+    auto step_loads = [&]() {
+      int node[NJ];
+      nodes_of(cp, node);
+      typedef const __attribute__((address_space(4))) unsigned* ConstUP;
+      const unsigned cm = ((ConstUP)A.own)[cp.e];
+      // the classes are unpacked here in every item (one register held
+      // across the loop instead of one per node)
+      unsigned cpk = cls_pack;
+      asm volatile("" : "+v"(cpk));
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) sown |= ((cm >> ((cpk >> (5 * j)) & 31u)) & 1u) << j;
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        sxv[j] = T(0);
+        syf[j] = 0.0;
+        if ((sown >> j) & 1u) {
+          sxv[j] = *elem(A.X, ldxb, n, node[j]);
+          syf[j] = A.y64[(int64_t)node[j] * A.ldy64 + n];
+        }
+      }
+    };
     int nxt_c = cur_c, nxt_t = cur_t;
     advance(nxt_c, nxt_t);
     const bool more = item + i_step < i_end;
@@ -703,24 +781,24 @@ k_cell_valu(CellArgs<T> A, int ncoltiles, int nitems, T fx, T fy, T fz) {
         if (!ln.on[r]) continue;
         if constexpr (CPLX) {
           T yi[NP];
-          line_g1<NP, NQ>(xp[r], yi);
+          line_g1<NP, NQ, SC>(xp[r], yi);
           sfor<NP>([&](auto a) { sI[offK<T>(a, ln.u[r], ln.v[r]) + col] = yi[a]; });
         }
         // each result is stored as soon as it is formed (fewer live registers)
         const EOIn<NP, T> eo = split_eo<NP>(x[r]);
         if constexpr (!MASS) {
           T yk[NP];
-          line_sym<NP, NQ, true>(eo, yk);
+          line_sym<NP, NQ, true, SC>(eo, yk);
           sfor<NP>([&](auto a) { sK[offK<T>(a, ln.u[r], ln.v[r]) + col] = yk[a]; });
         }
         {
           T ym[NP];
-          line_sym<NP, NQ, false>(eo, ym);
+          line_sym<NP, NQ, false, SC>(eo, ym);
           sfor<NP>([&](auto a) { sM[offK<T>(a, ln.u[r], ln.v[r]) + col] = ym[a]; });
         }
         if constexpr (!MASS) {
           T yb[NQ];
-          line_B<NP, NQ>(x[r], yb);
+          line_B<NP, NQ, SC>(x[r], yb);
           sfor<NQ>([&](auto q) { sU[offU<T>(q, ln.u[r], ln.v[r]) + col] = yb[q]; });
         }
       }
@@ -737,7 +815,7 @@ k_cell_valu(CellArgs<T> A, int ncoltiles, int nitems, T fx, T fy, T fz) {
         for (int r = 0; r < R; ++r) {
           if (!ln.on[r]) continue;
           T y[NQ];
-          line_B<NP, NQ>(x[r], y);
+          line_B<NP, NQ, SC>(x[r], y);
           sfor<NQ>([&](auto q) { sU[offU<T>(ln.u[r], q, ln.v[r]) + col] = y[q]; });
         }
       }
@@ -754,7 +832,7 @@ k_cell_valu(CellArgs<T> A, int ncoltiles, int nitems, T fx, T fy, T fz) {
         for (int r = 0; r < R; ++r) {
           if (!ln.on[r]) continue;
           T y[NQ];
-          line_B<NP, NQ>(x[r], y);
+          line_B<NP, NQ, SC>(x[r], y);
           const int q0 = ln.u[r] + NQ * ln.v[r];
           sfor<NQ>([&](auto q) { y[q] = y[q] * vws[q0 + NQ * NQ * q]; });
           T xo[NP];
@@ -774,7 +852,7 @@ k_cell_valu(CellArgs<T> A, int ncoltiles, int nitems, T fx, T fy, T fz) {
           for (int r = 0; r < R; ++r) {
             if (!ln.on[r]) continue;
             T y[NQ];
-            line_B<NP, NQ>(x[r], y);
+            line_B<NP, NQ, SC>(x[r], y);
             const int q0 = ln.u[r] + NQ * ln.v[r];
             T v[NQ], t[NQ];
             sfor<NQ>([&](auto q) { v[q] = vgs[2 * NQ3 + q0 + NQ * NQ * q]; });
@@ -893,19 +971,19 @@ k_cell_valu(CellArgs<T> A, int ncoltiles, int nitems, T fx, T fy, T fz) {
         if (!ln.on[r]) continue;
         if constexpr (CPLX) {
           T mi[NP], gm[NP];
-          line_sym<NP, NQ, false>(split_eo<NP>(iv[r]), mi);
-          line_g1<NP, NQ>(mp[r], gm);
+          line_sym<NP, NQ, false, SC>(split_eo<NP>(iv[r]), mi);
+          line_g1<NP, NQ, SC>(mp[r], gm);
           sfor<NP>([&](auto b) { sI[offK<T>(ln.u[r], b, ln.v[r]) + col] = fma_t(A.gk[0], mi[b], A.gk[1] * gm[b]); });
         }
         const EOIn<NP, T> em = split_eo<NP>(m[r]);
         if constexpr (!MASS) {
           T mk[NP], km[NP];
-          line_sym<NP, NQ, false>(split_eo<NP>(k[r]), mk);
-          line_sym<NP, NQ, true>(em, km);
+          line_sym<NP, NQ, false, SC>(split_eo<NP>(k[r]), mk);
+          line_sym<NP, NQ, true, SC>(em, km);
           sfor<NP>([&](auto b) { sK[offK<T>(ln.u[r], b, ln.v[r]) + col] = fma_t(ifx, mk[b], ify * km[b]); });
         }
         T mm[NP];
-        line_sym<NP, NQ, false>(em, mm);
+        line_sym<NP, NQ, false, SC>(em, mm);
         sfor<NP>([&](auto b) { sM[offK<T>(ln.u[r], b, ln.v[r]) + col] = mm[b]; });
       }
     }
@@ -931,26 +1009,26 @@ k_cell_valu(CellArgs<T> A, int ncoltiles, int nitems, T fx, T fy, T fz) {
         if (!ln.on[r]) continue;
         T acc[NP];
         if constexpr (MASS) {
-          line_sym<NP, NQ, false>(split_eo<NP>(m[r]), acc);
+          line_sym<NP, NQ, false, SC>(split_eo<NP>(m[r]), acc);
           sfor<NP>([&](auto c) { sK[offK<T>(ln.u[r], ln.v[r], c) + col] = acc[c]; });
         } else {
-          line_sym<NP, NQ, false>(split_eo<NP>(k[r]), acc);
+          line_sym<NP, NQ, false, SC>(split_eo<NP>(k[r]), acc);
           const EOIn<NP, T> em = split_eo<NP>(m[r]);
           {
             T km[NP];
-            line_sym<NP, NQ, true>(em, km);
+            line_sym<NP, NQ, true, SC>(em, km);
             sfor<NP>([&](auto c) { acc[c] = fma_t(ifz, km[c], acc[c]); });
           }
           if constexpr (RES) {   // - lambda_n det J M1 M (the S part of the residual, local term)
             T mm[NP];
-            line_sym<NP, NQ, false>(em, mm);
+            line_sym<NP, NQ, false, SC>(em, mm);
             const T ml = valid ? -(T)A.lam[n] * idet : T(0);
             sfor<NP>([&](auto c) { acc[c] = fma_t(ml, mm[c], acc[c]); });
           }
           if constexpr (CPLX) {
             T mi[NP], gm[NP];
-            line_sym<NP, NQ, false>(split_eo<NP>(iv[r]), mi);
-            line_g1<NP, NQ>(mp[r], gm);
+            line_sym<NP, NQ, false, SC>(split_eo<NP>(iv[r]), mi);
+            line_g1<NP, NQ, SC>(mp[r], gm);
             const T sg = (col & 1) ? T(1) : T(-1);
             sfor<NP>([&](auto c) { acc[c] = fma_t(sg, fma_t(A.gk[2], gm[c], mi[c]), acc[c]); });
           }
@@ -969,6 +1047,25 @@ k_cell_valu(CellArgs<T> A, int ncoltiles, int nitems, T fx, T fy, T fz) {
       if constexpr (MASS) f = f * idet * (A.lam ? (T)(-A.lam[n]) : T(1));
       int node[NJ];
       nodes_of(cp, node);
+      if constexpr (STEP) {
+        // Node part of the Chebyshev step at the first visit of a DOF, on
+        // the old value before any cell adds to it:
+        //   Y <- (-ac X - zz Y) + a lamY_n Yres
+        // the last product and sum in FP64, rounded once
+        if constexpr (kLateYo) {
+#pragma unroll
+          for (int j = 0; j < NJ; ++j) yo[j] = lreal(j) ? *elem(A.Y, ldyb, n, node[j]) : T(0);
+        }
+        step_loads();
+        const double ly = A.sa * A.lamY[n];
+        const T mac = (T)(-A.sac), zz = (T)A.szz;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {   // branch-free: a select per node
+          const T part = mac * sxv[j] - zz * yo[j];
+          const T upd = (T)((double)part + syf[j] * ly);
+          yo[j] = ((sown >> j) & 1u) ? upd : yo[j];
+        }
+      }
 #pragma unroll
       for (int j = 0; j < NJ; ++j)
         if (lreal(j))
@@ -1009,6 +1106,9 @@ pawfe_status run_cell_valu(const pawfe_op* op, const CellArgs<T>& a0, hipStream_
   if (MODE == kValuGenHG && !a.vg) return fail(PAWFE_EINVAL, "internal: GGA cell variant without its table");
   if ((MODE == kValuHRes || MODE == kValuHResC) && !a.lam)
     return fail(PAWFE_EINVAL, "internal: residual cell variant without lambda");
+  if ((MODE == kValuStep || MODE == kValuStepC) && (!a.own || !a.y64 || !a.lamY))
+    return fail(PAWFE_EINVAL, "internal: step cell variant without its tables");
+  if (MODE == kValuStepC && !op->cplx) return fail(PAWFE_EINVAL, "internal: complex step variant on a real operator");
   const int ncoltiles = (a.ncols + CB - 1) / CB;
   const T fx = (T)(0.5 * op->detJ * (2.0 / op->h[0]) * (2.0 / op->h[0]));
   const T fy = (T)(0.5 * op->detJ * (2.0 / op->h[1]) * (2.0 / op->h[1]));

@@ -54,6 +54,7 @@ struct DeviceTables {
   float* Minv_f = nullptr;
   int32_t* cells_by_colour = nullptr;  // [E]
   int32_t* cell_pack = nullptr;        // [E] the same cells as i | j << 10 | k << 20
+  uint32_t* cell_own = nullptr;        // [E] bit ca + 3 cb + 9 cc: the cell visits those nodes first
   // projector structure
   int32_t* node2srow = nullptr;   // [M]  support row of a DOF, -1 if none
   int32_t* srow_ptr = nullptr;    // [nsrow+1]
@@ -126,6 +127,7 @@ struct pawfe_op {
   std::vector<int32_t> colour_off;
   std::vector<int32_t> cells_by_colour;
   std::vector<int32_t> cell_colour;
+  std::vector<uint32_t> cell_own;   // [E] first-visit bits per local position class
   // atoms
   int natoms;
   int npj_total, npj_max, npj2_total;

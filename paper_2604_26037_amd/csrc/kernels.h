@@ -28,6 +28,12 @@ struct CellArgs {
   const T* vg;         // [E][3][nq^3] W_q det J (2/h_d) V_GGA,d (GGA term), or null
   T detJ;              // det J of every cell (residual mode of the vector-ALU kernel)
   T gk[3];             // complex operators: -k_d det J (2/h_d) (imaginary k term)
+  // Chebyshev step of the filter (vector-ALU step variants)
+  const uint32_t* own;   // [E] first-visit bits per local position class
+  const double* y64;     // residual block Y (FP64), row stride ldy64
+  int64_t ldy64;
+  const double* lamY;    // per-column Lambda_Y
+  double sa, sac, szz;   // a, a c, zeta zeta'
 };
 
 struct DensArgs {
@@ -73,6 +79,17 @@ pawfe_status launch_cell_valu(const pawfe_op* op, int mode, const CellArgs<T>& a
 template <typename T>
 pawfe_status launch_cell_gen(const pawfe_op* op, int mode, const CellArgs<T>& a, hipStream_t s);
 
+// Chebyshev step of the filter, local part, on the vector ALUs
+// (kernels_cell_step.hip): R_X <- -a c R_Y' - zz R_X + a Y lamY + a H_loc
+// M_D^{-1} R_Y' with the node part applied at the first visit of each DOF;
+// R_Y' = R_Y - C d is formed by the caller, the projector terms of R_X are
+// added after it.  cell_step_available: the operator has a step variant
+// (cells of one size, nq = p + 2, degree 2-6).
+bool cell_step_available(const pawfe_op* op);
+template <typename T>
+pawfe_status launch_cell_step(const pawfe_op* op, const T* RY, T* RX, int64_t ld, const double* Y, int64_t ldy,
+                              const double* lamY, double a, double ac, double zz, int ncols, hipStream_t s);
+
 // out[e][q] = W_q sum_n occ_n |u_n(x_{e,q})|^2
 pawfe_status launch_density(const pawfe_op* op, const double* X, int64_t ldx, int ncols,
                             const double* occ, double* out, hipStream_t s);
@@ -101,6 +118,18 @@ pawfe_status launch_atom_mul(const pawfe_op* op, const double* D1, const double*
 // out_a = c_a - sum_b G^{ab} d_b
 pawfe_status launch_atom_gcorr(const pawfe_op* op, const double* c, const double* d, double* out,
                                int ncols, hipStream_t s);
+
+// Projector part of the fused Chebyshev step: v = nw_prev + d,
+// nw = -q + ac d + zz d_prev, lamX = a lamY lam_in - ac lamY - zz lamX
+// (nw_prev, d_prev null: zero; q null: v only)
+pawfe_status launch_step_combine(const pawfe_op* op, const double* q, const double* d, const double* dprev,
+                                 const double* nwprev, double* v, double* nw, double* lamX, const double* lamY,
+                                 const double* lam_in, double a, double ac, double zz, int ncols, hipStream_t s);
+
+// out1 += s1 C v1 on the support rows (atom colour by colour)
+template <typename T>
+pawfe_status launch_node_fixup(const pawfe_op* op, const double* v1, double s1, int ncols, T* out1, int64_t ld1,
+                               hipStream_t s);
 
 // Y[I][n] = sum_{a: I in supp(a)} C^a[I] . q_a[n]   (0 outside the supports)
 template <typename T>

@@ -296,6 +296,32 @@ __global__ void __launch_bounds__(256) k_atom_gcorr(const double* __restrict__ c
   out[(int64_t)g * ncols + n] = acc;
 }
 
+// Projector part of the fused Chebyshev step (per projector row g, column n;
+// nw = -w, w the vector whose C w the step still owes R_X):
+//   v  = nw_prev + d                  (the step's fix-up R_Y -= C v)
+//   nw = -q + ac d + zz d_prev        (q already scaled by a)
+// and, on row 0, lamX = a lamY lam_in - ac lamY - zz lamX.  nw_prev and
+// d_prev may be null (zero: the first step); q null: v only, no nw, no lambda.
+__global__ void __launch_bounds__(256) k_step_combine(int npj, int ncols, const double* __restrict__ q,
+                                                      const double* __restrict__ dv,
+                                                      const double* __restrict__ dprev,
+                                                      const double* __restrict__ nwprev, double* __restrict__ v,
+                                                      double* __restrict__ nw, double* __restrict__ lamX,
+                                                      const double* __restrict__ lamY,
+                                                      const double* __restrict__ lam_in, double a, double ac,
+                                                      double zz) {
+  const int g = blockIdx.x;
+  const int n = blockIdx.y * 256 + threadIdx.x;
+  if (n >= ncols) return;
+  if (g < npj) {
+    const int64_t i = (int64_t)g * ncols + n;
+    const double d = dv[i];
+    v[i] = (nwprev ? nwprev[i] : 0.0) + d;
+    if (q) nw[i] = -q[i] + ac * d + (dprev ? zz * dprev[i] : 0.0);
+  }
+  if (g == 0 && q) lamX[n] = a * lamY[n] * lam_in[n] - ac * lamY[n] - zz * lamX[n];
+}
+
 // Row-wise kernels.  A 256-thread block is 4 waves; a wave takes R
 // consecutive DOF rows at a time, so the row index and its projector entries
 // are wave-uniform (scalar loads).  Each lane owns V consecutive columns:
@@ -825,6 +851,18 @@ pawfe_status launch_dup_pairs(const double* in, double* out, int n, hipStream_t 
   return PAWFE_OK;
 }
 
+pawfe_status launch_step_combine(const pawfe_op* op, const double* q, const double* d, const double* dprev,
+                                 const double* nwprev, double* v, double* nw, double* lamX, const double* lamY,
+                                 const double* lam_in, double a, double ac, double zz, int ncols, hipStream_t s) {
+  if (ncols <= 0) return PAWFE_OK;
+  if (op->npj_total == 0 && !q) return PAWFE_OK;
+  const dim3 grid(std::max(op->npj_total, 1), (ncols + 255) / 256), block(256);
+  hipLaunchKernelGGL(k_step_combine, grid, block, 0, s, op->npj_total, ncols, q, d, dprev, nwprev, v, nw, lamX, lamY,
+                     lam_in, a, ac, zz);
+  PAWFE_HIP(hipGetLastError());
+  return PAWFE_OK;
+}
+
 pawfe_status launch_atom_gcorr(const pawfe_op* op, const double* c, const double* dv, double* out, int ncols,
                                hipStream_t s) {
   if (op->natoms == 0 || ncols <= 0) return PAWFE_OK;
@@ -881,6 +919,16 @@ pawfe_status launch_node_nl_init(const pawfe_op* op, const double* q, int ncols,
 }
 template pawfe_status launch_node_nl_init<double>(const pawfe_op*, const double*, int, double*, int64_t, hipStream_t);
 template pawfe_status launch_node_nl_init<float>(const pawfe_op*, const double*, int, float*, int64_t, hipStream_t);
+
+template <typename T>
+pawfe_status launch_node_fixup(const pawfe_op* op, const double* v1, double s1, int ncols, T* out1, int64_t ld1,
+                               hipStream_t s) {
+  return nl_fixup<T, T, false, false>(op, ncols, v1, s1, out1, ld1, nullptr, (T*)nullptr, 0, s);
+}
+template pawfe_status launch_node_fixup<double>(const pawfe_op*, const double*, double, int, double*, int64_t,
+                                                hipStream_t);
+template pawfe_status launch_node_fixup<float>(const pawfe_op*, const double*, double, int, float*, int64_t,
+                                               hipStream_t);
 
 template <typename T>
 pawfe_status launch_node_sinv(const pawfe_op* op, const T* X, int64_t ldx, const double* dv, int ncols, T* Y,

@@ -1,6 +1,7 @@
 """Parity of every compiled element degree (p = 2..6 with n_q = p + 2) against
 the oracle, on small periodic meshes with ragged column counts: H, S and
-Sinv_hat applies in FP64 (and H in FP32), and a short FP64 filter."""
+Sinv_hat applies in FP64 (and H in FP32), and a short filter in FP64 and in
+mixed precision."""
 
 import numpy as np
 import pytest
@@ -47,3 +48,7 @@ def test_degree_applies_and_filter(p):
     got = op.cheb_filter(torch.from_numpy(Psi).to("cuda:0"), torch.from_numpy(lam), 7, b0, bW, bU,
                          block=5).cpu().numpy()
     assert _rel(got, want) < 1e-9
+    # mixed precision (FP32 recurrence, FP64 residual correction), element-wise per column
+    got32 = op.cheb_filter(torch.from_numpy(Psi).to("cuda:0"), torch.from_numpy(lam), 7, b0, bW, bU,
+                           block=5, prec=1).cpu().numpy()
+    assert float(np.max(np.abs(got32 - want).max(axis=0) / np.abs(want).max(axis=0))) < 1e-4
