@@ -36,7 +36,10 @@ PEAK_VALU_F32_TFLOPS = 157.3
 # the same without packed FP32 instructions (also the FP64 vector peak)
 PEAK_VALU_F32_SCALAR_TFLOPS = 78.6
 CELL_KERNEL_SRC = os.path.join(ROOT, "paper_2604_26037_amd", "csrc", "cell_valu.h")
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "cell_valu_f32_paper_counters.md")
+# node part of the fused step per DOF-column: -ac x, -zz y, their sum, and
+# the FP64 a lamY Y product-sum
+STEP_NODE_FLOPS = 5
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "cell_step_f32_paper_counters.md")
 METRIC = "ChFSI filter s/SCF pass & HX GFLOP/s, mixed vs FP64 at ≤1e-6 Ha eig err"
 
 
@@ -207,9 +210,34 @@ def cpu_baseline(system, nstates, degree, ncols=64):
     }
 
 
+def time_step_kernel(op, X, B, prec, dt, reps):
+    """Mean duration (s) of one colour launch of the filter's fused step
+    kernel (pawfe_cheb_step_local) on a block of B columns, timed with events
+    on the stream it is launched on (torch's current stream)."""
+    import torch
+    RY = X[:, :B].to(dt).contiguous()
+    RX = torch.zeros_like(RY)
+    Y = X[:, :B].contiguous()
+    lamY = torch.linspace(-1.0, 2.0, B, dtype=torch.float64, device=X.device)
+    # scalars of a degree-30 filter step (any values: the arithmetic does not depend on them)
+    a, ac, zz = 0.011, 0.0425, 0.36
+    op.cheb_step_local(RY, RX, Y, lamY, a, ac, zz, prec=prec)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        op.cheb_step_local(RY, RX, Y, lamY, a, ac, zz, prec=prec)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / reps / op.ncolour
+    del RY, RX, Y, lamY
+    return t
+
+
 def kernels_mode(op, s, gen, dev, args):
-    """Short run for hardware counters: the cell-local operator (FP32 and FP64)
-    on one block, then a plain device copy of known size (counter calibration)."""
+    """Short run for hardware counters: the cell-local operator and the
+    filter's fused step kernel (FP32 and FP64) on one block, then a plain
+    device copy of known size (counter calibration)."""
     import torch
 
     from paper_2604_26037_amd import BF16X3, FP32, FP64
@@ -228,6 +256,9 @@ def kernels_mode(op, s, gen, dev, args):
         torch.cuda.synchronize()
         res[name] = e0.elapsed_time(e1) / args.hx_reps / op.ncolour
         log(f"cell-local {name}: {res[name]:.3f} ms per colour launch")
+        # the filter's fused step kernel on the same block
+        res[name + "_step"] = time_step_kernel(op, X, B, prec, dt, args.hx_reps) * 1e3
+        log(f"filter step (cell part) {name}: {res[name + '_step']:.3f} ms per colour launch")
         # the whole H and Sinv_hat applies (projector reductions included)
         for _ in range(2):
             op.apply_H(Xs, out=Ys, prec=prec)
@@ -557,6 +588,13 @@ def main():
             f"local {t_loc * 1e3:.2f} ms ({hx[name]['local_tflops']:.2f} TFLOP/s)")
         del Xs, Ys
 
+    # --- the filter's fused step kernel (the dominant kernel of a filter pass) ---
+    step_t = {}
+    for name, prec, dt in (("fp64", FP64, torch.float64), ("fp32", FP32, torch.float32)):
+        step_t[name] = time_step_kernel(op, X, B, prec, dt, args.hx_reps)
+        log(f"filter step kernel {name}: {step_t[name] * 1e3:.3f} ms per colour launch "
+            f"({nloc_flops * B / op.ncolour / step_t[name] / 1e12:.2f} TFLOP/s of cell flops)")
+
     # --- BF16 halo of a z-slab (one GPU's part of the reduced-precision
     # nearest-neighbour exchange): pack and unpack-add of the two shared node
     # planes of a 5-layer slab, one 256-column block ---
@@ -603,16 +641,18 @@ def main():
 
     graded = None if args.skip_graded else graded_gga_leg(s, N, B, m, dev)
 
-    # roofline of the dominant kernel: the cell-local operator on the vector
-    # ALUs (FP32), one colour (1/8 of the cells) x 256 columns per launch;
-    # algorithmic flops = 72,668 per cell-column (sum-factorized K + V); the
-    # launch duration is the mean of the FP32 apply_local launches above,
-    # timed with events on the stream they run on
-    per_launch_flops = nloc_flops * B / op.ncolour
-    t_launch = hx["fp32"]["t_local"] / op.ncolour
+    # roofline of the dominant kernel of the filter pass: its fused step
+    # kernel on the vector ALUs (FP32), one colour (1/8 of the cells) x 256
+    # columns per launch; algorithmic flops = 72,668 per cell-column
+    # (sum-factorized K + V) plus 5 per DOF-column for the node part of the
+    # step (on average 1/8 of the DOFs per launch); the launch duration is the
+    # mean of the FP32 launches timed above with events on their stream
+    per_launch_flops = (nloc_flops + STEP_NODE_FLOPS * M) * B / op.ncolour
+    t_launch = step_t["fp32"]
     achieved = per_launch_flops / t_launch / 1e12
     roof = {
-        "kernel": "k_cell_valu<float,7,8,H> (cell-local K + V, one colour per launch)",
+        "kernel": "k_cell_valu<float,7,8,Step> (filter step: cell-local K + V on M_D^-1 R_Y, node part at the "
+                  "first visit; one colour per launch)",
         "bound": "alu",
         "achieved": achieved,
         "peak": PEAK_VALU_F32_TFLOPS,
@@ -656,6 +696,7 @@ def main():
         "band_energy_grad": grad_info,
         "halo_bf16": halo_info,
         "hx": hx,
+        "step_kernel_ms_per_launch": {k: v * 1e3 for k, v in step_t.items()},
         "graded_gga": graded,
         "roofline": roof,
     }

@@ -237,6 +237,31 @@ pawfe_status pawfe_halo_unpack_bf16(const pawfe_op* op, const uint16_t* buf, int
 pawfe_status pawfe_apply_local(const pawfe_op* op, int32_t which, const void* X, int64_t ldx, void* Y,
                                int64_t ldy, int64_t nvec, double alpha, int32_t prec, void* stream);
 
+/* Local part of one Chebyshev step of the filter (Algorithm 2, step 4, as
+ * the filter runs it on operators whose cells share one size), exposed to
+ * time and test the fused cell kernel on its own:
+ *   RX[I][n] <- (-ac RY[I][n] - zz RX[I][n]) + a lamY[n] Y[I][n]
+ *               + a (H_loc M_D^{-1} RY)[I][n]
+ * with H_loc = K + V the cell part of H (operator-action subsection; no
+ * PAW term) and M_D the lumped GLL mass (approximation (i) of eq. "Delta
+ * Sinv").  In the filter RY holds R_Y - sum_a C^a d_a, so M_D^{-1} RY is
+ * the block T = Sinv_hat R_Y of the step; the projector terms are added by
+ * the filter around this call.  One launch per cell colour; the first term
+ * is applied at the first visit of each DOF.
+ * Columns are real: nvec real columns; complex operators store (re, im)
+ * pairs of a complex column next to each other (nvec even), with lamY
+ * given per real column.  RY, RX: device [ndof][ld] in FP64 (prec
+ * PAWFE_FP64) or FP32 (PAWFE_FP32), same leading dimension; Y: device
+ * double [ndof][ldy]; lamY: device double [nvec].  a, ac, zz: the step's
+ * scalars a, a c and zeta zeta'.  RX must not overlap RY, Y or lamY; all
+ * buffers are caller-owned.  Errors: PAWFE_EINVAL (NULL buffer, leading
+ * dimension below nvec, odd nvec on a complex operator, nvec above 2^29);
+ * PAWFE_EUNSUPPORTED (PAWFE_BF16X3, graded meshes or the GGA term, or a
+ * degree / Gauss rule without a compiled variant). */
+pawfe_status pawfe_cheb_step_local(const pawfe_op* op, const void* RY, void* RX, int64_t ld, const double* Y,
+                                   int64_t ldy, const double* lamY, double a, double ac, double zz, int64_t nvec,
+                                   int32_t prec, void* stream);
+
 /* Bytes of workspace pawfe_cheb_filter needs for blocks of `block` columns:
  * room for two block states when nvec > block (two blocks in flight), else
  * one.  A workspace of one block state (the query with nvec = block) is

@@ -909,6 +909,25 @@ pawfe_status pawfe_apply_local(const pawfe_op* op, int32_t which, const void* X,
                             prec == PAWFE_BF16X3);
 }
 
+pawfe_status pawfe_cheb_step_local(const pawfe_op* op, const void* RY, void* RX, int64_t ld, const double* Y,
+                                   int64_t ldy, const double* lamY, double a, double ac, double zz, int64_t nvec,
+                                   int32_t prec, void* stream) {
+  if (!op) return fail(PAWFE_EINVAL, "op is NULL");
+  if (nvec < 0 || nvec > (int64_t)1 << 29) return fail(PAWFE_EINVAL, "nvec out of range");
+  if (nvec == 0) return PAWFE_OK;
+  if (!RY || !RX || !Y || !lamY) return fail(PAWFE_EINVAL, "NULL buffer");
+  if (ld < nvec || ldy < nvec) return fail(PAWFE_EINVAL, "leading dimension smaller than nvec");
+  if (op->cplx && (nvec & 1)) return fail(PAWFE_EINVAL, "complex operators take (re, im) column pairs");
+  if (prec != PAWFE_FP64 && prec != PAWFE_FP32)
+    return fail(PAWFE_EUNSUPPORTED, "the step kernel runs in FP64 or FP32");
+  if (!cell_step_available(op))
+    return fail(PAWFE_EUNSUPPORTED, "no step variant for this operator (graded mesh, GGA term or element)");
+  if (prec == PAWFE_FP64)
+    return launch_cell_step<double>(op, (const double*)RY, (double*)RX, ld, Y, ldy, lamY, a, ac, zz, (int)nvec,
+                                    S(stream));
+  return launch_cell_step<float>(op, (const float*)RY, (float*)RX, ld, Y, ldy, lamY, a, ac, zz, (int)nvec, S(stream));
+}
+
 pawfe_status pawfe_cheb_filter_workspace(const pawfe_op* op, int64_t nvec, int32_t block, int32_t prec,
                                          size_t* bytes) {
   if (!op || !bytes) return fail(PAWFE_EINVAL, "op or bytes is NULL");

@@ -27,6 +27,7 @@ EXPORTS = [
     "pawfe_build_operator", "pawfe_destroy_operator", "pawfe_query", "pawfe_get_dofmap",
     "pawfe_set_veff", "pawfe_set_vgga", "pawfe_set_dH", "pawfe_apply_H", "pawfe_apply_S", "pawfe_apply_Sinv",
     "pawfe_apply_local",
+    "pawfe_cheb_step_local",
     "pawfe_cheb_filter_workspace", "pawfe_cheb_filter", "pawfe_rayleigh_ritz_workspace",
     "pawfe_rayleigh_ritz", "pawfe_band_energy_grad", "pawfe_lanczos_bounds", "pawfe_last_error",
     "pawfe_chfsi_solve_workspace", "pawfe_chfsi_solve",
@@ -93,6 +94,7 @@ def load(path=LIB_PATH):
         "pawfe_apply_S": [vp, vp, i64, vp, i64, i64, i32, vp],
         "pawfe_apply_Sinv": [vp, vp, i64, vp, i64, i64, i32, vp],
         "pawfe_apply_local": [vp, i32, vp, i64, vp, i64, i64, dbl, i32, vp],
+        "pawfe_cheb_step_local": [vp, vp, vp, i64, vp, i64, vp, dbl, dbl, dbl, i64, i32, vp],
         "pawfe_cheb_filter_workspace": [vp, i64, i32, i32, P(sz)],
         "pawfe_cheb_filter": [vp, vp, i64, vp, i64, i64, i32, vp, i32, dbl, dbl, dbl, i32, vp, sz, vp],
         "pawfe_rayleigh_ritz_workspace": [vp, i64, P(sz)],
@@ -303,6 +305,16 @@ class Operator:
         _check(_lib.pawfe_apply_local(self._h, int(which), _tptr(X), X.stride(0), _tptr(Y), Y.stride(0),
                                       X.shape[1], float(alpha), _PREC[prec], _stream(stream)))
         return Y
+
+    def cheb_step_local(self, RY, RX, Y, lamY, a, ac, zz, prec=FP64, stream=None):
+        """RX <- (-ac RY - zz RX) + a lamY Y + a H_loc M_D^{-1} RY (local part of a
+        filter step, real columns; complex operators: (re, im) pairs); RX in place."""
+        assert RY.stride(1) == 1 and RX.stride(1) == 1 and Y.stride(1) == 1
+        assert RY.stride(0) == RX.stride(0) and RY.shape == RX.shape
+        _check(_lib.pawfe_cheb_step_local(self._h, _tptr(RY), _tptr(RX), RX.stride(0), _tptr(Y), Y.stride(0),
+                                          _tptr(lamY), float(a), float(ac), float(zz), RX.shape[1], _PREC[prec],
+                                          _stream(stream)))
+        return RX
 
     # -- filter / RR ------------------------------------------------------------
     def cheb_filter_workspace(self, nvec, block, prec=FP64):
