@@ -467,26 +467,21 @@ constexpr int kValuMass = 7;     // det J M, every cell of one size (real and co
 // applied to the old value of Y first (see the kernel)
 constexpr int kValuStep = 8;
 constexpr int kValuStepC = 9;
-// the real step variant whose first-visit loads and stores address X, Y and
-// the FP64 residual block by 32-bit byte offsets from the arrays' bases (one
-// register per node instead of an address pair per array; the host selects
-// it when every offset fits 32 bits)
-constexpr int kValuStepW = 10;
 // variants that read the per-cell geometry table (and need it non-null)
 constexpr bool is_general_mode(int mode) {
   return mode == kValuGenH || mode == kValuGenHG || mode == kValuGenMass;
 }
 static_assert(!is_general_mode(kValuH) && !is_general_mode(kValuHRes) && !is_general_mode(kValuHC) &&
                   !is_general_mode(kValuHResC) && !is_general_mode(kValuMass) && !is_general_mode(kValuStep) &&
-                  !is_general_mode(kValuStepC) && !is_general_mode(kValuStepW),
+                  !is_general_mode(kValuStepC),
               "uniform variants");
 // Waves per SIMD the registers are held to: FP32 six (three workgroups of
 // eight waves per CU, as many as the LDS holds), FP64 three; the GGA and the
 // complex variants hold one or two more slabs in LDS (two workgroups per
-// CU): FP32 four, FP64 two.  The FP32 step variant with 64-bit addresses is
-// held to four as well: at six its first-visit loads spill registers, and
-// the spills cost more than the third workgroup gains (measured on the
-// degree-6 filter step); the 32-bit-offset variant fits six.
+// CU): FP32 four, FP64 two.  The FP32 step variant is held to four as
+// well: the filter runs two blocks on two streams, and with six waves of
+// the step kernel the other stream's kernels find no room (degree-6 filter
+// pass of 1024 states: 0.585 s at four waves, 0.65 s at six).
 template <typename T, int MODE>
 constexpr int kWaves = (MODE == kValuGenHG || MODE == kValuHC || MODE == kValuHResC || MODE == kValuStepC)
                            ? (sizeof(T) == 4 ? 4 : 2)
@@ -533,8 +528,7 @@ k_cell_valu(CellArgs<T> A, int ncoltiles, int nitems, T fx, T fy, T fz) {
   constexpr bool GGA = MODE == kValuGenHG;
   constexpr bool MASS = MODE == kValuGenMass || MODE == kValuMass;
   constexpr bool RES = MODE == kValuHRes || MODE == kValuHResC;
-  constexpr bool STEP = MODE == kValuStep || MODE == kValuStepC || MODE == kValuStepW;
-  constexpr bool OFF32 = MODE == kValuStepW;
+  constexpr bool STEP = MODE == kValuStep || MODE == kValuStepC;
   constexpr bool CPLX = MODE == kValuHC || MODE == kValuHResC || MODE == kValuStepC;
   constexpr bool SC = STEP;   // input-side 1-D contractions with the scaled tables
   static_assert(!(RES && GEN), "the residual mode uses the uniform factors");
@@ -732,17 +726,7 @@ k_cell_valu(CellArgs<T> A, int ncoltiles, int nitems, T fx, T fy, T fz) {
     unsigned sown = 0;
     T sxv[STEP ? NJ : 1];
     double syf[STEP ? NJ : 1];
-    // element at byte offset o of an array (o is made opaque so that each
-    // access keeps the base-register + 32-bit-offset form rather than a
-    // shared 64-bit address)
-    auto at = [](auto* base, uint32_t o) {
-      using P = decltype(base);
-      using C = typename std::conditional<std::is_const<typename std::remove_pointer<P>::type>::value, const char,
-                                          char>::type;
-      asm volatile("" : "+v"(o));
-      return reinterpret_cast<P>(reinterpret_cast<C*>(base) + (uint64_t)o);
-    };
-    auto step_loads = [&](const int (&node)[NJ], const uint32_t (&off)[OFF32 ? NJ : 1]) {
+    auto step_loads = [&](const int (&node)[NJ]) {
       typedef const __attribute__((address_space(4))) unsigned* ConstUP;
       const unsigned cm = ((ConstUP)A.own)[cp.e];
       // the classes are unpacked here in every item (one register held
@@ -756,13 +740,8 @@ k_cell_valu(CellArgs<T> A, int ncoltiles, int nitems, T fx, T fy, T fz) {
         sxv[j] = T(0);
         syf[j] = 0.0;
         if ((sown >> j) & 1u) {
-          if constexpr (OFF32) {
-            sxv[j] = *at(A.X, off[j]);
-            syf[j] = *at(A.y64, off[j] * (uint32_t)(sizeof(double) / sizeof(T)));
-          } else {
-            sxv[j] = *elem(A.X, ldxb, n, node[j]);
-            syf[j] = A.y64[(int64_t)node[j] * A.ldy64 + n];
-          }
+          sxv[j] = *elem(A.X, ldxb, n, node[j]);
+          syf[j] = A.y64[(int64_t)node[j] * A.ldy64 + n];
         }
       }
     };
@@ -1067,11 +1046,6 @@ k_cell_valu(CellArgs<T> A, int ncoltiles, int nitems, T fx, T fy, T fz) {
       if constexpr (MASS) f = f * idet * (A.lam ? (T)(-A.lam[n]) : T(1));
       int node[NJ];
       nodes_of(cp, node);
-      uint32_t off[OFF32 ? NJ : 1];   // byte offset of (node j, column n) in X and Y
-      if constexpr (OFF32) {
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) off[j] = (uint32_t)node[j] * ldyb + (uint32_t)n * (uint32_t)sizeof(T);
-      }
       if constexpr (STEP) {
         // Node part of the Chebyshev step at the first visit of a DOF, on
         // the old value before any cell adds to it:
@@ -1079,14 +1053,9 @@ k_cell_valu(CellArgs<T> A, int ncoltiles, int nitems, T fx, T fy, T fz) {
         // the last product and sum in FP64, rounded once
         if constexpr (kLateYo) {
 #pragma unroll
-          for (int j = 0; j < NJ; ++j) {
-            if constexpr (OFF32)
-              yo[j] = lreal(j) ? *at(A.Y, off[j]) : T(0);
-            else
-              yo[j] = lreal(j) ? *elem(A.Y, ldyb, n, node[j]) : T(0);
-          }
+          for (int j = 0; j < NJ; ++j) yo[j] = lreal(j) ? *elem(A.Y, ldyb, n, node[j]) : T(0);
         }
-        step_loads(node, off);
+        step_loads(node);
         const double ly = A.sa * A.lamY[n];
         const T mac = (T)(-A.sac), zz = (T)A.szz;
 #pragma unroll
@@ -1098,14 +1067,10 @@ k_cell_valu(CellArgs<T> A, int ncoltiles, int nitems, T fx, T fy, T fz) {
       }
 #pragma unroll
       for (int j = 0; j < NJ; ++j)
-        if (lreal(j)) {
-          const T v = yo[j] + f * *reinterpret_cast<const T*>(reinterpret_cast<const char*>(sK) +
-                                                             k_of_u(pk[j] & ((1u << kLdsBits) - 1)));
-          if constexpr (OFF32)
-            *at(A.Y, off[j]) = v;
-          else
-            *elem(A.Y, ldyb, n, node[j]) = v;
-        }
+        if (lreal(j))
+          *elem(A.Y, ldyb, n, node[j]) =
+              yo[j] + f * *reinterpret_cast<const T*>(reinterpret_cast<const char*>(sK) +
+                                                      k_of_u(pk[j] & ((1u << kLdsBits) - 1)));
     }
     __syncthreads();
     cur_c = nxt_c;
@@ -1140,12 +1105,9 @@ pawfe_status run_cell_valu(const pawfe_op* op, const CellArgs<T>& a0, hipStream_
   if (MODE == kValuGenHG && !a.vg) return fail(PAWFE_EINVAL, "internal: GGA cell variant without its table");
   if ((MODE == kValuHRes || MODE == kValuHResC) && !a.lam)
     return fail(PAWFE_EINVAL, "internal: residual cell variant without lambda");
-  if ((MODE == kValuStep || MODE == kValuStepC || MODE == kValuStepW) && (!a.own || !a.y64 || !a.lamY))
+  if ((MODE == kValuStep || MODE == kValuStepC) && (!a.own || !a.y64 || !a.lamY))
     return fail(PAWFE_EINVAL, "internal: step cell variant without its tables");
   if (MODE == kValuStepC && !op->cplx) return fail(PAWFE_EINVAL, "internal: complex step variant on a real operator");
-  if (MODE == kValuStepW && (a.ldx != a.ldy || a.ldy64 != a.ldy ||
-                             (uint64_t)op->M * (uint64_t)a.ldy * sizeof(double) >= (uint64_t(1) << 32)))
-    return fail(PAWFE_EINVAL, "internal: 32-bit-offset step variant on arrays it cannot address");
   const int ncoltiles = (a.ncols + CB - 1) / CB;
   const T fx = (T)(0.5 * op->detJ * (2.0 / op->h[0]) * (2.0 / op->h[0]));
   const T fy = (T)(0.5 * op->detJ * (2.0 / op->h[1]) * (2.0 / op->h[1]));

@@ -54,19 +54,6 @@ pawfe_status launch_cell_step(const pawfe_op* op, const T* RY, T* RX, int64_t ld
       default: return run_cell_valu<T, 7, 8, kValuStepC>(op, c, s);
     }
   }
-  // FP32 with every byte offset of X, Y and the FP64 residual block below
-  // 4 GiB: the 32-bit-offset variant (six waves per SIMD instead of four)
-  if constexpr (std::is_same<T, float>::value) {
-    if (ldy == ld && (uint64_t)op->M * (uint64_t)ld * sizeof(double) < (uint64_t(1) << 32)) {
-      switch (op->p) {
-        case 2: return run_cell_valu<T, 3, 4, kValuStepW>(op, c, s);
-        case 3: return run_cell_valu<T, 4, 5, kValuStepW>(op, c, s);
-        case 4: return run_cell_valu<T, 5, 6, kValuStepW>(op, c, s);
-        case 5: return run_cell_valu<T, 6, 7, kValuStepW>(op, c, s);
-        default: return run_cell_valu<T, 7, 8, kValuStepW>(op, c, s);
-      }
-    }
-  }
   switch (op->p) {
     case 2: return run_cell_valu<T, 3, 4, kValuStep>(op, c, s);
     case 3: return run_cell_valu<T, 4, 5, kValuStep>(op, c, s);
