@@ -721,11 +721,16 @@ k_cell_valu(CellArgs<T> A, int ncoltiles, int nitems, T fx, T fy, T fz) {
       for (int j = 0; j < NJ; ++j) yo[j] = *elem(A.Y, ldyb, nn, node[j]);
     }
     // step mode: which of the thread's nodes this cell visits first (the
-    // cell of the lowest colour sharing a DOF), and X and the FP64 residual
-    // block at those nodes
+    // cell of the lowest colour sharing a DOF), this item's gathered X (kept
+    // from the registers the next item's prefetch overwrites) and the FP64
+    // residual block at those nodes
     unsigned sown = 0;
     T sxv[STEP ? NJ : 1];
     double syf[STEP ? NJ : 1];
+    if constexpr (STEP) {
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) sxv[j] = xr[j];
+    }
     auto step_loads = [&](const int (&node)[NJ]) {
       typedef const __attribute__((address_space(4))) unsigned* ConstUP;
       const unsigned cm = ((ConstUP)A.own)[cp.e];
@@ -737,12 +742,8 @@ k_cell_valu(CellArgs<T> A, int ncoltiles, int nitems, T fx, T fy, T fz) {
       for (int j = 0; j < NJ; ++j) sown |= ((cm >> ((cpk >> (5 * j)) & 31u)) & 1u) << j;
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
-        sxv[j] = T(0);
         syf[j] = 0.0;
-        if ((sown >> j) & 1u) {
-          sxv[j] = *elem(A.X, ldxb, n, node[j]);
-          syf[j] = A.y64[(int64_t)node[j] * A.ldy64 + n];
-        }
+        if ((sown >> j) & 1u) syf[j] = A.y64[(int64_t)node[j] * A.ldy64 + n];
       }
     };
     int nxt_c = cur_c, nxt_t = cur_t;
