@@ -746,6 +746,18 @@ k_cell_valu(CellArgs<T> A, int ncoltiles, int nitems, T fx, T fy, T fz) {
         if ((sown >> j) & 1u) syf[j] = A.y64[(int64_t)node[j] * A.ldy64 + n];
       }
     };
+    // FP32 step mode: the first-visit FP64 rows are requested here and wait
+    // in registers through the passes (FP64: at the assembly; requested
+    // here they cost more than they hide, pass of 1024 states 1.08 against
+    // 0.975 s, where FP32 gains 0.556 -> 0.548 s)
+    constexpr bool kEarlyY = STEP && sizeof(T) == 4;
+    if constexpr (kEarlyY) {
+      if (valid) {
+        int node[NJ];
+        nodes_of(cp, node);
+        step_loads(node);
+      }
+    }
     int nxt_c = cur_c, nxt_t = cur_t;
     advance(nxt_c, nxt_t);
     const bool more = item + i_step < i_end;
@@ -1056,7 +1068,7 @@ k_cell_valu(CellArgs<T> A, int ncoltiles, int nitems, T fx, T fy, T fz) {
 #pragma unroll
           for (int j = 0; j < NJ; ++j) yo[j] = lreal(j) ? *elem(A.Y, ldyb, n, node[j]) : T(0);
         }
-        step_loads(node);
+        if constexpr (!kEarlyY) step_loads(node);
         const double ly = A.sa * A.lamY[n];
         const T mac = (T)(-A.sac), zz = (T)A.szz;
 #pragma unroll
