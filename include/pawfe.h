@@ -264,8 +264,10 @@ pawfe_status pawfe_cheb_step_local(const pawfe_op* op, const void* RY, void* RX,
 
 /* Bytes of workspace pawfe_cheb_filter needs for blocks of `block` columns:
  * room for two block states when nvec > block (two blocks in flight), else
- * one.  A workspace of one block state (the query with nvec = block) is
- * also accepted by pawfe_cheb_filter; blocks then run one after another. */
+ * one.  Any whole number of block states (the query with nvec = block gives
+ * one) is accepted by pawfe_cheb_filter: one runs the blocks one after
+ * another, k > 1 keeps up to min(k, 4) blocks in flight (two was the
+ * fastest on the paper's workload). */
 pawfe_status pawfe_cheb_filter_workspace(const pawfe_op* op, int64_t nvec, int32_t block,
                                          int32_t prec, size_t* bytes);
 
@@ -280,11 +282,11 @@ pawfe_status pawfe_cheb_filter_workspace(const pawfe_op* op, int64_t nvec, int32
  * lambda_in: device FP64 [nvec] (estimates of the eigenvalues).
  * Requires b0 < bW < bU, degree >= 2, 1 <= block.  ws: device workspace of
  * at least one block state (pawfe_cheb_filter_workspace with nvec = block),
- * 256-byte aligned.  With room for two block states and more than one block,
- * even and odd blocks run on two internal streams of the operator (default
- * priority), forked from and joined back into `stream`, so that one block's
- * memory-bound node kernels overlap the other block's cell kernel; the
- * results are identical to the one-stream order. */
+ * 256-byte aligned.  With room for k >= 2 block states and more than one
+ * block, block b runs on internal stream b mod min(k, 4, blocks) of the
+ * operator (default priority), forked from and joined back into `stream`,
+ * so that one block's projector and node kernels overlap another block's
+ * cell kernel; the results are identical to the one-stream order. */
 pawfe_status pawfe_cheb_filter(const pawfe_op* op, const void* Xin, int64_t ldx, void* Xout,
                                int64_t ldo, int64_t nvec, int32_t block, const double* lambda_in,
                                int32_t degree, double b0, double bW, double bU, int32_t prec,

@@ -957,24 +957,26 @@ pawfe_status pawfe_cheb_filter(const pawfe_op* op, const void* Xin, int64_t ldx,
   const size_t one = filter_ws_bytes(op, B * cf, prec);
   if (ws_bytes < one) return fail(PAWFE_EINVAL, "workspace too small");
   hipStream_t s = S(stream);
-  // Blocks are uncoupled.  With room for two block states (and more than one
-  // block), even blocks run on one internal stream and odd blocks on the
-  // other, forked from and joined back into `s`: one block's HBM-bound node
-  // kernels then overlap the other's ALU-bound cell kernel.
-  const int nconc = (nvec > B && ws_bytes >= 2 * one) ? 2 : 1;
+  // Blocks are uncoupled.  With room for several block states (and more
+  // than one block), block b runs on internal stream b mod nconc, forked
+  // from and joined back into `s`: one block's projector and node kernels
+  // then overlap another's cell kernel.
+  const int64_t nblocks = (nvec + B - 1) / B;
+  const int nconc = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)kMaxConcBlocks, nblocks,
+                                                                  (int64_t)(ws_bytes / one)}));
   pawfe_op* mop = const_cast<pawfe_op*>(op);
-  if (nconc == 2) {
-    for (hipStream_t& st : mop->fstream)
-      if (!st) PAWFE_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-    for (hipEvent_t& e : mop->fevent)
-      if (!e) PAWFE_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  if (nconc > 1) {
+    for (int q = 0; q < nconc; ++q)
+      if (!mop->fstream[q]) PAWFE_HIP(hipStreamCreateWithFlags(&mop->fstream[q], hipStreamNonBlocking));
+    for (int q = 0; q <= nconc; ++q)
+      if (!mop->fevent[q]) PAWFE_HIP(hipEventCreateWithFlags(&mop->fevent[q], hipEventDisableTiming));
     PAWFE_HIP(hipEventRecord(mop->fevent[0], s));
-    for (hipStream_t st : mop->fstream) PAWFE_HIP(hipStreamWaitEvent(st, mop->fevent[0], 0));
+    for (int q = 0; q < nconc; ++q) PAWFE_HIP(hipStreamWaitEvent(mop->fstream[q], mop->fevent[0], 0));
   }
   for (int64_t j0 = 0, blk = 0; j0 < nvec; j0 += B, ++blk) {
     const int nc = (int)std::min<int64_t>(B, nvec - j0);
-    const int k = nconc == 2 ? (int)(blk & 1) : 0;
-    hipStream_t sb = nconc == 2 ? mop->fstream[k] : s;
+    const int k = nconc > 1 ? (int)(blk % nconc) : 0;
+    hipStream_t sb = nconc > 1 ? mop->fstream[k] : s;
     Carve cv((char*)ws + (size_t)k * one, one);
     const double* X = (const double*)Xin + j0 * cf;
     double* Xo = (double*)Xout + j0 * cf;
@@ -999,16 +1001,16 @@ pawfe_status pawfe_cheb_filter(const pawfe_op* op, const void* Xin, int64_t ldx,
                                sb, prec == PAWFE_BF16X3);
     }
     if (st != PAWFE_OK) {
-      if (nconc == 2)   // still join, so `s` never runs ahead of work already enqueued
-        for (int q = 0; q < 2; ++q) {
+      if (nconc > 1)   // still join, so `s` never runs ahead of work already enqueued
+        for (int q = 0; q < nconc; ++q) {
           (void)hipEventRecord(mop->fevent[1 + q], mop->fstream[q]);
           (void)hipStreamWaitEvent(s, mop->fevent[1 + q], 0);
         }
       return st;
     }
   }
-  if (nconc == 2)
-    for (int q = 0; q < 2; ++q) {
+  if (nconc > 1)
+    for (int q = 0; q < nconc; ++q) {
       PAWFE_HIP(hipEventRecord(mop->fevent[1 + q], mop->fstream[q]));
       PAWFE_HIP(hipStreamWaitEvent(s, mop->fevent[1 + q], 0));
     }

@@ -14,6 +14,7 @@ namespace pawfe {
 constexpr int kNpMax = 7;    // degree <= 6
 constexpr int kNqMax = 8;    // Gauss points per direction
 constexpr int kNpjMax = 32;  // projectors per atom
+constexpr int kMaxConcBlocks = 4;   // column blocks of a filter in flight at once
 
 // Error helper: records the message for pawfe_last_error and returns the code.
 pawfe_status fail(pawfe_status code, const std::string& msg);
@@ -161,10 +162,10 @@ struct pawfe_op {
   size_t scratch_bytes = 0;
   // dense solver handle (rocBLAS handle, opaque here)
   void* blas = nullptr;
-  // two streams (default priority) and fork/join events of the filter's
-  // two-block overlap, created on first use
-  hipStream_t fstream[2] = {nullptr, nullptr};
-  hipEvent_t fevent[3] = {nullptr, nullptr, nullptr};
+  // streams (default priority) and fork/join events of the filter's
+  // overlap of column blocks, created on first use
+  hipStream_t fstream[pawfe::kMaxConcBlocks] = {};
+  hipEvent_t fevent[pawfe::kMaxConcBlocks + 1] = {};
 };
 
 namespace pawfe {

@@ -1,5 +1,5 @@
-"""The filter with room for two block states runs even and odd blocks on two
-internal streams; every column must come out bit-identical to the
+"""The filter with room for k >= 2 block states runs block b on internal
+stream b mod k (at most 4); every column must come out bit-identical to the
 one-stream order (blocks are uncoupled and every kernel is deterministic),
 also for a ragged last block, in FP64 and FP32."""
 
@@ -32,6 +32,10 @@ def test_two_stream_blocks_bit_identical(prec):
     y2 = op.cheb_filter(X, lam, m, float(a[0]), float(a[-1]), bU, block=B, prec=prec, ws=two)
     torch.cuda.synchronize()
     np.testing.assert_array_equal(y1.cpu().numpy(), y2.cpu().numpy())
+    three = op.workspace(3 * one.numel())
+    y3 = op.cheb_filter(X, lam, m, float(a[0]), float(a[-1]), bU, block=B, prec=prec, ws=three)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(y1.cpu().numpy(), y3.cpu().numpy())
     if prec == 0:
         want = chfsi.rchfsi_filter(ref, X.cpu().numpy(), a, m, float(a[0]), float(a[-1]), bU, block=B)
         err = np.linalg.norm(y2.cpu().numpy() - want) / np.linalg.norm(want)
