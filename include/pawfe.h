@@ -238,12 +238,12 @@ pawfe_status pawfe_apply_local(const pawfe_op* op, int32_t which, const void* X,
                                int64_t ldy, int64_t nvec, double alpha, int32_t prec, void* stream);
 
 /* Local part of one Chebyshev step of the filter (Algorithm 2, step 4, as
- * the filter runs it on operators whose cells share one size), exposed to
- * time and test the fused cell kernel on its own:
+ * the filter runs it in FP64 and FP32), exposed to time and test the fused
+ * cell kernel on its own:
  *   RX[I][n] <- (-ac RY[I][n] - zz RX[I][n]) + a lamY[n] Y[I][n]
  *               + a (H_loc M_D^{-1} RY)[I][n]
- * with H_loc = K + V the cell part of H (operator-action subsection; no
- * PAW term) and M_D the lumped GLL mass (approximation (i) of eq. "Delta
+ * with H_loc = K + V (+ the GGA term) the cell part of H (operator-action
+ * subsection; no PAW term) and M_D the lumped GLL mass (approximation (i) of eq. "Delta
  * Sinv").  In the filter RY holds R_Y - sum_a C^a d_a, so M_D^{-1} RY is
  * the block T = Sinv_hat R_Y of the step; the projector terms are added by
  * the filter around this call.  One launch per cell colour; the first term
@@ -256,8 +256,8 @@ pawfe_status pawfe_apply_local(const pawfe_op* op, int32_t which, const void* X,
  * scalars a, a c and zeta zeta'.  RX must not overlap RY, Y or lamY; all
  * buffers are caller-owned.  Errors: PAWFE_EINVAL (NULL buffer, leading
  * dimension below nvec, odd nvec on a complex operator, nvec above 2^29);
- * PAWFE_EUNSUPPORTED (PAWFE_BF16X3, graded meshes or the GGA term, or a
- * degree / Gauss rule without a compiled variant). */
+ * PAWFE_EUNSUPPORTED (PAWFE_BF16X3, or a degree / Gauss rule without a
+ * compiled variant). */
 pawfe_status pawfe_cheb_step_local(const pawfe_op* op, const void* RY, void* RX, int64_t ld, const double* Y,
                                    int64_t ldy, const double* lamY, double a, double ac, double zz, int64_t nvec,
                                    int32_t prec, void* stream);

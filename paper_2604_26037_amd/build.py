@@ -23,7 +23,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libpawfe.so")
 
 SOURCES = ["builder.cpp", "kernels_cell.hip", "kernels_cell_mfma.hip", "kernels_cell_valu.hip",
-           "kernels_cell_gen_f32.hip", "kernels_cell_gen_f64.hip", "kernels_cell_step.hip", "kernels_nl.hip", "kernels_halo.hip", "api.hip", "batch.cpp"]
+           "kernels_cell_gen_f32.hip", "kernels_cell_gen_f64.hip", "kernels_cell_step.hip", "kernels_cell_step_gen.hip", "kernels_nl.hip", "kernels_halo.hip", "api.hip", "batch.cpp"]
 ARCH = os.environ.get("PAWFE_OFFLOAD_ARCH", "gfx950")
 
 

@@ -497,6 +497,25 @@ pawfe_status upload_general(pawfe_op* op, hipStream_t s) {
   CHECK(up(op, &d.geo, geo, s));
   std::vector<float> geof = to_f32(geo);
   CHECK(up(op, &d.geo_f, geof, s));
+  // face factors of the fused filter step: along axis k the lumped mass of
+  // a face node is w_0 (h_e + h_neighbour) / 2 per axis; the step kernel's
+  // tables assume w_0 h_e (two cells of the cell's own size)
+  if (!d.frho) {
+    std::vector<double> fr((size_t)E * 6, 1.0);
+    for (int e = 0; e < E; ++e) {
+      const int ijk[3] = {e % op->n[0], (e / op->n[0]) % op->n[1], e / (op->n[0] * op->n[1])};
+      for (int k = 0; k < 3; ++k) {
+        auto hk = [&](int i) { return op->graded ? op->bnd[k][i + 1] - op->bnd[k][i] : op->h[k]; };
+        const int n = op->n[k], i = ijk[k];
+        const double h = hk(i), hlo = hk((i + n - 1) % n), hhi = hk((i + 1) % n);
+        fr[(size_t)e * 6 + 2 * k] = 2.0 * h / (h + hlo);
+        fr[(size_t)e * 6 + 2 * k + 1] = 2.0 * h / (h + hhi);
+      }
+    }
+    CHECK(up(op, &d.frho, fr, s));
+    std::vector<float> frf = to_f32(fr);
+    CHECK(up(op, &d.frho_f, frf, s));
+  }
   if (op->graded) CHECK(up(op, &d.cscale, cs, s));
   if (op->gga) {
     std::vector<double> vg((size_t)E * 3 * nq3);

@@ -467,9 +467,16 @@ constexpr int kValuMass = 7;     // det J M, every cell of one size (real and co
 // applied to the old value of Y first (see the kernel)
 constexpr int kValuStep = 8;
 constexpr int kValuStepC = 9;
+// the step on general operators (graded mesh; with the GGA term): per-cell
+// geometry, and the gathered values at a cell's face nodes scaled by the
+// ratio of the lumped mass the uniform tables assume to the DOF's own
+// (the neighbour across a face may have another size)
+constexpr int kValuGenStep = 10;
+constexpr int kValuGenStepG = 11;
 // variants that read the per-cell geometry table (and need it non-null)
 constexpr bool is_general_mode(int mode) {
-  return mode == kValuGenH || mode == kValuGenHG || mode == kValuGenMass;
+  return mode == kValuGenH || mode == kValuGenHG || mode == kValuGenMass || mode == kValuGenStep ||
+         mode == kValuGenStepG;
 }
 static_assert(!is_general_mode(kValuH) && !is_general_mode(kValuHRes) && !is_general_mode(kValuHC) &&
                   !is_general_mode(kValuHResC) && !is_general_mode(kValuMass) && !is_general_mode(kValuStep) &&
@@ -483,9 +490,10 @@ static_assert(!is_general_mode(kValuH) && !is_general_mode(kValuHRes) && !is_gen
 // the step kernel the other stream's kernels find no room (degree-6 filter
 // pass of 1024 states: 0.585 s at four waves, 0.65 s at six).
 template <typename T, int MODE>
-constexpr int kWaves = (MODE == kValuGenHG || MODE == kValuHC || MODE == kValuHResC || MODE == kValuStepC)
+constexpr int kWaves = (MODE == kValuGenHG || MODE == kValuHC || MODE == kValuHResC || MODE == kValuStepC ||
+                        MODE == kValuGenStepG)
                            ? (sizeof(T) == 4 ? 4 : 2)
-                       : MODE == kValuStep ? (sizeof(T) == 4 ? 4 : 3)
+                       : (MODE == kValuStep || MODE == kValuGenStep) ? (sizeof(T) == 4 ? 4 : 3)
                                            : (sizeof(T) == 4 ? 6 : 3);
 constexpr int kXP = 9;
 // U: extents up to 8 x 8 x 8;  K, M: up to 7 x 7 x 7 (element offsets, col fastest)
@@ -525,15 +533,15 @@ template <typename T, int NP, int NQ, int MODE>
 __global__ void __launch_bounds__(kNT<T>) __attribute__((amdgpu_waves_per_eu((kWaves<T, MODE>))))
 k_cell_valu(CellArgs<T> A, int ncoltiles, int nitems, T fx, T fy, T fz) {
   constexpr bool GEN = is_general_mode(MODE);   // reads the per-cell table A.geo
-  constexpr bool GGA = MODE == kValuGenHG;
+  constexpr bool GGA = MODE == kValuGenHG || MODE == kValuGenStepG;
   constexpr bool MASS = MODE == kValuGenMass || MODE == kValuMass;
   constexpr bool RES = MODE == kValuHRes || MODE == kValuHResC;
-  constexpr bool STEP = MODE == kValuStep || MODE == kValuStepC;
+  constexpr bool STEP = MODE == kValuStep || MODE == kValuStepC || MODE == kValuGenStep || MODE == kValuGenStepG;
   constexpr bool CPLX = MODE == kValuHC || MODE == kValuHResC || MODE == kValuStepC;
   constexpr bool SC = STEP;   // input-side 1-D contractions with the scaled tables
   static_assert(!(RES && GEN), "the residual mode uses the uniform factors");
   static_assert(!(CPLX && GEN), "complex operators use the uniform factors");
-  static_assert(!(STEP && (GEN || RES)), "the step mode uses the uniform factors");
+  static_assert(!(STEP && RES), "the step and residual modes are separate");
   constexpr int CB = kCB<T>;
   constexpr int NT = kNT<T>;
   constexpr int S = NT / CB;                   // line slots
@@ -678,10 +686,34 @@ k_cell_valu(CellArgs<T> A, int ncoltiles, int nitems, T fx, T fy, T fz) {
       }
     }
   };
-  auto stage = [&]() {
+  // stage the gathered values of the item whose cell is cells[c]
+  auto stage = [&](int c) {
+    if constexpr (STEP && GEN) {
+      // general step: a node on a face of the cell is scaled by the cell's
+      // factor for that face (the uniform tables' lumped mass over the
+      // DOF's own), per face the node lies on
+      typedef const __attribute__((address_space(4))) T* ConstTP;
+      const ConstTP r = (ConstTP)A.frho + 6 * cell_pos(cells[c]).e;
+      T rf[6];
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      if (lreal(j)) *reinterpret_cast<T*>(reinterpret_cast<char*>(sU) + (pk[j] & ((1u << kLdsBits) - 1))) = xr[j];
+      for (int k = 0; k < 6; ++k) rf[k] = r[k];
+      unsigned cpk = cls_pack;   // opaque: the classes are unpacked here, not held per node
+      asm volatile("" : "+v"(cpk));
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const unsigned cl = (cpk >> (5 * j)) & 31u;
+        const unsigned ca = cl % 3u, cb = (cl / 3u) % 3u, cc = cl / 9u;
+        const T fa = ca == 0 ? rf[0] : (ca == 2 ? rf[1] : T(1));
+        const T fb = cb == 0 ? rf[2] : (cb == 2 ? rf[3] : T(1));
+        const T fc = cc == 0 ? rf[4] : (cc == 2 ? rf[5] : T(1));
+        if (lreal(j))
+          *reinterpret_cast<T*>(reinterpret_cast<char*>(sU) + (pk[j] & ((1u << kLdsBits) - 1))) = xr[j] * (fa * fb * fc);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        if (lreal(j)) *reinterpret_cast<T*>(reinterpret_cast<char*>(sU) + (pk[j] & ((1u << kLdsBits) - 1))) = xr[j];
+      }
     }
     if constexpr (!MASS) {
 #pragma unroll
@@ -697,7 +729,7 @@ k_cell_valu(CellArgs<T> A, int ncoltiles, int nitems, T fx, T fy, T fz) {
 
   if (item < i_end) load_item(cur_c, cur_t);
   __syncthreads();
-  if (item < i_end) stage();
+  if (item < i_end) stage(cur_c);
   __syncthreads();
 
   for (; item < i_end; item += i_step) {
@@ -1053,9 +1085,10 @@ k_cell_valu(CellArgs<T> A, int ncoltiles, int nitems, T fx, T fy, T fz) {
     __syncthreads();
     // the next item's values into U (free now), then this item's assembly:
     // colour-ordered read-modify-write of CB contiguous columns per DOF
-    stage();
+    stage(more ? nxt_c : cur_c);
     if (valid) {
       T f = A.alpha;
+      if constexpr (STEP && GEN) f = f / idet;   // the cell's det J of M_D^{-1}
       if constexpr (MASS) f = f * idet * (A.lam ? (T)(-A.lam[n]) : T(1));
       int node[NJ];
       nodes_of(cp, node);
@@ -1115,10 +1148,14 @@ pawfe_status run_cell_valu(const pawfe_op* op, const CellArgs<T>& a0, hipStream_
   if ((MODE == kValuHC || MODE == kValuHResC) && !op->cplx)
     return fail(PAWFE_EINVAL, "internal: complex cell variant on a real operator");
   if (is_general_mode(MODE) && !a.geo) return fail(PAWFE_EINVAL, "internal: general cell variant without geometry");
-  if (MODE == kValuGenHG && !a.vg) return fail(PAWFE_EINVAL, "internal: GGA cell variant without its table");
+  if ((MODE == kValuGenHG || MODE == kValuGenStepG) && !a.vg)
+    return fail(PAWFE_EINVAL, "internal: GGA cell variant without its table");
+  if ((MODE == kValuGenStep || MODE == kValuGenStepG) && !a.frho)
+    return fail(PAWFE_EINVAL, "internal: general step variant without its face factors");
   if ((MODE == kValuHRes || MODE == kValuHResC) && !a.lam)
     return fail(PAWFE_EINVAL, "internal: residual cell variant without lambda");
-  if ((MODE == kValuStep || MODE == kValuStepC) && (!a.own || !a.y64 || !a.lamY))
+  if ((MODE == kValuStep || MODE == kValuStepC || MODE == kValuGenStep || MODE == kValuGenStepG) &&
+      (!a.own || !a.y64 || !a.lamY))
     return fail(PAWFE_EINVAL, "internal: step cell variant without its tables");
   if (MODE == kValuStepC && !op->cplx) return fail(PAWFE_EINVAL, "internal: complex step variant on a real operator");
   const int ncoltiles = (a.ncols + CB - 1) / CB;

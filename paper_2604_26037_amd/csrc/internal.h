@@ -94,6 +94,11 @@ struct DeviceTables {
   double* vg = nullptr;           // [E][3][nq^3] W_q det J (2/h_d) V_GGA,d (GGA term)
   float* vg_f = nullptr;
   double* cscale = nullptr;       // [E] det J_e / det J (graded meshes; band-energy density)
+  // [E][6] per face of a cell (x lo, x hi, y lo, y hi, z lo, z hi): the
+  // lumped mass 2 w_0 h_e / 2 that the uniform tables assume for a node on
+  // that face over its own w_0 (h_e + h_neighbour) / 2 (1 on uniform meshes)
+  double* frho = nullptr;
+  float* frho_f = nullptr;
 };
 
 }  // namespace pawfe

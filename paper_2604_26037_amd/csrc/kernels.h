@@ -34,6 +34,7 @@ struct CellArgs {
   int64_t ldy64;
   const double* lamY;    // per-column Lambda_Y
   double sa, sac, szz;   // a, a c, zeta zeta'
+  const T* frho;         // general step: [E][6] face factors (x lo, x hi, y lo, y hi, z lo, z hi)
 };
 
 struct DensArgs {
@@ -84,11 +85,16 @@ pawfe_status launch_cell_gen(const pawfe_op* op, int mode, const CellArgs<T>& a,
 // M_D^{-1} R_Y' with the node part applied at the first visit of each DOF;
 // R_Y' = R_Y - C d is formed by the caller, the projector terms of R_X are
 // added after it.  cell_step_available: the operator has a step variant
-// (cells of one size, nq = p + 2, degree 2-6).
+// (nq = p + 2, degree 2-6; graded meshes and the GGA term on real operators).
 bool cell_step_available(const pawfe_op* op);
 template <typename T>
 pawfe_status launch_cell_step(const pawfe_op* op, const T* RY, T* RX, int64_t ld, const double* Y, int64_t ldy,
                               const double* lamY, double a, double ac, double zz, int ncols, hipStream_t s);
+
+// the same on general operators (kernels_cell_step_gen.hip; the arguments
+// already carry the per-cell tables)
+template <typename T>
+pawfe_status launch_cell_step_gen(const pawfe_op* op, const CellArgs<T>& c, hipStream_t s);
 
 // out[e][q] = W_q sum_n occ_n |u_n(x_{e,q})|^2
 pawfe_status launch_density(const pawfe_op* op, const double* X, int64_t ldx, int ncols,

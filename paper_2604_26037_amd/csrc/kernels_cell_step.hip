@@ -16,7 +16,8 @@
 namespace pawfe {
 
 bool cell_step_available(const pawfe_op* op) {
-  return !op->general && op->nq == op->p + 2 && op->p >= 2 && op->p <= 6 && op->d.cell_own != nullptr;
+  return op->nq == op->p + 2 && op->p >= 2 && op->p <= 6 && op->d.cell_own != nullptr &&
+         (!op->general || (op->d.frho != nullptr && !op->cplx));
 }
 
 template <typename T>
@@ -45,6 +46,13 @@ pawfe_status launch_cell_step(const pawfe_op* op, const T* RY, T* RX, int64_t ld
   c.sa = a;
   c.sac = ac;
   c.szz = zz;
+  if (op->general) {   // graded mesh / GGA term: per-cell geometry, det J_e applied in the kernel
+    c.alpha = (T)a;
+    c.geo = std::is_same<T, double>::value ? (const T*)op->d.geo : (const T*)op->d.geo_f;
+    c.vg = std::is_same<T, double>::value ? (const T*)op->d.vg : (const T*)op->d.vg_f;
+    c.frho = std::is_same<T, double>::value ? (const T*)op->d.frho : (const T*)op->d.frho_f;
+    return launch_cell_step_gen<T>(op, c, s);
+  }
   if (op->cplx) {
     switch (op->p) {
       case 2: return run_cell_valu<T, 3, 4, kValuStepC>(op, c, s);

@@ -1,14 +1,15 @@
 """Parity of the filter's fused local step against the oracle.
 
 pawfe_cheb_step_local is the part of one step of Algorithm 2 (step 4) that
-the cell kernel carries on operators whose cells share one size:
+the filter's cell kernel carries:
     RX <- (-a c RY - zeta zeta' RX) + a Y Lambda_Y + a H_loc M_D^{-1} RY
-with H_loc = K + V the cell part of H (operator-action subsection) and M_D
-the lumped GLL mass of eq. "Delta Sinv".  The oracle side is the same
-formula written with the oracle's cell operator and lumped mass, element by
-element, at every compiled degree, real and complex operators, FP64 and FP32,
-ragged column counts, and at the paper's size on sampled columns in the
-launch configuration of the bench (256 columns)."""
+with H_loc = K + V (+ the GGA term) the cell part of H (operator-action
+subsection) and M_D the lumped GLL mass of eq. "Delta Sinv".  The oracle
+side is the same formula written with the oracle's cell operator and lumped
+mass, element by element, at every compiled degree, real and complex
+operators, FP64 and FP32, ragged column counts, graded two-level meshes and
+the GGA term, and at the paper's size on sampled columns in the launch
+configuration of the bench (256 columns)."""
 
 import numpy as np
 import pytest
@@ -84,6 +85,26 @@ def test_step_local_every_degree(p, cplx):
     assert _colmax_rel(got, want) < 2e-5
 
 
+@pytest.mark.parametrize("name", ["graded", "gga", "graded_gga"])
+@pytest.mark.parametrize("p", [3, 6])
+def test_step_local_general(p, name):
+    """Graded two-level meshes and the GGA term: per-cell geometry, and the
+    face factors of the lumped mass where neighbouring cells differ."""
+    from oracle.paw import PAWOperator
+    from paper_2604_26037_amd import Operator
+    from workloads.configs import custom_system, with_two_level_gga
+    n = (3, 2, 4) if p < 5 else (2, 3, 2)
+    box = tuple(1.6 * v for v in n)
+    s = custom_system(n, box, p, p + 2, pos=[(1.0, 1.2, 1.4)], rcut=0.9, channels="spd8",
+                      wells=[(1.5, 1.0, 2.0)], s_H=0.5, s_S=0.4, seed=70 + p, nstates=9)
+    s = with_two_level_gga(s, r_fine=0.8, graded=name != "gga", gga=name != "graded")
+    ref, op = PAWOperator(s), Operator(s)
+    got, want = _case(ref, op, 11, False, 0, 30 + p)
+    assert _colmax_rel(got, want) < 1e-12
+    got, want = _case(ref, op, 11, False, 1, 40 + p)
+    assert _colmax_rel(got, want) < 2e-5
+
+
 def test_step_local_paper_sampled():
     """The paper's operator (20^3 cells of degree 6, 1,728,000 DOFs), 256
     columns as in a filter block; columns 0, 77 and 255 against the oracle
@@ -127,7 +148,7 @@ def test_step_local_refusals():
         op.cheb_step_local(z, z.clone(), y, lam, 1.0, 1.0, 1.0, prec=BF16X3)
     g = Operator(with_two_level_gga(s, r_fine=1.5))
     with pytest.raises(PawfeError):
-        g.cheb_step_local(z, z.clone(), y, lam, 1.0, 1.0, 1.0, prec=1)
+        g.cheb_step_local(z, z.clone(), y, lam, 1.0, 1.0, 1.0, prec=BF16X3)
     c = Operator(dataclasses.replace(s, kpoint=np.array([0.1, 0.0, 0.2]), is_complex=True))
     z3 = torch.zeros((M, 3), dtype=torch.float32, device="cuda:0")
     with pytest.raises(PawfeError):   # odd number of real columns on a complex operator
