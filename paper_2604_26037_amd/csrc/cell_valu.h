@@ -1,7 +1,8 @@
 // Cell operators on the vector ALUs: the implementation shared by the
 // translation units that instantiate it (kernels_cell_valu.hip: K + V on
 // cells of one size; kernels_cell_gen_f32.hip / _f64.hip: per-cell geometry,
-// the GGA term and the mass term).
+// the GGA term and the mass term; kernels_cell_step.hip /
+// kernels_cell_step_gen.hip: the filter's fused Chebyshev step).
 //
 // Local (cell) part of the Hamiltonian on the vector ALUs:
 // Y += alpha (K + V [+ GGA]) X over the cells of one colour (eq. "FEM Ham
@@ -55,6 +56,16 @@
 //     parts; P4 reads G;
 //   - the mass term det J_e M (the S apply and the -lambda M part of the
 //     residual): P1 (M1 only), P7 (M1 only) and P8 (M1 only).
+//
+// The filter's step (Algorithm 2, step 4) runs as the step variants: the
+// input-side 1-D tables have their columns divided by the GLL weights
+// (doubled on the end nodes), which applies det J M_D^{-1} to the gathered
+// R_Y' on the way in, so the block T = M_D^{-1} R_Y' is never stored (on
+// graded meshes a node on a face whose neighbour has another size is
+// scaled by the ratio of the two lumped masses when it is staged); and the
+// cell making the first visit of a DOF in the colour order first replaces
+// the old value by the node part of the step, -a c R_Y' - zeta zeta' R_X +
+// a lambda_n Y.
 
 #pragma once
 
