@@ -177,8 +177,9 @@ pawfe_status apply_entry(const pawfe_op* cop, int which, const void* X, int64_t 
 
 // ---- filter ------------------------------------------------------------------
 
-// The filter step fused into the cell kernel (cells of one size, FP64 or
-// FP32 recurrence); otherwise the node-wise step with an explicit T.
+// The filter step fused into the cell kernel (FP64 or FP32 recurrence, on
+// uniform and graded meshes); bf16x3 keeps the node-wise step with an
+// explicit T.
 bool fused_step(const pawfe_op* op, int32_t prec) { return prec != PAWFE_BF16X3 && cell_step_available(op); }
 
 // B: real columns of one block (two per complex column)
@@ -243,7 +244,7 @@ pawfe_status filter_block(const pawfe_op* op, const double* X, int64_t ldx, doub
 }
 
 // The same filter with the step's node part fused into the cell kernel
-// (cells of one size, FP64 or FP32 recurrence).  R_Y is kept as
+// (FP64 or FP32 recurrence).  R_Y is kept as
 // R~ = R - C w with w the projector vector whose C w the previous step still
 // owes it (nw = -w is stored), and R_X as R' = R - C d of its own step:
 //   c = C^T M_D^{-1} R = reduce(R~) - G nw_prev      (G = C^T M_D^{-1} C)

@@ -1,5 +1,6 @@
-// The Chebyshev step of the filter on operators whose cells share one
-// geometry: the vector-ALU kernel of cell_valu.h in its step variants.
+// The Chebyshev step of the filter: the vector-ALU kernel of cell_valu.h in
+// its step variants (cells of one size here; graded meshes and the GGA term
+// in kernels_cell_step_gen.hip).
 //
 // One step of Algorithm 2 (R_Y the current block, R_X the previous one,
 // T = M_D^{-1} R_Y' with R_Y' = R_Y - sum_a C^a d_a already formed in R_Y):
