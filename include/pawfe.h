@@ -169,6 +169,15 @@ pawfe_status pawfe_get_dofmap(const pawfe_op* op, int32_t* cell_dofs, int32_t* c
                               int64_t* supp_cell_off, int64_t* supp_cells,
                               int64_t* supp_node_off, int64_t* supp_nodes);
 
+/* Copies to the HOST array first_visit [E] the builder's first-visit bits
+ * of the colour-ordered assembly that the filter's fused step uses: bit
+ * ca + 3 cb + 9 cc of first_visit[e] is set when cell e is the cell of the
+ * lowest colour among the cells sharing its local nodes of position class
+ * (ca, cb, cc) (per axis 0: the low face, 1: inside, 2: the high face), so
+ * that every DOF has exactly one first visit.  Integer data, compared
+ * bit-exactly by the tests. */
+pawfe_status pawfe_get_first_visit(const pawfe_op* op, uint32_t* first_visit);
+
 /* Replaces V(q) (HOST array [E][nq^3]) / Delta_H (HOST, packed like desc.dH).
  * Enqueued on `stream`, synchronizes it.  Delta_Sinv does not depend on
  * either, so nothing else is rebuilt. */

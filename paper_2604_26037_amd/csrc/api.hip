@@ -799,6 +799,12 @@ pawfe_status pawfe_get_dofmap(const pawfe_op* op, int32_t* cell_dofs, int32_t* c
   return PAWFE_OK;
 }
 
+pawfe_status pawfe_get_first_visit(const pawfe_op* op, uint32_t* first_visit) {
+  if (!op || !first_visit) return fail(PAWFE_EINVAL, "op or first_visit is NULL");
+  std::copy(op->cell_own.begin(), op->cell_own.end(), first_visit);
+  return PAWFE_OK;
+}
+
 pawfe_status pawfe_set_veff(pawfe_op* op, const double* veff_q, void* stream) {
   if (!op || !veff_q) return fail(PAWFE_EINVAL, "op or veff_q is NULL");
   const size_t n = (size_t)op->E * op->nq3;

@@ -24,7 +24,7 @@ _STATUS = {1: "EINVAL", 2: "ENOMEM", 3: "EHIP", 4: "ENOTSPD", 5: "ENONFINITE", 6
 
 # every symbol include/pawfe.h declares
 EXPORTS = [
-    "pawfe_build_operator", "pawfe_destroy_operator", "pawfe_query", "pawfe_get_dofmap",
+    "pawfe_build_operator", "pawfe_destroy_operator", "pawfe_query", "pawfe_get_dofmap", "pawfe_get_first_visit",
     "pawfe_set_veff", "pawfe_set_vgga", "pawfe_set_dH", "pawfe_apply_H", "pawfe_apply_S", "pawfe_apply_Sinv",
     "pawfe_apply_local",
     "pawfe_cheb_step_local",
@@ -84,6 +84,7 @@ def load(path=LIB_PATH):
         "pawfe_destroy_operator": [vp],
         "pawfe_query": [vp, P(i64), P(i64), P(i32), P(i32), P(i64), P(i64)],
         "pawfe_get_dofmap": [vp, vp, vp, vp, vp, vp, vp],
+        "pawfe_get_first_visit": [vp, vp],
         "pawfe_set_veff": [vp, P(dbl), vp],
         "pawfe_set_vgga": [vp, P(dbl), vp],
         "pawfe_set_dH": [vp, P(dbl), vp],
@@ -233,6 +234,13 @@ class Operator:
         _check(_lib.pawfe_get_dofmap(self._h, cd.ctypes.data, col.ctypes.data, sco.ctypes.data,
                                      sc.ctypes.data, sno.ctypes.data, sn.ctypes.data))
         return cd, col, sco, sc[:self.nsupp_cells], sno, sn[:self.nsupp_nodes]
+
+    def first_visit(self):
+        """[E] uint32: bit ca + 3 cb + 9 cc set when the cell makes the first
+        visit of its local nodes of that position class in the colour order."""
+        out = np.empty(self.ncells, dtype=np.uint32)
+        _check(_lib.pawfe_get_first_visit(self._h, out.ctypes.data))
+        return out
 
     def set_veff(self, veff_q, stream=None):
         v = np.ascontiguousarray(veff_q, dtype=np.float64).ravel()
