@@ -74,6 +74,13 @@ def load(path=LIB_PATH):
     global _lib
     if _lib is not None:
         return _lib
+    # PyTorch (when present) loads its own HIP runtime; loading it first makes
+    # the library bind to that one instead of bringing a second runtime into
+    # the process (the binding takes streams and device memory from PyTorch)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing; build it with `python -m paper_2604_26037_amd.build`")
     lib = C.CDLL(path)
