@@ -309,8 +309,12 @@ pawfe_status pawfe_rayleigh_ritz_workspace(const pawfe_op* op, int64_t nvec, siz
  * projected generalized eigenproblem H^p Q = S^p Q Lambda, the rotation
  * X <- X Q (in place), and resnorm[i] = ||H x_i - lambda_i S x_i||_2 (the
  * eigen-residual check).  X device FP64 [ndof][ldx]; lambda (ascending)
- * and resnorm: device FP64 [nvec].  Returns PAWFE_ENOTSPD if S^p is not
- * positive definite. Synchronizes the stream (it reads the solver status).
+ * and resnorm: device FP64 [nvec].  The projected problem is reduced with
+ * the Cholesky factor S^p = U^H U (U^-H H^p U^-1 z = lambda z, Q = U^-1 Z).
+ * Returns PAWFE_ENOTSPD if S^p is not positive definite (a non-positive
+ * pivot of that factor; X is left unrotated) and PAWFE_ENONFINITE if the
+ * eigensolver does not converge.  Synchronizes the stream (it reads the
+ * factor's and the solver's status).
  * sr_prec: PAWFE_FP64 (the rotation as one FP64 GEMM) or PAWFE_FP32 (the
  * mixed-precision subspace rotation of the Rayleigh-Ritz subsection:
  * X diag(Q) in FP64 plus fl32(X) fl32(Q_off) as an FP32 GEMM, Q_off = Q with

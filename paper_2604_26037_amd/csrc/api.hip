@@ -370,6 +370,15 @@ __global__ void k_symmetrize(int N, double* __restrict__ A) {
   A[(int64_t)j * N + i] = v;
 }
 
+// column-major N x N symmetric matrix whose upper triangle holds the values:
+// copy it into the lower triangle
+__global__ void k_fill_lower(int N, double* __restrict__ A) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)N * N) return;
+  const int i = (int)(idx % N), j = (int)(idx / N);
+  if (i > j) A[idx] = A[(int64_t)i * N + j];
+}
+
 // Complex operators: the realified projection P (2N x 2N, row-major, real
 // view of (re, im) column pairs) -> the N x N complex Hermitian matrix
 // A_ij = x_i^H (A x)_j, column-major (i + j N), interleaved (re, im)
@@ -1147,36 +1156,75 @@ pawfe_status pawfe_rayleigh_ritz(const pawfe_op* cop, void* Xv, int64_t ldx, int
       hipLaunchKernelGGL(k_symmetrize, dim3((unsigned)((N * N + 255) / 256)), dim3(256), 0, s, (int)N, P);
   }
   PAWFE_HIP(hipGetLastError());
-  // projected generalized eigenproblem (dense, FP64); complex operators: the
-  // Hermitian N x N problem formed from the realified projections (in the
-  // split-K buffer, free by now), solved complex, and its eigenvectors
-  // turned into the real rotation of the (re, im) pairs (into Hp)
-  rocblas_status rs;
+  // projected generalized eigenproblem H^p q = lambda S^p q (dense, FP64),
+  // reduced to a standard one: S^p = U^H U (Cholesky), U^-H H^p U^-1 z =
+  // lambda z, q = U^-1 z (so Q^H S^p Q = I).  The two-sided transform and the
+  // back-transform are blocked triangular solves on the matrix cores.
+  // Complex operators: the Hermitian N x N problem formed from the realified
+  // projections (in the split-K buffer, free by now), solved complex, and its
+  // eigenvectors turned into the real rotation of the (re, im) pairs (into Hp)
   double* lam2 = nullptr;
+  double* Hc = part;
+  double* Sc = part + 2 * Nc * Nc;
+  const dim3 gq((unsigned)((Nc * Nc + 255) / 256));
+  const rocblas_double_complex onez(1.0, 0.0);
+  const double one = 1.0;
+  auto read_info = [&](rocblas_int* v) -> pawfe_status {
+    PAWFE_HIP(hipMemcpyAsync(v, info, sizeof(rocblas_int), hipMemcpyDeviceToHost, s));
+    PAWFE_HIP(hipStreamSynchronize(s));
+    return PAWFE_OK;
+  };
+  rocblas_status rs;
   if (!op->cplx) {
-    rs = rocsolver_dsygvd(h, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_upper, (rocblas_int)N, Hp,
-                          (rocblas_int)N, Sp, (rocblas_int)N, lambda, Ework, info);
+    hipLaunchKernelGGL(k_fill_lower, gq, dim3(256), 0, s, (int)N, Hp);
+    PAWFE_HIP(hipGetLastError());
+    rs = rocsolver_dpotrf(h, rocblas_fill_upper, (rocblas_int)N, Sp, (rocblas_int)N, info);
   } else {
-    double* Hc = part;
-    double* Sc = part + 2 * Nc * Nc;
     lam2 = part + 4 * Nc * Nc;
-    const dim3 gq((unsigned)((Nc * Nc + 255) / 256));
     hipLaunchKernelGGL(k_form_herm, gq, dim3(256), 0, s, (int)Nc, Hp, Hc);
     hipLaunchKernelGGL(k_form_herm, gq, dim3(256), 0, s, (int)Nc, Sp, Sc);
-    rs = rocsolver_zhegvd(h, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_upper, (rocblas_int)Nc,
-                          (rocblas_double_complex*)Hc, (rocblas_int)Nc, (rocblas_double_complex*)Sc, (rocblas_int)Nc,
-                          lambda, Ework, info);
-    if (rs == rocblas_status_success) {
-      hipLaunchKernelGGL(k_realify_rot, gq, dim3(256), 0, s, (int)Nc, Hc, Hp);
-      CHECK(launch_dup_pairs(lambda, lam2, (int)Nc, s));
-    }
+    PAWFE_HIP(hipGetLastError());
+    rs = rocsolver_zpotrf(h, rocblas_fill_upper, (rocblas_int)Nc, (rocblas_double_complex*)Sc, (rocblas_int)Nc, info);
   }
-  if (rs != rocblas_status_success) return fail(PAWFE_EHIP, "rocsolver generalized eigensolver failed");
+  if (rs != rocblas_status_success) return fail(PAWFE_EHIP, "rocsolver Cholesky factorization failed");
   rocblas_int hinfo = 0;
-  PAWFE_HIP(hipMemcpyAsync(&hinfo, info, sizeof(rocblas_int), hipMemcpyDeviceToHost, s));
-  PAWFE_HIP(hipStreamSynchronize(s));
-  if (hinfo > Nc) return fail(PAWFE_ENOTSPD, "projected overlap S^p is not positive definite");
+  CHECK(read_info(&hinfo));
+  if (hinfo > 0) return fail(PAWFE_ENOTSPD, "projected overlap S^p is not positive definite");
+  const rocblas_int n = (rocblas_int)Nc;
+  rocblas_status r1, r2, r3;
+  if (!op->cplx) {
+    r1 = rocblas_dtrsm(h, rocblas_side_left, rocblas_fill_upper, rocblas_operation_transpose,
+                       rocblas_diagonal_non_unit, n, n, &one, Sp, n, Hp, n);
+    r2 = rocblas_dtrsm(h, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none, rocblas_diagonal_non_unit,
+                       n, n, &one, Sp, n, Hp, n);
+    r3 = rocsolver_dsyevd(h, rocblas_evect_original, rocblas_fill_upper, n, Hp, n, lambda, Ework, info);
+  } else {
+    rocblas_double_complex* H = (rocblas_double_complex*)Hc;
+    const rocblas_double_complex* U = (const rocblas_double_complex*)Sc;
+    r1 = rocblas_ztrsm(h, rocblas_side_left, rocblas_fill_upper, rocblas_operation_conjugate_transpose,
+                       rocblas_diagonal_non_unit, n, n, &onez, U, n, H, n);
+    r2 = rocblas_ztrsm(h, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none, rocblas_diagonal_non_unit,
+                       n, n, &onez, U, n, H, n);
+    r3 = rocsolver_zheevd(h, rocblas_evect_original, rocblas_fill_upper, n, H, n, lambda, Ework, info);
+  }
+  if (r1 != rocblas_status_success || r2 != rocblas_status_success)
+    return fail(PAWFE_EHIP, "rocblas triangular solve (reduction) failed");
+  if (r3 != rocblas_status_success) return fail(PAWFE_EHIP, "rocsolver eigensolver failed");
+  CHECK(read_info(&hinfo));
   if (hinfo > 0) return fail(PAWFE_ENONFINITE, "projected eigensolver did not converge");
+  if (!op->cplx) {
+    r1 = rocblas_dtrsm(h, rocblas_side_left, rocblas_fill_upper, rocblas_operation_none, rocblas_diagonal_non_unit,
+                       n, n, &one, Sp, n, Hp, n);
+  } else {
+    r1 = rocblas_ztrsm(h, rocblas_side_left, rocblas_fill_upper, rocblas_operation_none, rocblas_diagonal_non_unit,
+                       n, n, &onez, (const rocblas_double_complex*)Sc, n, (rocblas_double_complex*)Hc, n);
+  }
+  if (r1 != rocblas_status_success) return fail(PAWFE_EHIP, "rocblas triangular solve (back-transform) failed");
+  if (op->cplx) {
+    hipLaunchKernelGGL(k_realify_rot, gq, dim3(256), 0, s, (int)Nc, Hc, Hp);
+    PAWFE_HIP(hipGetLastError());
+    CHECK(launch_dup_pairs(lambda, lam2, (int)Nc, s));
+  }
   // rotation X <- X Q (Q column-major in Hp; real form for complex operators)
   if (sr_prec == PAWFE_FP32) {
     // mixed precision (the paper's RR-SR strategy): X diag(Q) in FP64 plus

@@ -103,3 +103,29 @@ def test_more_columns_than_one_chunk():
     lam, res = lam.cpu().numpy(), res.cpu().numpy()
     assert np.abs(lam - lam_o).max() < 1e-9 * max(1.0, np.abs(lam_o).max())
     np.testing.assert_allclose(res, res_o, rtol=1e-6, atol=1e-9 * np.abs(res_o).max())
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_rayleigh_ritz_singular_overlap_is_refused(cplx):
+    """A zero column makes the projected overlap S^p singular (an exactly
+    zero pivot of its Cholesky factor): Rayleigh-Ritz reports ENOTSPD instead
+    of returning a rotation."""
+    from paper_2604_26037_amd import Operator
+    from paper_2604_26037_amd.pawfe import PAWFE_ENOTSPD, PawfeError
+    from workloads.configs import custom_system
+    n = (3, 3, 3)
+    box = tuple(1.7 * v for v in n)
+    rng = np.random.Generator(np.random.PCG64(77))
+    extra = dict(kpoint=(0.2, -0.1, 0.3), is_complex=True) if cplx else {}
+    s = custom_system(n, box, 3, 5, pos=rng.uniform(0.0, 1.0, size=(2, 3)) * np.asarray(box), rcut=1.4,
+                      channels="spd8", wells=rng.uniform(0.0, 1.0, size=(2, 3)) * np.asarray(box),
+                      s_H=0.5, s_S=0.2, seed=78, nstates=6, **extra)
+    op = Operator(s)
+    X = s.trial(6)
+    X[:, 3] = 0.0
+    with pytest.raises(PawfeError) as e:
+        op.rayleigh_ritz(_dev(X))
+    assert e.value.code == PAWFE_ENOTSPD
+    # the operator still serves a well-posed block afterwards
+    lam, _ = op.rayleigh_ritz(_dev(s.trial(6)))
+    assert bool(torch.isfinite(lam).all())
