@@ -293,9 +293,13 @@ pawfe_status pawfe_cheb_filter_workspace(const pawfe_op* op, int64_t nvec, int32
  * at least one block state (pawfe_cheb_filter_workspace with nvec = block),
  * 256-byte aligned.  With room for k >= 2 block states and more than one
  * block, block b runs on internal stream b mod min(k, 4, blocks) of the
- * operator (default priority), forked from and joined back into `stream`,
- * so that one block's projector and node kernels overlap another block's
- * cell kernel; the results are identical to the one-stream order. */
+ * library (default priority; one set per device, shared by all operators,
+ * created on first use and kept until the process ends), forked from and
+ * joined back into `stream`, so that one block's projector and node kernels
+ * overlap another block's cell kernel; the results are identical to the
+ * one-stream order.  Filters of different operators issued on different
+ * streams at the same time run their blocks one after another on those
+ * shared streams. */
 pawfe_status pawfe_cheb_filter(const pawfe_op* op, const void* Xin, int64_t ldx, void* Xout,
                                int64_t ldo, int64_t nvec, int32_t block, const double* lambda_in,
                                int32_t degree, double b0, double bW, double bU, int32_t prec,

@@ -6,6 +6,7 @@
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -688,10 +689,27 @@ void free_device(pawfe_op* op) {
     if (e) (void)hipEventDestroy(e);
     e = nullptr;
   }
-  for (hipStream_t& st : op->fstream) {
-    if (st) (void)hipStreamDestroy(st);
-    st = nullptr;
+}
+
+// The filter's block streams (default priority): one set per device, shared
+// by every operator, created on first use and kept until the process ends.
+// A process has few hardware queues (four by default) and streams beyond
+// them share queues, so a set of block streams per operator would leave the
+// blocks of one operator's filter serialized on one queue once other
+// operators had created theirs (measured: 12-19 % slower filter passes).
+pawfe_status block_streams(int n, hipStream_t* out) {
+  static std::mutex mu;
+  static std::vector<std::array<hipStream_t, kMaxConcBlocks>> per_dev;
+  int dev = 0;
+  PAWFE_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  if ((int)per_dev.size() <= dev) per_dev.resize(dev + 1);
+  for (int q = 0; q < n; ++q) {
+    hipStream_t& st = per_dev[dev][q];
+    if (!st) PAWFE_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    out[q] = st;
   }
+  return PAWFE_OK;
 }
 
 }  // namespace pawfe
@@ -1000,18 +1018,18 @@ pawfe_status pawfe_cheb_filter(const pawfe_op* op, const void* Xin, int64_t ldx,
   const int nconc = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)kMaxConcBlocks, nblocks,
                                                                   (int64_t)(ws_bytes / one)}));
   pawfe_op* mop = const_cast<pawfe_op*>(op);
+  hipStream_t bstream[kMaxConcBlocks] = {};
   if (nconc > 1) {
-    for (int q = 0; q < nconc; ++q)
-      if (!mop->fstream[q]) PAWFE_HIP(hipStreamCreateWithFlags(&mop->fstream[q], hipStreamNonBlocking));
+    CHECK(block_streams(nconc, bstream));
     for (int q = 0; q <= nconc; ++q)
       if (!mop->fevent[q]) PAWFE_HIP(hipEventCreateWithFlags(&mop->fevent[q], hipEventDisableTiming));
     PAWFE_HIP(hipEventRecord(mop->fevent[0], s));
-    for (int q = 0; q < nconc; ++q) PAWFE_HIP(hipStreamWaitEvent(mop->fstream[q], mop->fevent[0], 0));
+    for (int q = 0; q < nconc; ++q) PAWFE_HIP(hipStreamWaitEvent(bstream[q], mop->fevent[0], 0));
   }
   for (int64_t j0 = 0, blk = 0; j0 < nvec; j0 += B, ++blk) {
     const int nc = (int)std::min<int64_t>(B, nvec - j0);
     const int k = nconc > 1 ? (int)(blk % nconc) : 0;
-    hipStream_t sb = nconc > 1 ? mop->fstream[k] : s;
+    hipStream_t sb = nconc > 1 ? bstream[k] : s;
     Carve cv((char*)ws + (size_t)k * one, one);
     const double* X = (const double*)Xin + j0 * cf;
     double* Xo = (double*)Xout + j0 * cf;
@@ -1038,7 +1056,7 @@ pawfe_status pawfe_cheb_filter(const pawfe_op* op, const void* Xin, int64_t ldx,
     if (st != PAWFE_OK) {
       if (nconc > 1)   // still join, so `s` never runs ahead of work already enqueued
         for (int q = 0; q < nconc; ++q) {
-          (void)hipEventRecord(mop->fevent[1 + q], mop->fstream[q]);
+          (void)hipEventRecord(mop->fevent[1 + q], bstream[q]);
           (void)hipStreamWaitEvent(s, mop->fevent[1 + q], 0);
         }
       return st;
@@ -1046,7 +1064,7 @@ pawfe_status pawfe_cheb_filter(const pawfe_op* op, const void* Xin, int64_t ldx,
   }
   if (nconc > 1)
     for (int q = 0; q < nconc; ++q) {
-      PAWFE_HIP(hipEventRecord(mop->fevent[1 + q], mop->fstream[q]));
+      PAWFE_HIP(hipEventRecord(mop->fevent[1 + q], bstream[q]));
       PAWFE_HIP(hipStreamWaitEvent(s, mop->fevent[1 + q], 0));
     }
   return PAWFE_OK;

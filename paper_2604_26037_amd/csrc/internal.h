@@ -167,9 +167,9 @@ struct pawfe_op {
   size_t scratch_bytes = 0;
   // dense solver handle (rocBLAS handle, opaque here)
   void* blas = nullptr;
-  // streams (default priority) and fork/join events of the filter's
-  // overlap of column blocks, created on first use
-  hipStream_t fstream[pawfe::kMaxConcBlocks] = {};
+  // fork/join events of the filter's overlap of column blocks (the block
+  // streams themselves are the library's, one set per device), created on
+  // first use
   hipEvent_t fevent[pawfe::kMaxConcBlocks + 1] = {};
 };
 
