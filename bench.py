@@ -406,6 +406,32 @@ def complex_mode(dev, args):
                       "rayleigh_ritz_s": t_rr, "eig_err_mixed_vs_fp64_ha": err}), flush=True)
 
 
+def rr_mode(op, s, gen, dev, args):
+    """Rayleigh-Ritz alone on the workload's N states (FP64 rotation and
+    residual norms): one warm-up call, then `steps` timed calls, each on a
+    fresh copy of the same random block (the copy is outside the timing)."""
+    import torch
+
+    M, N = op.ndof, s.nstates
+    X = torch.randn((M, N), generator=gen, dtype=torch.float64, device=dev)
+    ws_r = op.workspace(op.rayleigh_ritz_workspace(N))
+    Xc = X.clone()
+    op.rayleigh_ritz(Xc, ws=ws_r)
+    ts = []
+    for k in range(max(1, args.steps)):
+        Xc.copy_(X)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        lam, res = op.rayleigh_ritz(Xc, ws=ws_r)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) / 1e3)
+        log(f"Rayleigh-Ritz {k}: {ts[-1]:.4f} s")
+    print(json.dumps({"mode": "rr", "M": M, "nstates": N, "rayleigh_ritz_s": float(np.mean(ts)),
+                      "calls_s": ts, "lambda_min": float(lam[0].item())}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -417,9 +443,9 @@ def main():
     ap.add_argument("--hx-reps", type=int, default=5)
     ap.add_argument("--skip-graded", action="store_true",
                     help="do not time the two-level-mesh GGA variant of the workload")
-    ap.add_argument("--mode", default="full", choices=["full", "kernels", "batch"],
+    ap.add_argument("--mode", default="full", choices=["full", "kernels", "rr", "batch"],
                     help="kernels: only the cell-local operator and a calibration copy (for counters); "
-                         "batch: the graph-captured filter of 24 uneven problems")
+                         "rr: Rayleigh-Ritz alone; batch: the graph-captured filter of 24 uneven problems")
     ap.add_argument("--batch-count", type=int, default=24)
     ap.add_argument("--one-stream", action="store_true",
                     help="filter blocks one after another on one stream (no two blocks in flight)")
@@ -457,6 +483,8 @@ def main():
     gen.manual_seed(int(s.x_seed) % (2 ** 63))
     if args.mode == "kernels":
         return kernels_mode(op, s, gen, dev, args)
+    if args.mode == "rr":
+        return rr_mode(op, s, gen, dev, args)
     X = torch.randn((M, N), generator=gen, dtype=torch.float64, device=dev)
 
     tmin, tmax, beta = op.lanczos_bounds(k=20)
