@@ -8,8 +8,8 @@ subsection) and M_D the lumped GLL mass of eq. "Delta Sinv".  The oracle
 side is the same formula written with the oracle's cell operator and lumped
 mass, element by element, at every compiled degree, real and complex
 operators, FP64 and FP32, ragged column counts, graded two-level meshes and
-the GGA term, and at the paper's size on sampled columns in the launch
-configuration of the bench (256 columns)."""
+the GGA term, and at the paper's size (uniform and two-level GGA meshes) on
+sampled columns in the launch configuration of the bench (256 columns)."""
 
 import numpy as np
 import pytest
@@ -105,14 +105,19 @@ def test_step_local_general(p, name):
     assert _colmax_rel(got, want) < 2e-5
 
 
-def test_step_local_paper_sampled():
-    """The paper's operator (20^3 cells of degree 6, 1,728,000 DOFs), 256
+@pytest.mark.parametrize("mesh", ["uniform", "graded_gga"])
+def test_step_local_paper_sampled(mesh):
+    """The paper's operator (20^3 cells of degree 6, 1,728,000 DOFs), and the
+    same operator on the bench's two-level mesh with the GGA term, 256
     columns as in a filter block; columns 0, 77 and 255 against the oracle
     (the step is column by column)."""
     from oracle.paw import PAWOperator
     from paper_2604_26037_amd import Operator
     from workloads import make_system
+    from workloads.configs import with_two_level_gga
     s = make_system("paper")
+    if mesh == "graded_gga":
+        s = with_two_level_gga(s, r_fine=1.0)
     ref, op = PAWOperator(s), Operator(s)
     M, nc = ref.mesh.M, 256
     rng = np.random.default_rng(5)
@@ -120,17 +125,22 @@ def test_step_local_paper_sampled():
     lam = rng.uniform(-1.0, 3.0, nc)
     a, ac, zz = 0.37, -0.81, 0.42
     cols = [0, 77, 255]
-    for prec, tol in ((0, 1e-12), (1, 2e-5)):
+    got = {}
+    for prec in (0, 1):
         dt = torch.float64 if prec == 0 else torch.float32
         RYd, RXd = _dev(RY).to(dt), _dev(RX).to(dt)
         op.cheb_step_local(RYd, RXd, _dev(Y), _dev(lam), a, ac, zz, prec=prec)
-        got = RXd.double().cpu().numpy()[:, cols]
-        ry, rx = RY[:, cols], RX[:, cols]
-        if prec == 1:
-            ry = ry.astype(np.float32).astype(np.float64)
-            rx = rx.astype(np.float32).astype(np.float64)
-        want = _want(ref, ry, rx, Y[:, cols], lam[cols], a, ac, zz)
-        assert _colmax_rel(got, want) < tol, prec
+        got[prec] = RXd.double().cpu().numpy()[:, cols]
+        del RYd, RXd
+    # one oracle call over both precisions' inputs (the step is column by
+    # column): the FP64 columns, then the same columns rounded to FP32
+    r32 = lambda z: z.astype(np.float32).astype(np.float64)
+    ry, rx = RY[:, cols], RX[:, cols]
+    want = _want(ref, np.hstack([ry, r32(ry)]), np.hstack([rx, r32(rx)]), np.hstack([Y[:, cols]] * 2),
+                 np.concatenate([lam[cols]] * 2), a, ac, zz)
+    k = len(cols)
+    assert _colmax_rel(got[0], want[:, :k]) < 1e-12
+    assert _colmax_rel(got[1], want[:, k:]) < 2e-5
 
 
 def test_step_local_refusals():
