@@ -305,6 +305,20 @@ pawfe_status pawfe_cheb_filter(const pawfe_op* op, const void* Xin, int64_t ldx,
                                int32_t degree, double b0, double bW, double bU, int32_t prec,
                                void* ws, size_t ws_bytes, void* stream);
 
+/* The filter with step 2 of Algorithm 2 (the residual R = H X - S X Lambda
+ * of the input pairs) supplied by the caller instead of formed here: R is
+ * device FP64 [ndof][ldr] (complex operators: complex128), read only, for
+ * the same nvec columns as Xin and the same lambda_in -- for instance the
+ * residual that pawfe_rayleigh_ritz_res leaves of the Ritz pairs it
+ * returns, which a ChFSI iteration filters next.  The output is then
+ * bit-identical to pawfe_cheb_filter's.  R must not overlap Xout.  Other
+ * arguments, workspace and errors as pawfe_cheb_filter; ldr < nvec or a
+ * NULL R gives PAWFE_EINVAL. */
+pawfe_status pawfe_cheb_filter_res(const pawfe_op* op, const void* Xin, int64_t ldx, const void* R,
+                                   int64_t ldr, void* Xout, int64_t ldo, int64_t nvec, int32_t block,
+                                   const double* lambda_in, int32_t degree, double b0, double bW,
+                                   double bU, int32_t prec, void* ws, size_t ws_bytes, void* stream);
+
 /* Bytes of workspace pawfe_rayleigh_ritz needs. */
 pawfe_status pawfe_rayleigh_ritz_workspace(const pawfe_op* op, int64_t nvec, size_t* bytes);
 
@@ -330,6 +344,16 @@ pawfe_status pawfe_rayleigh_ritz_workspace(const pawfe_op* op, int64_t nvec, siz
 pawfe_status pawfe_rayleigh_ritz(const pawfe_op* op, void* X, int64_t ldx, int64_t nvec,
                                  double* lambda, double* resnorm, int32_t sr_prec, void* ws,
                                  size_t ws_bytes, void* stream);
+
+/* Rayleigh-Ritz as pawfe_rayleigh_ritz, also writing the residual of the
+ * rotated pairs, R = H X - S X Lambda (the columns whose 2-norms are
+ * resnorm), into R: device FP64 [ndof][ldr] (complex operators:
+ * complex128), caller-owned, not overlapping X.  pawfe_cheb_filter_res then
+ * takes it as the filter's step 2.  ldr < nvec or a NULL R gives
+ * PAWFE_EINVAL; otherwise as pawfe_rayleigh_ritz. */
+pawfe_status pawfe_rayleigh_ritz_res(const pawfe_op* op, void* X, int64_t ldx, int64_t nvec,
+                                     double* lambda, double* resnorm, void* R, int64_t ldr,
+                                     int32_t sr_prec, void* ws, size_t ws_bytes, void* stream);
 
 /* Band energy E = sum_n occ_n x_n^H H x_n and its gradient (the density and
  * projector contractions of the FE governing equations):

@@ -200,9 +200,9 @@ size_t filter_ws_bytes(const pawfe_op* op, int64_t B, int32_t prec) {
 }
 
 template <typename TR>
-pawfe_status filter_block(const pawfe_op* op, const double* X, int64_t ldx, double* Xo, int64_t ldo, int nc,
-                          int64_t B, const double* lam_in, int m, double b0, double bW, double bU, Carve cv,
-                          hipStream_t s, bool bf3 = false) {
+pawfe_status filter_block(const pawfe_op* op, const double* X, int64_t ldx, const double* Rin, int64_t ldr,
+                          double* Xo, int64_t ldo, int nc, int64_t B, const double* lam_in, int m, double b0,
+                          double bW, double bU, Carve cv, hipStream_t s, bool bf3 = false) {
   double* Y = cv.take<double>((size_t)op->M * B);
   TR* RX = cv.take<TR>((size_t)op->M * B);
   TR* RY = cv.take<TR>((size_t)op->M * B);
@@ -216,10 +216,17 @@ pawfe_status filter_block(const pawfe_op* op, const double* X, int64_t ldx, doub
   const double e = (bU - bW) / 2.0, c = (bU + bW) / 2.0;
   double zeta = e / (b0 - c);
   const double zeta1 = zeta, gamma = 2.0 / zeta1;
-  // step 2: residual of the input pairs, FP64
-  CHECK(do_residual(op, X, ldx, lam_in, Y, ld, nc, nb, s));
+  // step 2: residual of the input pairs, FP64 (or the caller's)
+  const double* Yr = Y;
+  int64_t ldyr = ld;
+  if (Rin) {
+    Yr = Rin;
+    ldyr = ldr;
+  } else {
+    CHECK(do_residual(op, X, ldx, lam_in, Y, ld, nc, nb, s));
+  }
   // step 3
-  CHECK(launch_cheb_init<TR>(op, Y, ld, RY, RX, ld, zeta1 / e, c, lam_in, lamY, lamX, nc, s));
+  CHECK(launch_cheb_init<TR>(op, Yr, ldyr, RY, RX, ld, zeta1 / e, c, lam_in, lamY, lamX, nc, s));
   // step 4
   for (int theta = 2; theta <= m; ++theta) {
     const double znew = 1.0 / (gamma - zeta);
@@ -230,8 +237,8 @@ pawfe_status filter_block(const pawfe_op* op, const double* X, int64_t ldx, doub
     CHECK(launch_atom_gcorr(op, nb.c, nb.d, nb.t, nc, s));
     CHECK(launch_atom_mul(op, op->d.dH, nullptr, nullptr, a, nb.t, nb.c, nc, s));   // q = a Dh t (into c)
     // T = Sinv_hat R_Y; R_X <- -a c R_Y - zeta zeta' R_X + a C q + a Y Lambda_Y
-    CHECK(launch_node_cheb<TR>(op, RY, RX, Tb, ld, Y, ld, nb.d, nb.c, lamY, lamX, lam_in, a, a * c, zeta * znew,
-                               nc, s));
+    CHECK(launch_node_cheb<TR>(op, RY, RX, Tb, ld, Yr, ldyr, nb.d, nb.c, lamY, lamX, lam_in, a, a * c,
+                               zeta * znew, nc, s));
     // R_X += a H_loc T
     CHECK(launch_cell<TR>(op, kModeH, Tb, ld, RX, ld, nc, nullptr, a, s, bf3));
     std::swap(RX, RY);
@@ -257,9 +264,9 @@ pawfe_status filter_block(const pawfe_op* op, const double* X, int64_t ldx, doub
 //                                                      next step)
 // which is Algorithm 2's step 4 with T = M_D^{-1}(R_Y - C d) never stored.
 template <typename TR>
-pawfe_status filter_block_fused(const pawfe_op* op, const double* X, int64_t ldx, double* Xo, int64_t ldo, int nc,
-                                int64_t B, const double* lam_in, int m, double b0, double bW, double bU, Carve cv,
-                                hipStream_t s) {
+pawfe_status filter_block_fused(const pawfe_op* op, const double* X, int64_t ldx, const double* Rin, int64_t ldr,
+                                double* Xo, int64_t ldo, int nc, int64_t B, const double* lam_in, int m, double b0,
+                                double bW, double bU, Carve cv, hipStream_t s) {
   double* Y = cv.take<double>((size_t)op->M * B);
   TR* RX = cv.take<TR>((size_t)op->M * B);
   TR* RY = cv.take<TR>((size_t)op->M * B);
@@ -277,10 +284,17 @@ pawfe_status filter_block_fused(const pawfe_op* op, const double* X, int64_t ldx
   const double e = (bU - bW) / 2.0, c = (bU + bW) / 2.0;
   double zeta = e / (b0 - c);
   const double zeta1 = zeta, gamma = 2.0 / zeta1;
-  // step 2: residual of the input pairs, FP64
-  CHECK(do_residual(op, X, ldx, lam_in, Y, ld, nc, nb, s));
+  // step 2: residual of the input pairs, FP64 (or the caller's)
+  const double* Yr = Y;
+  int64_t ldyr = ld;
+  if (Rin) {
+    Yr = Rin;
+    ldyr = ldr;
+  } else {
+    CHECK(do_residual(op, X, ldx, lam_in, Y, ld, nc, nb, s));
+  }
   // step 3
-  CHECK(launch_cheb_init<TR>(op, Y, ld, RY, RX, ld, zeta1 / e, c, lam_in, lamY, lamX, nc, s));
+  CHECK(launch_cheb_init<TR>(op, Yr, ldyr, RY, RX, ld, zeta1 / e, c, lam_in, lamY, lamX, nc, s));
   // step 4
   double* dk = nb.d;
   bool first = true;
@@ -300,7 +314,7 @@ pawfe_status filter_block_fused(const pawfe_op* op, const double* X, int64_t ldx
     CHECK(launch_step_combine(op, nb.c, dk, first ? nullptr : dprev, first ? nullptr : nwp, nb.t, nwn, lamX, lamY,
                               lam_in, a, a * c, zz, nc, s));
     CHECK(launch_node_fixup<TR>(op, nb.t, -1.0, nc, RY, ld, s));
-    CHECK(launch_cell_step<TR>(op, RY, RX, ld, Y, ld, lamY, a, a * c, zz, nc, s));
+    CHECK(launch_cell_step<TR>(op, RY, RX, ld, Yr, ldyr, lamY, a, a * c, zz, nc, s));
     std::swap(RX, RY);
     std::swap(lamX, lamY);
     std::swap(dk, dprev);
@@ -992,9 +1006,12 @@ pawfe_status pawfe_cheb_filter_workspace(const pawfe_op* op, int64_t nvec, int32
   return PAWFE_OK;
 }
 
-pawfe_status pawfe_cheb_filter(const pawfe_op* op, const void* Xin, int64_t ldx, void* Xout, int64_t ldo,
-                               int64_t nvec, int32_t block, const double* lambda_in, int32_t degree, double b0,
-                               double bW, double bU, int32_t prec, void* ws, size_t ws_bytes, void* stream) {
+// the filter; R (ldr) is the caller's FP64 residual H X - S X Lambda of
+// the input columns, or NULL to form it (step 2 of Algorithm 2)
+static pawfe_status cheb_filter_impl(const pawfe_op* op, const void* Xin, int64_t ldx, const double* R, int64_t ldr,
+                                     void* Xout, int64_t ldo, int64_t nvec, int32_t block, const double* lambda_in,
+                                     int32_t degree, double b0, double bW, double bU, int32_t prec, void* ws,
+                                     size_t ws_bytes, void* stream) {
   if (!op) return fail(PAWFE_EINVAL, "op is NULL");
   if (!Xin || !Xout || !lambda_in || !ws) return fail(PAWFE_EINVAL, "NULL buffer");
   if (nvec < 1 || block < 1) return fail(PAWFE_EINVAL, "nvec and block must be >= 1");
@@ -1032,6 +1049,7 @@ pawfe_status pawfe_cheb_filter(const pawfe_op* op, const void* Xin, int64_t ldx,
     hipStream_t sb = nconc > 1 ? bstream[k] : s;
     Carve cv((char*)ws + (size_t)k * one, one);
     const double* X = (const double*)Xin + j0 * cf;
+    const double* Rb = R ? R + j0 * cf : nullptr;
     double* Xo = (double*)Xout + j0 * cf;
     const double* lam = lambda_in + j0;
     pawfe_status st = PAWFE_OK;
@@ -1042,16 +1060,17 @@ pawfe_status pawfe_cheb_filter(const pawfe_op* op, const void* Xin, int64_t ldx,
     }
     if (st != PAWFE_OK) {
     } else if (fused_step(op, prec)) {
-      st = prec == PAWFE_FP64 ? filter_block_fused<double>(op, X, ldx * cf, Xo, ldo * cf, (int)(nc * cf), B * cf, lam,
-                                                           degree, b0, bW, bU, cv, sb)
-                              : filter_block_fused<float>(op, X, ldx * cf, Xo, ldo * cf, (int)(nc * cf), B * cf, lam,
-                                                          degree, b0, bW, bU, cv, sb);
+      st = prec == PAWFE_FP64
+               ? filter_block_fused<double>(op, X, ldx * cf, Rb, ldr * cf, Xo, ldo * cf, (int)(nc * cf), B * cf, lam,
+                                            degree, b0, bW, bU, cv, sb)
+               : filter_block_fused<float>(op, X, ldx * cf, Rb, ldr * cf, Xo, ldo * cf, (int)(nc * cf), B * cf, lam,
+                                           degree, b0, bW, bU, cv, sb);
     } else if (prec == PAWFE_FP64) {
-      st = filter_block<double>(op, X, ldx * cf, Xo, ldo * cf, (int)(nc * cf), B * cf, lam, degree, b0, bW, bU, cv,
-                                sb);
+      st = filter_block<double>(op, X, ldx * cf, Rb, ldr * cf, Xo, ldo * cf, (int)(nc * cf), B * cf, lam, degree, b0,
+                                bW, bU, cv, sb);
     } else {
-      st = filter_block<float>(op, X, ldx * cf, Xo, ldo * cf, (int)(nc * cf), B * cf, lam, degree, b0, bW, bU, cv,
-                               sb, prec == PAWFE_BF16X3);
+      st = filter_block<float>(op, X, ldx * cf, Rb, ldr * cf, Xo, ldo * cf, (int)(nc * cf), B * cf, lam, degree, b0,
+                               bW, bU, cv, sb, prec == PAWFE_BF16X3);
     }
     if (st != PAWFE_OK) {
       if (nconc > 1)   // still join, so `s` never runs ahead of work already enqueued
@@ -1068,6 +1087,24 @@ pawfe_status pawfe_cheb_filter(const pawfe_op* op, const void* Xin, int64_t ldx,
       PAWFE_HIP(hipStreamWaitEvent(s, mop->fevent[1 + q], 0));
     }
   return PAWFE_OK;
+}
+
+pawfe_status pawfe_cheb_filter(const pawfe_op* op, const void* Xin, int64_t ldx, void* Xout, int64_t ldo,
+                               int64_t nvec, int32_t block, const double* lambda_in, int32_t degree, double b0,
+                               double bW, double bU, int32_t prec, void* ws, size_t ws_bytes, void* stream) {
+  return cheb_filter_impl(op, Xin, ldx, nullptr, 0, Xout, ldo, nvec, block, lambda_in, degree, b0, bW, bU, prec, ws,
+                          ws_bytes, stream);
+}
+
+pawfe_status pawfe_cheb_filter_res(const pawfe_op* op, const void* Xin, int64_t ldx, const void* R, int64_t ldr,
+                                   void* Xout, int64_t ldo, int64_t nvec, int32_t block, const double* lambda_in,
+                                   int32_t degree, double b0, double bW, double bU, int32_t prec, void* ws,
+                                   size_t ws_bytes, void* stream) {
+  if (!R) return fail(PAWFE_EINVAL, "R is NULL");
+  if (ldr < nvec) return fail(PAWFE_EINVAL, "leading dimension of R smaller than nvec");
+  if (R == Xout) return fail(PAWFE_EINVAL, "R must not be the output");
+  return cheb_filter_impl(op, Xin, ldx, (const double*)R, ldr, Xout, ldo, nvec, block, lambda_in, degree, b0, bW, bU,
+                          prec, ws, ws_bytes, stream);
 }
 
 // ---- Rayleigh-Ritz ------------------------------------------------------------
@@ -1092,8 +1129,11 @@ pawfe_status pawfe_rayleigh_ritz_workspace(const pawfe_op* op, int64_t nvec, siz
   return PAWFE_OK;
 }
 
-pawfe_status pawfe_rayleigh_ritz(const pawfe_op* cop, void* Xv, int64_t ldx, int64_t N, double* lambda,
-                                 double* resnorm, int32_t sr_prec, void* ws, size_t ws_bytes, void* stream) {
+// Rayleigh-Ritz; R (ldr), when not NULL, receives the FP64 residual
+// H x - lambda S x of the rotated columns (the blocks whose norms are taken)
+static pawfe_status rayleigh_ritz_impl(const pawfe_op* cop, void* Xv, int64_t ldx, int64_t N, double* lambda,
+                                       double* resnorm, double* R, int64_t ldr, int32_t sr_prec, void* ws,
+                                       size_t ws_bytes, void* stream) {
   if (!cop) return fail(PAWFE_EINVAL, "op is NULL");
   if (!Xv || !lambda || !resnorm || !ws) return fail(PAWFE_EINVAL, "NULL buffer");
   if (N < 1 || ldx < N) return fail(PAWFE_EINVAL, "bad nvec / ldx");
@@ -1109,6 +1149,7 @@ pawfe_status pawfe_rayleigh_ritz(const pawfe_op* cop, void* Xv, int64_t ldx, int
   if (op->cplx) {
     N *= 2;
     ldx *= 2;
+    ldr *= 2;
   }
   const int64_t B = std::min<int64_t>(256, N);
   Carve cv(ws, ws_bytes);
@@ -1277,8 +1318,10 @@ pawfe_status pawfe_rayleigh_ritz(const pawfe_op* cop, void* Xv, int64_t ldx, int
   double* sq = op->cplx ? lam2 + N : nullptr;
   for (int64_t j0 = 0; j0 < N; j0 += B) {
     const int nc = (int)std::min<int64_t>(B, N - j0);
-    CHECK(do_residual(op, X + j0, ldx, (op->cplx ? lam2 : lambda) + j0, HXb, nc, nc, nb, s));
-    CHECK(launch_coldot(HXb, nc, HXb, nc, op->M, nc, npart_buf, (op->cplx ? sq : resnorm) + j0, nullptr,
+    double* Rb = R ? R + j0 : HXb;
+    const int64_t ldb = R ? ldr : nc;
+    CHECK(do_residual(op, X + j0, ldx, (op->cplx ? lam2 : lambda) + j0, Rb, ldb, nc, nb, s));
+    CHECK(launch_coldot(Rb, ldb, Rb, ldb, op->M, nc, npart_buf, (op->cplx ? sq : resnorm) + j0, nullptr,
                         !op->cplx, false, s));
   }
   if (op->cplx) {
@@ -1286,6 +1329,20 @@ pawfe_status pawfe_rayleigh_ritz(const pawfe_op* cop, void* Xv, int64_t ldx, int
     PAWFE_HIP(hipGetLastError());
   }
   return PAWFE_OK;
+}
+
+pawfe_status pawfe_rayleigh_ritz(const pawfe_op* op, void* X, int64_t ldx, int64_t nvec, double* lambda,
+                                 double* resnorm, int32_t sr_prec, void* ws, size_t ws_bytes, void* stream) {
+  return rayleigh_ritz_impl(op, X, ldx, nvec, lambda, resnorm, nullptr, 0, sr_prec, ws, ws_bytes, stream);
+}
+
+pawfe_status pawfe_rayleigh_ritz_res(const pawfe_op* op, void* X, int64_t ldx, int64_t nvec, double* lambda,
+                                     double* resnorm, void* R, int64_t ldr, int32_t sr_prec, void* ws,
+                                     size_t ws_bytes, void* stream) {
+  if (!R) return fail(PAWFE_EINVAL, "R is NULL");
+  if (ldr < nvec) return fail(PAWFE_EINVAL, "leading dimension of R smaller than nvec");
+  if (R == X) return fail(PAWFE_EINVAL, "R must not be X");
+  return rayleigh_ritz_impl(op, X, ldx, nvec, lambda, resnorm, (double*)R, ldr, sr_prec, ws, ws_bytes, stream);
 }
 
 // ---- band energy gradient ----------------------------------------------------

@@ -28,8 +28,8 @@ EXPORTS = [
     "pawfe_set_veff", "pawfe_set_vgga", "pawfe_set_dH", "pawfe_apply_H", "pawfe_apply_S", "pawfe_apply_Sinv",
     "pawfe_apply_local",
     "pawfe_cheb_step_local",
-    "pawfe_cheb_filter_workspace", "pawfe_cheb_filter", "pawfe_rayleigh_ritz_workspace",
-    "pawfe_rayleigh_ritz", "pawfe_band_energy_grad", "pawfe_lanczos_bounds", "pawfe_last_error",
+    "pawfe_cheb_filter_workspace", "pawfe_cheb_filter", "pawfe_cheb_filter_res", "pawfe_rayleigh_ritz_workspace",
+    "pawfe_rayleigh_ritz", "pawfe_rayleigh_ritz_res", "pawfe_band_energy_grad", "pawfe_lanczos_bounds", "pawfe_last_error",
     "pawfe_chfsi_solve_workspace", "pawfe_chfsi_solve",
     "pawfe_batch_create", "pawfe_batch_run", "pawfe_batch_query", "pawfe_batch_destroy",
     "pawfe_apply_H_noalloc", "pawfe_halo_pack_bf16", "pawfe_halo_unpack_bf16",
@@ -105,8 +105,10 @@ def load(path=LIB_PATH):
         "pawfe_cheb_step_local": [vp, vp, vp, i64, vp, i64, vp, dbl, dbl, dbl, i64, i32, vp],
         "pawfe_cheb_filter_workspace": [vp, i64, i32, i32, P(sz)],
         "pawfe_cheb_filter": [vp, vp, i64, vp, i64, i64, i32, vp, i32, dbl, dbl, dbl, i32, vp, sz, vp],
+        "pawfe_cheb_filter_res": [vp, vp, i64, vp, i64, vp, i64, i64, i32, vp, i32, dbl, dbl, dbl, i32, vp, sz, vp],
         "pawfe_rayleigh_ritz_workspace": [vp, i64, P(sz)],
         "pawfe_rayleigh_ritz": [vp, vp, i64, i64, vp, vp, i32, vp, sz, vp],
+        "pawfe_rayleigh_ritz_res": [vp, vp, i64, i64, vp, vp, vp, i64, i32, vp, sz, vp],
         "pawfe_band_energy_grad": [vp, vp, i64, i64, vp, vp, vp, vp, vp],
         "pawfe_lanczos_bounds": [vp, i32, C.c_uint64, P(dbl), P(dbl), P(dbl), vp],
         "pawfe_chfsi_solve_workspace": [vp, i64, i32, i32, P(sz)],
@@ -342,7 +344,10 @@ class Operator:
         return torch.empty(nbytes, dtype=torch.uint8, device=device)
 
     def cheb_filter(self, X, lam, degree, b0, bW, bU, block=None, prec=FP64, out=None, ws=None,
-                    stream=None):
+                    stream=None, R=None):
+        """R: the residual H X - S X diag(lam) of the input pairs, as
+        rayleigh_ritz(..., R=...) leaves it (pawfe_cheb_filter_res), or None
+        to form it here."""
         assert X.is_cuda and X.dtype == self._dtype(FP64) and X.stride(1) == 1
         import torch
         n = X.shape[1]
@@ -352,9 +357,16 @@ class Operator:
         if ws is None:
             ws = self.workspace(self.cheb_filter_workspace(n, block, prec), X.device)
         lam = lam.to(device=X.device, dtype=torch.float64).contiguous()
-        _check(_lib.pawfe_cheb_filter(self._h, _tptr(X), X.stride(0), _tptr(out), out.stride(0), n, block,
-                                      _tptr(lam), int(degree), float(b0), float(bW), float(bU),
-                                      _PREC[prec], _tptr(ws), ws.numel(), _stream(stream)))
+        if R is None:
+            _check(_lib.pawfe_cheb_filter(self._h, _tptr(X), X.stride(0), _tptr(out), out.stride(0), n, block,
+                                          _tptr(lam), int(degree), float(b0), float(bW), float(bU),
+                                          _PREC[prec], _tptr(ws), ws.numel(), _stream(stream)))
+        else:
+            assert R.is_cuda and R.dtype == X.dtype and R.stride(1) == 1 and R.shape == X.shape
+            _check(_lib.pawfe_cheb_filter_res(self._h, _tptr(X), X.stride(0), _tptr(R), R.stride(0), _tptr(out),
+                                              out.stride(0), n, block, _tptr(lam), int(degree), float(b0),
+                                              float(bW), float(bU), _PREC[prec], _tptr(ws), ws.numel(),
+                                              _stream(stream)))
         return out
 
     def rayleigh_ritz_workspace(self, nvec):
@@ -362,9 +374,11 @@ class Operator:
         _check(_lib.pawfe_rayleigh_ritz_workspace(self._h, nvec, C.byref(b)))
         return b.value
 
-    def rayleigh_ritz(self, X, ws=None, stream=None, sr_prec=FP64):
+    def rayleigh_ritz(self, X, ws=None, stream=None, sr_prec=FP64, R=None):
         """In place on X; returns (lambda, resnorm) as device tensors.
-        sr_prec=FP32: mixed-precision subspace rotation."""
+        sr_prec=FP32: mixed-precision subspace rotation.  R (same shape and
+        type as X): receives the residual H X - S X diag(lambda) of the
+        rotated pairs (pawfe_rayleigh_ritz_res), for cheb_filter(..., R=R)."""
         import torch
         assert X.is_cuda and X.dtype == self._dtype(FP64) and X.stride(1) == 1
         n = X.shape[1]
@@ -372,8 +386,14 @@ class Operator:
         res = torch.empty(n, dtype=torch.float64, device=X.device)
         if ws is None:
             ws = self.workspace(self.rayleigh_ritz_workspace(n), X.device)
-        _check(_lib.pawfe_rayleigh_ritz(self._h, _tptr(X), X.stride(0), n, _tptr(lam), _tptr(res),
-                                        _PREC[sr_prec], _tptr(ws), ws.numel(), _stream(stream)))
+        if R is None:
+            _check(_lib.pawfe_rayleigh_ritz(self._h, _tptr(X), X.stride(0), n, _tptr(lam), _tptr(res),
+                                            _PREC[sr_prec], _tptr(ws), ws.numel(), _stream(stream)))
+        else:
+            assert R.is_cuda and R.dtype == X.dtype and R.stride(1) == 1 and R.shape == X.shape
+            _check(_lib.pawfe_rayleigh_ritz_res(self._h, _tptr(X), X.stride(0), n, _tptr(lam), _tptr(res),
+                                                _tptr(R), R.stride(0), _PREC[sr_prec], _tptr(ws), ws.numel(),
+                                                _stream(stream)))
         return lam, res
 
     def band_energy_grad(self, X, occ=None, want_E=True, want_dV=True, want_dH=True, stream=None):
