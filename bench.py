@@ -499,10 +499,10 @@ def main():
     torch.cuda.synchronize()
     log("initial Rayleigh-Ritz done")
 
-    def filt(Xc, lamc, prec):
+    def filt(Xc, lamc, prec, out=None, R=None):
         lc = lamc.cpu().numpy()
         return op.cheb_filter(Xc, lamc, m, float(lc[0]), float(lc[-1]), bU, block=B, prec=prec,
-                              out=Xc, ws=ws_f)
+                              out=Xc if out is None else out, ws=ws_f, R=R)
 
     # --- precision check: three ChFSI iterations (filter + FP64 Rayleigh-Ritz)
     # in FP64, FP32 and bf16x3 from the same Rayleigh-Ritz start; per
@@ -532,19 +532,24 @@ def main():
     eig_err = max(r["eig_err_vs_fp64_ha"] for r in precision["fp32"])
     del traj
 
-    # --- warmup and timed steps: mixed filter pass + FP64 RR ---
+    # --- warmup and timed steps: mixed filter pass + FP64 RR, as a ChFSI
+    # iteration runs them: Rayleigh-Ritz keeps the residual of the Ritz pairs
+    # it forms for the residual norms, and the next filter pass starts from it
+    # (step 2 of Algorithm 2 is not formed twice) ---
+    Rres = torch.empty_like(X)
+    lam, res = op.rayleigh_ritz(X, ws=ws_r, R=Rres)
     for _ in range(args.warmup):
-        filt(X, lam, FP32)
-        lam, res = op.rayleigh_ritz(X, ws=ws_r)
+        filt(X, lam, FP32, R=Rres)
+        lam, res = op.rayleigh_ritz(X, ws=ws_r, R=Rres)
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
            torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     t_wall = time.perf_counter()
     for k in range(args.steps):
         ev[k][0].record()
-        filt(X, lam, FP32)
+        filt(X, lam, FP32, R=Rres)
         ev[k][1].record()
-        lam, res = op.rayleigh_ritz(X, ws=ws_r)
+        lam, res = op.rayleigh_ritz(X, ws=ws_r, R=Rres)
         ev[k][2].record()
         log(f"step {k}: done")
     torch.cuda.synchronize()
@@ -567,28 +572,36 @@ def main():
     log(f"Rayleigh-Ritz with mixed-precision rotation {t_rr_mixed:.3f} s (FP64 rotation {t_rr:.3f} s); "
         f"wanted residual norms change by at most {sr_res_change:.2e} (relative)")
 
-    # --- FP64 filter pass timing (same work) ---
-    t_filter64 = None
-    if not args.skip_fp64:
+    # --- FP64 and bf16x3 filter passes (same work, from the same Ritz pairs
+    # and handed-over residual, into a separate output), and the mixed and
+    # FP64 passes that form the residual themselves (Algorithm 2 as a
+    # stand-alone call) ---
+    Xout = torch.empty_like(X)
+
+    def timed_pass(prec, R, reps):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         times = []
-        for k in range(args.steps):
+        for _ in range(reps):
             e0.record()
-            filt(X, lam, FP64)
+            filt(X, lam, prec, out=Xout, R=R)
             e1.record()
             torch.cuda.synchronize()
             times.append(e0.elapsed_time(e1) / 1e3)
-        t_filter64 = float(np.mean(times))
-        log(f"FP64 filter pass {t_filter64:.3f} s, mixed {t_filter:.3f} s")
+        return float(np.mean(times))
+
+    t_filter64 = t_filter64_own = None
+    if not args.skip_fp64:
+        t_filter64 = timed_pass(FP64, Rres, args.steps)
+        t_filter64_own = timed_pass(FP64, None, 1)
+        log(f"FP64 filter pass {t_filter64:.3f} s, mixed {t_filter:.3f} s (residual from Rayleigh-Ritz); "
+            f"FP64 {t_filter64_own:.3f} s forming it")
+    t_filter_own = timed_pass(FP32, None, args.steps)
+    log(f"mixed filter pass forming its own residual {t_filter_own:.3f} s")
 
     # --- bf16x3 filter pass timing (cell contractions as bf16x3 split products) ---
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    filt(X, lam, BF16X3)
-    e1.record()
-    torch.cuda.synchronize()
-    t_filter_bf3 = e0.elapsed_time(e1) / 1e3
+    t_filter_bf3 = timed_pass(BF16X3, Rres, 1)
     log(f"bf16x3 filter pass {t_filter_bf3:.3f} s")
+    del Xout
 
     # --- dominant kernel: cell-local operator (K + V) on one 256-column block ---
     cd, col, sco, sc, sno, sn = op.dofmap()
@@ -725,12 +738,15 @@ def main():
             "workload": f"{s.name}: periodic {s.ncell[0]}x{s.ncell[1]}x{s.ncell[2]} cells, degree "
                         f"{s.degree} ({M} DOFs), nq={s.nq}, {len(s.pos)} atoms x {int(s.nproj[0])} "
                         f"projectors, N={N}, block={B}, Chebyshev degree {m}",
-            "step": "mixed filter pass over all states + FP64 Rayleigh-Ritz + residual norms",
+            "step": "mixed filter pass over all states + FP64 Rayleigh-Ritz + residual norms; the filter "
+                    "starts from the residual of the Ritz pairs that the previous Rayleigh-Ritz formed",
             "filter_streams": 1 if args.one_stream else 2,
         },
         "filter_fp64_s_per_pass": t_filter64,
         "filter_bf16x3_s_per_pass": t_filter_bf3,
         "speedup_mixed_vs_fp64": (t_filter64 / t_filter) if t_filter64 else None,
+        "filter_mixed_s_per_pass_own_residual": t_filter_own,
+        "filter_fp64_s_per_pass_own_residual": t_filter64_own,
         "rayleigh_ritz_s": t_rr,
         "rayleigh_ritz_mixed_rotation_s": t_rr_mixed,
         "mixed_rotation_resnorm_rel_change": sr_res_change,

@@ -377,7 +377,9 @@ pawfe_status pawfe_lanczos_bounds(const pawfe_op* op, int32_t k, uint64_t seed, 
                                   double* theta_max, double* beta_k, void* stream);
 
 /* Bytes of workspace pawfe_chfsi_solve needs: the larger of the filter's
- * (two block states when nvec > block) and Rayleigh-Ritz's. */
+ * (two block states when nvec > block) and Rayleigh-Ritz's, plus the FP64
+ * residual of the Ritz pairs (ndof x nvec, complex operators twice that)
+ * that each Rayleigh-Ritz hands to the next filter pass. */
 pawfe_status pawfe_chfsi_solve_workspace(const pawfe_op* op, int64_t nvec, int32_t block, int32_t prec,
                                          size_t* bytes);
 
@@ -387,9 +389,11 @@ pawfe_status pawfe_chfsi_solve_workspace(const pawfe_op* op, int64_t nvec, int32
  * lanczos_k steps, seed 1234); Rayleigh-Ritz of the start X; then, while
  * the largest residual norm of the lowest nwanted Ritz pairs (all when
  * nwanted = 0) exceeds tol and fewer than max_iter passes have run: one
- * pawfe_cheb_filter pass in place (degree, block, prec; b_0 and b_W the
- * lowest and highest current Ritz values, lambda_in the Ritz values) and
- * one FP64 pawfe_rayleigh_ritz.  X device FP64 [ndof][ldx] (complex
+ * filter pass in place (degree, block, prec; b_0 and b_W the lowest and
+ * highest current Ritz values, lambda_in the Ritz values), started from the
+ * residual the last Rayleigh-Ritz formed (pawfe_cheb_filter_res), and one
+ * FP64 Rayleigh-Ritz (pawfe_rayleigh_ritz_res).  The ws pointer must be
+ * 256-byte aligned.  X device FP64 [ndof][ldx] (complex
  * operators: complex columns), replaced by the Ritz vectors; lambda and
  * resnorm device FP64 [nvec] (the last Rayleigh-Ritz); *iterations (host,
  * may be NULL) receives the number of filter passes.  Not reaching tol

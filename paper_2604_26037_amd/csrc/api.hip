@@ -1488,7 +1488,9 @@ pawfe_status pawfe_chfsi_solve_workspace(const pawfe_op* op, int64_t nvec, int32
   size_t f = 0, r = 0;
   CHECK(pawfe_cheb_filter_workspace(op, nvec, block, prec, &f));
   CHECK(pawfe_rayleigh_ritz_workspace(op, nvec, &r));
-  *bytes = std::max(f, r);   // the filter and Rayleigh-Ritz never overlap
+  // the filter and Rayleigh-Ritz never overlap; after their shared part, the
+  // residual Rayleigh-Ritz hands to the next filter pass
+  *bytes = align256(std::max(f, r)) + align256((size_t)op->M * nvec * (op->cplx ? 2 : 1) * 8);
   return PAWFE_OK;
 }
 
@@ -1506,6 +1508,11 @@ pawfe_status pawfe_chfsi_solve(const pawfe_op* op, void* X, int64_t ldx, int64_t
   size_t need = 0;
   CHECK(pawfe_chfsi_solve_workspace(op, nvec, block, prec, &need));
   if (ws_bytes < need) return fail(PAWFE_EINVAL, "workspace too small");
+  if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(PAWFE_EINVAL, "workspace must be 256-byte aligned");
+  // shared part of the filter and Rayleigh-Ritz, then the residual R of the
+  // Ritz pairs (written by each Rayleigh-Ritz, step 2 of the next filter)
+  const size_t shared = need - align256((size_t)op->M * nvec * (op->cplx ? 2 : 1) * 8);
+  void* R = (char*)ws + shared;
   const int64_t nw = nwanted > 0 ? nwanted : nvec;
   // step 1 of Algorithm 1: the upper bound of the spectrum (given, or Lanczos)
   if (!(bU > 0.0)) {
@@ -1522,15 +1529,16 @@ pawfe_status pawfe_chfsi_solve(const pawfe_op* op, void* X, int64_t ldx, int64_t
     return PAWFE_OK;
   };
   auto worst = [&]() { return *std::max_element(rh.begin(), rh.begin() + nw); };
-  CHECK(pawfe_rayleigh_ritz(op, X, ldx, nvec, lambda, resnorm, PAWFE_FP64, ws, ws_bytes, stream));
+  CHECK(pawfe_rayleigh_ritz_res(op, X, ldx, nvec, lambda, resnorm, R, nvec, PAWFE_FP64, ws, shared, stream));
   CHECK(fetch());
   int32_t it = 0;
   while (worst() > tol && it < max_iter) {
     // b_0, b_W: lowest and highest current Ritz values (lambda stays the
-    // filter's eigenvalue estimate; the filter runs in place)
-    CHECK(pawfe_cheb_filter(op, X, ldx, X, ldx, nvec, block, lambda, degree, lh.front(), lh.back(), bU, prec, ws,
-                            ws_bytes, stream));
-    CHECK(pawfe_rayleigh_ritz(op, X, ldx, nvec, lambda, resnorm, PAWFE_FP64, ws, ws_bytes, stream));
+    // filter's eigenvalue estimate; the filter runs in place, from the
+    // residual the last Rayleigh-Ritz left)
+    CHECK(pawfe_cheb_filter_res(op, X, ldx, R, nvec, X, ldx, nvec, block, lambda, degree, lh.front(), lh.back(), bU,
+                                prec, ws, shared, stream));
+    CHECK(pawfe_rayleigh_ritz_res(op, X, ldx, nvec, lambda, resnorm, R, nvec, PAWFE_FP64, ws, shared, stream));
     CHECK(fetch());
     ++it;
   }
