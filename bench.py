@@ -557,8 +557,12 @@ def main():
     t_filter = float(np.mean([a.elapsed_time(b) for a, b, _ in ev])) / 1e3
     t_rr = float(np.mean([b.elapsed_time(c) for _, b, c in ev])) / 1e3
 
-    # --- Rayleigh-Ritz with the mixed-precision subspace rotation, same input ---
+    # --- Rayleigh-Ritz with the mixed-precision subspace rotation, same input
+    # (one untimed call first: the first FP32 GEMM loads its kernels) ---
     Xm = X.clone()
+    op.rayleigh_ritz(Xm, ws=ws_r, sr_prec=FP32)
+    Xm.copy_(X)
+    torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     lam_m, res_m = op.rayleigh_ritz(Xm, ws=ws_r, sr_prec=FP32)

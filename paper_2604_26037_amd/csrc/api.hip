@@ -432,7 +432,8 @@ __global__ void k_pair_norm(int N, const double* __restrict__ sq, double* __rest
 // ld N) and Q32 = fl32(Q) with the diagonal blocks (1x1, or the 2x2 blocks
 // of a complex entry in the realified form) set to zero (column-major, ld N).
 __global__ void k_sr_prep(int64_t M, int N, int bs, const double* __restrict__ X, int64_t ldx,
-                          float* __restrict__ X32, const double* __restrict__ Q, float* __restrict__ Q32) {
+                          float* __restrict__ X32, const double* __restrict__ Q, float* __restrict__ Q32,
+                          double* __restrict__ Qd) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nx = M * N;
   if (t < nx) {
@@ -442,15 +443,19 @@ __global__ void k_sr_prep(int64_t M, int N, int bs, const double* __restrict__ X
   } else if (t < nx + (int64_t)N * N) {
     const int64_t u = t - nx;
     const int c = (int)(u / N), r = (int)(u - (int64_t)c * N);
-    Q32[u] = (r / bs == c / bs) ? 0.0f : (float)Q[u];
+    const bool diag = r / bs == c / bs;
+    Q32[u] = diag ? 0.0f : (float)Q[u];
+    if (diag) Qd[(int64_t)c * bs + r % bs] = Q[u];   // the diagonal blocks, compact
   }
 }
 
-// X <- X diag(Q) + Y32 (FP64), diag(Q) the diagonal blocks of Q (column-major,
-// ld N); one thread per row and diagonal block, so the in-place update reads
-// the block's inputs before it writes.
+// X <- X diag(Q) + Y32 (FP64), diag(Q) the diagonal blocks of Q, compact
+// (entry (r, c) of the block of columns j0 .. j0 + bs at Qd[(j0 + c) bs + r],
+// so neighbouring lanes read neighbouring entries); one thread per row and
+// diagonal block, so the in-place update reads the block's inputs before it
+// writes.
 __global__ void k_sr_combine(int64_t M, int N, int bs, double* __restrict__ X, int64_t ldx,
-                             const float* __restrict__ Y32, const double* __restrict__ Q) {
+                             const float* __restrict__ Y32, const double* __restrict__ Qd) {
   const int nb = N / bs;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= M * nb) return;
@@ -460,7 +465,7 @@ __global__ void k_sr_combine(int64_t M, int N, int bs, double* __restrict__ X, i
   for (int r = 0; r < bs; ++r) x[r] = X[i * ldx + j0 + r];
   for (int c = 0; c < bs; ++c) {
     double v = (double)Y32[i * N + j0 + c];
-    for (int r = 0; r < bs; ++r) v += x[r] * Q[(int64_t)(j0 + c) * N + j0 + r];
+    for (int r = 0; r < bs; ++r) v += x[r] * Qd[(int64_t)(j0 + c) * bs + r];
     o[c] = v;
   }
   for (int c = 0; c < bs; ++c) X[i * ldx + j0 + c] = o[c];
@@ -1293,9 +1298,12 @@ static pawfe_status rayleigh_ritz_impl(const pawfe_op* cop, void* Xv, int64_t ld
     float* X32 = reinterpret_cast<float*>(Xr);
     float* Y32 = X32 + (size_t)K * N;
     float* Q32 = reinterpret_cast<float*>(Sp);
+    // the compact diagonal blocks (N bs doubles) in the split-K buffer, past
+    // the complex path's lam2 and squared norms (N^2 + 2 N doubles in)
+    double* Qd = part + N * N + 2 * N;
     const int64_t nprep = K * N + N * N;
     hipLaunchKernelGGL(k_sr_prep, dim3((unsigned)((nprep + 255) / 256)), dim3(256), 0, s, K, (int)N, bs, X, ldx,
-                       X32, Hp, Q32);
+                       X32, Hp, Q32, Qd);
     const float onef = 1.0f, zerof = 0.0f;
     if (rocblas_sgemm(h, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)N, (rocblas_int)K,
                       (rocblas_int)N, &onef, Q32, (rocblas_int)N, X32, (rocblas_int)N, &zerof, Y32,
@@ -1303,7 +1311,7 @@ static pawfe_status rayleigh_ritz_impl(const pawfe_op* cop, void* Xv, int64_t ld
       return fail(PAWFE_EHIP, "rocblas_sgemm (rotation) failed");
     const int64_t ncomb = K * (N / bs);
     hipLaunchKernelGGL(k_sr_combine, dim3((unsigned)((ncomb + 255) / 256)), dim3(256), 0, s, K, (int)N, bs, X, ldx,
-                       Y32, Hp);
+                       Y32, Qd);
     PAWFE_HIP(hipGetLastError());
   } else {
     // Xr = X Q: column-major, Xr^T (N x K) = Q^T (N x N) X^T (N x K)
